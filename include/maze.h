@@ -1,0 +1,225 @@
+/*
+ * maze.h -- C ABI of libmaze.so, the MI355X (gfx950) implementation of the
+ * Poisson MaZe per-timestep hot path:
+ *
+ *   charge assignment onto a periodic grid  ->  PLCG solve of the SHAKE
+ *   constraint system, warm-started from the previous step  ->  force
+ *   interpolation back onto the ions.
+ *
+ * Paper: Troni, Grassano, Narayan, Roux, Bonella, "Mass-Zero constrained
+ * molecular dynamics for electrostatic interactions", arXiv 2505.20418.
+ *
+ * Common conventions
+ *  - Units are Gaussian inside: charge in e, length in A, potential in e/A.
+ *    `coulomb_k` scales every energy and force (1.0 -> e^2/A and e^2/A^2,
+ *    14.3996454784 -> eV and eV/A).
+ *  - Cubic periodic box of side `box`. N = lround(box / grid_spacing) grid
+ *    points per side, effective spacing h = box / N (Section 2, equation
+ *    "linearproblem"). Grid point (i, j, k) sits at (i h, j h, k h); grids
+ *    are N*N*N contiguous doubles, index (i*N + j)*N + k (z fastest).
+ *  - Positions are n*3 contiguous doubles (x, y, z per ion); positions may
+ *    lie outside [0, box) and are wrapped periodically. Forces use the same
+ *    layout.
+ *  - Every pointer argument named *_dev is DEVICE memory on the current HIP
+ *    device (e.g. torch.Tensor.data_ptr()); the caller owns it and keeps it
+ *    alive until the call returns. Host pointers are named explicitly.
+ *  - Work is queued on cfg.stream (NULL = the default stream). Each solve
+ *    polls its convergence flag from the host, so the step entry points
+ *    return once the solver has converged; the remaining kernels (field
+ *    update, force interpolation) may still be running on the stream. A
+ *    non-NULL maze_stats* makes the call synchronise the stream before it
+ *    returns.
+ *  - A session is not thread safe; different sessions are independent.
+ *  - Return codes: MAZE_OK; MAZE_NOT_CONVERGED (> 0, a warning: outputs
+ *    were written and the state advanced); negative = error, nothing was
+ *    written and the state is unchanged.
+ */
+#ifndef MAZE_H
+#define MAZE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MAZE_ABI_VERSION 1
+
+typedef struct maze_session maze_session;
+
+enum {
+  MAZE_OK = 0,
+  MAZE_NOT_CONVERGED = 1,   /* max_iter reached or CG breakdown */
+  MAZE_E_INVALID = -1,      /* bad argument, config or buffer */
+  MAZE_E_NOT_NEUTRAL = -2,  /* |sum Q| > 1e-10 sum |Q| */
+  MAZE_E_OOM = -3,          /* device allocation failed */
+  MAZE_E_DEVICE = -4,       /* HIP runtime error */
+  MAZE_E_NONFINITE = -5     /* NaN or Inf in the positions */
+};
+
+enum { MAZE_FP64 = 0, MAZE_MIXED = 1 };
+enum { MAZE_GUESS_ZERO = 0, MAZE_GUESS_STATIC = 1, MAZE_GUESS_TIMEPROP = 2 };
+enum { MAZE_NORM_REL2 = 0, MAZE_NORM_ABSMAX = 1 };
+
+typedef struct {
+  int32_t n_ions;         /* > 0 */
+  int32_t order;          /* assignment order: 2 = linear weights on the 8
+                             nearest grid points (default), 4 = centred
+                             cubic B-spline on 64 points */
+  double  box;            /* L [A], > 0 */
+  double  grid_spacing;   /* requested h [A]; 4 <= lround(L/h) <= 1024 */
+  double  tol;            /* stopping tolerance, > 0. MAZE_NORM_REL2:
+                             ||M y - sigma_p||_2 <= tol ||q||_2 for a step
+                             (identical to the Poisson relative residual
+                             ||M phi + 4 pi q/h|| / ||4 pi q/h||);
+                             MAZE_NORM_ABSMAX: max|residual| <= tol */
+  int32_t max_iter;       /* CG iteration cap per solve (>= 0) */
+  int32_t precision;      /* MAZE_FP64 or MAZE_MIXED (FP32 stencil and
+                             vectors, FP64 dots, norms, projection and an
+                             outer refinement on the FP64 residual) */
+  int32_t residual_norm;  /* MAZE_NORM_REL2 or MAZE_NORM_ABSMAX */
+  int32_t flags;          /* reserved, must be 0 */
+  double  coulomb_k;      /* energy/force scale, > 0 */
+  void*   stream;         /* hipStream_t or NULL */
+} maze_config;
+
+typedef struct {
+  int32_t grid_n;         /* N */
+  int32_t iters;          /* CG iterations (sum over refinements) */
+  int32_t refinements;    /* outer FP64 refinements (mixed), else 0 */
+  int32_t converged;      /* 1 if the stopping test was met */
+  double  h;              /* effective grid spacing */
+  double  rel_residual;   /* true ||residual||_2 / ||rhs scale||_2, FP64 */
+  double  max_abs_residual;
+  double  net_charge;     /* sum of the assigned grid charge before the
+                             zero-mode projection */
+  double  energy;         /* (1/2) k phi.q, equation "energy_discr" */
+} maze_stats;
+
+/* Library version of this header's ABI. */
+int maze_abi_version(void);
+
+/* Human-readable text of a status code (static storage). */
+const char* maze_strerror(int status);
+
+/* Device bytes a session with this config allocates (for admission by HBM
+ * budget). Returns 0 for an invalid config. */
+size_t maze_device_bytes(const maze_config* cfg);
+
+/* Creates a session: validates cfg, copies the charges (fixed for the
+ * session's lifetime), allocates every device buffer (the only allocation
+ * of the session), assigns the charges of pos0 and performs a cold Poisson
+ * solve from zero for phi^0 (the paper's pseudocode figure is not
+ * available; this reading also sets phi^{-1} = phi^0 and y = 0).
+ * charges_dev: n_ions doubles; pos0_dev: n_ions*3 doubles.
+ * On success *out holds the session (free with maze_destroy). Errors:
+ * MAZE_E_INVALID, MAZE_E_NOT_NEUTRAL, MAZE_E_NONFINITE, MAZE_E_OOM,
+ * MAZE_E_DEVICE; *out is NULL then. */
+int maze_init(const maze_config* cfg, const double* charges_dev,
+              const double* pos0_dev, maze_session** out, maze_stats* st);
+
+/* One MaZe step k -> k+1 (Section 2, equations "SHAKE", "SHAKEy" and
+ * "SHAKEPhiFinal"; Appendix B for the Jacobi PLCG):
+ *   q       = charge assigned from pos_dev (positions r^{k+1}), projected
+ *             to zero mean
+ *   phi_p   = 2 phi^k - phi^{k-1}
+ *   sigma_p = (h / 4 pi) M phi_p + q
+ *   M y     = sigma_p  by Jacobi PLCG from y* of the previous step
+ *   phi^{k+1} = phi_p - (4 pi / h) y*   (mean-zero gauge)
+ *   forces  = equation "F_nostra": -k Q_a sum_n W(r_a - r_n) (D phi)_n with
+ *             central differences
+ *   energy  = (1/2) k phi^{k+1} . q
+ * field_dev (N^3 doubles) and energy_dev (1 double) may be NULL;
+ * forces_dev (n_ions*3 doubles) may be NULL. */
+int maze_step(maze_session* s, const double* pos_dev, double* field_dev,
+              double* forces_dev, double* energy_dev, maze_stats* st);
+
+/* Direct Poisson solve of equation "linearproblem" for the charge of
+ * pos_dev, from the guess named by `guess` (zero, "static" phi^k, or
+ * "time-propagated" 2 phi^k - phi^{k-1}; convergence subsection). The MaZe
+ * history (phi^k, phi^{k-1}, y*) is left untouched. Outputs as maze_step. */
+int maze_solve(maze_session* s, int guess, const double* pos_dev,
+               double* field_dev, double* forces_dev, double* energy_dev,
+               maze_stats* st);
+
+/* Advances `count` independent sessions by one step each, with the CG
+ * iterations of all of them issued together (one launch per CG pass covers
+ * every unconverged session). All sessions must share the precision mode
+ * and stream of sessions[0]. Per-session semantics and outputs are those
+ * of maze_step; pos_dev[i], forces_dev[i] belong to session i;
+ * energies_dev (count doubles) and st (count entries) may be NULL. The
+ * return value is the most severe status over the sessions. */
+int maze_step_batch(maze_session* const* sessions, int32_t count,
+                    const double* const* pos_dev, double* const* forces_dev,
+                    double* energies_dev, maze_stats* st);
+
+/* Grid side N of a session (0 for NULL). */
+int maze_grid_n(const maze_session* s);
+
+/* Debug/inspection copy of one internal grid (N^3 doubles) into out_dev:
+ * which = 0 phi^k, 1 phi^{k-1}, 2 y*, 3 q (projected), 4 sigma_p. */
+int maze_get_grid(const maze_session* s, int which, double* out_dev);
+
+/* Checkpoint of the warm-start state (phi^k, phi^{k-1}, y*, step count and
+ * config) into a HOST buffer of maze_state_bytes() bytes. maze_load checks
+ * the header (MAZE_E_INVALID on mismatch or a short buffer). */
+size_t maze_state_bytes(const maze_session* s);
+int maze_save(const maze_session* s, void* host_buf, size_t bytes);
+int maze_load(maze_session* s, const void* host_buf, size_t bytes);
+
+/* Pass timing for measurement. When enabled, the runtime brackets every
+ * CG pass with HIP events on the session stream and accumulates the
+ * durations of the passes of iterations that did work (at most 4096 per
+ * solve). maze_profile_read copies 8 doubles into out8 (HOST memory):
+ * {FP64 pass-A launches, their total ms, FP64 pass-B launches, total ms,
+ *  FP32 pass-A launches, total ms, FP32 pass-B launches, total ms}
+ * and resets them. Enabling creates the events (the only allocation outside
+ * maze_init). */
+int maze_profile_enable(maze_session* s, int on);
+int maze_profile_read(maze_session* s, double* out8);
+
+/* Frees every device buffer of the session (NULL is a no-op). */
+void maze_destroy(maze_session* s);
+
+/* ---- molecular-dynamics driver around the step (not part of the
+ * electrostatic path; Section 2 uses velocity Verlet for the ions, the
+ * Results section a Born-Huggins-Mayer short-range term). ---- */
+typedef struct {
+  int32_t n_ions;
+  int32_t pad;
+  double* pos_dev;            /* n*3, updated in place (unwrapped) */
+  double* vel_dev;            /* n*3 [A/fs], updated in place */
+  const double* mass_dev;     /* n [amu] */
+  const int32_t* species_dev; /* n, 0 or 1; pair row = s_i + s_j */
+  double* f_es_dev;           /* n*3 electrostatic force [eV/A] */
+  double* f_sr_dev;           /* n*3 short-range force [eV/A] */
+  double* scratch_dev;        /* 6*n + 8*ceil(n/256) doubles of scratch */
+  double* scalars_dev;        /* 8 doubles: [0] work energy of the
+                                 electrostatic force (trapezoid rule),
+                                 [1] short-range energy, [2] kinetic
+                                 energy, [3..5] total momentum,
+                                 [6] electrostatic energy, [7] unused */
+  double dt;                  /* fs */
+  double accel;               /* (eV/(A amu)) -> A/fs^2 */
+  double cutoff;              /* short-range cutoff [A], <= box/2 */
+  double bmh_table[15];       /* 3 rows (Na-Na, Na-Cl, Cl-Cl) of
+                                 A [eV], B [1/A], s [A], C [eV A^6],
+                                 D [eV A^8]: V = A e^{B(s-r)} - C/r^6 - D/r^8,
+                                 shifted to zero at the cutoff */
+} maze_md_state;
+
+/* Forces at the current positions: runs maze_step on pos (advancing the
+ * MaZe history by one step at fixed positions) and the short-range term,
+ * zeroes the work accumulator and fills the scalars. */
+int maze_md_prime(maze_session* s, const maze_md_state* md, maze_stats* st);
+
+/* One velocity-Verlet step: half kick, drift, maze_step + short range at
+ * the new positions, work update, half kick, kinetic energy and momentum.
+ */
+int maze_md_step(maze_session* s, const maze_md_state* md, maze_stats* st);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MAZE_H */

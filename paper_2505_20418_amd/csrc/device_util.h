@@ -1,0 +1,78 @@
+// Device helpers shared by the HIP kernels: deterministic wavefront and
+// workgroup reductions (fixed shuffle tree, fixed LDS order), partial-slot
+// sums, and the XCD-aware workgroup remapping.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "maze_internal.h"
+
+namespace maze {
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;  // valid in lane 0
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, 64));
+  return v;
+}
+
+// Sum over the 256 threads of a workgroup; every thread gets the result.
+// sm: at least 4 doubles of LDS. Fixed order: shuffle tree per wave, then
+// waves 0..3 in order.
+__device__ __forceinline__ double block_sum(double v, double* sm) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sm[w] = v;
+  __syncthreads();
+  double s = sm[0];
+#pragma unroll
+  for (int i = 1; i < kThreads / 64; ++i) s += sm[i];
+  return s;
+}
+
+__device__ __forceinline__ double block_max(double v, double* sm) {
+  v = wave_max(v);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sm[w] = v;
+  __syncthreads();
+  double s = sm[0];
+#pragma unroll
+  for (int i = 1; i < kThreads / 64; ++i) s = fmax(s, sm[i]);
+  return s;
+}
+
+// Deterministic sum of n partials (each thread a strided subsequence in
+// order, then the fixed workgroup tree). Identical in every workgroup.
+__device__ __forceinline__ double sum_partials(const double* part, int n, double* sm) {
+  double v = 0.0;
+  for (int i = threadIdx.x; i < n; i += kThreads) v += part[i];
+  return block_sum(v, sm);
+}
+
+__device__ __forceinline__ double max_partials(const double* part, int n, double* sm) {
+  double v = 0.0;
+  for (int i = threadIdx.x; i < n; i += kThreads) v = fmax(v, part[i]);
+  return block_max(v, sm);
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs (workgroup b runs on
+// XCD b % 8). Remap so that each XCD receives a contiguous range of logical
+// workgroup ids: neighbouring segments of the same x planes then share one
+// XCD's L2, which serves their overlapping halo rows.
+__device__ __forceinline__ int xcd_remap(int b, int nwg) {
+  constexpr int X = 8;
+  const int q = nwg / X, rem = nwg % X;
+  const int xcd = b % X, i = b / X;
+  return (xcd < rem) ? xcd * (q + 1) + i : rem * (q + 1) + (xcd - rem) * q + i;
+}
+
+__device__ __forceinline__ volatile int32_t* vol(int32_t* p) { return p; }
+
+}  // namespace maze

@@ -1,0 +1,520 @@
+// Particle <-> grid kernels: binning of ions into grid tiles, atomic-free
+// charge assignment, force interpolation, the field update of the MaZe
+// step, and the single-workgroup finalisation of reductions.
+//
+// Charge assignment (Section 2.1, text after equation "F_nostra"):
+// q_n = sum_a Q_a W(r_a - r_n), W the tensor product of 1-D weights of order
+// 2 (linear, 8 points) or 4 (centred cubic B-spline, 64 points).
+//
+// Instead of scattering ion contributions with floating-point atomics, ions
+// are counting-sorted into tiles of 8^3 grid points and each workgroup owns
+// one tile of the grid: it walks the ions of the tiles whose support can
+// reach it, in a fixed order, and every thread sums the contributions to its
+// own grid points. Each grid value is written exactly once, and the sum
+// order (tile order, then ion index) does not depend on scheduling, so the
+// result is bitwise reproducible. Integer atomics only count and place ions;
+// a per-tile sort by ion index makes the order canonical.
+#include "device_util.h"
+
+namespace maze {
+
+// Periodic wrap of one coordinate and its split into a base cell and an
+// offset, computed without FMA contraction so the cell decision is the same
+// FP64 rounding sequence as a plain C implementation: xw = x - L floor(x/L),
+// u = xw / h, i0 = floor(u), t = u - i0.
+__device__ __forceinline__ void cell_of(double x, double box, double h, int N, int* cell,
+                                        double* t) {
+#pragma clang fp contract(off)
+  const double xw = x - box * floor(x / box);
+  const double u = xw / h;
+  const double fl = floor(u);
+  *t = u - fl;
+  long long i0 = (long long)fl % N;
+  if (i0 < 0) i0 += N;
+  *cell = (int)i0;
+}
+
+__device__ __forceinline__ double bspline3(double s) {
+#pragma clang fp contract(off)
+  const double a = fabs(s);
+  if (a < 1.0) return 2.0 / 3.0 - a * a + a * a * a / 2.0;
+  if (a < 2.0) {
+    const double t = 2.0 - a;
+    return t * t * t / 6.0;
+  }
+  return 0.0;
+}
+
+// 1-D weights for the order-p support starting at cell (order 2) or cell-1
+// (order 4).
+__device__ __forceinline__ void axis_weights(int order, double t, double* w) {
+#pragma clang fp contract(off)
+  if (order == 2) {
+    w[0] = 1.0 - t;
+    w[1] = t;
+  } else {
+    w[0] = bspline3(1.0 + t);
+    w[1] = bspline3(t);
+    w[2] = bspline3(1.0 - t);
+    w[3] = bspline3(2.0 - t);
+  }
+}
+
+__device__ __forceinline__ int tile_of(const int* c, int ntx) {
+  return ((c[0] / kTile) * ntx + c[1] / kTile) * ntx + c[2] / kTile;
+}
+
+// ---- binning ----------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void k_bin_ions(const double* __restrict__ pos, int n,
+                                                       double box, double h, int N, int ntx,
+                                                       int32_t* ion_cell, double* ion_t,
+                                                       int32_t* tile_count, Scalars* sc) {
+  const int i = blockIdx.x * kThreads + threadIdx.x;
+  if (i >= n) return;
+  const double x[3] = {pos[3 * i], pos[3 * i + 1], pos[3 * i + 2]};
+  if (!isfinite(x[0]) || !isfinite(x[1]) || !isfinite(x[2])) {
+    sc->err = 1;
+    return;
+  }
+  int c[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    double t;
+    cell_of(x[d], box, h, N, &c[d], &t);
+    ion_cell[3 * i + d] = c[d];
+    ion_t[3 * i + d] = t;
+  }
+  atomicAdd(&tile_count[tile_of(c, ntx)], 1);
+}
+
+// Exclusive scan of the tile counts (one workgroup; each thread scans a
+// contiguous chunk), cursor = start, counts reset to zero for the next step.
+__global__ __launch_bounds__(kThreads) void k_bin_scan(int32_t* tile_count, int32_t* tile_start,
+                                                       int32_t* tile_cursor, int ntiles,
+                                                       const Scalars* sc) {
+  __shared__ int32_t sums[kThreads];
+  if (sc->err) return;
+  const int tid = threadIdx.x;
+  const int per = (ntiles + kThreads - 1) / kThreads;
+  const int b = tid * per, e = min(ntiles, b + per);
+  int32_t s = 0;
+  for (int i = b; i < e; ++i) s += tile_count[i];
+  sums[tid] = s;
+  __syncthreads();
+  if (tid == 0) {
+    int32_t run = 0;
+    for (int k = 0; k < kThreads; ++k) {
+      const int32_t v = sums[k];
+      sums[k] = run;
+      run += v;
+    }
+    tile_start[ntiles] = run;
+  }
+  __syncthreads();
+  int32_t run = sums[tid];
+  for (int i = b; i < e; ++i) {
+    const int32_t v = tile_count[i];
+    tile_start[i] = run;
+    tile_cursor[i] = run;
+    tile_count[i] = 0;
+    run += v;
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_bin_scatter(int n, int ntx, const int32_t* ion_cell,
+                                                          int32_t* tile_cursor, int32_t* sorted_idx,
+                                                          const Scalars* sc) {
+  const int i = blockIdx.x * kThreads + threadIdx.x;
+  if (i >= n || sc->err) return;
+  const int c[3] = {ion_cell[3 * i], ion_cell[3 * i + 1], ion_cell[3 * i + 2]};
+  const int slot = atomicAdd(&tile_cursor[tile_of(c, ntx)], 1);
+  sorted_idx[slot] = i;
+}
+
+// One thread per tile: insertion sort of the tile's ions by index, then the
+// tile-ordered copies of cell, weights and charge used by spread and gather.
+__global__ __launch_bounds__(kThreads) void k_bin_sort(int ntiles, int order,
+                                                       const int32_t* tile_start,
+                                                       int32_t* sorted_idx,
+                                                       const int32_t* ion_cell,
+                                                       const double* ion_t, const double* Q,
+                                                       int32_t* s_cell, double* s_w, double* s_Q,
+                                                       const Scalars* sc) {
+  const int t = blockIdx.x * kThreads + threadIdx.x;
+  if (t >= ntiles || sc->err) return;
+  const int b = tile_start[t], e = tile_start[t + 1];
+  for (int i = b + 1; i < e; ++i) {
+    const int32_t v = sorted_idx[i];
+    int j = i - 1;
+    while (j >= b && sorted_idx[j] > v) {
+      sorted_idx[j + 1] = sorted_idx[j];
+      --j;
+    }
+    sorted_idx[j + 1] = v;
+  }
+  for (int s = b; s < e; ++s) {
+    const int ion = sorted_idx[s];
+    s_Q[s] = Q[ion];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      s_cell[3 * s + d] = ion_cell[3 * ion + d];
+      double w[kMaxOrder];
+      axis_weights(order, ion_t[3 * ion + d], w);
+      for (int m = 0; m < order; ++m) s_w[(3 * s + d) * order + m] = w[m];
+    }
+  }
+}
+
+hipError_t launch_bin(const DeviceState& d, const double* pos, hipStream_t st) {
+  const int nb = (d.n_ions + kThreads - 1) / kThreads;
+  hipLaunchKernelGGL(k_bin_ions, dim3(nb), dim3(kThreads), 0, st, pos, d.n_ions, d.box, d.h,
+                     d.N, d.ntx, d.ion_cell, d.ion_t, d.tile_count, d.sc);
+  hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(kThreads), 0, st, d.tile_count, d.tile_start,
+                     d.tile_cursor, d.ntiles, (const Scalars*)d.sc);
+  hipLaunchKernelGGL(k_bin_scatter, dim3(nb), dim3(kThreads), 0, st, d.n_ions, d.ntx,
+                     d.ion_cell, d.tile_cursor, d.sorted_idx, (const Scalars*)d.sc);
+  const int nt = (d.ntiles + kThreads - 1) / kThreads;
+  hipLaunchKernelGGL(k_bin_sort, dim3(nt), dim3(kThreads), 0, st, d.ntiles, d.order,
+                     d.tile_start, d.sorted_idx, d.ion_cell, d.ion_t, d.Q, d.s_cell, d.s_w,
+                     d.s_Q, (const Scalars*)d.sc);
+  return hipGetLastError();
+}
+
+// ---- charge assignment -------------------------------------------------------
+// Candidate tiles along one axis whose ions can reach grid tile T: ions with
+// base cell c touch points c .. c+1 (order 2) or c-1 .. c+2 (order 4), so
+// the neighbouring tiles below (order 2) or on both sides (order 4).
+__device__ __forceinline__ int candidate_tiles(int T, int ntx, int order, int* out) {
+  int n = 0;
+  const int lo = -1, hi = (order == 2) ? 0 : 1;
+  for (int o = lo; o <= hi; ++o) {
+    int c = T + o;
+    c = (c < 0) ? c + ntx : (c >= ntx ? c - ntx : c);
+    bool dup = false;
+    for (int k = 0; k < n; ++k) dup |= (out[k] == c);
+    if (!dup) out[n++] = c;
+  }
+  // fixed ascending order so the summation order is canonical
+  for (int a = 1; a < n; ++a) {
+    const int v = out[a];
+    int b = a - 1;
+    while (b >= 0 && out[b] > v) {
+      out[b + 1] = out[b];
+      --b;
+    }
+    out[b + 1] = v;
+  }
+  return n;
+}
+
+__global__ __launch_bounds__(kThreads) void k_spread(int N, int ntx, int order,
+                                                     const int32_t* __restrict__ tile_start,
+                                                     const int32_t* __restrict__ s_cell,
+                                                     const double* __restrict__ s_w,
+                                                     const double* __restrict__ s_Q,
+                                                     double* __restrict__ q, double* part,
+                                                     const Scalars* sc) {
+#pragma clang fp contract(off)
+  __shared__ double red[8];
+  if (sc->err) return;
+  const int T = blockIdx.x;
+  const int TX = T / (ntx * ntx), TY = (T / ntx) % ntx, TZ = T % ntx;
+  int cx[3], cy[3], cz[3];
+  const int nx = candidate_tiles(TX, ntx, order, cx);
+  const int ny = candidate_tiles(TY, ntx, order, cy);
+  const int nz = candidate_tiles(TZ, ntx, order, cz);
+  const int off = (order == 2) ? 0 : 1;
+
+  int gp[2][3];
+  bool valid[2];
+  double acc[2] = {0.0, 0.0};
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int pt = threadIdx.x + j * kThreads;
+    gp[j][0] = TX * kTile + (pt >> 6);
+    gp[j][1] = TY * kTile + ((pt >> 3) & 7);
+    gp[j][2] = TZ * kTile + (pt & 7);
+    valid[j] = gp[j][0] < N && gp[j][1] < N && gp[j][2] < N;
+  }
+  for (int a = 0; a < nx; ++a)
+    for (int b = 0; b < ny; ++b)
+      for (int c = 0; c < nz; ++c) {
+        const int ct = (cx[a] * ntx + cy[b]) * ntx + cz[c];
+        const int sb = tile_start[ct], se = tile_start[ct + 1];
+        for (int s = sb; s < se; ++s) {
+          const double Qs = s_Q[s];
+          const int bx = s_cell[3 * s] - off, by = s_cell[3 * s + 1] - off,
+                    bz = s_cell[3 * s + 2] - off;
+          const double* w = s_w + (size_t)3 * s * order;
+#pragma unroll
+          for (int j = 0; j < 2; ++j) {
+            int dx = gp[j][0] - bx, dy = gp[j][1] - by, dz = gp[j][2] - bz;
+            dx = (dx < 0) ? dx + N : (dx >= N ? dx - N : dx);
+            dy = (dy < 0) ? dy + N : (dy >= N ? dy - N : dy);
+            dz = (dz < 0) ? dz + N : (dz >= N ? dz - N : dz);
+            if (dx < order && dy < order && dz < order) {
+              double v = Qs * w[dx];
+              v = v * w[order + dy];
+              v = v * w[2 * order + dz];
+              acc[j] += v;
+            }
+          }
+        }
+      }
+  double local = 0.0;
+#pragma unroll
+  for (int j = 0; j < 2; ++j)
+    if (valid[j]) {
+      q[((long long)gp[j][0] * N + gp[j][1]) * N + gp[j][2]] = acc[j];
+      local += acc[j];
+    }
+  const double tot = block_sum(local, red);
+  if (threadIdx.x == 0) part[T] = tot;
+}
+
+hipError_t launch_spread(const DeviceState& d, hipStream_t st) {
+  hipLaunchKernelGGL(k_spread, dim3(d.ntiles), dim3(kThreads), 0, st, d.N, d.ntx, d.order,
+                     d.tile_start, d.s_cell, d.s_w, d.s_Q, d.q,
+                     d.part + (size_t)SL_QSUM * d.part_stride, (const Scalars*)d.sc);
+  return hipGetLastError();
+}
+
+// ---- force interpolation (equation "F_nostra") --------------------------------
+// One thread per ion in tile order (neighbouring threads read neighbouring
+// grid points); F_a = -k Q_a sum_n W(r_a - r_n) (phi_{n+e} - phi_{n-e}) / 2h.
+__global__ __launch_bounds__(kThreads) void k_gather(int n, int N, int order, double h,
+                                                     double coulomb_k,
+                                                     const int32_t* __restrict__ sorted_idx,
+                                                     const int32_t* __restrict__ s_cell,
+                                                     const double* __restrict__ s_w,
+                                                     const double* __restrict__ s_Q,
+                                                     const double* __restrict__ phi,
+                                                     double* __restrict__ forces,
+                                                     const Scalars* sc) {
+#pragma clang fp contract(off)
+  const int s = blockIdx.x * kThreads + threadIdx.x;
+  if (s >= n || sc->err) return;
+  const int off = (order == 2) ? 0 : 1;
+  int ix[kMaxOrder], iy[kMaxOrder], iz[kMaxOrder];
+  int ixm[kMaxOrder], ixp[kMaxOrder], iym[kMaxOrder], iyp[kMaxOrder], izm[kMaxOrder],
+      izp[kMaxOrder];
+  const double* w = s_w + (size_t)3 * s * order;
+  for (int m = 0; m < order; ++m) {
+    auto wrap = [N](int v) { return v < 0 ? v + N : (v >= N ? v - N : v); };
+    ix[m] = wrap(s_cell[3 * s] - off + m);
+    iy[m] = wrap(s_cell[3 * s + 1] - off + m);
+    iz[m] = wrap(s_cell[3 * s + 2] - off + m);
+    ixm[m] = wrap(ix[m] - 1);
+    ixp[m] = wrap(ix[m] + 1);
+    iym[m] = wrap(iy[m] - 1);
+    iyp[m] = wrap(iy[m] + 1);
+    izm[m] = wrap(iz[m] - 1);
+    izp[m] = wrap(iz[m] + 1);
+  }
+  const long long NN = (long long)N * N;
+  const double two_h = 2.0 * h;
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int a = 0; a < order; ++a)
+    for (int b = 0; b < order; ++b)
+      for (int c = 0; c < order; ++c) {
+        double W = w[a] * w[order + b];
+        W = W * w[2 * order + c];
+        const long long I = ix[a] * NN, J = (long long)iy[b] * N;
+        const double dx = (phi[ixp[a] * NN + J + iz[c]] - phi[ixm[a] * NN + J + iz[c]]) / two_h;
+        const double dy = (phi[I + (long long)iyp[b] * N + iz[c]] -
+                           phi[I + (long long)iym[b] * N + iz[c]]) / two_h;
+        const double dz = (phi[I + J + izp[c]] - phi[I + J + izm[c]]) / two_h;
+        acc[0] += W * dx;
+        acc[1] += W * dy;
+        acc[2] += W * dz;
+      }
+  const int ion = sorted_idx[s];
+  const double kq = -coulomb_k * s_Q[s];
+  forces[3 * ion + 0] = kq * acc[0];
+  forces[3 * ion + 1] = kq * acc[1];
+  forces[3 * ion + 2] = kq * acc[2];
+}
+
+hipError_t launch_gather(const DeviceState& d, const double* phi, double coulomb_k,
+                         double* forces, hipStream_t st) {
+  const int nb = (d.n_ions + kThreads - 1) / kThreads;
+  hipLaunchKernelGGL(k_gather, dim3(nb), dim3(kThreads), 0, st, d.n_ions, d.N, d.order, d.h,
+                     coulomb_k, d.sorted_idx, d.s_cell, d.s_w, d.s_Q, phi, forces,
+                     (const Scalars*)d.sc);
+  return hipGetLastError();
+}
+
+// ---- field update (equation "SHAKEPhiFinal") --------------------------------
+// phi^{k+1} = (phi_p - mean phi_p) - (4 pi / h)(y - mean y), written over
+// phi^{k-1}; y stored projected (warm start of the next step); partials of
+// phi^{k+1} . (q - qbar) for the energy of equation "energy_discr".
+constexpr int kElemPerThread = 4;
+
+__global__ __launch_bounds__(kThreads) void k_update(long long G, const double* __restrict__ phik,
+                                                     double* phikm1, double* y,
+                                                     const double* __restrict__ q,
+                                                     double* field_out, double c4,
+                                                     double* part_e, double* part_s,
+                                                     const Scalars* sc) {
+  __shared__ double red[8];
+  if (sc->err) return;
+  const double pbar = sc->pbar, ybar = sc->xbar, qbar = sc->qbar;
+  double e = 0.0, s = 0.0;
+  const long long base = (long long)blockIdx.x * kThreads * kElemPerThread + threadIdx.x;
+#pragma unroll
+  for (int j = 0; j < kElemPerThread; ++j) {
+    const long long g = base + (long long)j * kThreads;
+    if (g < G) {
+      const double php = 2.0 * phik[g] - phikm1[g];
+      const double yv = y[g] - ybar;
+      const double phn = (php - pbar) - c4 * yv;
+      phikm1[g] = phn;
+      y[g] = yv;
+      if (field_out) field_out[g] = phn;
+      e += phn * (q[g] - qbar);
+      s += phn;
+    }
+  }
+  const double te = block_sum(e, red);
+  const double ts = block_sum(s, red);
+  if (threadIdx.x == 0) {
+    part_e[blockIdx.x] = te;
+    part_s[blockIdx.x] = ts;
+  }
+}
+
+int update_blocks(long long G) {
+  return (int)((G + (long long)kThreads * kElemPerThread - 1) / ((long long)kThreads * kElemPerThread));
+}
+
+hipError_t launch_update(const DeviceState& d, double* field_out, hipStream_t st) {
+  hipLaunchKernelGGL(k_update, dim3(update_blocks(d.G)), dim3(kThreads), 0, st, d.G,
+                     (const double*)d.phi_cur, d.phi_prev, d.y, (const double*)d.q, field_out,
+                     4.0 * M_PI / d.h, d.part + (size_t)SL_ENERGY * d.part_stride,
+                     d.part + (size_t)SL_PHISUM * d.part_stride, (const Scalars*)d.sc);
+  return hipGetLastError();
+}
+
+// Direct solve: x -= mean(x); optional field copy; energy partials.
+__global__ __launch_bounds__(kThreads) void k_project(long long G, double* x,
+                                                      const double* __restrict__ q,
+                                                      double* field_out, double* part_e,
+                                                      double* part_s, const Scalars* sc) {
+  __shared__ double red[8];
+  if (sc->err) return;
+  const double xbar = sc->xbar, qbar = sc->qbar;
+  double e = 0.0, s = 0.0;
+  const long long base = (long long)blockIdx.x * kThreads * kElemPerThread + threadIdx.x;
+#pragma unroll
+  for (int j = 0; j < kElemPerThread; ++j) {
+    const long long g = base + (long long)j * kThreads;
+    if (g < G) {
+      const double v = x[g] - xbar;
+      x[g] = v;
+      if (field_out) field_out[g] = v;
+      e += v * (q[g] - qbar);
+      s += v;
+    }
+  }
+  const double te = block_sum(e, red);
+  const double ts = block_sum(s, red);
+  if (threadIdx.x == 0) {
+    part_e[blockIdx.x] = te;
+    part_s[blockIdx.x] = ts;
+  }
+}
+
+hipError_t launch_project(const DeviceState& d, double* x, double* field_out, hipStream_t st) {
+  hipLaunchKernelGGL(k_project, dim3(update_blocks(d.G)), dim3(kThreads), 0, st, d.G, x,
+                     (const double*)d.q, field_out, d.part + (size_t)SL_ENERGY * d.part_stride,
+                     d.part + (size_t)SL_PHISUM * d.part_stride, (const Scalars*)d.sc);
+  return hipGetLastError();
+}
+
+// ---- finalisation of reductions (one workgroup) ------------------------------
+__global__ __launch_bounds__(kThreads) void k_finalize(int mode, int count, long long G,
+                                                       double tol, double param,
+                                                       double coulomb_k, const double* part,
+                                                       int pstride, Scalars* sc,
+                                                       double* energy_out, int imax, int norm) {
+  __shared__ double red[8];
+  auto slot = [&](int s) { return part + (size_t)s * pstride; };
+  if (mode == FIN_QSUM) {
+    const double s = sum_partials(slot(SL_QSUM), count, red);
+    if (threadIdx.x == 0) {
+      sc->qsum = s;
+      sc->qbar = s / (double)G;
+    }
+  } else if (mode == FIN_SOLVE_START) {
+    const double qq = sum_partials(slot(SL_QQ), count, red);
+    const double pp = sum_partials(slot(SL_PHIP), count, red);
+    const double trr = sum_partials(slot(SL_TRR), count, red);
+    const double tmx = max_partials(slot(SL_TMAX), count, red);
+    if (threadIdx.x == 0) {
+      sc->norm = norm;
+      sc->max_iter = imax;
+      sc->qnorm = sqrt(qq);
+      sc->thr = (norm == MAZE_NORM_ABSMAX) ? tol : tol * sqrt(qq);
+      sc->pbar = pp / (double)G;
+      sc->true_rr = trr;
+      sc->true_max = tmx;
+      sc->it = 0;
+      sc->done = 0;
+      sc->iters = 0;
+    }
+  } else if (mode == FIN_SOLVE_END) {
+    const double xs = sum_partials(slot(SL_XSUM), count, red);
+    const double trr = sum_partials(slot(SL_TRR), count, red);
+    const double tmx = max_partials(slot(SL_TMAX), count, red);
+    if (threadIdx.x == 0) {
+      sc->xbar = xs / (double)G;
+      sc->true_rr = trr;
+      sc->true_max = tmx;
+    }
+  } else if (mode == FIN_ENERGY) {
+    if (sc->err) return;
+    const double e = sum_partials(slot(SL_ENERGY), count, red);
+    if (threadIdx.x == 0) {
+      sc->energy = 0.5 * coulomb_k * e;
+      if (energy_out) *energy_out = 0.5 * coulomb_k * e;
+    }
+  } else if (mode == FIN_INNER_START) {
+    if (threadIdx.x == 0) {
+      sc->thr = param;
+      sc->max_iter = imax;
+      sc->it = 0;
+      sc->done = 0;
+      sc->iters = 0;
+    }
+  }
+}
+
+hipError_t launch_finalize(const DeviceState& d, int mode, int count, double tol,
+                           double param, double coulomb_k, double* energy_out, int imax,
+                           int norm, hipStream_t st) {
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), 0, st, mode, count, d.G, tol, param,
+                     coulomb_k, (const double*)d.part, d.part_stride, d.sc, energy_out, imax,
+                     norm);
+  return hipGetLastError();
+}
+
+// Mixed precision: x += e (FP64 accumulation of the FP32 correction).
+__global__ __launch_bounds__(kThreads) void k_add_correction(long long G, double* x,
+                                                             const float* __restrict__ e,
+                                                             const Scalars* sc) {
+  if (sc->err) return;
+  const long long base = (long long)blockIdx.x * kThreads * kElemPerThread + threadIdx.x;
+#pragma unroll
+  for (int j = 0; j < kElemPerThread; ++j) {
+    const long long g = base + (long long)j * kThreads;
+    if (g < G) x[g] += (double)e[g];
+  }
+}
+
+hipError_t launch_add_correction(const DeviceState& d, double* x, hipStream_t st) {
+  hipLaunchKernelGGL(k_add_correction, dim3(update_blocks(d.G)), dim3(kThreads), 0, st, d.G, x,
+                     (const float*)d.e32, (const Scalars*)d.sc);
+  return hipGetLastError();
+}
+
+}  // namespace maze

@@ -1,0 +1,631 @@
+// Stencil passes of the PLCG solve of M y = sigma_p (and of the direct
+// Poisson solve M phi = -4 pi q / h): right-hand sides, the two fused CG
+// passes, the FP64 residual of the mixed-precision refinement, and the
+// true residual. All of them sweep the grid with one marching template.
+//
+// Layout: grids are N^3, index (x*N + y)*N + z, z fastest. A workgroup owns
+// a segment of S = 256*PPT consecutive points of the flattened (y, z) plane
+// and a run of cx consecutive x planes. It walks its planes in x order:
+//   - the x neighbours of a point are the same segment in planes x-1 and
+//     x+1, kept in registers (prev / cur / next);
+//   - the y and z neighbours come from an LDS copy of the plane's segment
+//     extended by one full row (N points) on each side, so every y+-1 and
+//     periodic z+-1 neighbour of the segment is in LDS;
+//   - plane x+2 is loaded while plane x is computed (double-buffered LDS,
+//     one barrier per plane).
+// All global accesses are z-fastest rows: consecutive lanes touch
+// consecutive addresses. Nothing here is a dense contraction, so there is
+// no MFMA; the passes are bound by HBM bandwidth.
+//
+// Reductions: every thread accumulates in FP64 in registers, the workgroup
+// reduces with a fixed shuffle/LDS tree, and one partial per workgroup goes
+// to a slot of the partial table. The next kernel sums the slot in a fixed
+// order (identically in every workgroup). No atomics anywhere, so results
+// are bitwise reproducible.
+#include "device_util.h"
+
+namespace maze {
+
+MarchGeom make_march_geom(int N, int ppt, int cx) {
+  MarchGeom g;
+  g.N = N;
+  g.P = (long long)N * N;
+  g.ppt = ppt;
+  g.S = kThreads * ppt;
+  g.nseg = (int)((g.P + g.S - 1) / g.S);
+  g.cx = cx < 1 ? 1 : (cx > N ? N : cx);
+  g.nchunk = (N + g.cx - 1) / g.cx;
+  g.nwg = g.nseg * g.nchunk;
+  g.nh = (2 * N + kThreads - 1) / kThreads;
+  return g;
+}
+
+// ---------------------------------------------------------------------------
+// The marching template.
+// Op supplies: T (LDS element type), K (staged fields), NACC (accumulators),
+//   skip(), prepare(sm) -> bool, load(g, T[K]), point(g, c, xm, xp, ym, yp,
+//   zm, zp, acc), acc_is_max(i), acc_slot(i), finish_wg0().
+// ---------------------------------------------------------------------------
+template <int PPT, int NH, class Op>
+__global__ __launch_bounds__(kThreads) void march_kernel(Op op, MarchGeom g) {
+  using T = typename Op::T;
+  constexpr int K = Op::K;
+  constexpr int NA = Op::NACC;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ double red[8];
+  if (op.skip()) return;
+  if (!op.prepare(red)) return;
+
+  const int tid = threadIdx.x;
+  const int N = g.N;
+  const long long P = g.P;
+  const int S = g.S;
+  const int E = S + 2 * N;
+  const int L = xcd_remap(blockIdx.x, g.nwg);
+  const int seg = L % g.nseg;
+  const int chunk = L / g.nseg;
+  const long long s0 = (long long)seg * S;
+  const int x0 = chunk * g.cx;
+  const int x1 = min(N, x0 + g.cx);
+  T* lds = reinterpret_cast<T*>(smem_raw);
+#define LDSAT(buf, f, e) lds[((buf) * K + (f)) * E + (e)]
+
+  long long fl[PPT];
+  bool valid[PPT];
+  int ezm[PPT], ezp[PPT];
+#pragma unroll
+  for (int j = 0; j < PPT; ++j) {
+    const long long f = s0 + tid + (long long)j * kThreads;
+    valid[j] = f < P;
+    const long long fw = valid[j] ? f : (f % P);
+    fl[j] = fw;
+    const int z = (int)(fw % N);
+    const int e = N + tid + j * kThreads;
+    ezm[j] = (z == 0) ? e + N - 1 : e - 1;
+    ezp[j] = (z == N - 1) ? e - N + 1 : e + 1;
+  }
+  long long hg[NH];
+  int he[NH];
+  bool hv[NH];
+#pragma unroll
+  for (int k = 0; k < NH; ++k) {
+    const int hh = tid + k * kThreads;
+    hv[k] = hh < 2 * N;
+    const int e = (hh < N) ? hh : (S + hh);
+    he[k] = e;
+    long long gi = (s0 - N + e) % P;
+    if (gi < 0) gi += P;
+    hg[k] = gi;
+  }
+
+  T prv[PPT][K], cur[PPT][K], nxt[PPT][K];
+  double acc[NA];
+#pragma unroll
+  for (int i = 0; i < NA; ++i) acc[i] = 0.0;
+
+  auto pbase = [&](int x) -> long long {
+    x = (x < 0) ? x + N : ((x >= N) ? x - N : x);
+    return (long long)x * P;
+  };
+
+  // prologue: centre of plane x0-1; plane x0 staged in buffer 0; plane x0+1
+  // centre (staged in buffer 1 if it is computed by this workgroup)
+  {
+    const long long b = pbase(x0 - 1);
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) op.load(b + fl[j], prv[j]);
+  }
+  {
+    const long long b = pbase(x0);
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+      op.load(b + fl[j], cur[j]);
+#pragma unroll
+      for (int f = 0; f < K; ++f) LDSAT(0, f, N + tid + j * kThreads) = cur[j][f];
+    }
+#pragma unroll
+    for (int k = 0; k < NH; ++k)
+      if (hv[k]) {
+        T v[K];
+        op.load(b + hg[k], v);
+#pragma unroll
+        for (int f = 0; f < K; ++f) LDSAT(0, f, he[k]) = v[f];
+      }
+  }
+  {
+    const long long b = pbase(x0 + 1);
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) op.load(b + fl[j], nxt[j]);
+    if (x0 + 1 < x1) {
+#pragma unroll
+      for (int j = 0; j < PPT; ++j)
+#pragma unroll
+        for (int f = 0; f < K; ++f) LDSAT(1, f, N + tid + j * kThreads) = nxt[j][f];
+#pragma unroll
+      for (int k = 0; k < NH; ++k)
+        if (hv[k]) {
+          T v[K];
+          op.load(b + hg[k], v);
+#pragma unroll
+          for (int f = 0; f < K; ++f) LDSAT(1, f, he[k]) = v[f];
+        }
+    }
+  }
+  __syncthreads();
+
+  for (int x = x0; x < x1; ++x) {
+    const int buf = (x - x0) & 1;
+    const bool need_c = (x + 2 <= x1);
+    const bool need_h = (x + 2 < x1);
+    T lc[PPT][K];
+    T lh[NH][K];
+    if (need_c) {
+      const long long b = pbase(x + 2);
+#pragma unroll
+      for (int j = 0; j < PPT; ++j) op.load(b + fl[j], lc[j]);
+      if (need_h) {
+#pragma unroll
+        for (int k = 0; k < NH; ++k)
+          if (hv[k]) op.load(b + hg[k], lh[k]);
+      }
+    }
+    const long long bx = (long long)x * P;
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+      if (valid[j]) {
+        const int e = N + tid + j * kThreads;
+        T ym[K], yp[K], zm[K], zp[K];
+#pragma unroll
+        for (int f = 0; f < K; ++f) {
+          ym[f] = LDSAT(buf, f, e - N);
+          yp[f] = LDSAT(buf, f, e + N);
+          zm[f] = LDSAT(buf, f, ezm[j]);
+          zp[f] = LDSAT(buf, f, ezp[j]);
+        }
+        op.point(bx + fl[j], cur[j], prv[j], nxt[j], ym, yp, zm, zp, acc);
+      }
+    }
+    __syncthreads();
+    if (need_h) {
+#pragma unroll
+      for (int j = 0; j < PPT; ++j)
+#pragma unroll
+        for (int f = 0; f < K; ++f) LDSAT(buf, f, N + tid + j * kThreads) = lc[j][f];
+#pragma unroll
+      for (int k = 0; k < NH; ++k)
+        if (hv[k]) {
+#pragma unroll
+          for (int f = 0; f < K; ++f) LDSAT(buf, f, he[k]) = lh[k][f];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < PPT; ++j)
+#pragma unroll
+      for (int f = 0; f < K; ++f) {
+        prv[j][f] = cur[j][f];
+        cur[j][f] = nxt[j][f];
+        if (need_c) nxt[j][f] = lc[j][f];
+      }
+  }
+#undef LDSAT
+
+  // workgroup reduction of each accumulator into its partial slot
+#pragma unroll
+  for (int i = 0; i < NA; ++i) {
+    const double v = Op::acc_is_max(i) ? block_max(acc[i], red) : block_sum(acc[i], red);
+    if (tid == 0) op.part[(long long)Op::acc_slot(i, op.parity) * op.pstride + L] = v;
+  }
+  if (blockIdx.x == 0 && tid == 0) op.finish_wg0();
+}
+
+// Sum of the six axis neighbours, paired by axis (fixed order).
+template <typename T>
+__device__ __forceinline__ T nbr_sum(T xm, T xp, T ym, T yp, T zm, T zp) {
+  return ((xm + xp) + (ym + yp)) + (zm + zp);
+}
+
+// ---------------------------------------------------------------------------
+// Right-hand side of the SHAKE system (Section 2, equations "SHAKE" and
+// "SHAKEy"): phi_p = 2 phi^k - phi^{k-1}, sigma_p = (h/4pi) M phi_p + (q - qbar),
+// first residual r = M y - sigma_p. Staged fields: phi_p and y.
+// ---------------------------------------------------------------------------
+template <bool MIXED>
+struct OpRhsMaze {
+  using T = double;
+  static constexpr int K = 2;
+  static constexpr int NACC = MIXED ? 7 : 5;
+  const double* phik;
+  const double* phikm1;
+  const double* y;
+  const double* q;
+  double* sigma;
+  double* r;
+  float* r32;
+  double* part;
+  int pstride;
+  int parity;
+  const Scalars* sc;
+  double c1;    // h / (4 pi)
+  double qbar;
+
+  __device__ bool skip() const { return sc->err != 0; }
+  __device__ bool prepare(double*) {
+    qbar = sc->qbar;
+    return true;
+  }
+  __device__ void load(long long g, double v[2]) const {
+    v[0] = 2.0 * phik[g] - phikm1[g];
+    v[1] = y[g];
+  }
+  __device__ void point(long long g, const double* c, const double* xm, const double* xp,
+                        const double* ym, const double* yp, const double* zm,
+                        const double* zp, double* a) const {
+    const double mphi = nbr_sum(xm[0], xp[0], ym[0], yp[0], zm[0], zp[0]) - 6.0 * c[0];
+    const double my = nbr_sum(xm[1], xp[1], ym[1], yp[1], zm[1], zp[1]) - 6.0 * c[1];
+    const double qv = q[g] - qbar;
+    const double s = c1 * mphi + qv;
+    sigma[g] = s;
+    const double rv = my - s;
+    a[0] += c[0];
+    a[1] += qv * qv;
+    a[4] += c[1];
+    if (MIXED) {
+      const float rf = (float)rv;
+      r32[g] = rf;
+      a[2] += (double)rf * (double)rf;
+      a[3] = fmax(a[3], fabs((double)rf));
+      a[5] += rv * rv;
+      a[6] = fmax(a[6], fabs(rv));
+    } else {
+      r[g] = rv;
+      a[2] += rv * rv;
+      a[3] = fmax(a[3], fabs(rv));
+    }
+  }
+  __device__ static bool acc_is_max(int i) { return i == 3 || i == 6; }
+  __device__ static int acc_slot(int i, int) {
+    const int s[7] = {SL_PHIP, SL_QQ, SL_RR0, SL_RMAX0, SL_XSUM, SL_TRR, SL_TMAX};
+    return s[i];
+  }
+  __device__ void finish_wg0() const {}
+};
+
+// ---------------------------------------------------------------------------
+// Right-hand side of the direct Poisson solve (equation "linearproblem"):
+// s = -(4 pi / h)(q - qbar), start vector x0 = 0, phi^k or 2 phi^k - phi^{k-1}
+// (convergence subsection), first residual r = M x0 - s. x0 is written to x.
+// ---------------------------------------------------------------------------
+template <bool MIXED>
+struct OpRhsPoisson {
+  using T = double;
+  static constexpr int K = 1;
+  static constexpr int NACC = MIXED ? 7 : 5;
+  const double* phik;
+  const double* phikm1;
+  const double* q;
+  double* sigma;
+  double* x;
+  double* r;
+  float* r32;
+  double* part;
+  int pstride;
+  int parity;
+  const Scalars* sc;
+  int guess;
+  double c4;    // -(4 pi / h)
+  double qbar;
+
+  __device__ bool skip() const { return sc->err != 0; }
+  __device__ bool prepare(double*) {
+    qbar = sc->qbar;
+    return true;
+  }
+  __device__ void load(long long g, double v[1]) const {
+    v[0] = (guess == MAZE_GUESS_ZERO) ? 0.0
+         : (guess == MAZE_GUESS_STATIC) ? phik[g] : 2.0 * phik[g] - phikm1[g];
+  }
+  __device__ void point(long long g, const double* c, const double* xm, const double* xp,
+                        const double* ym, const double* yp, const double* zm,
+                        const double* zp, double* a) const {
+    const double mx = nbr_sum(xm[0], xp[0], ym[0], yp[0], zm[0], zp[0]) - 6.0 * c[0];
+    const double s = c4 * (q[g] - qbar);
+    sigma[g] = s;
+    x[g] = c[0];
+    const double rv = mx - s;
+    a[0] += c[0];
+    a[1] += s * s;
+    a[4] += c[0];
+    if (MIXED) {
+      const float rf = (float)rv;
+      r32[g] = rf;
+      a[2] += (double)rf * (double)rf;
+      a[3] = fmax(a[3], fabs((double)rf));
+      a[5] += rv * rv;
+      a[6] = fmax(a[6], fabs(rv));
+    } else {
+      r[g] = rv;
+      a[2] += rv * rv;
+      a[3] = fmax(a[3], fabs(rv));
+    }
+  }
+  __device__ static bool acc_is_max(int i) { return i == 3 || i == 6; }
+  __device__ static int acc_slot(int i, int) {
+    const int s[7] = {SL_PHIP, SL_QQ, SL_RR0, SL_RMAX0, SL_XSUM, SL_TRR, SL_TMAX};
+    return s[i];
+  }
+  __device__ void finish_wg0() const {}
+};
+
+// ---------------------------------------------------------------------------
+// CG pass A (Appendix B, Jacobi PLCG with preconditioner diag(-M) = 6 I):
+// convergence test on ||r||, z = r/6, beta = rho_t / rho_{t-1},
+// p = z + beta p_old, and <p, A p> with A = -M evaluated on the fly.
+// Staged field: p (computed from r and p_old at load time).
+// ---------------------------------------------------------------------------
+template <typename TT>
+struct OpPassA {
+  using T = TT;
+  static constexpr int K = 1;
+  static constexpr int NACC = 1;
+  const T* r;
+  const T* pold;
+  T* p;
+  double* part;
+  int pstride;
+  int parity;
+  int nwg;
+  Scalars* sc;
+  T beta;
+  bool first;
+
+  __device__ bool skip() const { return sc->done != 0 || sc->err != 0; }
+  __device__ bool prepare(double* sm) {
+    const double gam = sum_partials(part + (long long)(SL_RR0 + parity) * pstride, nwg, sm);
+    bool conv;
+    if (sc->norm == MAZE_NORM_ABSMAX)
+      conv = max_partials(part + (long long)(SL_RMAX0 + parity) * pstride, nwg, sm) <= sc->thr;
+    else
+      conv = sqrt(gam) <= sc->thr;
+    const int it = sc->it;
+    const bool finite = isfinite(gam);
+    if (conv || !finite || it >= sc->max_iter) {
+      if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc->gamma[parity] = gam;
+        sc->iters = it;
+        sc->done = conv ? 1 : (finite ? 3 : 2);
+      }
+      return false;
+    }
+    first = (it == 0);
+    beta = first ? (T)0 : (T)(gam / sc->gamma[parity ^ 1]);
+    if (blockIdx.x == 0 && threadIdx.x == 0) sc->gamma[parity] = gam;
+    return true;
+  }
+  __device__ void load(long long g, T v[1]) const {
+    const T z = r[g] * (T)(1.0 / 6.0);
+    v[0] = first ? z : z + beta * pold[g];
+  }
+  __device__ void point(long long g, const T* c, const T* xm, const T* xp, const T* ym,
+                        const T* yp, const T* zm, const T* zp, double* a) const {
+    const T ap = (T)6 * c[0] - nbr_sum(xm[0], xp[0], ym[0], yp[0], zm[0], zp[0]);
+    p[g] = c[0];
+    a[0] += (double)c[0] * (double)ap;
+  }
+  __device__ static bool acc_is_max(int) { return false; }
+  __device__ static int acc_slot(int, int) { return SL_PAP; }
+  __device__ void finish_wg0() const {}
+};
+
+// ---------------------------------------------------------------------------
+// CG pass B: alpha = rho / <p, A p>, x += alpha p, r -= alpha A p (A p
+// recomputed from the staged p), ||r||^2, max |r|, sum x. On the first
+// iteration of an FP32 inner solve the correction starts from zero.
+// ---------------------------------------------------------------------------
+template <typename TT>
+struct OpPassB {
+  using T = TT;
+  static constexpr int K = 1;
+  static constexpr int NACC = 3;
+  const T* p;
+  T* x;
+  T* r;
+  double* part;
+  int pstride;
+  int parity;
+  int nwg;
+  Scalars* sc;
+  T alpha;
+  bool zero_x;
+  bool x_from_zero;  // FP32 correction: x is zero at the first iteration
+  int it;
+
+  __device__ bool skip() const { return sc->done != 0 || sc->err != 0; }
+  __device__ bool prepare(double* sm) {
+    const double gam = sc->gamma[parity];
+    const double pap = sum_partials(part + (long long)SL_PAP * pstride, nwg, sm);
+    it = sc->it;
+    if (!(pap > 0.0) || !isfinite(pap)) {
+      if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc->iters = it;
+        sc->done = 2;
+      }
+      return false;
+    }
+    alpha = (T)((gam / 6.0) / pap);
+    zero_x = x_from_zero && it == 0;
+    return true;
+  }
+  __device__ void load(long long g, T v[1]) const { v[0] = p[g]; }
+  __device__ void point(long long g, const T* c, const T* xm, const T* xp, const T* ym,
+                        const T* yp, const T* zm, const T* zp, double* a) const {
+    const T ap = (T)6 * c[0] - nbr_sum(xm[0], xp[0], ym[0], yp[0], zm[0], zp[0]);
+    const T xv = zero_x ? alpha * c[0] : x[g] + alpha * c[0];
+    x[g] = xv;
+    const T rv = r[g] - alpha * ap;
+    r[g] = rv;
+    a[0] += (double)rv * (double)rv;
+    a[1] = fmax(a[1], fabs((double)rv));
+    a[2] += (double)xv;
+  }
+  __device__ static bool acc_is_max(int i) { return i == 1; }
+  __device__ static int acc_slot(int i, int parity) {
+    return i == 0 ? SL_RR0 + (parity ^ 1) : (i == 1 ? SL_RMAX0 + (parity ^ 1) : SL_XSUM);
+  }
+  __device__ void finish_wg0() const { sc->it = it + 1; }
+};
+
+// ---------------------------------------------------------------------------
+// FP64 residual M x - s of the current solution: the true residual reported
+// at exit, and in mixed precision the outer refinement step that restores
+// an FP64 residual and hands its FP32 rounding to the next inner solve.
+// ---------------------------------------------------------------------------
+template <bool WRITE32>
+struct OpResidual {
+  using T = double;
+  static constexpr int K = 1;
+  static constexpr int NACC = WRITE32 ? 5 : 3;
+  const double* x;
+  const double* s;
+  float* r32;
+  double* part;
+  int pstride;
+  int parity;
+  const Scalars* sc;
+
+  __device__ bool skip() const { return sc->err != 0; }
+  __device__ bool prepare(double*) { return true; }
+  __device__ void load(long long g, double v[1]) const { v[0] = x[g]; }
+  __device__ void point(long long g, const double* c, const double* xm, const double* xp,
+                        const double* ym, const double* yp, const double* zm,
+                        const double* zp, double* a) const {
+    const double rv = (nbr_sum(xm[0], xp[0], ym[0], yp[0], zm[0], zp[0]) - 6.0 * c[0]) - s[g];
+    a[0] += rv * rv;
+    a[1] = fmax(a[1], fabs(rv));
+    a[2] += c[0];
+    if (WRITE32) {
+      const float rf = (float)rv;
+      r32[g] = rf;
+      a[3] += (double)rf * (double)rf;
+      a[4] = fmax(a[4], fabs((double)rf));
+    }
+  }
+  __device__ static bool acc_is_max(int i) { return i == 1 || i == 4; }
+  __device__ static int acc_slot(int i, int) {
+    const int s[5] = {SL_TRR, SL_TMAX, SL_XSUM, SL_RR0, SL_RMAX0};
+    return s[i];
+  }
+  __device__ void finish_wg0() const {}
+};
+
+// ---------------------------------------------------------------------------
+// Launch plumbing: pick the (PPT, NH) instantiation for the geometry.
+// ---------------------------------------------------------------------------
+template <int PPT, int NH, class Op>
+static hipError_t launch_march_t(const Op& op, const MarchGeom& g, hipStream_t st) {
+  const size_t lds = (size_t)2 * Op::K * (g.S + 2 * g.N) * sizeof(typename Op::T);
+  if (lds > 65536) {
+    // above the default dynamic LDS limit: raise it once for this kernel
+    static bool raised = false;
+    if (!raised) {
+      const hipError_t e = hipFuncSetAttribute((const void*)march_kernel<PPT, NH, Op>,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               160 * 1024 - 1024);
+      if (e != hipSuccess) return e;
+      raised = true;
+    }
+  }
+  hipLaunchKernelGGL((march_kernel<PPT, NH, Op>), dim3(g.nwg), dim3(kThreads), lds, st, op, g);
+  return hipGetLastError();
+}
+
+template <int PPT, class Op>
+static hipError_t launch_march_nh(const Op& op, const MarchGeom& g, hipStream_t st) {
+  switch (g.nh) {
+    case 1: return launch_march_t<PPT, 1>(op, g, st);
+    case 2: return launch_march_t<PPT, 2>(op, g, st);
+    case 3:
+    case 4: return launch_march_t<PPT, 4>(op, g, st);
+    default: return launch_march_t<PPT, 8>(op, g, st);
+  }
+}
+
+template <class Op>
+static hipError_t launch_march(const Op& op, const MarchGeom& g, hipStream_t st) {
+  if (g.nh > 8) return hipErrorInvalidValue;
+  switch (g.ppt) {
+    case 1: return launch_march_nh<1>(op, g, st);
+    case 2: return launch_march_nh<2>(op, g, st);
+    case 4: return launch_march_nh<4>(op, g, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_rhs_maze(const DeviceState& d, const MarchGeom& g, bool mixed,
+                           hipStream_t st) {
+  const double c1 = d.h / (4.0 * M_PI);
+  if (mixed) {
+    OpRhsMaze<true> op{d.phi_cur, d.phi_prev, d.y, d.q, d.sigma, nullptr, d.r32,
+                       d.part, d.part_stride, 0, d.sc, c1, 0.0};
+    return launch_march(op, g, st);
+  }
+  OpRhsMaze<false> op{d.phi_cur, d.phi_prev, d.y, d.q, d.sigma, d.r, nullptr,
+                      d.part, d.part_stride, 0, d.sc, c1, 0.0};
+  return launch_march(op, g, st);
+}
+
+hipError_t launch_rhs_poisson(const DeviceState& d, const MarchGeom& g, int guess,
+                              double* x, bool mixed, hipStream_t st) {
+  const double c4 = -(4.0 * M_PI / d.h);
+  if (mixed) {
+    OpRhsPoisson<true> op{d.phi_cur, d.phi_prev, d.q, d.sigma, x, nullptr, d.r32,
+                          d.part, d.part_stride, 0, d.sc, guess, c4, 0.0};
+    return launch_march(op, g, st);
+  }
+  OpRhsPoisson<false> op{d.phi_cur, d.phi_prev, d.q, d.sigma, x, d.r, nullptr,
+                         d.part, d.part_stride, 0, d.sc, guess, c4, 0.0};
+  return launch_march(op, g, st);
+}
+
+hipError_t launch_cg_pass(const DeviceState& d, const MarchGeom& g, int parity, double* x,
+                          bool fp32, int which, hipStream_t st) {
+  if (fp32) {
+    float* pn = d.p32 + (size_t)parity * d.G;
+    const float* po = d.p32 + (size_t)(parity ^ 1) * d.G;
+    if (which == 0) {
+      OpPassA<float> a{d.r32, po, pn, d.part, d.part_stride, parity, g.nwg, d.sc, 0.f, false};
+      return launch_march(a, g, st);
+    }
+    OpPassB<float> b{pn, d.e32, d.r32, d.part, d.part_stride, parity, g.nwg, d.sc,
+                     0.f, false, true, 0};
+    return launch_march(b, g, st);
+  }
+  double* pn = d.p + (size_t)parity * d.G;
+  const double* po = d.p + (size_t)(parity ^ 1) * d.G;
+  if (which == 0) {
+    OpPassA<double> a{d.r, po, pn, d.part, d.part_stride, parity, g.nwg, d.sc, 0.0, false};
+    return launch_march(a, g, st);
+  }
+  OpPassB<double> b{pn, x, d.r, d.part, d.part_stride, parity, g.nwg, d.sc, 0.0, false, false, 0};
+  return launch_march(b, g, st);
+}
+
+hipError_t launch_cg_iteration(const DeviceState& d, const MarchGeom& g, int parity,
+                               double* x, bool fp32, hipStream_t st) {
+  const hipError_t e = launch_cg_pass(d, g, parity, x, fp32, 0, st);
+  if (e != hipSuccess) return e;
+  return launch_cg_pass(d, g, parity, x, fp32, 1, st);
+}
+
+hipError_t launch_refine(const DeviceState& d, const MarchGeom& g, double* x, bool,
+                         hipStream_t st) {
+  OpResidual<true> op{x, d.sigma, d.r32, d.part, d.part_stride, 0, d.sc};
+  return launch_march(op, g, st);
+}
+
+hipError_t launch_true_residual(const DeviceState& d, const MarchGeom& g,
+                                const double* x, hipStream_t st) {
+  OpResidual<false> op{x, d.sigma, nullptr, d.part, d.part_stride, 0, d.sc};
+  return launch_march(op, g, st);
+}
+
+}  // namespace maze

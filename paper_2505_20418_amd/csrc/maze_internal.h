@@ -1,0 +1,177 @@
+// Internal declarations of the MI355X Poisson MaZe library: device state of
+// a session, the per-kernel launch geometry and the launch wrappers that
+// the runtime (maze_capi.hip) calls.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstddef>
+
+#include "../../include/maze.h"
+
+namespace maze {
+
+constexpr int kThreads = 256;   // threads per workgroup everywhere
+constexpr int kTile = 8;        // binning / spreading tile edge (grid points)
+constexpr int kMaxOrder = 4;
+
+// Slots of the per-workgroup partial-sum table. Every kernel that reduces
+// writes one double per workgroup into a slot; the consumer sums the slot in
+// a fixed order, so all reductions are deterministic and atomic-free.
+enum PartialSlot : int {
+  SL_QSUM = 0,     // sum of raw assigned charge (spread)
+  SL_PHIP,         // sum of phi_p, or of the start vector of a direct solve
+  SL_QQ,           // ||q - qbar||^2, or ||rhs||^2 of a direct solve
+  SL_RR0,          // ||r||^2, parity 0
+  SL_RR1,          // ||r||^2, parity 1
+  SL_RMAX0,        // max |r|, parity 0
+  SL_RMAX1,        // max |r|, parity 1
+  SL_PAP,          // <p, A p>
+  SL_XSUM,         // sum of the solution vector (y or phi)
+  SL_TRR,          // true FP64 residual ||M x - s||^2
+  SL_TMAX,         // true FP64 residual max
+  SL_ENERGY,       // phi . (q - qbar)
+  SL_PHISUM,       // sum of phi^{k+1}
+  SL_COUNT
+};
+
+// Device-resident solver scalars. Written only by workgroup 0 of the kernel
+// that owns each field, read by later kernels (stream order makes writes
+// visible at kernel boundaries).
+struct alignas(64) Scalars {
+  // control, polled by the host
+  int32_t done;        // 0 running, 1 converged, 2 breakdown, 3 max_iter
+  int32_t iters;       // iterations when done was set
+  int32_t it;          // iterations completed in the current solve
+  int32_t err;         // nonzero: non-finite input seen
+  // solve parameters and results
+  double thr;          // stopping threshold of the current solve
+  double gamma[2];     // ||r||^2 by iteration parity
+  double qsum;         // raw charge sum of the last assignment
+  double qbar;         // qsum / G
+  double qnorm;        // ||q - qbar||_2 (or ||rhs||_2 of a direct solve)
+  double xbar;         // mean of the solution vector at exit
+  double pbar;         // mean of phi_p (or the direct-solve start)
+  double true_rr;      // true residual ||.||_2^2 (FP64)
+  double true_max;     // true residual max
+  double energy;       // (1/2) k phi . q
+  int32_t max_iter;
+  int32_t norm;        // MAZE_NORM_*
+  double pad[2];
+};
+
+// Geometry of a marching stencil launch: each workgroup owns a contiguous
+// segment of S points of the (y, z) plane (flattened, z fastest) and a run
+// of cx consecutive x planes; it walks the x planes keeping the x
+// neighbours in registers and the y/z neighbours of one plane in LDS.
+struct MarchGeom {
+  int N;
+  int S;          // segment length = kThreads * PPT
+  int nseg;       // ceil(N*N / S)
+  int cx;         // planes per workgroup
+  int nchunk;     // ceil(N / cx)
+  int nwg;        // nseg * nchunk
+  int ppt;        // points per thread per plane
+  int nh;         // halo elements per thread per plane: ceil(2N / kThreads)
+  long long P;    // N*N
+};
+
+MarchGeom make_march_geom(int N, int ppt, int cx);
+
+// Device buffers of one session. All allocated in maze_init.
+struct DeviceState {
+  int N = 0;
+  long long G = 0;
+  int n_ions = 0;
+  int order = 2;
+  double box = 0, h = 0;
+  // grids (FP64): phi history, SHAKE solution, charge, constraint, and the
+  // direct-solve vector
+  double* phi_cur = nullptr;
+  double* phi_prev = nullptr;
+  double* y = nullptr;
+  double* q = nullptr;
+  double* sigma = nullptr;
+  double* xsolve = nullptr;
+  // CG work vectors: FP64 (r, p) and FP32 (r32, p32, e32)
+  double* r = nullptr;
+  double* p = nullptr;
+  float* r32 = nullptr;
+  float* p32 = nullptr;
+  float* e32 = nullptr;
+  // reduction partials [SL_COUNT][part_stride] and scalars
+  double* part = nullptr;
+  int part_stride = 0;
+  Scalars* sc = nullptr;
+  // ions
+  double* Q = nullptr;          // charges (input order)
+  // binning: tiles of kTile^3 grid points
+  int ntx = 0, ntiles = 0;
+  int32_t* tile_count = nullptr;  // ntiles
+  int32_t* tile_start = nullptr;  // ntiles + 1
+  int32_t* tile_cursor = nullptr; // ntiles
+  int32_t* ion_cell = nullptr;    // n*3 base cell per axis (input order)
+  double* ion_t = nullptr;        // n*3 fractional offsets (input order)
+  int32_t* sorted_idx = nullptr;  // n, ion index in tile order
+  int32_t* s_cell = nullptr;      // n*3, tile order
+  double* s_w = nullptr;          // n*3*order weights, tile order
+  double* s_Q = nullptr;          // n, tile order
+};
+
+// ---- launch wrappers (each queues work on `st`, returns hipError_t) ----
+hipError_t launch_bin(const DeviceState& d, const double* pos, hipStream_t st);
+hipError_t launch_spread(const DeviceState& d, hipStream_t st);
+hipError_t launch_gather(const DeviceState& d, const double* phi, double coulomb_k,
+                         double* forces, hipStream_t st);
+
+// finalize modes (single-workgroup reductions of partial slots into Scalars)
+enum FinalizeMode : int {
+  FIN_QSUM = 0,      // qsum, qbar from SL_QSUM over `count` partials
+  FIN_SOLVE_START,   // qnorm, thr, pbar; resets it/done/iters
+  FIN_SOLVE_END,     // xbar (from SL_XSUM), true residual
+  FIN_ENERGY,        // energy from SL_ENERGY, writes energy_out
+  FIN_INNER_START,   // mixed inner solve: thr from `param`, resets counters
+};
+// imax / norm: iteration cap and norm mode installed by the *_START modes.
+hipError_t launch_finalize(const DeviceState& d, int mode, int count, double tol,
+                           double param, double coulomb_k, double* energy_out,
+                           int imax, int norm, hipStream_t st);
+
+// Right-hand sides (write sigma / s, the first residual, and start partials)
+hipError_t launch_rhs_maze(const DeviceState& d, const MarchGeom& g, bool mixed,
+                           hipStream_t st);
+hipError_t launch_rhs_poisson(const DeviceState& d, const MarchGeom& g, int guess,
+                              double* x, bool mixed, hipStream_t st);
+// One CG pass (which = 0: pass A, 1: pass B) on the FP64 or FP32 vectors.
+hipError_t launch_cg_pass(const DeviceState& d, const MarchGeom& g, int parity, double* x,
+                          bool fp32, int which, hipStream_t st);
+// One CG iteration = pass A + pass B, on the FP64 or FP32 vectors.
+hipError_t launch_cg_iteration(const DeviceState& d, const MarchGeom& g, int parity,
+                               double* x, bool fp32, hipStream_t st);
+// Mixed precision: x += e (FP64), FP64 residual M x - s, r32 = float(residual),
+// e = 0; partials SL_TRR/SL_TMAX (FP64) and SL_RR0/SL_RMAX0 (of r32).
+hipError_t launch_refine(const DeviceState& d, const MarchGeom& g, double* x,
+                         bool add_e, hipStream_t st);
+// True FP64 residual of x (partials SL_TRR, SL_TMAX).
+hipError_t launch_true_residual(const DeviceState& d, const MarchGeom& g,
+                                const double* x, hipStream_t st);
+// phi^{k+1} = (phi_p - pbar) - (4 pi / h)(y - ybar) into phi_prev; y projected;
+// optional field copy; partials SL_ENERGY, SL_PHISUM.
+hipError_t launch_update(const DeviceState& d, double* field_out, hipStream_t st);
+// Projects a direct-solve vector to mean zero (into field_out if given) and
+// writes the energy partials.
+hipError_t launch_project(const DeviceState& d, double* x, double* field_out,
+                          hipStream_t st);
+// Mixed precision: x += e32 (FP64 accumulation of the FP32 correction).
+hipError_t launch_add_correction(const DeviceState& d, double* x, hipStream_t st);
+// Number of workgroups (= partials) of the elementwise grid kernels.
+int update_blocks(long long G);
+
+// MD driver
+hipError_t launch_md_kick_drift(const maze_md_state& md, hipStream_t st);
+hipError_t launch_md_bmh(const maze_md_state& md, double box, hipStream_t st);
+hipError_t launch_md_finish(const maze_md_state& md, hipStream_t st);
+hipError_t launch_md_prime(const maze_md_state& md, hipStream_t st);
+
+}  // namespace maze

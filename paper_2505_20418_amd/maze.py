@@ -1,0 +1,308 @@
+"""Python binding of libmaze.so (argument marshalling only).
+
+Every function named maze_* forwards to the C entry point of the same name
+declared in include/maze.h; torch tensors supply device memory and streams.
+All numerical work runs in the library's HIP kernels. If the library has
+not been built, importing works but every call raises: there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libmaze.so")
+
+MAZE_OK, MAZE_NOT_CONVERGED = 0, 1
+MAZE_E_INVALID, MAZE_E_NOT_NEUTRAL, MAZE_E_OOM, MAZE_E_DEVICE, MAZE_E_NONFINITE = -1, -2, -3, -4, -5
+MAZE_FP64, MAZE_MIXED = 0, 1
+MAZE_GUESS_ZERO, MAZE_GUESS_STATIC, MAZE_GUESS_TIMEPROP = 0, 1, 2
+MAZE_NORM_REL2, MAZE_NORM_ABSMAX = 0, 1
+GRID_PHI, GRID_PHI_PREV, GRID_Y, GRID_Q, GRID_SIGMA = 0, 1, 2, 3, 4
+
+EXPORTED = ("maze_abi_version", "maze_strerror", "maze_device_bytes", "maze_init", "maze_step",
+            "maze_solve", "maze_step_batch", "maze_grid_n", "maze_get_grid",
+            "maze_state_bytes", "maze_save", "maze_load", "maze_destroy", "maze_md_prime",
+            "maze_md_step", "maze_profile_enable", "maze_profile_read")
+
+
+class maze_config(ctypes.Structure):
+    _fields_ = [("n_ions", ctypes.c_int32), ("order", ctypes.c_int32),
+                ("box", ctypes.c_double), ("grid_spacing", ctypes.c_double),
+                ("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("residual_norm", ctypes.c_int32),
+                ("flags", ctypes.c_int32), ("coulomb_k", ctypes.c_double),
+                ("stream", ctypes.c_void_p)]
+
+
+class maze_stats(ctypes.Structure):
+    _fields_ = [("grid_n", ctypes.c_int32), ("iters", ctypes.c_int32),
+                ("refinements", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("h", ctypes.c_double), ("rel_residual", ctypes.c_double),
+                ("max_abs_residual", ctypes.c_double), ("net_charge", ctypes.c_double),
+                ("energy", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class maze_md_state(ctypes.Structure):
+    _fields_ = [("n_ions", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("pos_dev", ctypes.c_void_p), ("vel_dev", ctypes.c_void_p),
+                ("mass_dev", ctypes.c_void_p), ("species_dev", ctypes.c_void_p),
+                ("f_es_dev", ctypes.c_void_p), ("f_sr_dev", ctypes.c_void_p),
+                ("scratch_dev", ctypes.c_void_p), ("scalars_dev", ctypes.c_void_p),
+                ("dt", ctypes.c_double), ("accel", ctypes.c_double),
+                ("cutoff", ctypes.c_double), ("bmh_table", ctypes.c_double * 15)]
+
+
+class MazeError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {strerror(status)} (status {status})")
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libmaze.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -c 'import __graft_entry__ as g; g.build()'`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, dp, i32 = ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32
+        L.maze_abi_version.restype = ctypes.c_int
+        L.maze_strerror.restype = ctypes.c_char_p
+        L.maze_strerror.argtypes = [ctypes.c_int]
+        L.maze_device_bytes.restype = ctypes.c_size_t
+        L.maze_device_bytes.argtypes = [ctypes.POINTER(maze_config)]
+        L.maze_init.restype = ctypes.c_int
+        L.maze_init.argtypes = [ctypes.POINTER(maze_config), dp, dp, ctypes.POINTER(vp),
+                                ctypes.POINTER(maze_stats)]
+        L.maze_step.restype = ctypes.c_int
+        L.maze_step.argtypes = [vp, dp, dp, dp, dp, ctypes.POINTER(maze_stats)]
+        L.maze_solve.restype = ctypes.c_int
+        L.maze_solve.argtypes = [vp, ctypes.c_int, dp, dp, dp, dp, ctypes.POINTER(maze_stats)]
+        L.maze_step_batch.restype = ctypes.c_int
+        L.maze_step_batch.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(dp),
+                                      ctypes.POINTER(dp), dp, ctypes.POINTER(maze_stats)]
+        L.maze_grid_n.restype = ctypes.c_int
+        L.maze_grid_n.argtypes = [vp]
+        L.maze_get_grid.restype = ctypes.c_int
+        L.maze_get_grid.argtypes = [vp, ctypes.c_int, dp]
+        L.maze_state_bytes.restype = ctypes.c_size_t
+        L.maze_state_bytes.argtypes = [vp]
+        L.maze_save.restype = ctypes.c_int
+        L.maze_save.argtypes = [vp, ctypes.c_void_p, ctypes.c_size_t]
+        L.maze_load.restype = ctypes.c_int
+        L.maze_load.argtypes = [vp, ctypes.c_void_p, ctypes.c_size_t]
+        L.maze_destroy.restype = None
+        L.maze_destroy.argtypes = [vp]
+        L.maze_md_prime.restype = ctypes.c_int
+        L.maze_md_prime.argtypes = [vp, ctypes.POINTER(maze_md_state), ctypes.POINTER(maze_stats)]
+        L.maze_md_step.restype = ctypes.c_int
+        L.maze_md_step.argtypes = [vp, ctypes.POINTER(maze_md_state), ctypes.POINTER(maze_stats)]
+        L.maze_profile_enable.restype = ctypes.c_int
+        L.maze_profile_enable.argtypes = [vp, ctypes.c_int]
+        L.maze_profile_read.restype = ctypes.c_int
+        L.maze_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+        _lib = L
+    return _lib
+
+
+def strerror(status: int) -> str:
+    try:
+        return lib().maze_strerror(status).decode()
+    except RuntimeError:
+        return f"status {status}"
+
+
+def _ptr(t: Optional[torch.Tensor], dtype=torch.float64, numel: Optional[int] = None):
+    if t is None:
+        return None
+    if not t.is_cuda or t.dtype != dtype or not t.is_contiguous():
+        raise ValueError(f"expected a contiguous {dtype} device tensor, got {t.dtype} "
+                         f"on {t.device} (contiguous={t.is_contiguous()})")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"expected {numel} elements, got {t.numel()}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _check(rc: int, where: str) -> int:
+    if rc < 0:
+        raise MazeError(rc, where)
+    return rc
+
+
+# ---- thin functions with the C names ----------------------------------------
+def maze_abi_version() -> int:
+    return lib().maze_abi_version()
+
+
+def maze_device_bytes(cfg: maze_config) -> int:
+    return int(lib().maze_device_bytes(ctypes.byref(cfg)))
+
+
+def maze_init(cfg: maze_config, charges: torch.Tensor, pos0: torch.Tensor):
+    h = ctypes.c_void_p()
+    st = maze_stats()
+    rc = lib().maze_init(ctypes.byref(cfg), _ptr(charges, numel=cfg.n_ions),
+                         _ptr(pos0, numel=3 * cfg.n_ions), ctypes.byref(h), ctypes.byref(st))
+    _check(rc, "maze_init")
+    return h, rc, st.as_dict()
+
+
+def maze_step(handle, pos, field=None, forces=None, energy=None, want_stats=True):
+    st = maze_stats() if want_stats else None
+    rc = lib().maze_step(handle, _ptr(pos), _ptr(field), _ptr(forces), _ptr(energy),
+                         ctypes.byref(st) if st is not None else None)
+    _check(rc, "maze_step")
+    return rc, (st.as_dict() if st is not None else None)
+
+
+def maze_solve(handle, guess, pos, field=None, forces=None, energy=None, want_stats=True):
+    st = maze_stats() if want_stats else None
+    rc = lib().maze_solve(handle, guess, _ptr(pos), _ptr(field), _ptr(forces), _ptr(energy),
+                          ctypes.byref(st) if st is not None else None)
+    _check(rc, "maze_solve")
+    return rc, (st.as_dict() if st is not None else None)
+
+
+def maze_step_batch(handles: Sequence, pos: Sequence[torch.Tensor],
+                    forces: Optional[Sequence[torch.Tensor]] = None,
+                    energies: Optional[torch.Tensor] = None, want_stats=True):
+    n = len(handles)
+    H = (ctypes.c_void_p * n)(*[h.value if isinstance(h, ctypes.c_void_p) else h for h in handles])
+    P = (ctypes.c_void_p * n)(*[p.data_ptr() for p in pos])
+    F = (ctypes.c_void_p * n)(*[f.data_ptr() for f in forces]) if forces is not None else None
+    st = (maze_stats * n)() if want_stats else None
+    rc = lib().maze_step_batch(H, n, P, F, _ptr(energies), st)
+    _check(rc, "maze_step_batch")
+    return rc, ([s.as_dict() for s in st] if st is not None else None)
+
+
+def maze_grid_n(handle) -> int:
+    return lib().maze_grid_n(handle)
+
+
+def maze_get_grid(handle, which: int, out: torch.Tensor):
+    _check(lib().maze_get_grid(handle, which, _ptr(out)), "maze_get_grid")
+    return out
+
+
+def maze_state_bytes(handle) -> int:
+    return int(lib().maze_state_bytes(handle))
+
+
+def maze_save(handle) -> bytes:
+    n = maze_state_bytes(handle)
+    buf = ctypes.create_string_buffer(n)
+    _check(lib().maze_save(handle, buf, n), "maze_save")
+    return buf.raw
+
+
+def maze_load(handle, blob: bytes):
+    buf = ctypes.create_string_buffer(blob, len(blob))
+    _check(lib().maze_load(handle, buf, len(blob)), "maze_load")
+
+
+def maze_destroy(handle):
+    lib().maze_destroy(handle)
+
+
+def maze_md_prime(handle, md: maze_md_state, want_stats=True):
+    st = maze_stats() if want_stats else None
+    rc = _check(lib().maze_md_prime(handle, ctypes.byref(md),
+                                    ctypes.byref(st) if st is not None else None), "maze_md_prime")
+    return rc, (st.as_dict() if st is not None else None)
+
+
+def maze_md_step(handle, md: maze_md_state, want_stats=True):
+    st = maze_stats() if want_stats else None
+    rc = _check(lib().maze_md_step(handle, ctypes.byref(md),
+                                   ctypes.byref(st) if st is not None else None), "maze_md_step")
+    return rc, (st.as_dict() if st is not None else None)
+
+
+def maze_profile_enable(handle, on: bool = True):
+    _check(lib().maze_profile_enable(handle, int(bool(on))), "maze_profile_enable")
+
+
+def maze_profile_read(handle) -> dict:
+    out = (ctypes.c_double * 8)()
+    _check(lib().maze_profile_read(handle, out), "maze_profile_read")
+    v = list(out)
+    return dict(fp64_a=(int(v[0]), v[1]), fp64_b=(int(v[2]), v[3]),
+                fp32_a=(int(v[4]), v[5]), fp32_b=(int(v[6]), v[7]))
+
+
+# ---- convenience wrapper -------------------------------------------------------
+def make_config(n_ions, box, grid_spacing, tol=1e-9, order=2, max_iter=100000,
+                precision=MAZE_FP64, residual_norm=MAZE_NORM_REL2, coulomb_k=1.0,
+                stream=None) -> maze_config:
+    if stream is None:
+        stream = torch.cuda.current_stream().cuda_stream
+    return maze_config(int(n_ions), int(order), float(box), float(grid_spacing), float(tol),
+                       int(max_iter), int(precision), int(residual_norm), 0, float(coulomb_k),
+                       ctypes.c_void_p(int(stream)))
+
+
+class Session:
+    """One MaZe session: owns the device state of one system."""
+
+    def __init__(self, charges: torch.Tensor, pos0: torch.Tensor, box: float,
+                 grid_spacing: float, tol: float = 1e-9, order: int = 2,
+                 max_iter: int = 100000, precision: int = MAZE_FP64,
+                 residual_norm: int = MAZE_NORM_REL2, coulomb_k: float = 1.0,
+                 stream=None):
+        self.cfg = make_config(charges.numel(), box, grid_spacing, tol, order, max_iter,
+                               precision, residual_norm, coulomb_k, stream)
+        self.device = charges.device
+        self.handle, self.init_status, self.init_stats = maze_init(
+            self.cfg, charges.contiguous(), pos0.contiguous())
+        self.N = maze_grid_n(self.handle)
+        self.n_ions = int(charges.numel())
+
+    def _new(self, *shape):
+        return torch.empty(*shape, dtype=torch.float64, device=self.device)
+
+    def step(self, pos, want_field=False, want_forces=True, want_stats=True):
+        field = self._new(self.N, self.N, self.N) if want_field else None
+        forces = self._new(self.n_ions, 3) if want_forces else None
+        energy = self._new(1)
+        rc, st = maze_step(self.handle, pos.contiguous(), field, forces, energy, want_stats)
+        return dict(status=rc, field=field, forces=forces, energy=energy, stats=st)
+
+    def solve(self, pos, guess=MAZE_GUESS_ZERO, want_field=True):
+        field = self._new(self.N, self.N, self.N) if want_field else None
+        forces = self._new(self.n_ions, 3)
+        energy = self._new(1)
+        rc, st = maze_solve(self.handle, guess, pos.contiguous(), field, forces, energy)
+        return dict(status=rc, field=field, forces=forces, energy=energy, stats=st)
+
+    def grid(self, which: int) -> torch.Tensor:
+        return maze_get_grid(self.handle, which, self._new(self.N, self.N, self.N))
+
+    def save(self) -> bytes:
+        return maze_save(self.handle)
+
+    def load(self, blob: bytes):
+        maze_load(self.handle, blob)
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            maze_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
