@@ -1,0 +1,282 @@
+#!/usr/bin/env python3
+"""Benchmark of the Poisson MaZe MD step on one MI355X.
+
+Workload (default): molten NaCl, 32768 ions (16^3 rock-salt cells, seeded
+jitter, Maxwell-Boltzmann velocities at 1200 K), L = 102 A, 256^3 grid,
+dt = 1 fs, PLCG relative residual 1e-8. Each step is a full device-resident
+MD step: velocity-Verlet kick/drift, charge assignment, the warm-started
+MaZe PLCG solve, field update, force interpolation and the Tosi-Fumi short
+range. The mixed-precision path (FP32 stencil and vectors, FP64 dots and
+refinement) is the headline value; the FP64 path runs side by side, and the
+mixed path's field, force and energy error against FP64 is reported on a
+replay of the FP64 trajectory.
+
+Prints ONE JSON line. `roofline` describes the dominant kernel (CG pass B
+of the mixed path; the FP64 pass B is in `roofline_fp64`), timed with HIP
+events on the stream it runs on. `cpu_baseline` times the plain FP64 CPU
+oracle on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_cg_pass_b_nacl32768_g256.json")
+STENCIL_SRC = os.path.join(ROOT, "paper_2505_20418_amd", "csrc", "k_stencil.hip")
+# algorithmic HBM bytes per grid point of one CG pass B launch: reads p, x, r
+# and writes x, r (FP64: 8 B each, FP32: 4 B each)
+PASS_B_BYTES = {"fp64": 40, "fp32": 20}
+PASS_A_BYTES = {"fp64": 24, "fp32": 12}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def stencil_hash() -> str:
+    return hashlib.sha256(open(STENCIL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def run_md(system, tol, precision, steps, warmup, record_positions=False):
+    import torch
+    from paper_2505_20418_amd import maze, md
+
+    run = md.MDRun(system, tol=tol, precision=precision)
+    h = run.session.handle
+    for _ in range(warmup):
+        run.step()
+    maze.maze_profile_enable(h, True)
+    stream = torch.cuda.current_stream()
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    traj = None
+    if record_positions:
+        traj = torch.empty((steps,) + tuple(run.pos.shape), dtype=run.pos.dtype,
+                           device=run.pos.device)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        evs[k].record(stream)
+        run.step()
+        if traj is not None:
+            traj[k].copy_(run.pos)
+    evs[steps].record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = maze.maze_profile_read(h)
+    maze.maze_profile_enable(h, False)
+    lat = np.array([evs[k].elapsed_time(evs[k + 1]) for k in range(steps)])
+    obs = run.observables()
+    out = dict(steps_per_s=steps / (t1 - t0), wall_s=t1 - t0, lat_ms=lat, prof=prof,
+               obs=obs, grid_n=run.session.N, traj=traj)
+    run.close()
+    return out
+
+
+def replay_errors(system, traj, tol, n_replay):
+    """Drive a fresh mixed session and a fresh FP64 session through the same
+    recorded positions; errors of mixed against FP64 per step."""
+    import torch
+    from paper_2505_20418_amd import inputs, maze
+
+    dev = torch.device("cuda")
+    Q = torch.tensor(system.charges, dtype=torch.float64, device=dev)
+    p0 = torch.tensor(system.pos, dtype=torch.float64, device=dev)
+    s64 = maze.Session(Q, p0, system.box, system.grid_spacing, tol=tol,
+                       precision=maze.MAZE_FP64, coulomb_k=inputs.COULOMB_K_EV_A)
+    s32 = maze.Session(Q, p0, system.box, system.grid_spacing, tol=tol,
+                       precision=maze.MAZE_MIXED, coulomb_k=inputs.COULOMB_K_EV_A)
+    ef, eF, eE = [], [], []
+    for k in range(min(n_replay, traj.shape[0])):
+        a = s64.step(traj[k], want_field=True)
+        b = s32.step(traj[k], want_field=True)
+        ef.append((torch.linalg.norm(b["field"] - a["field"]) / torch.linalg.norm(a["field"])).item())
+        eF.append((torch.linalg.norm(b["forces"] - a["forces"]) / torch.linalg.norm(a["forces"])).item())
+        eE.append(abs((b["energy"] - a["energy"]).item()) / abs(a["energy"].item()))
+    s64.close()
+    s32.close()
+    return dict(field_rel_l2_max=max(ef), forces_rel_l2_max=max(eF), energy_rel_max=max(eE),
+                steps_compared=len(ef))
+
+
+def roofline(prof_key, prof, G, dtype_key):
+    n, ms = prof[prof_key]
+    if n == 0:
+        return None
+    avg_s = ms / n / 1e3
+    bpl = PASS_B_BYTES[dtype_key] * G
+    achieved = bpl / avg_s / 1e9
+    r = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+         "kernel": f"CG pass B ({dtype_key})", "avg_launch_us": round(avg_s * 1e6, 2),
+         "launches": n, "algorithmic_bytes_per_launch": bpl}
+    return r
+
+
+def attach_traffic(r, key):
+    """HBM bytes per launch from the committed counter summary, if it was
+    taken with the current stencil source."""
+    if r is None or not os.path.exists(TRAFFIC_FILE):
+        return
+    try:
+        t = json.load(open(TRAFFIC_FILE))
+    except Exception:
+        return
+    if t.get("stencil_sha") != stencil_hash() or key not in t:
+        return
+    r["traffic"] = t[key]["hbm_bytes_per_launch"]
+
+
+def cpu_baseline(system, tol, iters_per_step):
+    """Plain FP64 oracle on the host: one MD step with the solve capped at
+    zero iterations (assignment, constraint, residual, update, forces, short
+    range) plus a fixed number of CG iterations at full size, extrapolated
+    to the iterations per step the GPU FP64 path needed."""
+    import oracle
+    from paper_2505_20418_amd import inputs
+
+    oracle.build(force=False)
+    n_cg = 12
+    t_start = time.perf_counter()
+    sess = oracle.Session(system.charges, system.pos, system.box, system.grid_spacing, tol=tol,
+                          max_iter=0, coulomb_k=inputs.COULOMB_K_EV_A)
+    pos, vel = system.pos.copy(), system.vel.copy()
+    F_es = np.zeros_like(pos)
+    F_sr = np.zeros_like(pos)
+    work = np.zeros(1)
+    t0 = time.perf_counter()
+    sess.md_step(pos, vel, system.masses, system.species, inputs.BMH_TABLE, inputs.BMH_CUTOFF,
+                 1.0, inputs.ACCEL_FACTOR, F_es, F_sr, work)
+    t_other = time.perf_counter() - t0
+    N = sess.N
+    b = 4 * np.pi * sess.state()["q"] / (system.box / N)
+    t0 = time.perf_counter()
+    oracle.pcg(b, thr=0.0, max_iter=n_cg)
+    t_iter = (time.perf_counter() - t0) / n_cg
+    sess.close()
+    total = time.perf_counter() - t_start
+    per_step = t_other + iters_per_step * t_iter
+    return {"value": round(1.0 / per_step, 6), "unit": "MD steps/s", "cores": 1, "kind": "oracle",
+            "sample": (f"one oracle MD step at {N}^3 with the solve capped at 0 iterations "
+                       f"({t_other:.2f} s) plus {n_cg} oracle PLCG iterations at {N}^3 "
+                       f"({t_iter:.3f} s each), extrapolated to {iters_per_step:.1f} "
+                       f"iterations per step (GPU FP64 path); {total:.1f} s of CPU work, "
+                       f"single-threaded plain C, -O2 -ffp-contract=off")}
+
+
+def copy_calibration(gib: float = 2.0, reps: int = 5):
+    """A plain device copy of known size, for scaling the HBM counters."""
+    import torch
+    n = int(gib * (1 << 30)) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read_per_launch": n * 8, "copy_bytes_written_per_launch": n * 8,
+                      "launches": reps}))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="nacl32768_g256")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--mixed-only", action="store_true",
+                    help="skip the FP64 side-by-side run (for profiling)")
+    ap.add_argument("--replay", type=int, default=6, help="steps replayed for the error report")
+    ap.add_argument("--copy-calibration", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the multi-GPU layout is described, not built).", file=sys.stderr)
+        sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration()
+        return
+
+    import torch
+    from paper_2505_20418_amd import inputs, maze
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    wl = inputs.WORKLOADS[args.workload]
+    system = inputs.workload(args.workload)
+    tol = wl["tol"]
+    G = (inputs.GRID_PER_CELL * wl["n_cells"]) ** 3
+
+    log(f"bench: {args.workload} ions={system.n_ions} grid={inputs.GRID_PER_CELL * wl['n_cells']}^3 "
+        f"tol={tol} mixed: warmup {args.warmup}, {args.steps} timed steps")
+    mixed = run_md(system, tol, maze.MAZE_MIXED, args.steps, args.warmup)
+    log(f"bench: mixed {mixed['steps_per_s']:.3f} steps/s")
+    fp64 = None
+    errors = None
+    if not args.mixed_only:
+        fp64 = run_md(system, tol, maze.MAZE_FP64, args.steps, args.warmup,
+                      record_positions=True)
+        log(f"bench: fp64 {fp64['steps_per_s']:.3f} steps/s")
+        errors = replay_errors(system, fp64["traj"], tol, args.replay)
+        log(f"bench: mixed vs fp64 errors {errors}")
+
+    r_mixed = roofline("fp32_b", mixed["prof"], G, "fp32")
+    attach_traffic(r_mixed, "fp32_pass_b")
+    r_fp64 = roofline("fp64_b", fp64["prof"], G, "fp64") if fp64 else None
+    attach_traffic(r_fp64, "fp64_pass_b")
+
+    it_mixed = mixed["prof"]["fp32_b"][0] / args.steps
+    it_fp64 = fp64["prof"]["fp64_b"][0] / args.steps if fp64 else None
+    cpu = None
+    if not args.no_cpu_baseline and it_fp64:
+        log("bench: timing the CPU oracle sample")
+        cpu = cpu_baseline(system, tol, it_fp64)
+
+    value = mixed["steps_per_s"]
+    line = {
+        "metric": "MD steps/s + stencil-CG HBM GB/s (NaCl 32k ions, 256^3); mixed vs FP64; p99",
+        "value": round(value, 4),
+        "unit": "MD steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1000.0 / value, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "ions": system.n_ions,
+                   "grid": inputs.GRID_PER_CELL * wl["n_cells"], "box_A": system.box,
+                   "tol_rel_residual": tol, "dt_fs": 1.0, "temperature_K": system.temperature,
+                   "assignment_order": 2, "precision": "mixed (fp32 stencil/vectors, fp64 dots "
+                   "and refinement)", "parallelism": "single GPU"},
+        "latency_ms": {"p50": round(float(np.percentile(mixed["lat_ms"], 50)), 3),
+                       "p99": round(float(np.percentile(mixed["lat_ms"], 99)), 3)},
+        "cg_iterations_per_step": {"mixed_fp32_inner": round(it_mixed, 1)},
+        "roofline": r_mixed,
+    }
+    if fp64:
+        line["fp64"] = {"value": round(fp64["steps_per_s"], 4), "unit": "MD steps/s",
+                        "latency_ms": {"p50": round(float(np.percentile(fp64["lat_ms"], 50)), 3),
+                                       "p99": round(float(np.percentile(fp64["lat_ms"], 99)), 3)}}
+        line["speedup_mixed_vs_fp64"] = round(value / fp64["steps_per_s"], 3)
+        line["cg_iterations_per_step"]["fp64"] = round(it_fp64, 1)
+        line["roofline_fp64"] = r_fp64
+        line["mixed_error_vs_fp64"] = errors
+    line["cpu_baseline"] = cpu
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()
