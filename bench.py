@@ -11,10 +11,11 @@ refinement) is the headline value; the FP64 path runs side by side, and the
 mixed path's field, force and energy error against FP64 is reported on a
 replay of the FP64 trajectory.
 
-Prints ONE JSON line. `roofline` describes the dominant kernel (CG pass B
-of the mixed path; the FP64 pass B is in `roofline_fp64`), timed with HIP
-events on the stream it runs on. `cpu_baseline` times the plain FP64 CPU
-oracle on a bounded sample of the same workload.
+Prints ONE JSON line. `roofline` describes the dominant kernel, the fused
+CG sweep of the mixed path's FP32 inner solves (the FP64 sweep is in
+`roofline_fp64`), timed with HIP events that the library records around
+sampled sweeps on the stream they run on. `cpu_baseline` times the plain
+FP64 CPU oracle on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -32,12 +33,11 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_cg_pass_b_nacl32768_g256.json")
-STENCIL_SRC = os.path.join(ROOT, "paper_2505_20418_amd", "csrc", "k_stencil.hip")
-# algorithmic HBM bytes per grid point of one CG pass B launch: reads p, x, r
-# and writes x, r (FP64: 8 B each, FP32: 4 B each)
-PASS_B_BYTES = {"fp64": 40, "fp32": 20}
-PASS_A_BYTES = {"fp64": 24, "fp32": 12}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_cg_sweep_nacl32768_g256.json")
+STENCIL_SRC = os.path.join(ROOT, "paper_2505_20418_amd", "csrc", "k_cg.hip")
+# algorithmic HBM bytes per grid point of one fused CG sweep: reads x, r, p
+# and writes x, r, p once (FP64: 8 B each, FP32: 4 B each)
+SWEEP_BYTES = {"fp64": 48, "fp32": 24}
 
 
 def log(msg):
@@ -114,12 +114,12 @@ def roofline(prof_key, prof, G, dtype_key):
     if n == 0:
         return None
     avg_s = ms / n / 1e3
-    bpl = PASS_B_BYTES[dtype_key] * G
+    bpl = SWEEP_BYTES[dtype_key] * G
     achieved = bpl / avg_s / 1e9
     r = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
          "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-         "kernel": f"CG pass B ({dtype_key})", "avg_launch_us": round(avg_s * 1e6, 2),
-         "launches": n, "algorithmic_bytes_per_launch": bpl}
+         "kernel": f"k_cg_sweep ({dtype_key})", "avg_launch_us": round(avg_s * 1e6, 2),
+         "launches_timed": n, "algorithmic_bytes_per_launch": bpl}
     return r
 
 
@@ -146,7 +146,7 @@ def cpu_baseline(system, tol, iters_per_step):
     from paper_2505_20418_amd import inputs
 
     oracle.build(force=False)
-    n_cg = 12
+    n_cg = 60
     t_start = time.perf_counter()
     sess = oracle.Session(system.charges, system.pos, system.box, system.grid_spacing, tol=tol,
                           max_iter=0, coulomb_k=inputs.COULOMB_K_EV_A)
@@ -230,13 +230,13 @@ def main():
         errors = replay_errors(system, fp64["traj"], tol, args.replay)
         log(f"bench: mixed vs fp64 errors {errors}")
 
-    r_mixed = roofline("fp32_b", mixed["prof"], G, "fp32")
-    attach_traffic(r_mixed, "fp32_pass_b")
-    r_fp64 = roofline("fp64_b", fp64["prof"], G, "fp64") if fp64 else None
-    attach_traffic(r_fp64, "fp64_pass_b")
+    r_mixed = roofline("fp32_sweep", mixed["prof"], G, "fp32")
+    attach_traffic(r_mixed, "fp32_sweep")
+    r_fp64 = roofline("fp64_sweep", fp64["prof"], G, "fp64") if fp64 else None
+    attach_traffic(r_fp64, "fp64_sweep")
 
-    it_mixed = mixed["prof"]["fp32_b"][0] / args.steps
-    it_fp64 = fp64["prof"]["fp64_b"][0] / args.steps if fp64 else None
+    it_mixed = mixed["prof"]["fp32_iters"] / args.steps
+    it_fp64 = fp64["prof"]["fp64_iters"] / args.steps if fp64 else None
     cpu = None
     if not args.no_cpu_baseline and it_fp64:
         log("bench: timing the CPU oracle sample")

@@ -168,12 +168,13 @@ size_t maze_state_bytes(const maze_session* s);
 int maze_save(const maze_session* s, void* host_buf, size_t bytes);
 int maze_load(maze_session* s, const void* host_buf, size_t bytes);
 
-/* Pass timing for measurement. When enabled, the runtime brackets every
- * CG pass with HIP events on the session stream and accumulates the
- * durations of the passes of iterations that did work (at most 4096 per
- * solve). maze_profile_read copies 8 doubles into out8 (HOST memory):
- * {FP64 pass-A launches, their total ms, FP64 pass-B launches, total ms,
- *  FP32 pass-A launches, total ms, FP32 pass-B launches, total ms}
+/* Sweep timing for measurement. When enabled, the runtime brackets every
+ * fourth CG sweep of each solve (at most 512 per solve) with a pair of HIP
+ * events on the session stream, and keeps the durations of the sampled
+ * sweeps that did work. maze_profile_read copies 8 doubles into out8 (HOST
+ * memory):
+ *   {FP64 sweeps timed, their total ms, FP32 sweeps timed, their total ms,
+ *    FP64 CG iterations, FP32 CG iterations, 0, 0}
  * and resets them. Enabling creates the events (the only allocation outside
  * maze_init). */
 int maze_profile_enable(maze_session* s, int on);

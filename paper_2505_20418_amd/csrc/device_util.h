@@ -75,4 +75,18 @@ __device__ __forceinline__ int xcd_remap(int b, int nwg) {
 
 __device__ __forceinline__ volatile int32_t* vol(int32_t* p) { return p; }
 
+// Access to the device scalars (Scalars) that one kernel writes and a later
+// kernel reads. Plain uniform loads of them may be compiled to scalar-cache
+// loads, and the scalar cache is not kept coherent with vector stores of an
+// earlier kernel, so every such access is an agent-scope relaxed atomic:
+// a vector load or store that reaches the coherent level of the hierarchy.
+template <typename T>
+__device__ __forceinline__ T ctl_ld(const T* p) {
+  return __hip_atomic_load(const_cast<T*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void ctl_st(T* p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 }  // namespace maze

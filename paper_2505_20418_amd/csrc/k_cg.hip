@@ -1,0 +1,498 @@
+// One fused sweep per iteration of the Jacobi PLCG solve of M y = sigma_p
+// (Appendix B; equation "SHAKEy"), and of the direct Poisson solve
+// (equation "linearproblem"), on FP64 or FP32 vectors.
+//
+// The solve is written for A = -M (symmetric positive definite on mean-zero
+// vectors) with residual r = b - A x and the Jacobi preconditioner
+// diag(A) = 6 I, i.e. z = r / 6. Hestenes-Stiefel PCG needs two global
+// reductions per iteration: <p, A p> before the update of x and r, and
+// <r, z> before the next search direction. This kernel uses the
+// single-reduction rearrangement of D'Azevedo, Eijkhout and Romine (1992):
+// with w = A p, the squared norm of the next residual is predicted from
+// dots that are all available in the same sweep,
+//
+//   ||r - alpha w||^2 = ||r||^2 - 2 alpha <r, w> + alpha^2 <w, w>,
+//
+// so one sweep k (k >= 1) performs, per grid point,
+//
+//   w_{k-1} = A p_{k-1}                      (stencil of p_{k-1})
+//   x_k     = x_{k-1} + alpha_{k-1} p_{k-1}
+//   r_k     = r_{k-1} - alpha_{k-1} w_{k-1}
+//   p_k     = r_k / 6 + beta_k p_{k-1}
+//   w_k     = A p_k                          (stencil of p_k)
+//
+// and accumulates ||r_k||^2, max|r_k|, <p_k, w_k>, <r_k, w_k>, <w_k, w_k>.
+// The next sweep turns those five sums into alpha_k = (||r_k||^2/6)/<p_k,w_k>
+// and beta_{k+1} = ||r_{k+1}||^2_predicted / ||r_k||^2. In exact arithmetic
+// the iterates are those of Hestenes-Stiefel PCG; the norm used by the
+// stopping test is the directly computed ||r_k||, not the prediction.
+//
+// Neither w vector is stored: w_{k-1} is recomputed from p_{k-1}, which
+// needs p_{k-1} two points away from the points whose p_k enters the stencil
+// of w_k. Per point a sweep reads x, r, p and writes x, r, p once: 48 bytes
+// in FP64 and 24 in FP32, against 64 / 32 for the two-pass form.
+//
+// Layout and marching: grids are N^3 with index (x*N + y)*N + z. A
+// workgroup owns a segment of S = 256*PPT consecutive points of the
+// flattened (y, z) plane and a run of consecutive x planes. It walks the
+// planes in x order. Stage U at plane u produces r_k and p_k on the segment
+// extended by N points (one row) on each side; stage W at plane u-1 forms
+// w_k on the segment. The x neighbours live in registers; the y and z
+// neighbours come from LDS copies of p_{k-1}(u) (segment plus two rows on
+// each side) and p_k(u-1) (segment plus one row), both double-buffered so
+// one barrier per plane suffices. Loads of the next plane are issued at the
+// start of a step and consumed in the next one. r and p are double-buffered
+// in HBM: neighbouring workgroups still read r_{k-1} and p_{k-1} at this
+// workgroup's points while it writes r_k and p_k; x is updated in place
+// (only its owner reads it).
+//
+// Reductions are atomic-free and deterministic: one partial per workgroup
+// per sum, summed in a fixed order by every workgroup of the next sweep.
+#include "device_util.h"
+
+namespace maze {
+
+SweepGeom make_sweep_geom(int N, int ppt, int cx) {
+  SweepGeom g;
+  g.N = N;
+  g.P = N * N;
+  g.ppt = ppt;
+  g.S = kThreads * ppt;
+  g.nseg = (g.P + g.S - 1) / g.S;
+  g.cx = cx < 1 ? 1 : (cx > N ? N : cx);
+  g.nchunk = (N + g.cx - 1) / g.cx;
+  g.nwg = g.nseg * g.nchunk;
+  g.nh = (2 * N + kThreads - 1) / kThreads;
+  return g;
+}
+
+size_t sweep_lds_bytes(const SweepGeom& g, bool fp32, bool first) {
+  const size_t es = fp32 ? sizeof(float) : sizeof(double);
+  const size_t e1 = (size_t)g.S + 4 * (size_t)g.N, e2 = (size_t)g.S + 2 * (size_t)g.N;
+  return es * (2 * e2 + (first ? 0 : 2 * e1));
+}
+
+// Five per-thread sums (index 1 is a max) reduced over the workgroup in a
+// fixed order; every thread receives the results.
+__device__ __forceinline__ void block_reduce5(double v[5], double* sm) {
+#pragma unroll
+  for (int i = 0; i < 5; ++i) v[i] = (i == 1) ? wave_max(v[i]) : wave_sum(v[i]);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int i = 0; i < 5; ++i) sm[i * (kThreads / 64) + w] = v[i];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    double s = sm[i * (kThreads / 64)];
+#pragma unroll
+    for (int k = 1; k < kThreads / 64; ++k)
+      s = (i == 1) ? fmax(s, sm[i * (kThreads / 64) + k]) : s + sm[i * (kThreads / 64) + k];
+    v[i] = s;
+  }
+}
+
+// Sums the partials of the previous kernel: ||r||^2, max|r| and (not FIRST)
+// <p, w>, <r, w>, <w, w> of parity set `par`.
+template <bool FIRST>
+__device__ __forceinline__ void read_sweep_partials(const double* part, int ps, int par,
+                                                    int nprev, double v[5], double* sm) {
+  for (int i = 0; i < 5; ++i) v[i] = 0.0;
+  const double* rr = part + (size_t)(SL_RR0 + par) * ps;
+  const double* rm = part + (size_t)(SL_RMAX0 + par) * ps;
+  const double* mu = part + (size_t)(SL_MU0 + par) * ps;
+  const double* rw = part + (size_t)(SL_RW0 + par) * ps;
+  const double* ww = part + (size_t)(SL_WW0 + par) * ps;
+  for (int i = threadIdx.x; i < nprev; i += kThreads) {
+    v[0] += rr[i];
+    v[1] = fmax(v[1], rm[i]);
+    if (!FIRST) {
+      v[2] += mu[i];
+      v[3] += rw[i];
+      v[4] += ww[i];
+    }
+  }
+  block_reduce5(v, sm);
+}
+
+template <typename T>
+struct SweepArgs {
+  const T* r_in;
+  T* r_out;
+  const T* p_in;
+  T* p_out;
+  T* x;
+  double* part;
+  int pstride;
+  int nprev;     // number of partials written by the previous kernel
+  int zero_x;    // FIRST only: write x = 0 (start of an FP32 correction solve)
+  Scalars* sc;
+};
+
+__device__ __forceinline__ int wrap_plane(int u, int N) {
+  return u < 0 ? u + N : (u >= N ? u - N : u);
+}
+
+template <typename T, bool FIRST, int PPT, int NH>
+__global__ __launch_bounds__(kThreads) void k_cg_sweep(SweepArgs<T> a, SweepGeom g, int par) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ double red[5 * (kThreads / 64)];
+  Scalars* sc = a.sc;
+  if (ctl_ld(&sc->done) != 0 || ctl_ld(&sc->err) != 0) return;
+  const int tid = threadIdx.x;
+
+  // ---- step scalars from the previous kernel's partials -------------------
+  T alpha = (T)0, beta = (T)0;
+  {
+    double v[5];
+    read_sweep_partials<FIRST>(a.part, a.pstride, par, a.nprev, v, red);
+    const double gam = v[0];
+    const double thr = ctl_ld(&sc->thr);
+    const bool conv = (ctl_ld(&sc->norm) == MAZE_NORM_ABSMAX) ? (v[1] <= thr) : (sqrt(gam) <= thr);
+    bool stop = conv || !isfinite(gam);
+    int code = conv ? 1 : 2;
+    if (!FIRST && !stop) {
+      const double mu = v[2];
+      if (!(mu > 0.0) || !isfinite(mu)) {
+        stop = true;
+        code = 2;
+      } else {
+        const double al = gam / (6.0 * mu);
+        const double gnext = gam - 2.0 * al * v[3] + al * al * v[4];
+        alpha = (T)al;
+        beta = (T)((gnext > 0.0) ? gnext / gam : 0.0);
+      }
+    }
+    if (stop) {
+      if (blockIdx.x == 0 && tid == 0) {
+        ctl_st(&sc->gamma[par], gam);
+        ctl_st(&sc->iters, ctl_ld(&sc->it));
+        ctl_st(&sc->done, code);
+      }
+      return;
+    }
+  }
+
+  // ---- geometry of this workgroup -----------------------------------------
+  const int N = g.N, P = g.P, S = g.S;
+  const int L = xcd_remap(blockIdx.x, g.nwg);
+  const int seg = L % g.nseg, chunk = L / g.nseg;
+  const int s0 = seg * S;
+  const int x0 = chunk * g.cx, x1 = min(N, x0 + g.cx);
+  const int E1 = S + 4 * N, E2 = S + 2 * N;
+  T* P2 = reinterpret_cast<T*>(smem_raw);  // [2][E2] p_k of plane u-1 / u
+  T* P1 = P2 + 2 * E2;                     // [2][E1] p_{k-1} of plane u (not FIRST)
+  constexpr int NU = PPT + NH;             // stage-U slots: segment, then inner halo
+
+  int off[NU], e1[NU], e1zm[NU], e1zp[NU], e2[NU];
+  bool uval[NU];
+  int e2zm[PPT], e2zp[PPT];
+  bool cval[PPT];
+  int offo[NH], e1o[NH];
+  bool oval[NH];
+#pragma unroll
+  for (int i = 0; i < NU; ++i) {
+    int f, ee2;
+    if (i < PPT) {
+      const int loc = tid + i * kThreads;
+      f = s0 + loc;
+      ee2 = N + loc;
+      uval[i] = true;
+      cval[i] = f < P;
+    } else {
+      const int h = tid + (i - PPT) * kThreads;
+      uval[i] = h < 2 * N;
+      const int hh = uval[i] ? h : 0;
+      ee2 = (hh < N) ? hh : S + hh;
+      f = s0 - N + ee2;
+    }
+    int o = f % P;
+    if (o < 0) o += P;
+    off[i] = o;
+    e2[i] = ee2;
+    e1[i] = ee2 + N;
+    const int z = o % N;
+    e1zm[i] = (z == 0) ? e1[i] + N - 1 : e1[i] - 1;
+    e1zp[i] = (z == N - 1) ? e1[i] - N + 1 : e1[i] + 1;
+    if (i < PPT) {
+      e2zm[i] = (z == 0) ? ee2 + N - 1 : ee2 - 1;
+      e2zp[i] = (z == N - 1) ? ee2 - N + 1 : ee2 + 1;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NH; ++k) {
+    const int h = tid + k * kThreads;
+    oval[k] = h < 2 * N;
+    const int hh = oval[k] ? h : 0;
+    e1o[k] = (hh < N) ? hh : S + 2 * N + hh;
+    int o = (s0 - 2 * N + e1o[k]) % P;
+    if (o < 0) o += P;
+    offo[k] = o;
+  }
+
+  const T c6 = (T)(1.0 / 6.0);
+  const size_t Ps = (size_t)P;
+  T pm[NU], pc[NU], pn[NU], pon[NH];  // p_{k-1}: planes u-1, u, u+1; outer halo u+1
+  T rc[NU], xc[PPT];                  // r_{k-1}, x_{k-1} at plane u
+  T qm[PPT], qc[PPT], qn[PPT], sv[PPT];  // p_k at planes u-2, u-1, u; r_k at u-1
+  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+
+  // ---- prologue: planes x0-2 .. x0 of p_{k-1}, plane x0-1 of r_{k-1} ------
+  {
+    const T* r0 = a.r_in + (size_t)wrap_plane(x0 - 1, N) * Ps;
+#pragma unroll
+    for (int i = 0; i < NU; ++i) rc[i] = r0[off[i]];
+    if (!FIRST) {
+      const T* pa = a.p_in + (size_t)wrap_plane(x0 - 2, N) * Ps;
+      const T* pb = a.p_in + (size_t)wrap_plane(x0 - 1, N) * Ps;
+      const T* pd = a.p_in + (size_t)wrap_plane(x0, N) * Ps;
+      T ob[NH];
+#pragma unroll
+      for (int i = 0; i < NU; ++i) {
+        pm[i] = pa[off[i]];
+        pc[i] = pb[off[i]];
+        pn[i] = pd[off[i]];
+      }
+#pragma unroll
+      for (int k = 0; k < NH; ++k) {
+        ob[k] = pb[offo[k]];
+        pon[k] = pd[offo[k]];
+      }
+#pragma unroll
+      for (int i = 0; i < NU; ++i)
+        if (uval[i]) P1[e1[i]] = pc[i];
+#pragma unroll
+      for (int k = 0; k < NH; ++k)
+        if (oval[k]) P1[e1o[k]] = ob[k];
+    }
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+      xc[j] = (T)0;
+      qm[j] = qc[j] = qn[j] = sv[j] = (T)0;
+    }
+  }
+  __syncthreads();
+  // Complete the prologue loads here: every value entering the loop is then
+  // known to be resident, and the waits inside the loop only cover the loads
+  // issued for the next step (which stay in flight across its compute).
+  __builtin_amdgcn_s_waitcnt(0);
+
+  const int nsteps = x1 - x0 + 2;  // stage U on planes x0-1 .. x1
+  for (int t = 0; t < nsteps; ++t) {
+    const int u = x0 - 1 + t;
+    const bool more = t + 1 < nsteps;
+    const bool own_u = (u >= x0) && (u < x1);
+    const bool own_n = (u + 1 >= x0) && (u + 1 < x1);
+    // issue the loads of the next step
+    T pf[NU], pof[NH], rf[NU], xf[PPT];
+    if (more) {
+      const T* rp = a.r_in + (size_t)wrap_plane(u + 1, N) * Ps;
+#pragma unroll
+      for (int i = 0; i < NU; ++i) rf[i] = rp[off[i]];
+      if (!FIRST) {
+        const T* pp = a.p_in + (size_t)wrap_plane(u + 2, N) * Ps;
+#pragma unroll
+        for (int i = 0; i < NU; ++i) pf[i] = pp[off[i]];
+#pragma unroll
+        for (int k = 0; k < NH; ++k) pof[k] = pp[offo[k]];
+        if (own_n) {
+          const T* xp = a.x + (size_t)(u + 1) * Ps;
+#pragma unroll
+          for (int j = 0; j < PPT; ++j) xf[j] = xp[off[j]];
+        }
+      }
+    }
+
+    // stage U at plane u: r_k, p_k (segment + inner halo), x_k (segment)
+    const int tb = t & 1;
+    T* P1b = P1 + tb * E1;
+    T* P2w = P2 + tb * E2;
+    T rk[PPT], pk[PPT];
+#pragma unroll
+    for (int i = 0; i < NU; ++i) {
+      T r_new, p_new;
+      if (FIRST) {
+        r_new = rc[i];
+        p_new = c6 * r_new;
+      } else {
+        const T w = (T)6 * pc[i] - (((pm[i] + pn[i]) + (P1b[e1[i] - N] + P1b[e1[i] + N])) +
+                                    (P1b[e1zm[i]] + P1b[e1zp[i]]));
+        r_new = rc[i] - alpha * w;
+        p_new = c6 * r_new + beta * pc[i];
+      }
+      if (uval[i]) P2w[e2[i]] = p_new;
+      if (i < PPT) {
+        rk[i] = r_new;
+        pk[i] = p_new;
+      }
+    }
+    if (own_u) {
+      const size_t pb = (size_t)u * Ps;
+#pragma unroll
+      for (int j = 0; j < PPT; ++j) {
+        if (cval[j]) {
+          a.r_out[pb + off[j]] = rk[j];
+          a.p_out[pb + off[j]] = pk[j];
+          if (!FIRST) a.x[pb + off[j]] = xc[j] + alpha * pc[j];
+          else if (a.zero_x) a.x[pb + off[j]] = (T)0;
+          const double rd = (double)rk[j];
+          acc[0] += rd * rd;
+          acc[1] = fmax(acc[1], fabs(rd));
+        }
+      }
+    }
+
+    // stage W at plane u-1: w_k = A p_k on the segment, dots
+    if (t >= 2) {
+      const T* P2r = P2 + (tb ^ 1) * E2;
+#pragma unroll
+      for (int j = 0; j < PPT; ++j) {
+        const T w = (T)6 * qc[j] - (((qm[j] + pk[j]) + (P2r[e2[j] - N] + P2r[e2[j] + N])) +
+                                    (P2r[e2zm[j]] + P2r[e2zp[j]]));
+        if (cval[j]) {
+          const double wd = (double)w;
+          acc[2] += (double)qc[j] * wd;
+          acc[3] += (double)sv[j] * wd;
+          acc[4] += wd * wd;
+        }
+      }
+    }
+
+    // stage p_{k-1} of plane u+1 for the next step
+    if (!FIRST && more) {
+      T* P1n = P1 + (tb ^ 1) * E1;
+#pragma unroll
+      for (int i = 0; i < NU; ++i)
+        if (uval[i]) P1n[e1[i]] = pn[i];
+#pragma unroll
+      for (int k = 0; k < NH; ++k)
+        if (oval[k]) P1n[e1o[k]] = pon[k];
+    }
+    __syncthreads();
+
+    // rotate
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+      qm[j] = qc[j];
+      qc[j] = pk[j];
+      sv[j] = rk[j];
+    }
+    if (more) {
+#pragma unroll
+      for (int i = 0; i < NU; ++i) {
+        rc[i] = rf[i];
+        if (!FIRST) {
+          pm[i] = pc[i];
+          pc[i] = pn[i];
+          pn[i] = pf[i];
+        }
+      }
+      if (!FIRST) {
+#pragma unroll
+        for (int k = 0; k < NH; ++k) pon[k] = pof[k];
+        if (own_n) {
+#pragma unroll
+          for (int j = 0; j < PPT; ++j) xc[j] = xf[j];
+        }
+      }
+    }
+  }
+
+  block_reduce5(acc, red);
+  if (tid == 0) {
+    const int po = par ^ 1;
+    a.part[(size_t)(SL_RR0 + po) * a.pstride + L] = acc[0];
+    a.part[(size_t)(SL_RMAX0 + po) * a.pstride + L] = acc[1];
+    a.part[(size_t)(SL_MU0 + po) * a.pstride + L] = acc[2];
+    a.part[(size_t)(SL_RW0 + po) * a.pstride + L] = acc[3];
+    a.part[(size_t)(SL_WW0 + po) * a.pstride + L] = acc[4];
+    if (blockIdx.x == 0) ctl_st(&sc->it, FIRST ? 0 : ctl_ld(&sc->it) + 1);
+  }
+}
+
+// Stopping test after the last permitted sweep: converged or iteration cap.
+__global__ __launch_bounds__(kThreads) void k_cg_check(double* part, int pstride, int par,
+                                                        int nprev, Scalars* sc) {
+  __shared__ double red[5 * (kThreads / 64)];
+  if (ctl_ld(&sc->done) != 0 || ctl_ld(&sc->err) != 0) return;
+  double v[5];
+  read_sweep_partials<true>(part, pstride, par, nprev, v, red);
+  if (threadIdx.x == 0) {
+    const double thr = ctl_ld(&sc->thr);
+    const bool conv = (ctl_ld(&sc->norm) == MAZE_NORM_ABSMAX) ? (v[1] <= thr) : (sqrt(v[0]) <= thr);
+    ctl_st(&sc->gamma[par], v[0]);
+    ctl_st(&sc->iters, ctl_ld(&sc->it));
+    ctl_st(&sc->done, conv ? 1 : 3);
+  }
+}
+
+// ---- launch plumbing ---------------------------------------------------------
+template <typename T, bool FIRST, int PPT, int NH>
+static hipError_t launch_sweep_t(const SweepArgs<T>& a, const SweepGeom& g, int par,
+                                 hipStream_t st) {
+  const size_t lds = sweep_lds_bytes(g, sizeof(T) == 4, FIRST);
+  if (lds > 65536) {
+    static bool raised = false;
+    if (!raised) {
+      const hipError_t e = hipFuncSetAttribute((const void*)k_cg_sweep<T, FIRST, PPT, NH>,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               160 * 1024 - 1024);
+      if (e != hipSuccess) return e;
+      raised = true;
+    }
+  }
+  hipLaunchKernelGGL((k_cg_sweep<T, FIRST, PPT, NH>), dim3(g.nwg), dim3(kThreads), lds, st, a, g,
+                     par);
+  return hipGetLastError();
+}
+
+template <typename T, bool FIRST, int PPT>
+static hipError_t launch_sweep_nh(const SweepArgs<T>& a, const SweepGeom& g, int par,
+                                  hipStream_t st) {
+  switch (g.nh) {
+    case 1: return launch_sweep_t<T, FIRST, PPT, 1>(a, g, par, st);
+    case 2: return launch_sweep_t<T, FIRST, PPT, 2>(a, g, par, st);
+    case 3:
+    case 4: return launch_sweep_t<T, FIRST, PPT, 4>(a, g, par, st);
+    default: return launch_sweep_t<T, FIRST, PPT, 8>(a, g, par, st);
+  }
+}
+
+template <typename T, bool FIRST>
+static hipError_t launch_sweep_ppt(const SweepArgs<T>& a, const SweepGeom& g, int par,
+                                   hipStream_t st) {
+  if (g.nh > 8) return hipErrorInvalidValue;
+  switch (g.ppt) {
+    case 1: return launch_sweep_nh<T, FIRST, 1>(a, g, par, st);
+    case 2: return launch_sweep_nh<T, FIRST, 2>(a, g, par, st);
+    case 4: return launch_sweep_nh<T, FIRST, 4>(a, g, par, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_cg_sweep(const DeviceState& d, const SweepGeom& g, int k, int nprev,
+                           void* x, bool fp32, bool zero_x, hipStream_t st) {
+  const int par = k & 1;
+  const size_t G = (size_t)d.G;
+  if (fp32) {
+    SweepArgs<float> a{d.r32 + par * G, d.r32 + (par ^ 1) * G, d.p32 + par * G,
+                       d.p32 + (par ^ 1) * G, (float*)x, d.part, d.part_stride, nprev,
+                       zero_x ? 1 : 0, d.sc};
+    return k == 0 ? launch_sweep_ppt<float, true>(a, g, par, st)
+                  : launch_sweep_ppt<float, false>(a, g, par, st);
+  }
+  SweepArgs<double> a{d.r + par * G, d.r + (par ^ 1) * G, d.p + par * G, d.p + (par ^ 1) * G,
+                      (double*)x, d.part, d.part_stride, nprev, 0, d.sc};
+  return k == 0 ? launch_sweep_ppt<double, true>(a, g, par, st)
+                : launch_sweep_ppt<double, false>(a, g, par, st);
+}
+
+hipError_t launch_cg_check(const DeviceState& d, int k, int nprev, hipStream_t st) {
+  hipLaunchKernelGGL(k_cg_check, dim3(1), dim3(kThreads), 0, st, d.part, d.part_stride, k & 1,
+                     nprev, d.sc);
+  return hipGetLastError();
+}
+
+}  // namespace maze

@@ -73,7 +73,7 @@ __global__ __launch_bounds__(kThreads) void k_bin_ions(const double* __restrict_
   if (i >= n) return;
   const double x[3] = {pos[3 * i], pos[3 * i + 1], pos[3 * i + 2]};
   if (!isfinite(x[0]) || !isfinite(x[1]) || !isfinite(x[2])) {
-    sc->err = 1;
+    ctl_st(&sc->err, 1);
     return;
   }
   int c[3];
@@ -93,7 +93,7 @@ __global__ __launch_bounds__(kThreads) void k_bin_scan(int32_t* tile_count, int3
                                                        int32_t* tile_cursor, int ntiles,
                                                        const Scalars* sc) {
   __shared__ int32_t sums[kThreads];
-  if (sc->err) return;
+  if (ctl_ld(&sc->err)) return;
   const int tid = threadIdx.x;
   const int per = (ntiles + kThreads - 1) / kThreads;
   const int b = tid * per, e = min(ntiles, b + per);
@@ -125,7 +125,7 @@ __global__ __launch_bounds__(kThreads) void k_bin_scatter(int n, int ntx, const 
                                                           int32_t* tile_cursor, int32_t* sorted_idx,
                                                           const Scalars* sc) {
   const int i = blockIdx.x * kThreads + threadIdx.x;
-  if (i >= n || sc->err) return;
+  if (i >= n || ctl_ld(&sc->err)) return;
   const int c[3] = {ion_cell[3 * i], ion_cell[3 * i + 1], ion_cell[3 * i + 2]};
   const int slot = atomicAdd(&tile_cursor[tile_of(c, ntx)], 1);
   sorted_idx[slot] = i;
@@ -141,7 +141,7 @@ __global__ __launch_bounds__(kThreads) void k_bin_sort(int ntiles, int order,
                                                        int32_t* s_cell, double* s_w, double* s_Q,
                                                        const Scalars* sc) {
   const int t = blockIdx.x * kThreads + threadIdx.x;
-  if (t >= ntiles || sc->err) return;
+  if (t >= ntiles || ctl_ld(&sc->err)) return;
   const int b = tile_start[t], e = tile_start[t + 1];
   for (int i = b + 1; i < e; ++i) {
     const int32_t v = sorted_idx[i];
@@ -216,7 +216,7 @@ __global__ __launch_bounds__(kThreads) void k_spread(int N, int ntx, int order,
                                                      const Scalars* sc) {
 #pragma clang fp contract(off)
   __shared__ double red[8];
-  if (sc->err) return;
+  if (ctl_ld(&sc->err)) return;
   const int T = blockIdx.x;
   const int TX = T / (ntx * ntx), TY = (T / ntx) % ntx, TZ = T % ntx;
   int cx[3], cy[3], cz[3];
@@ -293,7 +293,7 @@ __global__ __launch_bounds__(kThreads) void k_gather(int n, int N, int order, do
                                                      const Scalars* sc) {
 #pragma clang fp contract(off)
   const int s = blockIdx.x * kThreads + threadIdx.x;
-  if (s >= n || sc->err) return;
+  if (s >= n || ctl_ld(&sc->err)) return;
   const int off = (order == 2) ? 0 : 1;
   int ix[kMaxOrder], iy[kMaxOrder], iz[kMaxOrder];
   int ixm[kMaxOrder], ixp[kMaxOrder], iym[kMaxOrder], iyp[kMaxOrder], izm[kMaxOrder],
@@ -357,8 +357,8 @@ __global__ __launch_bounds__(kThreads) void k_update(long long G, const double* 
                                                      double* part_e, double* part_s,
                                                      const Scalars* sc) {
   __shared__ double red[8];
-  if (sc->err) return;
-  const double pbar = sc->pbar, ybar = sc->xbar, qbar = sc->qbar;
+  if (ctl_ld(&sc->err)) return;
+  const double pbar = ctl_ld(&sc->pbar), ybar = ctl_ld(&sc->xbar), qbar = ctl_ld(&sc->qbar);
   double e = 0.0, s = 0.0;
   const long long base = (long long)blockIdx.x * kThreads * kElemPerThread + threadIdx.x;
 #pragma unroll
@@ -401,8 +401,8 @@ __global__ __launch_bounds__(kThreads) void k_project(long long G, double* x,
                                                       double* field_out, double* part_e,
                                                       double* part_s, const Scalars* sc) {
   __shared__ double red[8];
-  if (sc->err) return;
-  const double xbar = sc->xbar, qbar = sc->qbar;
+  if (ctl_ld(&sc->err)) return;
+  const double xbar = ctl_ld(&sc->xbar), qbar = ctl_ld(&sc->qbar);
   double e = 0.0, s = 0.0;
   const long long base = (long long)blockIdx.x * kThreads * kElemPerThread + threadIdx.x;
 #pragma unroll
@@ -442,8 +442,8 @@ __global__ __launch_bounds__(kThreads) void k_finalize(int mode, int count, long
   if (mode == FIN_QSUM) {
     const double s = sum_partials(slot(SL_QSUM), count, red);
     if (threadIdx.x == 0) {
-      sc->qsum = s;
-      sc->qbar = s / (double)G;
+      ctl_st(&sc->qsum, s);
+      ctl_st(&sc->qbar, s / (double)G);
     }
   } else if (mode == FIN_SOLVE_START) {
     const double qq = sum_partials(slot(SL_QQ), count, red);
@@ -451,40 +451,40 @@ __global__ __launch_bounds__(kThreads) void k_finalize(int mode, int count, long
     const double trr = sum_partials(slot(SL_TRR), count, red);
     const double tmx = max_partials(slot(SL_TMAX), count, red);
     if (threadIdx.x == 0) {
-      sc->norm = norm;
-      sc->max_iter = imax;
-      sc->qnorm = sqrt(qq);
-      sc->thr = (norm == MAZE_NORM_ABSMAX) ? tol : tol * sqrt(qq);
-      sc->pbar = pp / (double)G;
-      sc->true_rr = trr;
-      sc->true_max = tmx;
-      sc->it = 0;
-      sc->done = 0;
-      sc->iters = 0;
+      ctl_st(&sc->norm, norm);
+      ctl_st(&sc->max_iter, imax);
+      ctl_st(&sc->qnorm, sqrt(qq));
+      ctl_st(&sc->thr, (norm == MAZE_NORM_ABSMAX) ? tol : tol * sqrt(qq));
+      ctl_st(&sc->pbar, pp / (double)G);
+      ctl_st(&sc->true_rr, trr);
+      ctl_st(&sc->true_max, tmx);
+      ctl_st(&sc->it, 0);
+      ctl_st(&sc->done, 0);
+      ctl_st(&sc->iters, 0);
     }
   } else if (mode == FIN_SOLVE_END) {
     const double xs = sum_partials(slot(SL_XSUM), count, red);
     const double trr = sum_partials(slot(SL_TRR), count, red);
     const double tmx = max_partials(slot(SL_TMAX), count, red);
     if (threadIdx.x == 0) {
-      sc->xbar = xs / (double)G;
-      sc->true_rr = trr;
-      sc->true_max = tmx;
+      ctl_st(&sc->xbar, xs / (double)G);
+      ctl_st(&sc->true_rr, trr);
+      ctl_st(&sc->true_max, tmx);
     }
   } else if (mode == FIN_ENERGY) {
-    if (sc->err) return;
+    if (ctl_ld(&sc->err)) return;
     const double e = sum_partials(slot(SL_ENERGY), count, red);
     if (threadIdx.x == 0) {
-      sc->energy = 0.5 * coulomb_k * e;
+      ctl_st(&sc->energy, 0.5 * coulomb_k * e);
       if (energy_out) *energy_out = 0.5 * coulomb_k * e;
     }
   } else if (mode == FIN_INNER_START) {
     if (threadIdx.x == 0) {
-      sc->thr = param;
-      sc->max_iter = imax;
-      sc->it = 0;
-      sc->done = 0;
-      sc->iters = 0;
+      ctl_st(&sc->thr, param);
+      ctl_st(&sc->max_iter, imax);
+      ctl_st(&sc->it, 0);
+      ctl_st(&sc->done, 0);
+      ctl_st(&sc->iters, 0);
     }
   }
 }
@@ -502,7 +502,7 @@ hipError_t launch_finalize(const DeviceState& d, int mode, int count, double tol
 __global__ __launch_bounds__(kThreads) void k_add_correction(long long G, double* x,
                                                              const float* __restrict__ e,
                                                              const Scalars* sc) {
-  if (sc->err) return;
+  if (ctl_ld(&sc->err)) return;
   const long long base = (long long)blockIdx.x * kThreads * kElemPerThread + threadIdx.x;
 #pragma unroll
   for (int j = 0; j < kElemPerThread; ++j) {

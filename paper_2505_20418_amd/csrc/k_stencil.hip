@@ -1,7 +1,8 @@
-// Stencil passes of the PLCG solve of M y = sigma_p (and of the direct
-// Poisson solve M phi = -4 pi q / h): right-hand sides, the two fused CG
-// passes, the FP64 residual of the mixed-precision refinement, and the
-// true residual. All of them sweep the grid with one marching template.
+// Stencil passes around the PLCG solve of M y = sigma_p (and of the direct
+// Poisson solve M phi = -4 pi q / h): right-hand sides, the FP64 residual of
+// the mixed-precision refinement, and the true residual. All of them sweep
+// the grid with one marching template. The CG iterations themselves are the
+// fused sweeps of k_cg.hip.
 //
 // Layout: grids are N^3, index (x*N + y)*N + z, z fastest. A workgroup owns
 // a segment of S = 256*PPT consecutive points of the flattened (y, z) plane
@@ -248,9 +249,9 @@ struct OpRhsMaze {
   double c1;    // h / (4 pi)
   double qbar;
 
-  __device__ bool skip() const { return sc->err != 0; }
+  __device__ bool skip() const { return ctl_ld(&sc->err) != 0; }
   __device__ bool prepare(double*) {
-    qbar = sc->qbar;
+    qbar = ctl_ld(&sc->qbar);
     return true;
   }
   __device__ void load(long long g, double v[2]) const {
@@ -315,9 +316,9 @@ struct OpRhsPoisson {
   double c4;    // -(4 pi / h)
   double qbar;
 
-  __device__ bool skip() const { return sc->err != 0; }
+  __device__ bool skip() const { return ctl_ld(&sc->err) != 0; }
   __device__ bool prepare(double*) {
-    qbar = sc->qbar;
+    qbar = ctl_ld(&sc->qbar);
     return true;
   }
   __device__ void load(long long g, double v[1]) const {
@@ -357,124 +358,6 @@ struct OpRhsPoisson {
 };
 
 // ---------------------------------------------------------------------------
-// CG pass A (Appendix B, Jacobi PLCG with preconditioner diag(-M) = 6 I):
-// convergence test on ||r||, z = r/6, beta = rho_t / rho_{t-1},
-// p = z + beta p_old, and <p, A p> with A = -M evaluated on the fly.
-// Staged field: p (computed from r and p_old at load time).
-// ---------------------------------------------------------------------------
-template <typename TT>
-struct OpPassA {
-  using T = TT;
-  static constexpr int K = 1;
-  static constexpr int NACC = 1;
-  const T* r;
-  const T* pold;
-  T* p;
-  double* part;
-  int pstride;
-  int parity;
-  int nwg;
-  Scalars* sc;
-  T beta;
-  bool first;
-
-  __device__ bool skip() const { return sc->done != 0 || sc->err != 0; }
-  __device__ bool prepare(double* sm) {
-    const double gam = sum_partials(part + (long long)(SL_RR0 + parity) * pstride, nwg, sm);
-    bool conv;
-    if (sc->norm == MAZE_NORM_ABSMAX)
-      conv = max_partials(part + (long long)(SL_RMAX0 + parity) * pstride, nwg, sm) <= sc->thr;
-    else
-      conv = sqrt(gam) <= sc->thr;
-    const int it = sc->it;
-    const bool finite = isfinite(gam);
-    if (conv || !finite || it >= sc->max_iter) {
-      if (blockIdx.x == 0 && threadIdx.x == 0) {
-        sc->gamma[parity] = gam;
-        sc->iters = it;
-        sc->done = conv ? 1 : (finite ? 3 : 2);
-      }
-      return false;
-    }
-    first = (it == 0);
-    beta = first ? (T)0 : (T)(gam / sc->gamma[parity ^ 1]);
-    if (blockIdx.x == 0 && threadIdx.x == 0) sc->gamma[parity] = gam;
-    return true;
-  }
-  __device__ void load(long long g, T v[1]) const {
-    const T z = r[g] * (T)(1.0 / 6.0);
-    v[0] = first ? z : z + beta * pold[g];
-  }
-  __device__ void point(long long g, const T* c, const T* xm, const T* xp, const T* ym,
-                        const T* yp, const T* zm, const T* zp, double* a) const {
-    const T ap = (T)6 * c[0] - nbr_sum(xm[0], xp[0], ym[0], yp[0], zm[0], zp[0]);
-    p[g] = c[0];
-    a[0] += (double)c[0] * (double)ap;
-  }
-  __device__ static bool acc_is_max(int) { return false; }
-  __device__ static int acc_slot(int, int) { return SL_PAP; }
-  __device__ void finish_wg0() const {}
-};
-
-// ---------------------------------------------------------------------------
-// CG pass B: alpha = rho / <p, A p>, x += alpha p, r -= alpha A p (A p
-// recomputed from the staged p), ||r||^2, max |r|, sum x. On the first
-// iteration of an FP32 inner solve the correction starts from zero.
-// ---------------------------------------------------------------------------
-template <typename TT>
-struct OpPassB {
-  using T = TT;
-  static constexpr int K = 1;
-  static constexpr int NACC = 3;
-  const T* p;
-  T* x;
-  T* r;
-  double* part;
-  int pstride;
-  int parity;
-  int nwg;
-  Scalars* sc;
-  T alpha;
-  bool zero_x;
-  bool x_from_zero;  // FP32 correction: x is zero at the first iteration
-  int it;
-
-  __device__ bool skip() const { return sc->done != 0 || sc->err != 0; }
-  __device__ bool prepare(double* sm) {
-    const double gam = sc->gamma[parity];
-    const double pap = sum_partials(part + (long long)SL_PAP * pstride, nwg, sm);
-    it = sc->it;
-    if (!(pap > 0.0) || !isfinite(pap)) {
-      if (blockIdx.x == 0 && threadIdx.x == 0) {
-        sc->iters = it;
-        sc->done = 2;
-      }
-      return false;
-    }
-    alpha = (T)((gam / 6.0) / pap);
-    zero_x = x_from_zero && it == 0;
-    return true;
-  }
-  __device__ void load(long long g, T v[1]) const { v[0] = p[g]; }
-  __device__ void point(long long g, const T* c, const T* xm, const T* xp, const T* ym,
-                        const T* yp, const T* zm, const T* zp, double* a) const {
-    const T ap = (T)6 * c[0] - nbr_sum(xm[0], xp[0], ym[0], yp[0], zm[0], zp[0]);
-    const T xv = zero_x ? alpha * c[0] : x[g] + alpha * c[0];
-    x[g] = xv;
-    const T rv = r[g] - alpha * ap;
-    r[g] = rv;
-    a[0] += (double)rv * (double)rv;
-    a[1] = fmax(a[1], fabs((double)rv));
-    a[2] += (double)xv;
-  }
-  __device__ static bool acc_is_max(int i) { return i == 1; }
-  __device__ static int acc_slot(int i, int parity) {
-    return i == 0 ? SL_RR0 + (parity ^ 1) : (i == 1 ? SL_RMAX0 + (parity ^ 1) : SL_XSUM);
-  }
-  __device__ void finish_wg0() const { sc->it = it + 1; }
-};
-
-// ---------------------------------------------------------------------------
 // FP64 residual M x - s of the current solution: the true residual reported
 // at exit, and in mixed precision the outer refinement step that restores
 // an FP64 residual and hands its FP32 rounding to the next inner solve.
@@ -492,7 +375,7 @@ struct OpResidual {
   int parity;
   const Scalars* sc;
 
-  __device__ bool skip() const { return sc->err != 0; }
+  __device__ bool skip() const { return ctl_ld(&sc->err) != 0; }
   __device__ bool prepare(double*) { return true; }
   __device__ void load(long long g, double v[1]) const { v[0] = x[g]; }
   __device__ void point(long long g, const double* c, const double* xm, const double* xp,
@@ -584,36 +467,6 @@ hipError_t launch_rhs_poisson(const DeviceState& d, const MarchGeom& g, int gues
   OpRhsPoisson<false> op{d.phi_cur, d.phi_prev, d.q, d.sigma, x, d.r, nullptr,
                          d.part, d.part_stride, 0, d.sc, guess, c4, 0.0};
   return launch_march(op, g, st);
-}
-
-hipError_t launch_cg_pass(const DeviceState& d, const MarchGeom& g, int parity, double* x,
-                          bool fp32, int which, hipStream_t st) {
-  if (fp32) {
-    float* pn = d.p32 + (size_t)parity * d.G;
-    const float* po = d.p32 + (size_t)(parity ^ 1) * d.G;
-    if (which == 0) {
-      OpPassA<float> a{d.r32, po, pn, d.part, d.part_stride, parity, g.nwg, d.sc, 0.f, false};
-      return launch_march(a, g, st);
-    }
-    OpPassB<float> b{pn, d.e32, d.r32, d.part, d.part_stride, parity, g.nwg, d.sc,
-                     0.f, false, true, 0};
-    return launch_march(b, g, st);
-  }
-  double* pn = d.p + (size_t)parity * d.G;
-  const double* po = d.p + (size_t)(parity ^ 1) * d.G;
-  if (which == 0) {
-    OpPassA<double> a{d.r, po, pn, d.part, d.part_stride, parity, g.nwg, d.sc, 0.0, false};
-    return launch_march(a, g, st);
-  }
-  OpPassB<double> b{pn, x, d.r, d.part, d.part_stride, parity, g.nwg, d.sc, 0.0, false, false, 0};
-  return launch_march(b, g, st);
-}
-
-hipError_t launch_cg_iteration(const DeviceState& d, const MarchGeom& g, int parity,
-                               double* x, bool fp32, hipStream_t st) {
-  const hipError_t e = launch_cg_pass(d, g, parity, x, fp32, 0, st);
-  if (e != hipSuccess) return e;
-  return launch_cg_pass(d, g, parity, x, fp32, 1, st);
 }
 
 hipError_t launch_refine(const DeviceState& d, const MarchGeom& g, double* x, bool,

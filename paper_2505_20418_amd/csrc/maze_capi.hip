@@ -19,7 +19,8 @@ constexpr int kPollBatch = 8;          // CG iterations queued between polls
 constexpr int kMaxRefinements = 40;    // mixed precision outer iterations
 constexpr double kInnerReduction = 1e-5;  // FP32 inner solve target (relative)
 constexpr uint64_t kMagic = 0x4d415a4531534553ull;  // "MAZE1SES"
-constexpr int kProfMax = 4096;         // CG iterations timed per solve
+constexpr int kProfMax = 512;          // sweeps timed per solve
+constexpr int kProfStride = 4;         // every kProfStride-th sweep is timed
 
 struct SaveHeader {
   uint64_t magic;
@@ -35,6 +36,7 @@ struct maze_session {
   maze_config cfg{};
   DeviceState d;
   MarchGeom geom{};
+  SweepGeom sweep{};
   hipStream_t stream = nullptr;
   int device = 0;
   Scalars* host_sc = nullptr;   // pinned, 2 slots for pipelined polling
@@ -46,7 +48,7 @@ struct maze_session {
   // inner iteration counts of the previous mixed solve, per refinement
   int last_inner[kMaxRefinements] = {0};
   char* base = nullptr;         // the session's single device allocation
-  // optional pass timing: events before pass A, between A and B, after B
+  // optional sweep timing: event pairs around sampled sweeps
   bool prof = false;
   std::vector<hipEvent_t> pev;
   double prof_acc[8] = {0};
@@ -89,8 +91,18 @@ static MarchGeom choose_geom(int N) {
   return make_march_geom(N, 1, 2);
 }
 
-static int part_stride_for(const DeviceState& d, const MarchGeom& g) {
-  return std::max({g.nwg, update_blocks(d.G), d.ntiles, 1});
+// Launch shape of the fused CG sweep. A run of cx planes re-reads four halo
+// planes of p and two of r, so runs are long; segments are sized to give
+// about two workgroups per CU at 256^3.
+static SweepGeom choose_sweep(int N) {
+  if (N >= 192) return make_sweep_geom(N, 4, 32);
+  if (N >= 96) return make_sweep_geom(N, 2, 16);
+  if (N >= 48) return make_sweep_geom(N, 1, 8);
+  return make_sweep_geom(N, 1, 4);
+}
+
+static int part_stride_for(const DeviceState& d, const MarchGeom& g, const SweepGeom& w) {
+  return std::max({g.nwg, w.nwg, update_blocks(d.G), d.ntiles, 1});
 }
 
 struct Layout {
@@ -114,8 +126,7 @@ static Layout layout_for(const maze_config* c, int N, int* ntx_out, int* ntiles_
   DeviceState tmp;
   tmp.G = G;
   tmp.ntiles = ntiles;
-  const MarchGeom g = choose_geom(N);
-  const int stride = part_stride_for(tmp, g);
+  const int stride = part_stride_for(tmp, choose_geom(N), choose_sweep(N));
   const bool mixed = c->precision == MAZE_MIXED;
   const size_t n = (size_t)c->n_ions;
   Layout L;
@@ -126,9 +137,9 @@ static Layout layout_for(const maze_config* c, int N, int* ntx_out, int* ntiles_
   L.add(gd);                 // 3 q
   L.add(gd);                 // 4 sigma
   L.add(gd);                 // 5 xsolve
-  L.add(mixed ? 0 : gd);     // 6 r
+  L.add(mixed ? 0 : 2 * gd); // 6 r (two buffers)
   L.add(mixed ? 0 : 2 * gd); // 7 p (two buffers)
-  L.add(mixed ? gf : 0);     // 8 r32
+  L.add(mixed ? 2 * gf : 0); // 8 r32 (two buffers)
   L.add(mixed ? 2 * gf : 0); // 9 p32 (two buffers)
   L.add(mixed ? gf : 0);     // 10 e32
   L.add(sizeof(double) * (size_t)SL_COUNT * stride);  // 11 partials
@@ -150,69 +161,70 @@ static Layout layout_for(const maze_config* c, int N, int* ntx_out, int* ntiles_
 }
 
 // ---------------------------------------------------------------------------
-// Host loop of one CG solve: queue iterations in batches, copy the device
+// Host loop of one CG solve: queue sweeps in batches, copy the device
 // scalars to pinned memory after each batch, and stop queueing once a
-// completed batch reports done (the batch in flight then exits early).
+// completed batch reports done (sweeps queued after convergence return at
+// once). At most max_iter + 1 sweeps are queued (sweep 0 only forms p_0);
+// after the last one a check kernel applies the stopping test.
 // ---------------------------------------------------------------------------
-static void prof_collect(maze_session* s, int iters, bool fp32) {
-  const int n = std::min(iters, kProfMax);
-  double* acc = s->prof_acc + (fp32 ? 4 : 0);
-  for (int t = 0; t < n; ++t) {
-    float a = 0.f, b = 0.f;
-    if (hipEventElapsedTime(&a, s->pev[2 * t], s->pev[2 * t + 1]) == hipSuccess &&
-        hipEventElapsedTime(&b, s->pev[2 * t + 1], s->pev[2 * t + 2]) == hipSuccess) {
+static void prof_collect(maze_session* s, int timed, int iters, bool fp32) {
+  double* acc = s->prof_acc + (fp32 ? 2 : 0);
+  for (int j = 0; j < timed; ++j) {
+    // sample j timed sweep k = 1 + j * kProfStride; sweeps past `iters`
+    // returned without work and are not counted
+    if (1 + j * kProfStride > iters) break;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, s->pev[2 * j], s->pev[2 * j + 1]) == hipSuccess) {
       acc[0] += 1;
-      acc[1] += a;
-      acc[2] += 1;
-      acc[3] += b;
+      acc[1] += ms;
     }
   }
+  s->prof_acc[fp32 ? 5 : 4] += iters;
 }
 
-static int run_cg(maze_session* s, double* x, bool fp32, int first_batch, int* iters,
-                  int* done_code) {
+static int run_cg(maze_session* s, void* x, bool fp32, bool zero_x, int max_iter,
+                  int first_batch, int* iters, int* done_code) {
   DeviceState& d = s->d;
-  int t = 0, batch = 0;
-  bool have_prev = false;
+  const SweepGeom& w = s->sweep;
+  const long long cap = (long long)max_iter + 1;
+  long long k = 0;
+  int batch = 0, timed = 0;
+  bool have_prev = false, capped = false;
   const bool prof = s->prof;
   for (;;) {
     const int nb = (batch == 0) ? std::max(kPollBatch, first_batch) : kPollBatch;
-    for (int k = 0; k < nb; ++k, ++t) {
-      const bool timed = prof && t < kProfMax;
-      if (timed && t == 0) HIP_TRY(hipEventRecord(s->pev[0], s->stream));
-      HIP_TRY(launch_cg_pass(d, s->geom, t & 1, x, fp32, 0, s->stream));
-      if (timed) HIP_TRY(hipEventRecord(s->pev[2 * t + 1], s->stream));
-      HIP_TRY(launch_cg_pass(d, s->geom, t & 1, x, fp32, 1, s->stream));
-      if (timed) HIP_TRY(hipEventRecord(s->pev[2 * t + 2], s->stream));
+    for (int b = 0; b < nb && k < cap; ++b, ++k) {
+      const int nprev = (k == 0) ? s->geom.nwg : w.nwg;
+      const bool timeit = prof && k >= 1 && (k - 1) % kProfStride == 0 && timed < kProfMax;
+      if (timeit) HIP_TRY(hipEventRecord(s->pev[2 * timed], s->stream));
+      HIP_TRY(launch_cg_sweep(d, w, (int)k, nprev, x, fp32, zero_x, s->stream));
+      if (timeit) {
+        HIP_TRY(hipEventRecord(s->pev[2 * timed + 1], s->stream));
+        ++timed;
+      }
+    }
+    if (k == cap && !capped) {
+      HIP_TRY(launch_cg_check(d, (int)(k & 1), w.nwg, s->stream));
+      capped = true;
     }
     const int slot = batch & 1;
     HIP_TRY(hipMemcpyAsync(&s->host_sc[slot], d.sc, sizeof(Scalars), hipMemcpyDeviceToHost,
                            s->stream));
     HIP_TRY(hipEventRecord(s->ev[slot], s->stream));
-    if (have_prev) {
-      const int ps = slot ^ 1;
-      HIP_TRY(hipEventSynchronize(s->ev[ps]));
-      const Scalars& h = s->host_sc[ps];
+    const int wait_slot = capped ? slot : (slot ^ 1);
+    if (have_prev || capped) {
+      HIP_TRY(hipEventSynchronize(s->ev[wait_slot]));
+      const Scalars& h = s->host_sc[wait_slot];
       if (h.err) return MAZE_E_NONFINITE;
-      if (h.done) {
+      if (h.done || capped) {
         *iters = h.iters;
-        *done_code = h.done;
-        if (prof) prof_collect(s, h.iters, fp32);
+        *done_code = h.done ? h.done : 3;
+        if (prof) prof_collect(s, timed, h.iters, fp32);
         return MAZE_OK;
       }
     }
     have_prev = true;
     ++batch;
-    // the device stops at max_iter by itself; this only guards the host
-    if (t > s->cfg.max_iter + 4 * kPollBatch + first_batch + 64) {
-      HIP_TRY(hipEventSynchronize(s->ev[slot]));
-      const Scalars& h = s->host_sc[slot];
-      if (h.err) return MAZE_E_NONFINITE;
-      *iters = h.iters;
-      *done_code = h.done ? h.done : 3;
-      if (prof) prof_collect(s, h.iters, fp32);
-      return MAZE_OK;
-    }
   }
 }
 
@@ -246,7 +258,8 @@ static int solve(maze_session* s, double* x) {
   s->converged = 0;
   if (!mixed) {
     int it = 0, code = 0;
-    const int rc = run_cg(s, x, false, std::max(0, s->last_iters - 2 * kPollBatch), &it, &code);
+    const int rc = run_cg(s, x, false, false, s->cfg.max_iter,
+                          std::max(0, s->last_iters - 2 * kPollBatch), &it, &code);
     if (rc != MAZE_OK) return rc;
     s->iters = it;
     s->converged = (code == 1);
@@ -274,7 +287,8 @@ static int solve(maze_session* s, double* x) {
                             s->cfg.max_iter - total, s->cfg.residual_norm, s->stream));
     int it = 0, code = 0;
     const int guess_it = s->last_inner[s->refinements];
-    rc = run_cg(s, nullptr, true, std::max(0, guess_it - 2 * kPollBatch), &it, &code);
+    rc = run_cg(s, d.e32, true, true, s->cfg.max_iter - total,
+                std::max(0, guess_it - 2 * kPollBatch), &it, &code);
     if (rc != MAZE_OK) return rc;
     s->last_inner[s->refinements] = it;
     total += it;
@@ -424,6 +438,7 @@ int maze_init(const maze_config* cfg, const double* charges_dev, const double* p
   d.box = cfg->box;
   d.h = cfg->box / d.N;
   s->geom = choose_geom(d.N);
+  s->sweep = choose_sweep(d.N);
   const Layout L = layout_for(cfg, d.N, &d.ntx, &d.ntiles, &d.part_stride);
   char* base = nullptr;
   if (hipMalloc((void**)&base, L.total) != hipSuccess) {
@@ -621,7 +636,7 @@ int maze_profile_enable(maze_session* s, int on) {
   if (!s) return MAZE_E_INVALID;
   hipSetDevice(s->device);
   if (on && s->pev.empty()) {
-    s->pev.assign(2 * kProfMax + 1, nullptr);
+    s->pev.assign(2 * kProfMax, nullptr);
     for (auto& e : s->pev)
       if (hipEventCreate(&e) != hipSuccess) return MAZE_E_DEVICE;
   }

@@ -23,11 +23,16 @@ enum PartialSlot : int {
   SL_QSUM = 0,     // sum of raw assigned charge (spread)
   SL_PHIP,         // sum of phi_p, or of the start vector of a direct solve
   SL_QQ,           // ||q - qbar||^2, or ||rhs||^2 of a direct solve
-  SL_RR0,          // ||r||^2, parity 0
-  SL_RR1,          // ||r||^2, parity 1
-  SL_RMAX0,        // max |r|, parity 0
-  SL_RMAX1,        // max |r|, parity 1
-  SL_PAP,          // <p, A p>
+  SL_RR0,          // ||r||^2, parity 0 (SL_RR0 + 1: parity 1)
+  SL_RR1,
+  SL_RMAX0,        // max |r|, parity 0 / 1
+  SL_RMAX1,
+  SL_MU0,          // <p, A p> of a CG sweep, parity 0 / 1
+  SL_MU1,
+  SL_RW0,          // <r, A p>, parity 0 / 1
+  SL_RW1,
+  SL_WW0,          // <A p, A p>, parity 0 / 1
+  SL_WW1,
   SL_XSUM,         // sum of the solution vector (y or phi)
   SL_TRR,          // true FP64 residual ||M x - s||^2
   SL_TMAX,         // true FP64 residual max
@@ -79,6 +84,24 @@ struct MarchGeom {
 
 MarchGeom make_march_geom(int N, int ppt, int cx);
 
+// Geometry of a fused CG sweep (k_cg.hip): segments of S = kThreads * ppt
+// points of the (y, z) plane times runs of cx x planes; nh = halo slots per
+// thread for one row on each side of the segment.
+struct SweepGeom {
+  int N;
+  int P;          // N*N
+  int S;
+  int nseg;
+  int cx;
+  int nchunk;
+  int nwg;
+  int ppt;
+  int nh;
+};
+
+SweepGeom make_sweep_geom(int N, int ppt, int cx);
+size_t sweep_lds_bytes(const SweepGeom& g, bool fp32, bool first);
+
 // Device buffers of one session. All allocated in maze_init.
 struct DeviceState {
   int N = 0;
@@ -94,7 +117,8 @@ struct DeviceState {
   double* q = nullptr;
   double* sigma = nullptr;
   double* xsolve = nullptr;
-  // CG work vectors: FP64 (r, p) and FP32 (r32, p32, e32)
+  // CG work vectors, each double-buffered (G elements per buffer): FP64
+  // (r, p) and FP32 (r32, p32), plus the FP32 correction e32
   double* r = nullptr;
   double* p = nullptr;
   float* r32 = nullptr;
@@ -143,12 +167,14 @@ hipError_t launch_rhs_maze(const DeviceState& d, const MarchGeom& g, bool mixed,
                            hipStream_t st);
 hipError_t launch_rhs_poisson(const DeviceState& d, const MarchGeom& g, int guess,
                               double* x, bool mixed, hipStream_t st);
-// One CG pass (which = 0: pass A, 1: pass B) on the FP64 or FP32 vectors.
-hipError_t launch_cg_pass(const DeviceState& d, const MarchGeom& g, int parity, double* x,
-                          bool fp32, int which, hipStream_t st);
-// One CG iteration = pass A + pass B, on the FP64 or FP32 vectors.
-hipError_t launch_cg_iteration(const DeviceState& d, const MarchGeom& g, int parity,
-                               double* x, bool fp32, hipStream_t st);
+// CG sweep k of a solve (k = 0 is the first sweep: p_0 = r_0 / 6, no update)
+// on the FP64 (x: double*) or FP32 (x: float*) vectors; nprev = partials
+// written by the previous kernel; zero_x: the first sweep zeroes x.
+hipError_t launch_cg_sweep(const DeviceState& d, const SweepGeom& g, int k, int nprev,
+                           void* x, bool fp32, bool zero_x, hipStream_t st);
+// Stopping test after the last permitted sweep (k sweeps done): sets done to
+// 1 (converged) or 3 (iteration cap).
+hipError_t launch_cg_check(const DeviceState& d, int k, int nprev, hipStream_t st);
 // Mixed precision: x += e (FP64), FP64 residual M x - s, r32 = float(residual),
 // e = 0; partials SL_TRR/SL_TMAX (FP64) and SL_RR0/SL_RMAX0 (of r32).
 hipError_t launch_refine(const DeviceState& d, const MarchGeom& g, double* x,

@@ -239,8 +239,8 @@ def maze_profile_read(handle) -> dict:
     out = (ctypes.c_double * 8)()
     _check(lib().maze_profile_read(handle, out), "maze_profile_read")
     v = list(out)
-    return dict(fp64_a=(int(v[0]), v[1]), fp64_b=(int(v[2]), v[3]),
-                fp32_a=(int(v[4]), v[5]), fp32_b=(int(v[6]), v[7]))
+    return dict(fp64_sweep=(int(v[0]), v[1]), fp32_sweep=(int(v[2]), v[3]),
+                fp64_iters=int(v[4]), fp32_iters=int(v[5]))
 
 
 # ---- convenience wrapper -------------------------------------------------------
