@@ -227,8 +227,9 @@ def main():
         fp64 = run_md(system, tol, maze.MAZE_FP64, args.steps, args.warmup,
                       record_positions=True)
         log(f"bench: fp64 {fp64['steps_per_s']:.3f} steps/s")
-        errors = replay_errors(system, fp64["traj"], tol, args.replay)
-        log(f"bench: mixed vs fp64 errors {errors}")
+        if args.replay > 0:
+            errors = replay_errors(system, fp64["traj"], tol, args.replay)
+            log(f"bench: mixed vs fp64 errors {errors}")
 
     r_mixed = roofline("fp32_sweep", mixed["prof"], G, "fp32")
     attach_traffic(r_mixed, "fp32_sweep")
