@@ -180,6 +180,22 @@ int maze_load(maze_session* s, const void* host_buf, size_t bytes);
 int maze_profile_enable(maze_session* s, int on);
 int maze_profile_read(maze_session* s, double* out8);
 
+/* Residual trace of the last solve (for convergence studies such as the
+ * residual-versus-iteration comparison of Appendix B). When enabled, each
+ * solve records, per CG iteration k, the norm of the recursive residual
+ * ||r_k||_2 divided by the right-hand-side scale (||q - qbar||_2 for a MaZe
+ * step, ||4 pi q / h||_2 for a direct solve), as rows of three doubles
+ * {pass, k, ||r_k|| / scale}; pass counts the FP32 inner solves of the
+ * mixed-precision refinement (0 in FP64). Mixed precision also records the
+ * FP64 true residual before each pass as {pass, -1, residual / scale}.
+ * Recording copies the history to the host after every solve (a stream
+ * synchronisation), so it is for studies, not for timing. Enabling clears
+ * the trace; every solve replaces it.
+ * maze_trace_read copies min(max_rows, n) rows into out (HOST memory, 3 *
+ * max_rows doubles) and stores the number of rows n in *n_rows. */
+int maze_trace_enable(maze_session* s, int on);
+int maze_trace_read(const maze_session* s, double* out, int max_rows, int* n_rows);
+
 /* Frees every device buffer of the session (NULL is a no-op). */
 void maze_destroy(maze_session* s);
 

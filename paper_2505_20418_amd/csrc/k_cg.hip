@@ -129,6 +129,8 @@ struct SweepArgs {
   int nprev;     // number of partials written by the previous kernel
   int zero_x;    // FIRST only: write x = 0 (start of an FP32 correction solve)
   Scalars* sc;
+  double* hist;  // residual history: hist[k] = ||r_k||_2 of the current solve
+  int hist_cap;
 };
 
 __device__ __forceinline__ int wrap_plane(int u, int N) {
@@ -151,6 +153,12 @@ __global__ __launch_bounds__(kThreads) void k_cg_sweep(SweepArgs<T> a, SweepGeom
     const double gam = v[0];
     const double thr = ctl_ld(&sc->thr);
     const bool conv = (ctl_ld(&sc->norm) == MAZE_NORM_ABSMAX) ? (v[1] <= thr) : (sqrt(gam) <= thr);
+    if (blockIdx.x == 0 && tid == 0) {
+      // ||r_it|| of the sweep that wrote these partials (it = number of
+      // updates done so far in this solve)
+      const int it = ctl_ld(&sc->it);
+      if (it < a.hist_cap) a.hist[it] = sqrt(gam);
+    }
     bool stop = conv || !isfinite(gam);
     int code = conv ? 1 : 2;
     if (!FIRST && !stop) {
@@ -414,7 +422,8 @@ __global__ __launch_bounds__(kThreads) void k_cg_sweep(SweepArgs<T> a, SweepGeom
 
 // Stopping test after the last permitted sweep: converged or iteration cap.
 __global__ __launch_bounds__(kThreads) void k_cg_check(double* part, int pstride, int par,
-                                                        int nprev, Scalars* sc) {
+                                                        int nprev, Scalars* sc, double* hist,
+                                                        int hist_cap) {
   __shared__ double red[5 * (kThreads / 64)];
   if (ctl_ld(&sc->done) != 0 || ctl_ld(&sc->err) != 0) return;
   double v[5];
@@ -422,8 +431,10 @@ __global__ __launch_bounds__(kThreads) void k_cg_check(double* part, int pstride
   if (threadIdx.x == 0) {
     const double thr = ctl_ld(&sc->thr);
     const bool conv = (ctl_ld(&sc->norm) == MAZE_NORM_ABSMAX) ? (v[1] <= thr) : (sqrt(v[0]) <= thr);
+    const int it = ctl_ld(&sc->it);
+    if (it < hist_cap) hist[it] = sqrt(v[0]);
     ctl_st(&sc->gamma[par], v[0]);
-    ctl_st(&sc->iters, ctl_ld(&sc->it));
+    ctl_st(&sc->iters, it);
     ctl_st(&sc->done, conv ? 1 : 3);
   }
 }
@@ -479,19 +490,19 @@ hipError_t launch_cg_sweep(const DeviceState& d, const SweepGeom& g, int k, int 
   if (fp32) {
     SweepArgs<float> a{d.r32 + par * G, d.r32 + (par ^ 1) * G, d.p32 + par * G,
                        d.p32 + (par ^ 1) * G, (float*)x, d.part, d.part_stride, nprev,
-                       zero_x ? 1 : 0, d.sc};
+                       zero_x ? 1 : 0, d.sc, d.hist, d.hist_cap};
     return k == 0 ? launch_sweep_ppt<float, true>(a, g, par, st)
                   : launch_sweep_ppt<float, false>(a, g, par, st);
   }
   SweepArgs<double> a{d.r + par * G, d.r + (par ^ 1) * G, d.p + par * G, d.p + (par ^ 1) * G,
-                      (double*)x, d.part, d.part_stride, nprev, 0, d.sc};
+                      (double*)x, d.part, d.part_stride, nprev, 0, d.sc, d.hist, d.hist_cap};
   return k == 0 ? launch_sweep_ppt<double, true>(a, g, par, st)
                 : launch_sweep_ppt<double, false>(a, g, par, st);
 }
 
 hipError_t launch_cg_check(const DeviceState& d, int k, int nprev, hipStream_t st) {
   hipLaunchKernelGGL(k_cg_check, dim3(1), dim3(kThreads), 0, st, d.part, d.part_stride, k & 1,
-                     nprev, d.sc);
+                     nprev, d.sc, d.hist, d.hist_cap);
   return hipGetLastError();
 }
 

@@ -5,8 +5,11 @@
 //
 // Scratch layout (md.scratch_dev): [0, 3n) positions before the drift,
 // [3n, 6n) electrostatic forces before the drift, then per-workgroup
-// partials: 5 slots of `nb` doubles (short-range energy, kinetic energy,
-// work increment, unused, unused) followed by 3*nb momentum partials.
+// partials: 5 slots of `nb` doubles (unused, kinetic energy, work increment,
+// unused, unused) followed by 3*nb momentum partials. The short-range
+// energy partials go to the session's own buffer (DeviceState::md_epart).
+#include <cmath>
+
 #include "device_util.h"
 
 namespace maze {
@@ -106,6 +109,87 @@ __global__ __launch_bounds__(kThreads) void k_md_bmh(MdParams p, const double* _
   if (threadIdx.x == 0) part_e[blockIdx.x] = te;
 }
 
+// Short range over the tiles of the MaZe binning (tiles of kTile^3 grid
+// points, filled by the assignment of the step at the same positions): each
+// ion visits the (2R+1)^3 tiles around its own, R tiles covering the cutoff.
+// Eight lanes share one ion, each taking every eighth tile of the block in a
+// fixed order, and the lanes' sums are combined by a fixed butterfly, so the
+// result is deterministic. Energy counts each pair once (j > i) and is
+// reduced per workgroup into e_part.
+constexpr int kBmhLanes = 8;
+
+struct BmhTiles {
+  const int32_t* tile_start;
+  const int32_t* sorted_idx;
+  const int32_t* s_cell;
+  int ntx;
+  int R;
+};
+
+__global__ __launch_bounds__(kThreads) void k_md_bmh_tiles(MdParams p, BmhTiles t,
+                                                           const double* __restrict__ pos,
+                                                           const int32_t* __restrict__ species,
+                                                           double* __restrict__ f_sr,
+                                                           double* e_part) {
+  __shared__ double red[8];
+  const int gt = blockIdx.x * kThreads + threadIdx.x;
+  const int s = gt / kBmhLanes, lane = gt % kBmhLanes;
+  const bool act = s < p.n;
+  double fx = 0, fy = 0, fz = 0, e = 0;
+  int i = 0;
+  if (act) {
+    i = t.sorted_idx[s];
+    const double xi = pos[3 * i], yi = pos[3 * i + 1], zi = pos[3 * i + 2];
+    const int si = species[i];
+    const int tx = t.s_cell[3 * s] / kTile, ty = t.s_cell[3 * s + 1] / kTile,
+              tz = t.s_cell[3 * s + 2] / kTile;
+    double vshift[3];
+    for (int q = 0; q < 3; ++q) vshift[q] = bmh_v(p.tab + 5 * q, p.cutoff);
+    const double rc2 = p.cutoff * p.cutoff;
+    const int W = 2 * t.R + 1, ntot = W * W * W;
+    for (int c = lane; c < ntot; c += kBmhLanes) {
+      int ax = tx + c / (W * W) - t.R, ay = ty + (c / W) % W - t.R, az = tz + c % W - t.R;
+      ax = (ax < 0) ? ax + t.ntx : (ax >= t.ntx ? ax - t.ntx : ax);
+      ay = (ay < 0) ? ay + t.ntx : (ay >= t.ntx ? ay - t.ntx : ay);
+      az = (az < 0) ? az + t.ntx : (az >= t.ntx ? az - t.ntx : az);
+      const int ct = (ax * t.ntx + ay) * t.ntx + az;
+      const int b = t.tile_start[ct], en = t.tile_start[ct + 1];
+      for (int s2 = b; s2 < en; ++s2) {
+        const int j = t.sorted_idx[s2];
+        if (j == i) continue;
+        double dx = xi - pos[3 * j], dy = yi - pos[3 * j + 1], dz = zi - pos[3 * j + 2];
+        dx -= p.box * rint(dx * p.inv_box);
+        dy -= p.box * rint(dy * p.inv_box);
+        dz -= p.box * rint(dz * p.inv_box);
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        if (r2 >= rc2) continue;
+        const double r = sqrt(r2);
+        const int q = si + species[j];
+        const double* row = p.tab + 5 * q;
+        const double f = -bmh_dvdr(row, r) / r;
+        fx += f * dx;
+        fy += f * dy;
+        fz += f * dz;
+        if (j > i) e += bmh_v(row, r) - vshift[q];
+      }
+    }
+  }
+#pragma unroll
+  for (int m = kBmhLanes / 2; m > 0; m >>= 1) {
+    fx += __shfl_xor(fx, m, 64);
+    fy += __shfl_xor(fy, m, 64);
+    fz += __shfl_xor(fz, m, 64);
+    e += __shfl_xor(e, m, 64);
+  }
+  if (act && lane == 0) {
+    f_sr[3 * i] = fx;
+    f_sr[3 * i + 1] = fy;
+    f_sr[3 * i + 2] = fz;
+  }
+  const double te = block_sum((lane == 0) ? e : 0.0, red);
+  if (threadIdx.x == 0) e_part[blockIdx.x] = te;
+}
+
 // First half kick and drift; remembers the positions and electrostatic
 // forces before the drift for the work integral.
 __global__ __launch_bounds__(kThreads) void k_md_kick_drift(MdParams p, double* pos, double* vel,
@@ -171,10 +255,11 @@ __global__ __launch_bounds__(kThreads) void k_md_kick2(MdParams p, const double*
   }
 }
 
-__global__ __launch_bounds__(kThreads) void k_md_finish(const double* part, int nb, int prime,
+__global__ __launch_bounds__(kThreads) void k_md_finish(const double* part, int nb,
+                                                        const double* e_part, int ne, int prime,
                                                         double* scalars) {
   __shared__ double red[8];
-  const double e_sr = sum_partials(part + 0 * nb, nb, red);
+  const double e_sr = sum_partials(e_part, ne, red);
   const double ke = sum_partials(part + 1 * nb, nb, red);
   const double w = sum_partials(part + 2 * nb, nb, red);
   const double px = sum_partials(part + 5 * nb, nb, red);
@@ -199,16 +284,41 @@ hipError_t launch_md_kick_drift(const maze_md_state& md, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_md_bmh(const maze_md_state& md, double box, hipStream_t st) {
-  MdParams p = md_params(md, box);
+// Tile search radius covering the cutoff (one more tile when the last tile
+// of an axis is partial); 0 when the tile block would wrap onto itself, in
+// which case the all-pairs kernel runs.
+static int bmh_tile_radius(const DeviceState& d, double cutoff) {
+  const double edge = kTile * d.h;
+  int R = (int)std::ceil(cutoff / edge);
+  if (d.N % kTile != 0) R += 1;
+  return (2 * R + 1 <= d.ntx) ? R : 0;
+}
+
+int md_energy_partials(const DeviceState& d, double cutoff) {
+  const int n = d.n_ions;
+  if (bmh_tile_radius(d, cutoff) > 0)
+    return (int)(((long long)n * kBmhLanes + kThreads - 1) / kThreads);
+  return md_blocks(n);
+}
+
+hipError_t launch_md_bmh(const maze_md_state& md, const DeviceState& d, hipStream_t st) {
+  MdParams p = md_params(md, d.box);
   const int n = md.n_ions;
-  hipLaunchKernelGGL(k_md_bmh, dim3(md_blocks(n)), dim3(kThreads), 0, st, p,
-                     (const double*)md.pos_dev, md.species_dev, md.f_sr_dev,
-                     md.scratch_dev + 6 * (size_t)n);
+  const int R = bmh_tile_radius(d, md.cutoff);
+  if (R > 0) {
+    BmhTiles t{d.tile_start, d.sorted_idx, d.s_cell, d.ntx, R};
+    hipLaunchKernelGGL(k_md_bmh_tiles, dim3(md_energy_partials(d, md.cutoff)), dim3(kThreads), 0,
+                       st, p, t, (const double*)md.pos_dev, md.species_dev, md.f_sr_dev,
+                       d.md_epart);
+  } else {
+    hipLaunchKernelGGL(k_md_bmh, dim3(md_blocks(n)), dim3(kThreads), 0, st, p,
+                       (const double*)md.pos_dev, md.species_dev, md.f_sr_dev, d.md_epart);
+  }
   return hipGetLastError();
 }
 
-static hipError_t md_finish(const maze_md_state& md, int do_kick, hipStream_t st) {
+static hipError_t md_finish(const maze_md_state& md, const DeviceState& d, int do_kick,
+                            hipStream_t st) {
   MdParams p = md_params(md, 1.0);
   const int n = md.n_ions, nb = md_blocks(n);
   double* part = md.scratch_dev + 6 * (size_t)n;
@@ -217,11 +327,16 @@ static hipError_t md_finish(const maze_md_state& md, int do_kick, hipStream_t st
                      (const double*)md.f_sr_dev, (const double*)md.scratch_dev,
                      (const double*)(md.scratch_dev + 3 * (size_t)n), do_kick, part, nb);
   hipLaunchKernelGGL(k_md_finish, dim3(1), dim3(kThreads), 0, st, (const double*)part, nb,
+                     (const double*)d.md_epart, md_energy_partials(d, md.cutoff),
                      do_kick ? 0 : 1, md.scalars_dev);
   return hipGetLastError();
 }
 
-hipError_t launch_md_finish(const maze_md_state& md, hipStream_t st) { return md_finish(md, 1, st); }
-hipError_t launch_md_prime(const maze_md_state& md, hipStream_t st) { return md_finish(md, 0, st); }
+hipError_t launch_md_finish(const maze_md_state& md, const DeviceState& d, hipStream_t st) {
+  return md_finish(md, d, 1, st);
+}
+hipError_t launch_md_prime(const maze_md_state& md, const DeviceState& d, hipStream_t st) {
+  return md_finish(md, d, 0, st);
+}
 
 }  // namespace maze

@@ -17,7 +17,14 @@ namespace {
 
 constexpr int kPollBatch = 8;          // CG iterations queued between polls
 constexpr int kMaxRefinements = 40;    // mixed precision outer iterations
-constexpr double kInnerReduction = 1e-5;  // FP32 inner solve target (relative)
+// Mixed precision: one FP32 inner solve may reduce the residual it starts
+// from by at most kInnerReduction, and aims at kInnerMargin times the final
+// threshold. The FP32 recursive residual tracks the FP64 true residual to a
+// few parts in 1e4 over such a reduction (measured at 256^3), so a warm step
+// normally finishes in one pass; restarting the inner CG earlier discards its
+// Krylov space and costs iterations.
+constexpr double kInnerReduction = 1e-7;
+constexpr double kInnerMargin = 0.95;
 constexpr uint64_t kMagic = 0x4d415a4531534553ull;  // "MAZE1SES"
 constexpr int kProfMax = 512;          // sweeps timed per solve
 constexpr int kProfStride = 4;         // every kProfStride-th sweep is timed
@@ -52,6 +59,11 @@ struct maze_session {
   bool prof = false;
   std::vector<hipEvent_t> pev;
   double prof_acc[8] = {0};
+  // optional residual trace of the last solve: rows (pass, iteration, rel)
+  bool trace = false;
+  int trace_pass = 0;
+  std::vector<double> trace_rows;
+  std::vector<double> hist_host;
 };
 
 #define HIP_TRY(expr)                         \
@@ -154,6 +166,8 @@ static Layout layout_for(const maze_config* c, int N, int* ntx_out, int* ntiles_
   L.add(sizeof(int32_t) * 3 * n);         // 20 s_cell
   L.add(sizeof(double) * 3 * n * c->order);  // 21 s_w
   L.add(sizeof(double) * n);              // 22 s_Q
+  L.add(sizeof(double) * (n + 1));        // 23 md_epart
+  L.add(sizeof(double) * kHistCap);       // 24 residual history
   if (ntx_out) *ntx_out = ntx;
   if (ntiles_out) *ntiles_out = ntiles;
   if (stride_out) *stride_out = stride;
@@ -220,6 +234,19 @@ static int run_cg(maze_session* s, void* x, bool fp32, bool zero_x, int max_iter
         *iters = h.iters;
         *done_code = h.done ? h.done : 3;
         if (prof) prof_collect(s, timed, h.iters, fp32);
+        if (s->trace) {
+          const int n = std::min(h.iters + 1, s->d.hist_cap);
+          s->hist_host.resize(n);
+          HIP_TRY(hipMemcpyAsync(s->hist_host.data(), s->d.hist, sizeof(double) * n,
+                                 hipMemcpyDeviceToHost, s->stream));
+          HIP_TRY(hipStreamSynchronize(s->stream));
+          const double qn = h.qnorm > 0 ? h.qnorm : 1.0;
+          for (int t = 0; t < n; ++t) {
+            s->trace_rows.push_back(s->trace_pass);
+            s->trace_rows.push_back(t);
+            s->trace_rows.push_back(s->hist_host[t] / qn);
+          }
+        }
         return MAZE_OK;
       }
     }
@@ -256,6 +283,8 @@ static int solve(maze_session* s, double* x) {
   s->iters = 0;
   s->refinements = 0;
   s->converged = 0;
+  s->trace_rows.clear();
+  s->trace_pass = 0;
   if (!mixed) {
     int it = 0, code = 0;
     const int rc = run_cg(s, x, false, false, s->cfg.max_iter,
@@ -277,12 +306,18 @@ static int solve(maze_session* s, double* x) {
   int total = 0;
   for (;;) {
     const double res = absmax ? h.true_max : std::sqrt(h.true_rr);
+    if (s->trace) {
+      s->trace_rows.push_back(s->refinements);
+      s->trace_rows.push_back(-1);
+      s->trace_rows.push_back(std::sqrt(h.true_rr) / (h.qnorm > 0 ? h.qnorm : 1.0));
+    }
+    s->trace_pass = s->refinements;
     if (res <= thr) {
       s->converged = 1;
       break;
     }
     if (s->refinements >= kMaxRefinements || total >= s->cfg.max_iter) break;
-    const double inner = std::max(kInnerReduction * res, 0.5 * thr);
+    const double inner = std::max(kInnerReduction * res, kInnerMargin * thr);
     HIP_TRY(launch_finalize(d, FIN_INNER_START, 0, 0.0, inner, 0.0, nullptr,
                             s->cfg.max_iter - total, s->cfg.residual_norm, s->stream));
     int it = 0, code = 0;
@@ -472,6 +507,9 @@ int maze_init(const maze_config* cfg, const double* charges_dev, const double* p
   d.s_cell = (int32_t*)at(20);
   d.s_w = (double*)at(21);
   d.s_Q = (double*)at(22);
+  d.md_epart = (double*)at(23);
+  d.hist = (double*)at(24);
+  d.hist_cap = kHistCap;
   if (hipHostMalloc((void**)&s->host_sc, 2 * sizeof(Scalars), hipHostMallocDefault) !=
           hipSuccess ||
       hipEventCreateWithFlags(&s->ev[0], hipEventDisableTiming) != hipSuccess ||
@@ -654,6 +692,22 @@ int maze_profile_read(maze_session* s, double* out8) {
   return MAZE_OK;
 }
 
+int maze_trace_enable(maze_session* s, int on) {
+  if (!s) return MAZE_E_INVALID;
+  s->trace = on != 0;
+  s->trace_rows.clear();
+  return MAZE_OK;
+}
+
+int maze_trace_read(const maze_session* s, double* out, int max_rows, int* n_rows) {
+  if (!s || (!out && max_rows > 0) || max_rows < 0) return MAZE_E_INVALID;
+  const int n = (int)(s->trace_rows.size() / 3);
+  const int m = std::min(n, max_rows);
+  if (m > 0) std::memcpy(out, s->trace_rows.data(), sizeof(double) * 3 * (size_t)m);
+  if (n_rows) *n_rows = n;
+  return MAZE_OK;
+}
+
 static int md_check(const maze_session* s, const maze_md_state* md) {
   if (!s || !md || md->n_ions != s->d.n_ions || !md->pos_dev || !md->vel_dev || !md->mass_dev ||
       !md->species_dev || !md->f_es_dev || !md->f_sr_dev || !md->scratch_dev || !md->scalars_dev)
@@ -668,8 +722,8 @@ int maze_md_prime(maze_session* s, const maze_md_state* md, maze_stats* st) {
   if (rc != MAZE_OK) return rc;
   rc = maze_step(s, md->pos_dev, nullptr, md->f_es_dev, md->scalars_dev + 6, nullptr);
   if (rc < 0) return rc;
-  HIP_TRY(launch_md_bmh(*md, s->d.box, s->stream));
-  HIP_TRY(launch_md_prime(*md, s->stream));
+  HIP_TRY(launch_md_bmh(*md, s->d, s->stream));
+  HIP_TRY(launch_md_prime(*md, s->d, s->stream));
   const int rc2 = finish_call(s, st);
   return rc2 < 0 ? rc2 : rc;
 }
@@ -681,8 +735,8 @@ int maze_md_step(maze_session* s, const maze_md_state* md, maze_stats* st) {
   HIP_TRY(launch_md_kick_drift(*md, s->stream));
   rc = maze_step(s, md->pos_dev, nullptr, md->f_es_dev, md->scalars_dev + 6, nullptr);
   if (rc < 0) return rc;
-  HIP_TRY(launch_md_bmh(*md, s->d.box, s->stream));
-  HIP_TRY(launch_md_finish(*md, s->stream));
+  HIP_TRY(launch_md_bmh(*md, s->d, s->stream));
+  HIP_TRY(launch_md_finish(*md, s->d, s->stream));
   const int rc2 = finish_call(s, st);
   return rc2 < 0 ? rc2 : rc;
 }

@@ -141,7 +141,14 @@ struct DeviceState {
   int32_t* s_cell = nullptr;      // n*3, tile order
   double* s_w = nullptr;          // n*3*order weights, tile order
   double* s_Q = nullptr;          // n, tile order
+  // MD driver: per-workgroup short-range energy partials (n_ions + 1)
+  double* md_epart = nullptr;
+  // residual history of the current CG solve (written by the sweeps)
+  double* hist = nullptr;
+  int hist_cap = 0;
 };
+
+constexpr int kHistCap = 16384;
 
 // ---- launch wrappers (each queues work on `st`, returns hipError_t) ----
 hipError_t launch_bin(const DeviceState& d, const double* pos, hipStream_t st);
@@ -196,8 +203,10 @@ int update_blocks(long long G);
 
 // MD driver
 hipError_t launch_md_kick_drift(const maze_md_state& md, hipStream_t st);
-hipError_t launch_md_bmh(const maze_md_state& md, double box, hipStream_t st);
-hipError_t launch_md_finish(const maze_md_state& md, hipStream_t st);
-hipError_t launch_md_prime(const maze_md_state& md, hipStream_t st);
+hipError_t launch_md_bmh(const maze_md_state& md, const DeviceState& d, hipStream_t st);
+hipError_t launch_md_finish(const maze_md_state& md, const DeviceState& d, hipStream_t st);
+hipError_t launch_md_prime(const maze_md_state& md, const DeviceState& d, hipStream_t st);
+// Number of short-range energy partials for this cutoff (<= n_ions).
+int md_energy_partials(const DeviceState& d, double cutoff);
 
 }  // namespace maze

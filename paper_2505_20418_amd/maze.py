@@ -27,7 +27,8 @@ GRID_PHI, GRID_PHI_PREV, GRID_Y, GRID_Q, GRID_SIGMA = 0, 1, 2, 3, 4
 EXPORTED = ("maze_abi_version", "maze_strerror", "maze_device_bytes", "maze_init", "maze_step",
             "maze_solve", "maze_step_batch", "maze_grid_n", "maze_get_grid",
             "maze_state_bytes", "maze_save", "maze_load", "maze_destroy", "maze_md_prime",
-            "maze_md_step", "maze_profile_enable", "maze_profile_read")
+            "maze_md_step", "maze_profile_enable", "maze_profile_read", "maze_trace_enable",
+            "maze_trace_read")
 
 
 class maze_config(ctypes.Structure):
@@ -113,6 +114,11 @@ def lib():
         L.maze_profile_enable.argtypes = [vp, ctypes.c_int]
         L.maze_profile_read.restype = ctypes.c_int
         L.maze_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+        L.maze_trace_enable.restype = ctypes.c_int
+        L.maze_trace_enable.argtypes = [vp, ctypes.c_int]
+        L.maze_trace_read.restype = ctypes.c_int
+        L.maze_trace_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.c_int,
+                                      ctypes.POINTER(ctypes.c_int)]
         _lib = L
     return _lib
 
@@ -241,6 +247,21 @@ def maze_profile_read(handle) -> dict:
     v = list(out)
     return dict(fp64_sweep=(int(v[0]), v[1]), fp32_sweep=(int(v[2]), v[3]),
                 fp64_iters=int(v[4]), fp32_iters=int(v[5]))
+
+
+def maze_trace_enable(handle, on: bool = True):
+    _check(lib().maze_trace_enable(handle, int(bool(on))), "maze_trace_enable")
+
+
+def maze_trace_read(handle):
+    """Rows (pass, iteration, relative residual) of the last solve, as a
+    list of tuples; iteration -1 marks an FP64 true residual."""
+    n = ctypes.c_int(0)
+    _check(lib().maze_trace_read(handle, None, 0, ctypes.byref(n)), "maze_trace_read")
+    buf = (ctypes.c_double * (3 * max(n.value, 1)))()
+    _check(lib().maze_trace_read(handle, buf, n.value, ctypes.byref(n)), "maze_trace_read")
+    v = list(buf)
+    return [(int(v[3 * i]), int(v[3 * i + 1]), v[3 * i + 2]) for i in range(n.value)]
 
 
 # ---- convenience wrapper -------------------------------------------------------

@@ -306,3 +306,21 @@ def test_md_matches_oracle_md(maze):
     obs = run.observables()
     assert abs(obs["work"] - work[0]) <= 1e-8 * max(1.0, abs(work[0]))
     assert np.abs(obs["momentum"]).max() <= 1e-8
+
+
+@pytest.mark.parametrize("n_cells,grid_n", [(8, 128), (4, 60)])
+def test_short_range_tiles_match_oracle(maze, n_cells, grid_n):
+    """The short-range term searched over the MaZe tiles (a 5^3 or 7^3 tile
+    block) against the oracle's all-pairs sum, including a grid whose last
+    tile along each axis is partial."""
+    from paper_2505_20418_amd.md import MDRun
+    s = inputs.molten_nacl(n_cells, seed=7)
+    s.grid_spacing = s.box / grid_n
+    print(f"case: short range ions={s.n_ions} N={grid_n}", flush=True)
+    run = MDRun(s, tol=1e-6)
+    assert run.session.N == grid_n
+    F_ref, e_ref = oracle.bmh(s.pos, s.species, s.box, inputs.BMH_TABLE, inputs.BMH_CUTOFF)
+    F = run.f_sr.cpu().numpy()
+    assert np.abs(F - F_ref).max() <= 1e-10 * max(1.0, np.abs(F_ref).max())
+    assert abs(run.observables()["v_sr"] - e_ref) <= 1e-10 * abs(e_ref)
+    run.close()
