@@ -89,6 +89,8 @@ typedef struct {
   int32_t iters;          /* CG iterations (sum over refinements) */
   int32_t refinements;    /* outer FP64 refinements (mixed), else 0 */
   int32_t converged;      /* 1 if the stopping test was met */
+  int32_t status;         /* status of the call for this session (batch) */
+  int32_t pad;
   double  h;              /* effective grid spacing */
   double  rel_residual;   /* true ||residual||_2 / ||rhs scale||_2, FP64 */
   double  max_abs_residual;
@@ -143,13 +145,21 @@ int maze_solve(maze_session* s, int guess, const double* pos_dev,
                double* field_dev, double* forces_dev, double* energy_dev,
                maze_stats* st);
 
-/* Advances `count` independent sessions by one step each, with the CG
- * iterations of all of them issued together (one launch per CG pass covers
- * every unconverged session). All sessions must share the precision mode
- * and stream of sessions[0]. Per-session semantics and outputs are those
- * of maze_step; pos_dev[i], forces_dev[i] belong to session i;
- * energies_dev (count doubles) and st (count entries) may be NULL. The
- * return value is the most severe status over the sessions. */
+/* Advances `count` distinct sessions by one step each, with the CG sweeps
+ * of all of them issued together: per CG iteration, one launch per template
+ * class (segment length and halo width of the session's grid) covers every
+ * unconverged session of a precision, and sessions that have converged drop
+ * out. Sessions may differ in grid size and precision; they must share the
+ * device and the stream of sessions[0]. Per-session semantics and outputs are
+ * those of maze_step, and each session's result is bitwise the one it gets
+ * stepped alone. pos_dev[i], forces_dev[i] (forces_dev or an entry may be
+ * NULL) belong to session i; energies_dev (count doubles, device) and st
+ * (count entries, host) may be NULL; st[i].status holds session i's status.
+ * A session whose positions are rejected is left unchanged while the others
+ * advance. The return value is the most severe status over the sessions.
+ * The first call with more sessions than any call before on a device
+ * allocates that device's batch table (device and pinned host memory kept
+ * until the process ends); calls on one device must not overlap. */
 int maze_step_batch(maze_session* const* sessions, int32_t count,
                     const double* const* pos_dev, double* const* forces_dev,
                     double* energies_dev, maze_stats* st);

@@ -117,50 +117,48 @@ __device__ __forceinline__ void read_sweep_partials(const double* part, int ps, 
   block_reduce5(v, sm);
 }
 
-template <typename T>
-struct SweepArgs {
-  const T* r_in;
-  T* r_out;
-  const T* p_in;
-  T* p_out;
-  T* x;
-  double* part;
-  int pstride;
-  int nprev;     // number of partials written by the previous kernel
-  int zero_x;    // FIRST only: write x = 0 (start of an FP32 correction solve)
-  Scalars* sc;
-  double* hist;  // residual history: hist[k] = ||r_k||_2 of the current solve
-  int hist_cap;
-};
+
 
 __device__ __forceinline__ int wrap_plane(int u, int N) {
   return u < 0 ? u + N : (u >= N ? u - N : u);
 }
 
+// The work of one workgroup of a sweep: logical index L of the session's
+// grid (L = 0 also writes the session's control scalars). Shared by the
+// single-session and the batched kernels, so a session gets bitwise the same
+// result alone and in a batch.
 template <typename T, bool FIRST, int PPT, int NH>
-__global__ __launch_bounds__(kThreads) void k_cg_sweep(SweepArgs<T> a, SweepGeom g, int par) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  __shared__ double red[5 * (kThreads / 64)];
+__device__ __forceinline__ void sweep_wg(const SweepArgs<T>& a, const SweepGeom& g, int par,
+                                         int L, unsigned char* smem_raw, double* red) {
   Scalars* sc = a.sc;
   if (ctl_ld(&sc->done) != 0 || ctl_ld(&sc->err) != 0) return;
   const int tid = threadIdx.x;
+  const bool leader = (L == 0) && (tid == 0);
+  const T* r_in = a.r[par];
+  T* r_out = a.r[par ^ 1];
+  const T* p_in = a.p[par];
+  T* p_out = a.p[par ^ 1];
+  // number of updates done so far in this solve; a per-parity counter, so
+  // the leader's write for the next sweep never races with this sweep's reads
+  const int it = ctl_ld(&sc->itp[par]);
 
   // ---- step scalars from the previous kernel's partials -------------------
   T alpha = (T)0, beta = (T)0;
   {
     double v[5];
-    read_sweep_partials<FIRST>(a.part, a.pstride, par, a.nprev, v, red);
+    read_sweep_partials<FIRST>(a.part, a.pstride, par, FIRST ? a.nprev_first : a.nprev_sweep, v,
+                               red);
     const double gam = v[0];
     const double thr = ctl_ld(&sc->thr);
     const bool conv = (ctl_ld(&sc->norm) == MAZE_NORM_ABSMAX) ? (v[1] <= thr) : (sqrt(gam) <= thr);
-    if (blockIdx.x == 0 && tid == 0) {
-      // ||r_it|| of the sweep that wrote these partials (it = number of
-      // updates done so far in this solve)
-      const int it = ctl_ld(&sc->it);
-      if (it < a.hist_cap) a.hist[it] = sqrt(gam);
-    }
+    if (leader && it < a.hist_cap) a.hist[it] = sqrt(gam);
     bool stop = conv || !isfinite(gam);
     int code = conv ? 1 : 2;
+    // iteration cap: this sweep would perform update it + 1
+    if (!FIRST && !stop && it >= ctl_ld(&sc->max_iter)) {
+      stop = true;
+      code = 3;
+    }
     if (!FIRST && !stop) {
       const double mu = v[2];
       if (!(mu > 0.0) || !isfinite(mu)) {
@@ -174,9 +172,9 @@ __global__ __launch_bounds__(kThreads) void k_cg_sweep(SweepArgs<T> a, SweepGeom
       }
     }
     if (stop) {
-      if (blockIdx.x == 0 && tid == 0) {
+      if (leader) {
         ctl_st(&sc->gamma[par], gam);
-        ctl_st(&sc->iters, ctl_ld(&sc->it));
+        ctl_st(&sc->iters, it);
         ctl_st(&sc->done, code);
       }
       return;
@@ -185,7 +183,6 @@ __global__ __launch_bounds__(kThreads) void k_cg_sweep(SweepArgs<T> a, SweepGeom
 
   // ---- geometry of this workgroup -----------------------------------------
   const int N = g.N, P = g.P, S = g.S;
-  const int L = xcd_remap(blockIdx.x, g.nwg);
   const int seg = L % g.nseg, chunk = L / g.nseg;
   const int s0 = seg * S;
   const int x0 = chunk * g.cx, x1 = min(N, x0 + g.cx);
@@ -249,13 +246,13 @@ __global__ __launch_bounds__(kThreads) void k_cg_sweep(SweepArgs<T> a, SweepGeom
 
   // ---- prologue: planes x0-2 .. x0 of p_{k-1}, plane x0-1 of r_{k-1} ------
   {
-    const T* r0 = a.r_in + (size_t)wrap_plane(x0 - 1, N) * Ps;
+    const T* r0 = r_in + (size_t)wrap_plane(x0 - 1, N) * Ps;
 #pragma unroll
     for (int i = 0; i < NU; ++i) rc[i] = r0[off[i]];
     if (!FIRST) {
-      const T* pa = a.p_in + (size_t)wrap_plane(x0 - 2, N) * Ps;
-      const T* pb = a.p_in + (size_t)wrap_plane(x0 - 1, N) * Ps;
-      const T* pd = a.p_in + (size_t)wrap_plane(x0, N) * Ps;
+      const T* pa = p_in + (size_t)wrap_plane(x0 - 2, N) * Ps;
+      const T* pb = p_in + (size_t)wrap_plane(x0 - 1, N) * Ps;
+      const T* pd = p_in + (size_t)wrap_plane(x0, N) * Ps;
       T ob[NH];
 #pragma unroll
       for (int i = 0; i < NU; ++i) {
@@ -296,11 +293,11 @@ __global__ __launch_bounds__(kThreads) void k_cg_sweep(SweepArgs<T> a, SweepGeom
     // issue the loads of the next step
     T pf[NU], pof[NH], rf[NU], xf[PPT];
     if (more) {
-      const T* rp = a.r_in + (size_t)wrap_plane(u + 1, N) * Ps;
+      const T* rp = r_in + (size_t)wrap_plane(u + 1, N) * Ps;
 #pragma unroll
       for (int i = 0; i < NU; ++i) rf[i] = rp[off[i]];
       if (!FIRST) {
-        const T* pp = a.p_in + (size_t)wrap_plane(u + 2, N) * Ps;
+        const T* pp = p_in + (size_t)wrap_plane(u + 2, N) * Ps;
 #pragma unroll
         for (int i = 0; i < NU; ++i) pf[i] = pp[off[i]];
 #pragma unroll
@@ -341,8 +338,8 @@ __global__ __launch_bounds__(kThreads) void k_cg_sweep(SweepArgs<T> a, SweepGeom
 #pragma unroll
       for (int j = 0; j < PPT; ++j) {
         if (cval[j]) {
-          a.r_out[pb + off[j]] = rk[j];
-          a.p_out[pb + off[j]] = pk[j];
+          r_out[pb + off[j]] = rk[j];
+          p_out[pb + off[j]] = pk[j];
           if (!FIRST) a.x[pb + off[j]] = xc[j] + alpha * pc[j];
           else if (a.zero_x) a.x[pb + off[j]] = (T)0;
           const double rd = (double)rk[j];
@@ -416,93 +413,177 @@ __global__ __launch_bounds__(kThreads) void k_cg_sweep(SweepArgs<T> a, SweepGeom
     a.part[(size_t)(SL_MU0 + po) * a.pstride + L] = acc[2];
     a.part[(size_t)(SL_RW0 + po) * a.pstride + L] = acc[3];
     a.part[(size_t)(SL_WW0 + po) * a.pstride + L] = acc[4];
-    if (blockIdx.x == 0) ctl_st(&sc->it, FIRST ? 0 : ctl_ld(&sc->it) + 1);
+    if (L == 0) ctl_st(&sc->itp[par ^ 1], FIRST ? 0 : it + 1);
   }
 }
 
-// Stopping test after the last permitted sweep: converged or iteration cap.
-__global__ __launch_bounds__(kThreads) void k_cg_check(double* part, int pstride, int par,
-                                                        int nprev, Scalars* sc, double* hist,
-                                                        int hist_cap) {
+template <typename T, bool FIRST, int PPT, int NH>
+__global__ __launch_bounds__(kThreads) void k_cg_sweep(SweepArgs<T> a, SweepGeom g, int par) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ double red[5 * (kThreads / 64)];
-  if (ctl_ld(&sc->done) != 0 || ctl_ld(&sc->err) != 0) return;
-  double v[5];
-  read_sweep_partials<true>(part, pstride, par, nprev, v, red);
-  if (threadIdx.x == 0) {
-    const double thr = ctl_ld(&sc->thr);
-    const bool conv = (ctl_ld(&sc->norm) == MAZE_NORM_ABSMAX) ? (v[1] <= thr) : (sqrt(v[0]) <= thr);
-    const int it = ctl_ld(&sc->it);
-    if (it < hist_cap) hist[it] = sqrt(v[0]);
-    ctl_st(&sc->gamma[par], v[0]);
-    ctl_st(&sc->iters, it);
-    ctl_st(&sc->done, conv ? 1 : 3);
+  sweep_wg<T, FIRST, PPT, NH>(a, g, par, xcd_remap(blockIdx.x, g.nwg), smem_raw, red);
+}
+
+// Batched sweep: the workgroups of `count` sessions in one launch. Session i
+// owns workgroups [wg_begin[i], wg_begin[i+1]); sessions that have converged
+// return at once. All sessions of a launch share T, PPT and NH.
+template <typename T, bool FIRST, int PPT, int NH>
+__global__ __launch_bounds__(kThreads) void k_cg_sweep_batch(const SweepArgs<T>* __restrict__ args,
+                                                             const SweepGeom* __restrict__ geoms,
+                                                             const int* __restrict__ wg_begin,
+                                                             int count, int par) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ double red[5 * (kThreads / 64)];
+  const int b = blockIdx.x;
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (wg_begin[mid] <= b) lo = mid;
+    else hi = mid - 1;
   }
+  const SweepArgs<T> a = args[lo];
+  const SweepGeom g = geoms[lo];
+  sweep_wg<T, FIRST, PPT, NH>(a, g, par, b - wg_begin[lo], smem_raw, red);
+}
+
+// Status of every session of a batch in one compact array: done, iters, err.
+__global__ __launch_bounds__(kThreads) void k_batch_poll(Scalars* const* scs, int count,
+                                                         int32_t* out) {
+  const int i = blockIdx.x * kThreads + threadIdx.x;
+  if (i >= count) return;
+  const Scalars* sc = scs[i];
+  out[3 * i] = ctl_ld(&sc->done);
+  out[3 * i + 1] = ctl_ld(&sc->iters);
+  out[3 * i + 2] = ctl_ld(&sc->err);
+}
+
+// Copies the scalars of every session of a batch into one array.
+__global__ __launch_bounds__(kThreads) void k_batch_scalars(Scalars* const* scs, int count,
+                                                            Scalars* out) {
+  const int i = blockIdx.x;
+  if (i >= count) return;
+  const int32_t* src = reinterpret_cast<const int32_t*>(scs[i]);
+  int32_t* dst = reinterpret_cast<int32_t*>(out + i);
+  constexpr int nw = (int)(sizeof(Scalars) / sizeof(int32_t));
+  for (int w = threadIdx.x; w < nw; w += kThreads) dst[w] = ctl_ld(src + w);
 }
 
 // ---- launch plumbing ---------------------------------------------------------
+// Raises the dynamic LDS limit of a kernel once per process when a launch
+// needs more than the default 64 KiB.
+static hipError_t raise_lds(const void* fn, size_t lds, bool* raised) {
+  if (lds <= 65536 || *raised) return hipSuccess;
+  const hipError_t e =
+      hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 1024);
+  if (e == hipSuccess) *raised = true;
+  return e;
+}
+
 template <typename T, bool FIRST, int PPT, int NH>
-static hipError_t launch_sweep_t(const SweepArgs<T>& a, const SweepGeom& g, int par,
-                                 hipStream_t st) {
-  const size_t lds = sweep_lds_bytes(g, sizeof(T) == 4, FIRST);
-  if (lds > 65536) {
+static hipError_t launch_t(const SweepLaunch& L, hipStream_t st) {
+  if (!L.batch) {
     static bool raised = false;
-    if (!raised) {
-      const hipError_t e = hipFuncSetAttribute((const void*)k_cg_sweep<T, FIRST, PPT, NH>,
-                                               hipFuncAttributeMaxDynamicSharedMemorySize,
-                                               160 * 1024 - 1024);
-      if (e != hipSuccess) return e;
-      raised = true;
-    }
+    const size_t lds = sweep_lds_bytes(L.g, sizeof(T) == 4, FIRST);
+    const hipError_t e = raise_lds((const void*)k_cg_sweep<T, FIRST, PPT, NH>, lds, &raised);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_cg_sweep<T, FIRST, PPT, NH>), dim3(L.g.nwg), dim3(kThreads), lds, st,
+                       *static_cast<const SweepArgs<T>*>(L.args), L.g, L.par);
+  } else {
+    static bool raised = false;
+    const hipError_t e =
+        raise_lds((const void*)k_cg_sweep_batch<T, FIRST, PPT, NH>, L.lds, &raised);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_cg_sweep_batch<T, FIRST, PPT, NH>), dim3(L.nwg_total), dim3(kThreads),
+                       L.lds, st, static_cast<const SweepArgs<T>*>(L.args), L.geoms, L.wg_begin,
+                       L.count, L.par);
   }
-  hipLaunchKernelGGL((k_cg_sweep<T, FIRST, PPT, NH>), dim3(g.nwg), dim3(kThreads), lds, st, a, g,
-                     par);
   return hipGetLastError();
 }
 
 template <typename T, bool FIRST, int PPT>
-static hipError_t launch_sweep_nh(const SweepArgs<T>& a, const SweepGeom& g, int par,
-                                  hipStream_t st) {
-  switch (g.nh) {
-    case 1: return launch_sweep_t<T, FIRST, PPT, 1>(a, g, par, st);
-    case 2: return launch_sweep_t<T, FIRST, PPT, 2>(a, g, par, st);
-    case 3:
-    case 4: return launch_sweep_t<T, FIRST, PPT, 4>(a, g, par, st);
-    default: return launch_sweep_t<T, FIRST, PPT, 8>(a, g, par, st);
-  }
-}
-
-template <typename T, bool FIRST>
-static hipError_t launch_sweep_ppt(const SweepArgs<T>& a, const SweepGeom& g, int par,
-                                   hipStream_t st) {
-  if (g.nh > 8) return hipErrorInvalidValue;
-  switch (g.ppt) {
-    case 1: return launch_sweep_nh<T, FIRST, 1>(a, g, par, st);
-    case 2: return launch_sweep_nh<T, FIRST, 2>(a, g, par, st);
-    case 4: return launch_sweep_nh<T, FIRST, 4>(a, g, par, st);
+static hipError_t launch_nh(const SweepLaunch& L, hipStream_t st) {
+  switch (L.nh) {
+    case 1: return launch_t<T, FIRST, PPT, 1>(L, st);
+    case 2: return launch_t<T, FIRST, PPT, 2>(L, st);
+    case 4: return launch_t<T, FIRST, PPT, 4>(L, st);
+    case 8: return launch_t<T, FIRST, PPT, 8>(L, st);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_cg_sweep(const DeviceState& d, const SweepGeom& g, int k, int nprev,
-                           void* x, bool fp32, bool zero_x, hipStream_t st) {
-  const int par = k & 1;
-  const size_t G = (size_t)d.G;
-  if (fp32) {
-    SweepArgs<float> a{d.r32 + par * G, d.r32 + (par ^ 1) * G, d.p32 + par * G,
-                       d.p32 + (par ^ 1) * G, (float*)x, d.part, d.part_stride, nprev,
-                       zero_x ? 1 : 0, d.sc, d.hist, d.hist_cap};
-    return k == 0 ? launch_sweep_ppt<float, true>(a, g, par, st)
-                  : launch_sweep_ppt<float, false>(a, g, par, st);
+template <typename T, bool FIRST>
+static hipError_t launch_ppt(const SweepLaunch& L, hipStream_t st) {
+  switch (L.ppt) {
+    case 1: return launch_nh<T, FIRST, 1>(L, st);
+    case 2: return launch_nh<T, FIRST, 2>(L, st);
+    case 4: return launch_nh<T, FIRST, 4>(L, st);
+    default: return hipErrorInvalidValue;
   }
-  SweepArgs<double> a{d.r + par * G, d.r + (par ^ 1) * G, d.p + par * G, d.p + (par ^ 1) * G,
-                      (double*)x, d.part, d.part_stride, nprev, 0, d.sc, d.hist, d.hist_cap};
-  return k == 0 ? launch_sweep_ppt<double, true>(a, g, par, st)
-                : launch_sweep_ppt<double, false>(a, g, par, st);
 }
 
-hipError_t launch_cg_check(const DeviceState& d, int k, int nprev, hipStream_t st) {
-  hipLaunchKernelGGL(k_cg_check, dim3(1), dim3(kThreads), 0, st, d.part, d.part_stride, k & 1,
-                     nprev, d.sc, d.hist, d.hist_cap);
+int sweep_nh_class(int nh) { return nh <= 1 ? 1 : nh <= 2 ? 2 : nh <= 4 ? 4 : nh <= 8 ? 8 : 0; }
+
+hipError_t launch_sweep(const SweepLaunch& L, bool fp32, bool first, hipStream_t st) {
+  if (fp32) return first ? launch_ppt<float, true>(L, st) : launch_ppt<float, false>(L, st);
+  return first ? launch_ppt<double, true>(L, st) : launch_ppt<double, false>(L, st);
+}
+
+template <typename T>
+SweepArgs<T> make_sweep_args(const DeviceState& d, T* x, int nprev_first, int nprev_sweep,
+                             bool zero_x) {
+  const size_t G = (size_t)d.G;
+  SweepArgs<T> a{};
+  if constexpr (sizeof(T) == 4) {
+    a.r[0] = d.r32;
+    a.r[1] = d.r32 + G;
+    a.p[0] = d.p32;
+    a.p[1] = d.p32 + G;
+  } else {
+    a.r[0] = d.r;
+    a.r[1] = d.r + G;
+    a.p[0] = d.p;
+    a.p[1] = d.p + G;
+  }
+  a.x = x;
+  a.part = d.part;
+  a.sc = d.sc;
+  a.hist = d.hist;
+  a.pstride = d.part_stride;
+  a.nprev_first = nprev_first;
+  a.nprev_sweep = nprev_sweep;
+  a.zero_x = zero_x ? 1 : 0;
+  a.hist_cap = d.hist_cap;
+  return a;
+}
+template SweepArgs<float> make_sweep_args<float>(const DeviceState&, float*, int, int, bool);
+template SweepArgs<double> make_sweep_args<double>(const DeviceState&, double*, int, int, bool);
+
+hipError_t launch_cg_sweep(const DeviceState& d, const SweepGeom& g, int k, int nprev_first,
+                           void* x, bool fp32, bool zero_x, hipStream_t st) {
+  SweepLaunch L{};
+  L.batch = false;
+  L.g = g;
+  L.par = k & 1;
+  L.ppt = g.ppt;
+  L.nh = sweep_nh_class(g.nh);
+  if (fp32) {
+    const SweepArgs<float> a = make_sweep_args<float>(d, (float*)x, nprev_first, g.nwg, zero_x);
+    L.args = &a;
+    return launch_sweep(L, true, k == 0, st);
+  }
+  const SweepArgs<double> a = make_sweep_args<double>(d, (double*)x, nprev_first, g.nwg, zero_x);
+  L.args = &a;
+  return launch_sweep(L, false, k == 0, st);
+}
+
+hipError_t launch_batch_poll(Scalars* const* scs, int count, int32_t* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_batch_poll, dim3((count + kThreads - 1) / kThreads), dim3(kThreads), 0, st,
+                     scs, count, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_scalars(Scalars* const* scs, int count, Scalars* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_batch_scalars, dim3(count), dim3(64), 0, st, scs, count, out);
   return hipGetLastError();
 }
 

@@ -458,7 +458,8 @@ __global__ __launch_bounds__(kThreads) void k_finalize(int mode, int count, long
       ctl_st(&sc->pbar, pp / (double)G);
       ctl_st(&sc->true_rr, trr);
       ctl_st(&sc->true_max, tmx);
-      ctl_st(&sc->it, 0);
+      ctl_st(&sc->itp[0], 0);
+      ctl_st(&sc->itp[1], 0);
       ctl_st(&sc->done, 0);
       ctl_st(&sc->iters, 0);
     }
@@ -482,7 +483,8 @@ __global__ __launch_bounds__(kThreads) void k_finalize(int mode, int count, long
     if (threadIdx.x == 0) {
       ctl_st(&sc->thr, param);
       ctl_st(&sc->max_iter, imax);
-      ctl_st(&sc->it, 0);
+      ctl_st(&sc->itp[0], 0);
+      ctl_st(&sc->itp[1], 0);
       ctl_st(&sc->done, 0);
       ctl_st(&sc->iters, 0);
     }

@@ -108,7 +108,7 @@ static MarchGeom choose_geom(int N) {
 // about two workgroups per CU at 256^3.
 static SweepGeom choose_sweep(int N) {
   if (N >= 192) return make_sweep_geom(N, 4, 32);
-  if (N >= 96) return make_sweep_geom(N, 2, 16);
+  if (N >= 128) return make_sweep_geom(N, 2, 16);
   if (N >= 48) return make_sweep_geom(N, 1, 8);
   return make_sweep_geom(N, 1, 4);
 }
@@ -175,11 +175,12 @@ static Layout layout_for(const maze_config* c, int N, int* ntx_out, int* ntiles_
 }
 
 // ---------------------------------------------------------------------------
-// Host loop of one CG solve: queue sweeps in batches, copy the device
-// scalars to pinned memory after each batch, and stop queueing once a
-// completed batch reports done (sweeps queued after convergence return at
-// once). At most max_iter + 1 sweeps are queued (sweep 0 only forms p_0);
-// after the last one a check kernel applies the stopping test.
+// CG host loops. Sweeps are queued in groups of kPollBatch; after each group
+// the solve's status is copied to pinned memory, and the status of the group
+// before is waited for, so the device always has a group queued. Sweeps
+// queued after convergence return at once. The device applies the stopping
+// test and the iteration cap itself (sweep k stops when k - 1 updates reach
+// max_iter), so the host only counts sweeps as a guard.
 // ---------------------------------------------------------------------------
 static void prof_collect(maze_session* s, int timed, int iters, bool fp32) {
   double* acc = s->prof_acc + (fp32 ? 2 : 0);
@@ -196,57 +197,74 @@ static void prof_collect(maze_session* s, int timed, int iters, bool fp32) {
   s->prof_acc[fp32 ? 5 : 4] += iters;
 }
 
-static int run_cg(maze_session* s, void* x, bool fp32, bool zero_x, int max_iter,
-                  int first_batch, int* iters, int* done_code) {
+// Appends the residual history of the solve that just ended to the trace.
+static int trace_collect(maze_session* s, int iters, double qnorm) {
+  const int n = std::min(iters + 1, s->d.hist_cap);
+  s->hist_host.resize(n);
+  HIP_TRY(hipMemcpyAsync(s->hist_host.data(), s->d.hist, sizeof(double) * n,
+                         hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  const double qn = qnorm > 0 ? qnorm : 1.0;
+  for (int t = 0; t < n; ++t) {
+    s->trace_rows.push_back(s->trace_pass);
+    s->trace_rows.push_back(t);
+    s->trace_rows.push_back(s->hist_host[t] / qn);
+  }
+  return MAZE_OK;
+}
+
+// One CG solve on one session: x is double* (FP64) or float* (FP32, then
+// zero_x starts it from zero). max_iter bounds the host guard only.
+struct CgJob {
+  maze_session* s;
+  void* x;
+  int max_iter;
+  int iters = 0, code = 0, err = 0;
+};
+
+static long long sweep_guard(int max_iter, int first_batch) {
+  return (long long)max_iter + 4LL * kPollBatch + first_batch + 64;
+}
+
+static int run_cg(CgJob& job, bool fp32, bool zero_x, int first_batch) {
+  maze_session* s = job.s;
   DeviceState& d = s->d;
   const SweepGeom& w = s->sweep;
-  const long long cap = (long long)max_iter + 1;
+  const long long guard = sweep_guard(job.max_iter, first_batch);
   long long k = 0;
   int batch = 0, timed = 0;
-  bool have_prev = false, capped = false;
+  bool have_prev = false;
   const bool prof = s->prof;
   for (;;) {
     const int nb = (batch == 0) ? std::max(kPollBatch, first_batch) : kPollBatch;
-    for (int b = 0; b < nb && k < cap; ++b, ++k) {
-      const int nprev = (k == 0) ? s->geom.nwg : w.nwg;
+    for (int b = 0; b < nb; ++b, ++k) {
       const bool timeit = prof && k >= 1 && (k - 1) % kProfStride == 0 && timed < kProfMax;
       if (timeit) HIP_TRY(hipEventRecord(s->pev[2 * timed], s->stream));
-      HIP_TRY(launch_cg_sweep(d, w, (int)k, nprev, x, fp32, zero_x, s->stream));
+      HIP_TRY(launch_cg_sweep(d, w, (int)(k & 0x7fffffff), s->geom.nwg, job.x, fp32, zero_x,
+                              s->stream));
       if (timeit) {
         HIP_TRY(hipEventRecord(s->pev[2 * timed + 1], s->stream));
         ++timed;
       }
     }
-    if (k == cap && !capped) {
-      HIP_TRY(launch_cg_check(d, (int)(k & 1), w.nwg, s->stream));
-      capped = true;
-    }
+    const bool last = k > guard;
     const int slot = batch & 1;
     HIP_TRY(hipMemcpyAsync(&s->host_sc[slot], d.sc, sizeof(Scalars), hipMemcpyDeviceToHost,
                            s->stream));
     HIP_TRY(hipEventRecord(s->ev[slot], s->stream));
-    const int wait_slot = capped ? slot : (slot ^ 1);
-    if (have_prev || capped) {
-      HIP_TRY(hipEventSynchronize(s->ev[wait_slot]));
-      const Scalars& h = s->host_sc[wait_slot];
-      if (h.err) return MAZE_E_NONFINITE;
-      if (h.done || capped) {
-        *iters = h.iters;
-        *done_code = h.done ? h.done : 3;
+    if (have_prev || last) {
+      const int ws = last ? slot : (slot ^ 1);
+      HIP_TRY(hipEventSynchronize(s->ev[ws]));
+      const Scalars& h = s->host_sc[ws];
+      if (h.err) {
+        job.err = 1;
+        return MAZE_OK;
+      }
+      if (h.done || last) {
+        job.iters = h.iters;
+        job.code = h.done ? h.done : 3;
         if (prof) prof_collect(s, timed, h.iters, fp32);
-        if (s->trace) {
-          const int n = std::min(h.iters + 1, s->d.hist_cap);
-          s->hist_host.resize(n);
-          HIP_TRY(hipMemcpyAsync(s->hist_host.data(), s->d.hist, sizeof(double) * n,
-                                 hipMemcpyDeviceToHost, s->stream));
-          HIP_TRY(hipStreamSynchronize(s->stream));
-          const double qn = h.qnorm > 0 ? h.qnorm : 1.0;
-          for (int t = 0; t < n; ++t) {
-            s->trace_rows.push_back(s->trace_pass);
-            s->trace_rows.push_back(t);
-            s->trace_rows.push_back(s->hist_host[t] / qn);
-          }
-        }
+        if (s->trace) return trace_collect(s, h.iters, h.qnorm);
         return MAZE_OK;
       }
     }
@@ -255,12 +273,201 @@ static int run_cg(maze_session* s, void* x, bool fp32, bool zero_x, int max_iter
   }
 }
 
-static int read_scalars(maze_session* s, Scalars* out) {
-  HIP_TRY(hipMemcpyAsync(&s->host_sc[0], s->d.sc, sizeof(Scalars), hipMemcpyDeviceToHost,
-                         s->stream));
-  HIP_TRY(hipStreamSynchronize(s->stream));
-  *out = s->host_sc[0];
+// ---- batch tables: device arrays describing the sessions of a batched
+// launch, with a pinned host mirror; one per device, grown on demand ----------
+static_assert(sizeof(SweepArgs<float>) == sizeof(SweepArgs<double>),
+              "batched sweep arguments share one layout");
+
+struct BatchTable {
+  int cap = 0;
+  char* dev = nullptr;
+  char* host = nullptr;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  size_t o_args = 0, o_geom = 0, o_wgb = 0, o_scs = 0, o_poll = 0, o_sco = 0, bytes = 0;
+};
+static BatchTable g_tables[64];
+
+static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+static int ensure_table(int device, int count, BatchTable** out) {
+  if (device < 0 || device >= 64) return MAZE_E_DEVICE;
+  BatchTable& t = g_tables[device];
+  if (t.cap < count) {
+    int cap = std::max(64, t.cap);
+    while (cap < count) cap *= 2;
+    BatchTable n;
+    n.cap = cap;
+    size_t o = 0;
+    n.o_args = o; o = align256(o + sizeof(SweepArgs<double>) * cap);
+    n.o_geom = o; o = align256(o + sizeof(SweepGeom) * cap);
+    n.o_wgb = o;  o = align256(o + sizeof(int) * (2 * cap + 16));
+    n.o_scs = o;  o = align256(o + sizeof(Scalars*) * cap);
+    n.o_poll = o; o = align256(o + sizeof(int32_t) * 6 * cap);
+    n.o_sco = o;  o = align256(o + sizeof(Scalars) * cap);
+    n.bytes = o;
+    if (hipMalloc((void**)&n.dev, n.bytes) != hipSuccess) {
+      hipGetLastError();
+      return MAZE_E_OOM;
+    }
+    if (hipHostMalloc((void**)&n.host, n.bytes, hipHostMallocDefault) != hipSuccess) {
+      hipFree(n.dev);
+      return MAZE_E_OOM;
+    }
+    if (hipEventCreateWithFlags(&n.ev[0], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&n.ev[1], hipEventDisableTiming) != hipSuccess)
+      return MAZE_E_DEVICE;
+    if (t.dev) {
+      hipDeviceSynchronize();
+      hipFree(t.dev);
+      hipHostFree(t.host);
+      hipEventDestroy(t.ev[0]);
+      hipEventDestroy(t.ev[1]);
+    }
+    t = n;
+  }
+  *out = &t;
   return MAZE_OK;
+}
+
+// Scalars of several sessions (one device copy and one transfer).
+static int gather_scalars(std::vector<maze_session*>& ss, std::vector<Scalars>& out) {
+  const int n = (int)ss.size();
+  out.resize(n);
+  if (n == 1) {
+    maze_session* s = ss[0];
+    HIP_TRY(hipMemcpyAsync(&s->host_sc[0], s->d.sc, sizeof(Scalars), hipMemcpyDeviceToHost,
+                           s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    out[0] = s->host_sc[0];
+    return MAZE_OK;
+  }
+  BatchTable* t = nullptr;
+  int rc = ensure_table(ss[0]->device, n, &t);
+  if (rc != MAZE_OK) return rc;
+  hipStream_t st = ss[0]->stream;
+  Scalars** hs = (Scalars**)(t->host + t->o_scs);
+  for (int i = 0; i < n; ++i) hs[i] = ss[i]->d.sc;
+  HIP_TRY(hipMemcpyAsync(t->dev + t->o_scs, hs, sizeof(Scalars*) * n, hipMemcpyHostToDevice, st));
+  HIP_TRY(launch_batch_scalars((Scalars* const*)(t->dev + t->o_scs), n,
+                               (Scalars*)(t->dev + t->o_sco), st));
+  HIP_TRY(hipMemcpyAsync(t->host + t->o_sco, t->dev + t->o_sco, sizeof(Scalars) * n,
+                         hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  std::memcpy(out.data(), t->host + t->o_sco, sizeof(Scalars) * n);
+  return MAZE_OK;
+}
+
+// Batched CG solves: one launch per sweep and template class covers every
+// session; a compact status array is polled.
+static int run_cg_batch(std::vector<CgJob>& jobs, bool fp32, bool zero_x, int first_batch) {
+  const int n = (int)jobs.size();
+  if (n == 1) return run_cg(jobs[0], fp32, zero_x, first_batch);
+  BatchTable* t = nullptr;
+  int rc = ensure_table(jobs[0].s->device, n, &t);
+  if (rc != MAZE_OK) return rc;
+  hipStream_t st = jobs[0].s->stream;
+  // order the sessions by template class (ppt, nh)
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  auto cls = [&](int i) {
+    const SweepGeom& g = jobs[i].s->sweep;
+    return g.ppt * 16 + sweep_nh_class(g.nh);
+  };
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cls(a) < cls(b); });
+  struct Cls { int c0, c1, wgb0, nwg, ppt, nh; size_t lds; };
+  std::vector<Cls> classes;
+  char* H = t->host;
+  SweepGeom* hg = (SweepGeom*)(H + t->o_geom);
+  int* hw = (int*)(H + t->o_wgb);
+  Scalars** hs = (Scalars**)(H + t->o_scs);
+  int wpos = 0;
+  long long guard = 0;
+  for (int q = 0; q < n; ++q) {
+    const int i = order[q];
+    maze_session* s = jobs[i].s;
+    const SweepGeom& g = s->sweep;
+    if (classes.empty() || cls(order[classes.back().c0]) != cls(i)) {
+      if (!classes.empty()) hw[wpos++] = classes.back().nwg;
+      classes.push_back({q, q, wpos, 0, g.ppt, sweep_nh_class(g.nh), 0});
+    }
+    Cls& c = classes.back();
+    hw[wpos++] = c.nwg;
+    c.nwg += g.nwg;
+    c.c1 = q + 1;
+    c.lds = std::max(c.lds, sweep_lds_bytes(g, fp32, false));
+    hg[q] = g;
+    hs[q] = s->d.sc;
+    if (fp32) {
+      ((SweepArgs<float>*)(H + t->o_args))[q] =
+          make_sweep_args<float>(s->d, (float*)jobs[i].x, s->geom.nwg, g.nwg, zero_x);
+    } else {
+      ((SweepArgs<double>*)(H + t->o_args))[q] =
+          make_sweep_args<double>(s->d, (double*)jobs[i].x, s->geom.nwg, g.nwg, zero_x);
+    }
+    guard = std::max(guard, sweep_guard(jobs[i].max_iter, first_batch));
+  }
+  hw[wpos++] = classes.back().nwg;
+  for (const Cls& c : classes)
+    if (c.nh == 0 || c.lds > 160 * 1024 - 1024) return MAZE_E_INVALID;
+  HIP_TRY(hipMemcpyAsync(t->dev, H, t->o_poll, hipMemcpyHostToDevice, st));
+  int32_t* poll_h = (int32_t*)(H + t->o_poll);
+  int32_t* poll_d = (int32_t*)(t->dev + t->o_poll);
+  long long k = 0;
+  int batch = 0;
+  bool have_prev = false;
+  for (;;) {
+    const int nb = (batch == 0) ? std::max(kPollBatch, first_batch) : kPollBatch;
+    for (int b = 0; b < nb; ++b, ++k) {
+      for (const Cls& c : classes) {
+        SweepLaunch L{};
+        L.batch = true;
+        L.par = (int)(k & 1);
+        L.ppt = c.ppt;
+        L.nh = c.nh;
+        L.args = t->dev + t->o_args + (size_t)c.c0 * sizeof(SweepArgs<double>);
+        L.geoms = (const SweepGeom*)(t->dev + t->o_geom) + c.c0;
+        L.wg_begin = (const int*)(t->dev + t->o_wgb) + c.wgb0;
+        L.count = c.c1 - c.c0;
+        L.nwg_total = c.nwg;
+        L.lds = c.lds;
+        HIP_TRY(launch_sweep(L, fp32, k == 0, st));
+      }
+    }
+    const bool last = k > guard;
+    const int slot = batch & 1;
+    HIP_TRY(launch_batch_poll((Scalars* const*)(t->dev + t->o_scs), n, poll_d + 3 * n * slot, st));
+    HIP_TRY(hipMemcpyAsync(poll_h + 3 * n * slot, poll_d + 3 * n * slot, sizeof(int32_t) * 3 * n,
+                           hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipEventRecord(t->ev[slot], st));
+    if (have_prev || last) {
+      const int ws = last ? slot : (slot ^ 1);
+      HIP_TRY(hipEventSynchronize(t->ev[ws]));
+      const int32_t* p = poll_h + 3 * n * ws;
+      bool all = true;
+      for (int q = 0; q < n; ++q) all &= (p[3 * q] != 0 || p[3 * q + 2] != 0);
+      if (all || last) {
+        for (int q = 0; q < n; ++q) {
+          CgJob& j = jobs[order[q]];
+          j.err = p[3 * q + 2] != 0;
+          j.iters = p[3 * q + 1];
+          j.code = p[3 * q] ? p[3 * q] : 3;
+        }
+        for (CgJob& j : jobs) {
+          if (!j.err && j.s->trace) {
+            std::vector<maze_session*> one{j.s};
+            std::vector<Scalars> h;
+            rc = gather_scalars(one, h);
+            if (rc != MAZE_OK) return rc;
+            rc = trace_collect(j.s, j.iters, h[0].qnorm);
+            if (rc != MAZE_OK) return rc;
+          }
+        }
+        return MAZE_OK;
+      }
+    }
+    have_prev = true;
+    ++batch;
+  }
 }
 
 // Resets the binning counters and the error flag after a rejected input.
@@ -273,69 +480,141 @@ static int recover_error(maze_session* s) {
   return MAZE_E_NONFINITE;
 }
 
-// Solve of M x = s (s already in d.sigma, first residual and its partials
-// written by a right-hand-side kernel, thresholds set by FIN_SOLVE_START).
-// Leaves the true residual and mean of x in the scalars (FIN_SOLVE_END).
-static int solve(maze_session* s, double* x) {
-  DeviceState& d = s->d;
-  const MarchGeom& g = s->geom;
-  const bool mixed = s->cfg.precision == MAZE_MIXED;
-  s->iters = 0;
-  s->refinements = 0;
-  s->converged = 0;
-  s->trace_rows.clear();
-  s->trace_pass = 0;
-  if (!mixed) {
-    int it = 0, code = 0;
-    const int rc = run_cg(s, x, false, false, s->cfg.max_iter,
-                          std::max(0, s->last_iters - 2 * kPollBatch), &it, &code);
-    if (rc != MAZE_OK) return rc;
-    s->iters = it;
-    s->converged = (code == 1);
-    HIP_TRY(launch_true_residual(d, g, x, s->stream));
-    HIP_TRY(launch_finalize(d, FIN_SOLVE_END, g.nwg, 0.0, 0.0, 0.0, nullptr, 0, 0, s->stream));
-    return MAZE_OK;
+// Solves M x = s for every session (s in d.sigma, the first residual and its
+// partials written by a right-hand-side kernel, thresholds set by
+// FIN_SOLVE_START). Sessions of one precision are solved together. Leaves
+// the true residual and the mean of x in each session's scalars
+// (FIN_SOLVE_END). rcs[i]: MAZE_OK or MAZE_E_NONFINITE for session i.
+static int solve_multi(std::vector<maze_session*>& ss, std::vector<double*>& xs,
+                       std::vector<int>& rcs) {
+  const int n = (int)ss.size();
+  rcs.assign(n, MAZE_OK);
+  for (maze_session* s : ss) {
+    s->iters = 0;
+    s->refinements = 0;
+    s->converged = 0;
+    s->trace_rows.clear();
+    s->trace_pass = 0;
   }
-  // Mixed precision: FP32 inner CG on the correction, FP64 outer residual.
-  Scalars h;
-  int rc = read_scalars(s, &h);
+  // FP64 sessions: one CG solve each, batched
+  {
+    std::vector<CgJob> jobs;
+    std::vector<int> idx;
+    int fb = 1 << 30;
+    for (int i = 0; i < n; ++i)
+      if (ss[i]->cfg.precision != MAZE_MIXED) {
+        CgJob j;
+        j.s = ss[i];
+        j.x = xs[i];
+        j.max_iter = ss[i]->cfg.max_iter;
+        jobs.push_back(j);
+        idx.push_back(i);
+        fb = std::min(fb, std::max(0, ss[i]->last_iters - 2 * kPollBatch));
+      }
+    if (!jobs.empty()) {
+      const int rc = run_cg_batch(jobs, false, false, fb);
+      if (rc != MAZE_OK) return rc;
+      for (size_t q = 0; q < jobs.size(); ++q) {
+        maze_session* s = jobs[q].s;
+        if (jobs[q].err) {
+          rcs[idx[q]] = MAZE_E_NONFINITE;
+          continue;
+        }
+        s->iters = jobs[q].iters;
+        s->converged = (jobs[q].code == 1);
+        HIP_TRY(launch_true_residual(s->d, s->geom, xs[idx[q]], s->stream));
+        HIP_TRY(launch_finalize(s->d, FIN_SOLVE_END, s->geom.nwg, 0.0, 0.0, 0.0, nullptr, 0, 0,
+                                s->stream));
+      }
+    }
+  }
+  // Mixed sessions: FP32 inner CG on the correction, FP64 outer residual.
+  std::vector<int> act;
+  for (int i = 0; i < n; ++i)
+    if (ss[i]->cfg.precision == MAZE_MIXED) act.push_back(i);
+  if (act.empty()) return MAZE_OK;
+  std::vector<maze_session*> as;
+  for (int i : act) as.push_back(ss[i]);
+  std::vector<Scalars> h;
+  int rc = gather_scalars(as, h);
   if (rc != MAZE_OK) return rc;
-  if (h.err) return MAZE_E_NONFINITE;
-  const double thr = h.thr;
-  const bool absmax = s->cfg.residual_norm == MAZE_NORM_ABSMAX;
-  int total = 0;
-  for (;;) {
-    const double res = absmax ? h.true_max : std::sqrt(h.true_rr);
-    if (s->trace) {
-      s->trace_rows.push_back(s->refinements);
-      s->trace_rows.push_back(-1);
-      s->trace_rows.push_back(std::sqrt(h.true_rr) / (h.qnorm > 0 ? h.qnorm : 1.0));
-    }
-    s->trace_pass = s->refinements;
-    if (res <= thr) {
-      s->converged = 1;
-      break;
-    }
-    if (s->refinements >= kMaxRefinements || total >= s->cfg.max_iter) break;
-    const double inner = std::max(kInnerReduction * res, kInnerMargin * thr);
-    HIP_TRY(launch_finalize(d, FIN_INNER_START, 0, 0.0, inner, 0.0, nullptr,
-                            s->cfg.max_iter - total, s->cfg.residual_norm, s->stream));
-    int it = 0, code = 0;
-    const int guess_it = s->last_inner[s->refinements];
-    rc = run_cg(s, d.e32, true, true, s->cfg.max_iter - total,
-                std::max(0, guess_it - 2 * kPollBatch), &it, &code);
-    if (rc != MAZE_OK) return rc;
-    s->last_inner[s->refinements] = it;
-    total += it;
-    s->refinements += 1;
-    HIP_TRY(launch_add_correction(d, x, s->stream));
-    HIP_TRY(launch_refine(d, g, x, true, s->stream));
-    HIP_TRY(launch_finalize(d, FIN_SOLVE_END, g.nwg, 0.0, 0.0, 0.0, nullptr, 0, 0, s->stream));
-    rc = read_scalars(s, &h);
-    if (rc != MAZE_OK) return rc;
-    if (code == 2 && it == 0) break;  // breakdown without progress
+  std::vector<double> thr(n, 0.0);
+  std::vector<int> total(n, 0);
+  std::vector<Scalars> hs(n);
+  for (size_t q = 0; q < act.size(); ++q) {
+    hs[act[q]] = h[q];
+    thr[act[q]] = h[q].thr;
   }
-  s->iters = total;
+  for (;;) {
+    std::vector<int> next;
+    for (int i : act) {
+      maze_session* s = ss[i];
+      const Scalars& hh = hs[i];
+      if (hh.err) {
+        rcs[i] = MAZE_E_NONFINITE;
+        continue;
+      }
+      const bool absmax = s->cfg.residual_norm == MAZE_NORM_ABSMAX;
+      const double res = absmax ? hh.true_max : std::sqrt(hh.true_rr);
+      if (s->trace) {
+        s->trace_rows.push_back(s->refinements);
+        s->trace_rows.push_back(-1);
+        s->trace_rows.push_back(std::sqrt(hh.true_rr) / (hh.qnorm > 0 ? hh.qnorm : 1.0));
+      }
+      s->trace_pass = s->refinements;
+      if (res <= thr[i]) {
+        s->converged = 1;
+        continue;
+      }
+      if (s->refinements >= kMaxRefinements || total[i] >= s->cfg.max_iter) continue;
+      const double inner = std::max(kInnerReduction * res, kInnerMargin * thr[i]);
+      HIP_TRY(launch_finalize(s->d, FIN_INNER_START, 0, 0.0, inner, 0.0, nullptr,
+                              s->cfg.max_iter - total[i], s->cfg.residual_norm, s->stream));
+      next.push_back(i);
+    }
+    if (next.empty()) break;
+    std::vector<CgJob> jobs;
+    int fb = 1 << 30;
+    for (int i : next) {
+      maze_session* s = ss[i];
+      CgJob j;
+      j.s = s;
+      j.x = s->d.e32;
+      j.max_iter = s->cfg.max_iter - total[i];
+      jobs.push_back(j);
+      fb = std::min(fb, std::max(0, s->last_inner[s->refinements] - 2 * kPollBatch));
+    }
+    rc = run_cg_batch(jobs, true, true, fb);
+    if (rc != MAZE_OK) return rc;
+    std::vector<int> keep;
+    std::vector<maze_session*> ks;
+    for (size_t q = 0; q < next.size(); ++q) {
+      const int i = next[q];
+      maze_session* s = ss[i];
+      if (jobs[q].err) {
+        rcs[i] = MAZE_E_NONFINITE;
+        continue;
+      }
+      const int it = jobs[q].iters;
+      s->last_inner[s->refinements] = it;
+      total[i] += it;
+      s->refinements += 1;
+      HIP_TRY(launch_add_correction(s->d, xs[i], s->stream));
+      HIP_TRY(launch_refine(s->d, s->geom, xs[i], true, s->stream));
+      HIP_TRY(launch_finalize(s->d, FIN_SOLVE_END, s->geom.nwg, 0.0, 0.0, 0.0, nullptr, 0, 0,
+                              s->stream));
+      if (jobs[q].code == 2 && it == 0) continue;  // breakdown without progress
+      keep.push_back(i);
+      ks.push_back(s);
+    }
+    if (keep.empty()) break;
+    rc = gather_scalars(ks, h);
+    if (rc != MAZE_OK) return rc;
+    for (size_t q = 0; q < keep.size(); ++q) hs[keep[q]] = h[q];
+    act = keep;
+  }
+  for (int i = 0; i < n; ++i)
+    if (ss[i]->cfg.precision == MAZE_MIXED) ss[i]->iters = total[i];
   return MAZE_OK;
 }
 
@@ -353,10 +632,12 @@ static void fill_stats(maze_session* s, const Scalars& h, maze_stats* st) {
 
 static int finish_call(maze_session* s, maze_stats* st) {
   if (st) {
-    Scalars h;
-    const int rc = read_scalars(s, &h);
+    std::vector<maze_session*> one{s};
+    std::vector<Scalars> h;
+    const int rc = gather_scalars(one, h);
     if (rc != MAZE_OK) return rc;
-    fill_stats(s, h, st);
+    fill_stats(s, h[0], st);
+    st->status = s->converged ? MAZE_OK : MAZE_NOT_CONVERGED;
   }
   return s->converged ? MAZE_OK : MAZE_NOT_CONVERGED;
 }
@@ -381,13 +662,54 @@ static int direct_solve(maze_session* s, int guess, const double* pos, double* x
   HIP_TRY(launch_rhs_poisson(d, s->geom, guess, x, mixed, s->stream));
   HIP_TRY(launch_finalize(d, FIN_SOLVE_START, s->geom.nwg, s->cfg.tol, 0.0, 0.0, nullptr,
                           s->cfg.max_iter, s->cfg.residual_norm, s->stream));
-  rc = solve(s, x);
-  if (rc == MAZE_E_NONFINITE) return recover_error(s);
+  std::vector<maze_session*> one{s};
+  std::vector<double*> xs{x};
+  std::vector<int> rcs;
+  rc = solve_multi(one, xs, rcs);
   if (rc != MAZE_OK) return rc;
+  if (rcs[0] == MAZE_E_NONFINITE) return recover_error(s);
   HIP_TRY(launch_project(d, x, field, s->stream));
   HIP_TRY(launch_finalize(d, FIN_ENERGY, update_blocks(d.G), 0.0, 0.0, s->cfg.coulomb_k,
                           energy, 0, 0, s->stream));
   if (forces) HIP_TRY(launch_gather(d, x, s->cfg.coulomb_k, forces, s->stream));
+  return MAZE_OK;
+}
+
+// One MaZe step of every session (all on one stream). Per-session status in
+// rcs (MAZE_OK, or an error that left the session unchanged).
+static int step_multi(std::vector<maze_session*>& ss, const double* const* pos,
+                      double* const* field, double* const* forces, double* energies,
+                      std::vector<int>& rcs) {
+  const int n = (int)ss.size();
+  std::vector<double*> ys(n);
+  for (int i = 0; i < n; ++i) {
+    maze_session* s = ss[i];
+    DeviceState& d = s->d;
+    const int rc = assign(s, pos[i]);
+    if (rc != MAZE_OK) return rc;
+    HIP_TRY(launch_rhs_maze(d, s->geom, s->cfg.precision == MAZE_MIXED, s->stream));
+    HIP_TRY(launch_finalize(d, FIN_SOLVE_START, s->geom.nwg, s->cfg.tol, 0.0, 0.0, nullptr,
+                            s->cfg.max_iter, s->cfg.residual_norm, s->stream));
+    ys[i] = d.y;
+  }
+  int rc = solve_multi(ss, ys, rcs);
+  if (rc != MAZE_OK) return rc;
+  for (int i = 0; i < n; ++i) {
+    maze_session* s = ss[i];
+    DeviceState& d = s->d;
+    if (rcs[i] == MAZE_E_NONFINITE) {
+      rcs[i] = recover_error(s);
+      continue;
+    }
+    s->last_iters = s->iters;
+    HIP_TRY(launch_update(d, field ? field[i] : nullptr, s->stream));
+    HIP_TRY(launch_finalize(d, FIN_ENERGY, update_blocks(d.G), 0.0, 0.0, s->cfg.coulomb_k,
+                            energies ? energies + i : nullptr, 0, 0, s->stream));
+    if (forces && forces[i])
+      HIP_TRY(launch_gather(d, d.phi_prev, s->cfg.coulomb_k, forces[i], s->stream));
+    std::swap(d.phi_cur, d.phi_prev);
+    s->step += 1;
+  }
   return MAZE_OK;
 }
 
@@ -556,23 +878,11 @@ int maze_step(maze_session* s, const double* pos_dev, double* field_dev, double*
               double* energy_dev, maze_stats* st) {
   if (!s || !pos_dev) return MAZE_E_INVALID;
   hipSetDevice(s->device);
-  DeviceState& d = s->d;
-  const bool mixed = s->cfg.precision == MAZE_MIXED;
-  int rc = assign(s, pos_dev);
+  std::vector<maze_session*> one{s};
+  std::vector<int> rcs;
+  const int rc = step_multi(one, &pos_dev, &field_dev, &forces_dev, energy_dev, rcs);
   if (rc != MAZE_OK) return rc;
-  HIP_TRY(launch_rhs_maze(d, s->geom, mixed, s->stream));
-  HIP_TRY(launch_finalize(d, FIN_SOLVE_START, s->geom.nwg, s->cfg.tol, 0.0, 0.0, nullptr,
-                          s->cfg.max_iter, s->cfg.residual_norm, s->stream));
-  rc = solve(s, d.y);
-  if (rc == MAZE_E_NONFINITE) return recover_error(s);
-  if (rc != MAZE_OK) return rc;
-  s->last_iters = s->iters;
-  HIP_TRY(launch_update(d, field_dev, s->stream));
-  HIP_TRY(launch_finalize(d, FIN_ENERGY, update_blocks(d.G), 0.0, 0.0, s->cfg.coulomb_k,
-                          energy_dev, 0, 0, s->stream));
-  if (forces_dev) HIP_TRY(launch_gather(d, d.phi_prev, s->cfg.coulomb_k, forces_dev, s->stream));
-  std::swap(d.phi_cur, d.phi_prev);
-  s->step += 1;
+  if (rcs[0] != MAZE_OK) return rcs[0];
   return finish_call(s, st);
 }
 
@@ -592,12 +902,33 @@ int maze_solve(maze_session* s, int guess, const double* pos_dev, double* field_
 int maze_step_batch(maze_session* const* sessions, int32_t count, const double* const* pos_dev,
                     double* const* forces_dev, double* energies_dev, maze_stats* st) {
   if (!sessions || count <= 0 || !pos_dev) return MAZE_E_INVALID;
-  int worst = MAZE_OK;
+  std::vector<maze_session*> ss(sessions, sessions + count);
   for (int i = 0; i < count; ++i) {
-    const int rc = maze_step(sessions[i], pos_dev[i], nullptr, forces_dev ? forces_dev[i] : nullptr,
-                             energies_dev ? energies_dev + i : nullptr, st ? st + i : nullptr);
-    if (rc < 0 && (worst >= 0 || rc < worst)) worst = rc;
-    else if (worst >= 0 && rc > worst) worst = rc;
+    if (!ss[i] || !pos_dev[i]) return MAZE_E_INVALID;
+    if (ss[i]->stream != ss[0]->stream || ss[i]->device != ss[0]->device) return MAZE_E_INVALID;
+    for (int j = 0; j < i; ++j)
+      if (ss[j] == ss[i]) return MAZE_E_INVALID;
+  }
+  hipSetDevice(ss[0]->device);
+  std::vector<int> rcs;
+  int rc = step_multi(ss, pos_dev, nullptr, forces_dev, energies_dev, rcs);
+  if (rc != MAZE_OK) return rc;
+  int worst = MAZE_OK;
+  std::vector<Scalars> h;
+  if (st) {
+    rc = gather_scalars(ss, h);
+    if (rc != MAZE_OK) return rc;
+  }
+  for (int i = 0; i < count; ++i) {
+    int r = rcs[i];
+    if (r == MAZE_OK && !ss[i]->converged) r = MAZE_NOT_CONVERGED;
+    if (st) {
+      std::memset(&st[i], 0, sizeof(maze_stats));
+      if (r >= 0) fill_stats(ss[i], h[i], &st[i]);
+      st[i].status = r;
+    }
+    if (r < 0 && (worst >= 0 || r < worst)) worst = r;
+    else if (worst >= 0 && r > worst) worst = r;
   }
   return worst;
 }

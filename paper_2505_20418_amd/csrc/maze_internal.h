@@ -48,8 +48,9 @@ struct alignas(64) Scalars {
   // control, polled by the host
   int32_t done;        // 0 running, 1 converged, 2 breakdown, 3 max_iter
   int32_t iters;       // iterations when done was set
-  int32_t it;          // iterations completed in the current solve
   int32_t err;         // nonzero: non-finite input seen
+  int32_t itp[2];      // updates done in the current solve, as read by the
+                       // sweep of parity 0 / 1 (written by the sweep before)
   // solve parameters and results
   double thr;          // stopping threshold of the current solve
   double gamma[2];     // ||r||^2 by iteration parity
@@ -63,6 +64,7 @@ struct alignas(64) Scalars {
   double energy;       // (1/2) k phi . q
   int32_t max_iter;
   int32_t norm;        // MAZE_NORM_*
+  int32_t pad_i;
   double pad[2];
 };
 
@@ -174,14 +176,56 @@ hipError_t launch_rhs_maze(const DeviceState& d, const MarchGeom& g, bool mixed,
                            hipStream_t st);
 hipError_t launch_rhs_poisson(const DeviceState& d, const MarchGeom& g, int guess,
                               double* x, bool mixed, hipStream_t st);
-// CG sweep k of a solve (k = 0 is the first sweep: p_0 = r_0 / 6, no update)
-// on the FP64 (x: double*) or FP32 (x: float*) vectors; nprev = partials
-// written by the previous kernel; zero_x: the first sweep zeroes x.
-hipError_t launch_cg_sweep(const DeviceState& d, const SweepGeom& g, int k, int nprev,
+// Arguments of the CG sweeps of one session (both parities; the sweep of
+// parity par reads r[par], p[par] and writes r[par ^ 1], p[par ^ 1]).
+template <typename T>
+struct SweepArgs {
+  T* r[2];         // residual, double-buffered: sweep of parity par reads r[par]
+  T* p[2];         // search direction, double-buffered the same way
+  T* x;            // solution (updated in place)
+  double* part;    // partial-sum table of the session
+  Scalars* sc;
+  double* hist;    // residual history: hist[k] = ||r_k||_2 of the current solve
+  int pstride;
+  int nprev_first; // partials written by the kernel before the first sweep
+  int nprev_sweep; // partials written by a sweep (its workgroup count)
+  int zero_x;      // first sweep only: write x = 0 (start of an FP32 correction)
+  int hist_cap;
+  int pad;
+};
+
+template <typename T>
+SweepArgs<T> make_sweep_args(const DeviceState& d, T* x, int nprev_first, int nprev_sweep,
+                             bool zero_x);
+
+// One sweep launch: a single session (args -> host SweepArgs<T>, geometry g)
+// or a batch (args -> device array of SweepArgs<T>, geoms / wg_begin device
+// arrays of count and count + 1 entries, nwg_total workgroups, lds bytes).
+struct SweepLaunch {
+  bool batch;
+  int par;
+  int ppt, nh;        // template class shared by every session of the launch
+  const void* args;
+  SweepGeom g;
+  const SweepGeom* geoms;
+  const int* wg_begin;
+  int count;
+  int nwg_total;
+  size_t lds;
+};
+// Template class of a halo slot count (1, 2, 4 or 8; 0 if too large).
+int sweep_nh_class(int nh);
+hipError_t launch_sweep(const SweepLaunch& L, bool fp32, bool first, hipStream_t st);
+// Sweep k of a single-session solve (k = 0: p_0 = r_0 / 6, no update).
+// nprev_first: partials written by the kernel before sweep 0. x: double* or
+// float* by fp32; zero_x: sweep 0 writes x = 0.
+hipError_t launch_cg_sweep(const DeviceState& d, const SweepGeom& g, int k, int nprev_first,
                            void* x, bool fp32, bool zero_x, hipStream_t st);
-// Stopping test after the last permitted sweep (k sweeps done): sets done to
-// 1 (converged) or 3 (iteration cap).
-hipError_t launch_cg_check(const DeviceState& d, int k, int nprev, hipStream_t st);
+// Batch helpers: {done, iters, err} of every session into out[3 * count];
+// copies of every session's scalars into out[count].
+hipError_t launch_batch_poll(Scalars* const* scs, int count, int32_t* out, hipStream_t st);
+hipError_t launch_batch_scalars(Scalars* const* scs, int count, Scalars* out, hipStream_t st);
+
 // Mixed precision: x += e (FP64), FP64 residual M x - s, r32 = float(residual),
 // e = 0; partials SL_TRR/SL_TMAX (FP64) and SL_RR0/SL_RMAX0 (of r32).
 hipError_t launch_refine(const DeviceState& d, const MarchGeom& g, double* x,

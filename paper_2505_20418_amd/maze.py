@@ -43,7 +43,7 @@ class maze_config(ctypes.Structure):
 class maze_stats(ctypes.Structure):
     _fields_ = [("grid_n", ctypes.c_int32), ("iters", ctypes.c_int32),
                 ("refinements", ctypes.c_int32), ("converged", ctypes.c_int32),
-                ("h", ctypes.c_double), ("rel_residual", ctypes.c_double),
+                ("status", ctypes.c_int32), ("pad", ctypes.c_int32), ("h", ctypes.c_double), ("rel_residual", ctypes.c_double),
                 ("max_abs_residual", ctypes.c_double), ("net_charge", ctypes.c_double),
                 ("energy", ctypes.c_double)]
 
@@ -182,16 +182,24 @@ def maze_solve(handle, guess, pos, field=None, forces=None, energy=None, want_st
 
 
 def maze_step_batch(handles: Sequence, pos: Sequence[torch.Tensor],
-                    forces: Optional[Sequence[torch.Tensor]] = None,
+                    forces: Optional[Sequence[Optional[torch.Tensor]]] = None,
                     energies: Optional[torch.Tensor] = None, want_stats=True):
+    """Steps the sessions together. Returns (worst status, per-session stats
+    with their own "status"). Raises only for errors of the call as a whole
+    (invalid arguments, device or allocation failure); a rejected session is
+    reported in its stats entry."""
     n = len(handles)
     H = (ctypes.c_void_p * n)(*[h.value if isinstance(h, ctypes.c_void_p) else h for h in handles])
-    P = (ctypes.c_void_p * n)(*[p.data_ptr() for p in pos])
-    F = (ctypes.c_void_p * n)(*[f.data_ptr() for f in forces]) if forces is not None else None
+    P = (ctypes.c_void_p * n)(*[_ptr(p).value for p in pos])
+    F = None
+    if forces is not None:
+        F = (ctypes.c_void_p * n)(*[(_ptr(f).value if f is not None else None) for f in forces])
     st = (maze_stats * n)() if want_stats else None
-    rc = lib().maze_step_batch(H, n, P, F, _ptr(energies), st)
-    _check(rc, "maze_step_batch")
-    return rc, ([s.as_dict() for s in st] if st is not None else None)
+    rc = lib().maze_step_batch(H, n, P, F, _ptr(energies, numel=n) if energies is not None else None,
+                               st)
+    if rc in (MAZE_E_INVALID, MAZE_E_OOM, MAZE_E_DEVICE):
+        raise MazeError(rc, "maze_step_batch")
+    return rc, ([x.as_dict() for x in st] if st is not None else None)
 
 
 def maze_grid_n(handle) -> int:

@@ -74,7 +74,7 @@ int main(void) {
   printf("maze_config %zu\nmaze_stats %zu\nmaze_md_state %zu\n", sizeof(maze_config),
          sizeof(maze_stats), sizeof(maze_md_state));
   F(maze_config, tol); F(maze_config, coulomb_k); F(maze_config, stream);
-  F(maze_stats, h); F(maze_stats, energy);
+  F(maze_stats, h); F(maze_stats, energy); F(maze_stats, status);
   F(maze_md_state, scalars_dev); F(maze_md_state, dt); F(maze_md_state, bmh_table);
   return 0;
 }
