@@ -187,6 +187,82 @@ def copy_calibration(gib: float = 2.0, reps: int = 5):
                       "launches": reps}))
 
 
+def bench_ensemble(steps: int, warmup: int, tol: float = 1e-8):
+    """64 molten-NaCl replicas of uneven size (2..6 cells per side, 32^3 to
+    96^3 grids, 1100-1400 K), mixed precision, advanced together with one
+    batched MD step per round; the same replicas stepped one by one for
+    comparison."""
+    import torch
+    from paper_2505_20418_amd import inputs, maze, md
+
+    reps = inputs.ensemble_replicas(64, master_seed=4)
+    runs = [md.MDRun(inputs.molten_nacl(r.n_cells, seed=r.seed, temperature=r.temperature),
+                     tol=tol, precision=maze.MAZE_MIXED) for r in reps]
+    for _ in range(warmup):
+        md.step_many(runs, want_stats=False)
+    torch.cuda.synchronize()
+    lat = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        a = time.perf_counter()
+        md.step_many(runs, want_stats=False)
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - a)
+    t_batch = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for r in runs:
+            r.step()
+    torch.cuda.synchronize()
+    t_serial = time.perf_counter() - t0
+    pts = sum((inputs.GRID_PER_CELL * r.n_cells) ** 3 for r in reps)
+    ions = sum(8 * r.n_cells ** 3 for r in reps)
+    for r in runs:
+        r.close()
+    lat_ms = np.array(lat) * 1e3
+    return {"replicas": len(reps), "ions_total": ions, "grid_points_total": pts,
+            "tol_rel_residual": tol, "precision": "mixed", "steps": steps,
+            "replica_steps_per_s": round(len(reps) * steps / t_batch, 1),
+            "ensemble_steps_per_s": round(steps / t_batch, 3),
+            "step_ms": {"p50": round(float(np.percentile(lat_ms, 50)), 3),
+                        "p99": round(float(np.percentile(lat_ms, 99)), 3)},
+            "serial_replica_steps_per_s": round(len(reps) * steps / t_serial, 1),
+            "batching_speedup": round(t_serial / t_batch, 3)}
+
+
+def bench_serving(full: bool):
+    """Poisson stream (mean 200 requests/s) of MD-step requests over molten-
+    NaCl sessions of log-uniform size, half mixed at 1e-6, half FP64 at
+    1e-10, admitted by HBM budget and served with continuous batching."""
+    from paper_2505_20418_amd import serve
+
+    if full:
+        n_sess, max_cells, n_req, budget = 256, 16, 2000, 64 << 30
+    else:
+        n_sess, max_cells, n_req, budget = 64, 8, 400, 16 << 30
+    specs = serve.specs_from_inputs(count=n_sess, seed=5, max_cells=max_cells)
+    srv = serve.Server(serve.GpuBackend(), specs, budget, max_batch=64)
+    t0 = time.perf_counter()
+    resident = srv.prefill()
+    t_prefill = time.perf_counter() - t0
+    reqs = serve.poisson_requests(n_req, n_sess, rate_hz=200.0, seed=5)
+    rep = srv.serve(reqs)
+    srv.close()
+    rep = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in rep.items()}
+    for key in ("latency_ms", "service_ms"):
+        rep[key] = {k: (round(v, 3) if v is not None else None) for k, v in rep[key].items()}
+    rep.update({"sessions": n_sess, "max_ions": 8 * max_cells ** 3,
+                "max_grid": inputs_grid(max_cells), "arrival_rate_hz": 200.0,
+                "prefilled_resident": resident, "prefill_s": round(t_prefill, 2),
+                "mix": "full" if full else "reduced (sessions up to 4096 ions, 128^3)"})
+    return rep
+
+
+def inputs_grid(n_cells):
+    from paper_2505_20418_amd import inputs
+    return inputs.GRID_PER_CELL * n_cells
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -198,6 +274,10 @@ def main():
                     help="skip the FP64 side-by-side run (for profiling)")
     ap.add_argument("--replay", type=int, default=6, help="steps replayed for the error report")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--no-ensemble", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-full", action="store_true",
+                    help="serve the full 256-session mix (up to 32768 ions) instead of 64")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -275,6 +355,14 @@ def main():
         line["cg_iterations_per_step"]["fp64"] = round(it_fp64, 1)
         line["roofline_fp64"] = r_fp64
         line["mixed_error_vs_fp64"] = errors
+    if not args.no_ensemble:
+        log("bench: ensemble of 64 replicas")
+        line["ensemble"] = bench_ensemble(max(3, args.steps // 3), 4)
+        log(f"bench: ensemble {line['ensemble']}")
+    if not args.no_serving:
+        log("bench: serving")
+        line["serving"] = bench_serving(args.serving_full)
+        log(f"bench: serving {line['serving']}")
     line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)
 

@@ -246,6 +246,17 @@ int maze_md_prime(maze_session* s, const maze_md_state* md, maze_stats* st);
  */
 int maze_md_step(maze_session* s, const maze_md_state* md, maze_stats* st);
 
+/* One velocity-Verlet step of `count` distinct sessions together: the
+ * half kick and drift of each, their MaZe steps batched as in
+ * maze_step_batch, then the short range and the closing half kick of each.
+ * mds[i] belongs to sessions[i]; all sessions share a device and stream.
+ * st (count entries, host, nullable) receives per-session stats and status.
+ * Note: a session whose MaZe step is rejected has still been kicked and
+ * drifted; its caller owns the recovery of the particle state. Returns the
+ * most severe status. */
+int maze_md_step_batch(maze_session* const* sessions, const maze_md_state* const* mds,
+                       int32_t count, maze_stats* st);
+
 #ifdef __cplusplus
 }
 #endif

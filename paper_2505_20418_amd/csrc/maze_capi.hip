@@ -678,7 +678,7 @@ static int direct_solve(maze_session* s, int guess, const double* pos, double* x
 // One MaZe step of every session (all on one stream). Per-session status in
 // rcs (MAZE_OK, or an error that left the session unchanged).
 static int step_multi(std::vector<maze_session*>& ss, const double* const* pos,
-                      double* const* field, double* const* forces, double* energies,
+                      double* const* field, double* const* forces, double* const* energies,
                       std::vector<int>& rcs) {
   const int n = (int)ss.size();
   std::vector<double*> ys(n);
@@ -704,7 +704,7 @@ static int step_multi(std::vector<maze_session*>& ss, const double* const* pos,
     s->last_iters = s->iters;
     HIP_TRY(launch_update(d, field ? field[i] : nullptr, s->stream));
     HIP_TRY(launch_finalize(d, FIN_ENERGY, update_blocks(d.G), 0.0, 0.0, s->cfg.coulomb_k,
-                            energies ? energies + i : nullptr, 0, 0, s->stream));
+                            energies ? energies[i] : nullptr, 0, 0, s->stream));
     if (forces && forces[i])
       HIP_TRY(launch_gather(d, d.phi_prev, s->cfg.coulomb_k, forces[i], s->stream));
     std::swap(d.phi_cur, d.phi_prev);
@@ -880,7 +880,7 @@ int maze_step(maze_session* s, const double* pos_dev, double* field_dev, double*
   hipSetDevice(s->device);
   std::vector<maze_session*> one{s};
   std::vector<int> rcs;
-  const int rc = step_multi(one, &pos_dev, &field_dev, &forces_dev, energy_dev, rcs);
+  const int rc = step_multi(one, &pos_dev, &field_dev, &forces_dev, &energy_dev, rcs);
   if (rc != MAZE_OK) return rc;
   if (rcs[0] != MAZE_OK) return rcs[0];
   return finish_call(s, st);
@@ -911,7 +911,10 @@ int maze_step_batch(maze_session* const* sessions, int32_t count, const double* 
   }
   hipSetDevice(ss[0]->device);
   std::vector<int> rcs;
-  int rc = step_multi(ss, pos_dev, nullptr, forces_dev, energies_dev, rcs);
+  std::vector<double*> eptr(count, nullptr);
+  if (energies_dev)
+    for (int i = 0; i < count; ++i) eptr[i] = energies_dev + i;
+  int rc = step_multi(ss, pos_dev, nullptr, forces_dev, eptr.data(), rcs);
   if (rc != MAZE_OK) return rc;
   int worst = MAZE_OK;
   std::vector<Scalars> h;
@@ -1070,6 +1073,54 @@ int maze_md_step(maze_session* s, const maze_md_state* md, maze_stats* st) {
   HIP_TRY(launch_md_finish(*md, s->d, s->stream));
   const int rc2 = finish_call(s, st);
   return rc2 < 0 ? rc2 : rc;
+}
+
+int maze_md_step_batch(maze_session* const* sessions, const maze_md_state* const* mds,
+                       int32_t count, maze_stats* st) {
+  if (!sessions || !mds || count <= 0) return MAZE_E_INVALID;
+  std::vector<maze_session*> ss(sessions, sessions + count);
+  for (int i = 0; i < count; ++i) {
+    const int rc = md_check(ss[i], mds[i]);
+    if (rc != MAZE_OK) return rc;
+    if (ss[i]->stream != ss[0]->stream || ss[i]->device != ss[0]->device) return MAZE_E_INVALID;
+    for (int j = 0; j < i; ++j)
+      if (ss[j] == ss[i]) return MAZE_E_INVALID;
+  }
+  hipSetDevice(ss[0]->device);
+  std::vector<const double*> pos(count);
+  std::vector<double*> forces(count), energies(count);
+  for (int i = 0; i < count; ++i) {
+    HIP_TRY(launch_md_kick_drift(*mds[i], ss[i]->stream));
+    pos[i] = mds[i]->pos_dev;
+    forces[i] = mds[i]->f_es_dev;
+    energies[i] = mds[i]->scalars_dev + 6;
+  }
+  std::vector<int> rcs;
+  int rc = step_multi(ss, pos.data(), nullptr, forces.data(), energies.data(), rcs);
+  if (rc != MAZE_OK) return rc;
+  for (int i = 0; i < count; ++i) {
+    if (rcs[i] != MAZE_OK) continue;
+    HIP_TRY(launch_md_bmh(*mds[i], ss[i]->d, ss[i]->stream));
+    HIP_TRY(launch_md_finish(*mds[i], ss[i]->d, ss[i]->stream));
+  }
+  std::vector<Scalars> h;
+  if (st) {
+    rc = gather_scalars(ss, h);
+    if (rc != MAZE_OK) return rc;
+  }
+  int worst = MAZE_OK;
+  for (int i = 0; i < count; ++i) {
+    int r = rcs[i];
+    if (r == MAZE_OK && !ss[i]->converged) r = MAZE_NOT_CONVERGED;
+    if (st) {
+      std::memset(&st[i], 0, sizeof(maze_stats));
+      if (r >= 0) fill_stats(ss[i], h[i], &st[i]);
+      st[i].status = r;
+    }
+    if (r < 0 && (worst >= 0 || r < worst)) worst = r;
+    else if (worst >= 0 && r > worst) worst = r;
+  }
+  return worst;
 }
 
 }  // extern "C"

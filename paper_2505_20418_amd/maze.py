@@ -28,7 +28,7 @@ EXPORTED = ("maze_abi_version", "maze_strerror", "maze_device_bytes", "maze_init
             "maze_solve", "maze_step_batch", "maze_grid_n", "maze_get_grid",
             "maze_state_bytes", "maze_save", "maze_load", "maze_destroy", "maze_md_prime",
             "maze_md_step", "maze_profile_enable", "maze_profile_read", "maze_trace_enable",
-            "maze_trace_read")
+            "maze_trace_read", "maze_md_step_batch")
 
 
 class maze_config(ctypes.Structure):
@@ -114,6 +114,9 @@ def lib():
         L.maze_profile_enable.argtypes = [vp, ctypes.c_int]
         L.maze_profile_read.restype = ctypes.c_int
         L.maze_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+        L.maze_md_step_batch.restype = ctypes.c_int
+        L.maze_md_step_batch.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(vp), i32,
+                                         ctypes.POINTER(maze_stats)]
         L.maze_trace_enable.restype = ctypes.c_int
         L.maze_trace_enable.argtypes = [vp, ctypes.c_int]
         L.maze_trace_read.restype = ctypes.c_int
@@ -243,6 +246,19 @@ def maze_md_step(handle, md: maze_md_state, want_stats=True):
     rc = _check(lib().maze_md_step(handle, ctypes.byref(md),
                                    ctypes.byref(st) if st is not None else None), "maze_md_step")
     return rc, (st.as_dict() if st is not None else None)
+
+
+def maze_md_step_batch(handles: Sequence, mds: Sequence[maze_md_state], want_stats=True):
+    """One MD step of several sessions together; (worst status, per-session
+    stats). Raises only for errors of the call as a whole."""
+    n = len(handles)
+    H = (ctypes.c_void_p * n)(*[h.value if isinstance(h, ctypes.c_void_p) else h for h in handles])
+    M = (ctypes.c_void_p * n)(*[ctypes.cast(ctypes.pointer(m), ctypes.c_void_p).value for m in mds])
+    st = (maze_stats * n)() if want_stats else None
+    rc = lib().maze_md_step_batch(H, M, n, st)
+    if rc in (MAZE_E_INVALID, MAZE_E_OOM, MAZE_E_DEVICE):
+        raise MazeError(rc, "maze_md_step_batch")
+    return rc, ([x.as_dict() for x in st] if st is not None else None)
 
 
 def maze_profile_enable(handle, on: bool = True):

@@ -18,14 +18,19 @@ from . import inputs, maze
 class MDRun:
     def __init__(self, system: inputs.NaClSystem, tol: float = 1e-9,
                  precision: int = maze.MAZE_FP64, order: int = 2, dt: float = 1.0,
-                 device: str = "cuda", max_iter: int = 100000, stream=None):
+                 device: str = "cuda", max_iter: int = 100000, stream=None,
+                 restore: dict = None):
+        """restore: a dict from save_state(); the run then continues exactly
+        where the saved one stopped (particles, forces, observables and the
+        MaZe warm-start history), without the priming step."""
         self.system = system
         dev = torch.device(device)
         f64 = dict(dtype=torch.float64, device=dev)
         n = system.n_ions
         self.n = n
-        self.pos = torch.tensor(system.pos, **f64).contiguous()
-        self.vel = torch.tensor(system.vel, **f64).contiguous()
+        src = restore if restore is not None else dict(pos=system.pos, vel=system.vel)
+        self.pos = torch.tensor(np.asarray(src["pos"]), **f64).contiguous()
+        self.vel = torch.tensor(np.asarray(src["vel"]), **f64).contiguous()
         self.mass = torch.tensor(system.masses, **f64)
         self.species = torch.tensor(system.species, dtype=torch.int32, device=dev)
         self.charges = torch.tensor(system.charges, **f64)
@@ -45,12 +50,25 @@ class MDRun:
             self.scratch.data_ptr(), self.scalars.data_ptr(), float(dt),
             inputs.ACCEL_FACTOR, inputs.BMH_CUTOFF, table)
         self.last = None
-        self.prime_stats = maze.maze_md_prime(self.session.handle, self.md)[1]
+        if restore is None:
+            self.prime_stats = maze.maze_md_prime(self.session.handle, self.md)[1]
+        else:
+            self.session.load(restore["maze"])
+            self.f_es.copy_(torch.as_tensor(np.asarray(restore["f_es"])))
+            self.f_sr.copy_(torch.as_tensor(np.asarray(restore["f_sr"])))
+            self.scalars.copy_(torch.as_tensor(np.asarray(restore["scalars"])))
+            self.prime_stats = None
 
     def step(self, want_stats: bool = False):
         rc, st = maze.maze_md_step(self.session.handle, self.md, want_stats)
         self.last = st
         return rc, st
+
+    def save_state(self) -> dict:
+        """Host copy of everything needed to continue this run exactly."""
+        return dict(maze=self.session.save(), pos=self.pos.cpu().numpy(),
+                    vel=self.vel.cpu().numpy(), f_es=self.f_es.cpu().numpy(),
+                    f_sr=self.f_sr.cpu().numpy(), scalars=self.scalars.cpu().numpy())
 
     def observables(self) -> dict:
         s = self.scalars.cpu().numpy()
@@ -60,3 +78,9 @@ class MDRun:
 
     def close(self):
         self.session.close()
+
+
+def step_many(runs, want_stats: bool = True):
+    """One MD step of several runs together (maze_md_step_batch)."""
+    return maze.maze_md_step_batch([r.session.handle for r in runs], [r.md for r in runs],
+                                   want_stats)

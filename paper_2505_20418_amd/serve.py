@@ -1,0 +1,294 @@
+"""Continuous-batching service of MD-step requests over resident MaZe sessions.
+
+Requests ask to advance one session by one MD step and arrive over time.
+The scheduler works at step granularity:
+
+* every round it forms a batch from the requests that have arrived: at most
+  one request per session (its oldest), oldest request first, up to
+  ``max_batch`` sessions;
+* a session stays resident on the device between its steps, so its MaZe
+  warm start (phi^k, phi^{k-1}, y*) and its particles persist;
+* a session that is not resident is admitted when its device bytes fit in
+  the HBM budget; otherwise resident sessions outside the batch are parked
+  least-recently-used first (their state copied to the host with the
+  library's checkpoint and restored exactly on their next admission);
+* one round is one batched MD step of all its sessions (the sessions' CG
+  iterations share their launches on the device); requests that arrive
+  while a round runs join the next round.
+
+Per request the server records latency (completion minus arrival) and the
+service time of its round. The backend does the device work; the GPU
+backend calls the library through ``maze_md_step_batch``. The clock and the
+sleep function are injectable so the scheduling logic can be exercised with
+a simulated clock.
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import time
+from typing import Callable, Dict, List, Optional, Sequence
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class SessionSpec:
+    """One served MD session of synthetic molten NaCl."""
+    n_cells: int
+    seed: int
+    mixed: bool
+    tol: float
+    temperature: float = 1200.0
+
+
+@dataclasses.dataclass
+class Request:
+    arrival_s: float      # seconds after the start of the stream
+    session: int
+
+
+@dataclasses.dataclass
+class Completion:
+    session: int
+    arrival_s: float
+    done_s: float
+    service_s: float
+    batch_size: int
+    status: int
+    iters: int
+
+    @property
+    def latency_s(self) -> float:
+        return self.done_s - self.arrival_s
+
+
+class GpuBackend:
+    """Sessions as device-resident MD runs of the library."""
+
+    def __init__(self, device: str = "cuda", dt: float = 1.0):
+        from . import inputs, maze, md  # noqa: F401  (fails loudly without the library)
+        self.device = device
+        self.dt = dt
+        maze.lib()
+
+    def _system(self, spec: SessionSpec):
+        from . import inputs
+        return inputs.molten_nacl(spec.n_cells, seed=spec.seed, temperature=spec.temperature)
+
+    def bytes_needed(self, spec: SessionSpec) -> int:
+        from . import inputs, maze
+        s = self._system(spec)
+        cfg = maze.maze_config(s.n_ions, 2, s.box, s.grid_spacing, spec.tol, 100000,
+                               maze.MAZE_MIXED if spec.mixed else maze.MAZE_FP64, 0, 0,
+                               inputs.COULOMB_K_EV_A, None)
+        n = s.n_ions
+        particles = 8 * (3 * 5 + 2) * n + 8 * (6 * n + 8 * ((n + 255) // 256) + 8) + 4 * n
+        return int(maze.maze_device_bytes(cfg)) + particles
+
+    def create(self, spec: SessionSpec):
+        from . import maze, md
+        return md.MDRun(self._system(spec), tol=spec.tol,
+                        precision=maze.MAZE_MIXED if spec.mixed else maze.MAZE_FP64,
+                        dt=self.dt, device=self.device)
+
+    def park(self, run) -> dict:
+        state = run.save_state()
+        run.close()
+        return state
+
+    def restore(self, spec: SessionSpec, state: dict):
+        from . import maze, md
+        return md.MDRun(self._system(spec), tol=spec.tol,
+                        precision=maze.MAZE_MIXED if spec.mixed else maze.MAZE_FP64,
+                        dt=self.dt, device=self.device, restore=state)
+
+    def step(self, runs: Sequence) -> List[dict]:
+        from . import md
+        _, stats = md.step_many(list(runs), want_stats=True)
+        return stats
+
+    def destroy(self, run):
+        run.close()
+
+
+@dataclasses.dataclass
+class _Slot:
+    spec: SessionSpec
+    obj: object = None            # resident backend object
+    parked: Optional[dict] = None  # host checkpoint while not resident
+    nbytes: int = 0
+    last_used: float = -1.0
+    steps: int = 0
+
+
+class Server:
+    """Continuous-batching scheduler over a backend (see module docstring)."""
+
+    def __init__(self, backend, specs: Sequence[SessionSpec], hbm_budget: int,
+                 max_batch: int = 64, clock: Callable[[], float] = time.perf_counter,
+                 sleep: Callable[[float], None] = time.sleep):
+        self.backend = backend
+        self.slots = [_Slot(spec=s) for s in specs]
+        self.budget = int(hbm_budget)
+        self.max_batch = int(max_batch)
+        self.clock = clock
+        self.sleep = sleep
+        self.used = 0
+        self.peak_used = 0
+        self.admitted = 0
+        self.parked = 0
+        self.restored = 0
+        self.refused: List[Request] = []
+        self.completions: List[Completion] = []
+        self.rounds: List[int] = []
+
+    # ---- residency -----------------------------------------------------------
+    def _bytes(self, sid: int) -> int:
+        sl = self.slots[sid]
+        if sl.nbytes == 0:
+            sl.nbytes = int(self.backend.bytes_needed(sl.spec))
+        return sl.nbytes
+
+    def resident(self, sid: int) -> bool:
+        return self.slots[sid].obj is not None
+
+    def _evict_one(self, protect: set, queued: set) -> bool:
+        cands = [i for i, s in enumerate(self.slots) if s.obj is not None and i not in protect]
+        if not cands:
+            return False
+        # idle sessions (nothing queued) first, then least recently used
+        cands.sort(key=lambda i: (i in queued, self.slots[i].last_used))
+        victim = cands[0]
+        sl = self.slots[victim]
+        sl.parked = self.backend.park(sl.obj)
+        sl.obj = None
+        self.used -= sl.nbytes
+        self.parked += 1
+        return True
+
+    def admit(self, sid: int, protect: set = frozenset(), queued: set = frozenset()) -> bool:
+        """Makes session sid resident if the budget allows (parking others
+        outside `protect` as needed). False if it cannot fit now."""
+        if self.resident(sid):
+            return True
+        need = self._bytes(sid)
+        if need > self.budget:
+            return False
+        while self.used + need > self.budget:
+            if not self._evict_one(protect | {sid}, queued):
+                return False
+        sl = self.slots[sid]
+        if sl.parked is not None:
+            sl.obj = self.backend.restore(sl.spec, sl.parked)
+            sl.parked = None
+            self.restored += 1
+        else:
+            sl.obj = self.backend.create(sl.spec)
+            self.admitted += 1
+        self.used += need
+        self.peak_used = max(self.peak_used, self.used)
+        return True
+
+    def prefill(self, sids: Optional[Sequence[int]] = None) -> int:
+        """Creates sessions up front while they fit in the budget; returns
+        the number made resident."""
+        n = 0
+        for sid in (range(len(self.slots)) if sids is None else sids):
+            if self.used + self._bytes(sid) > self.budget:
+                break
+            if self.admit(sid):
+                n += 1
+        return n
+
+    # ---- serving loop ----------------------------------------------------------
+    def serve(self, requests: Sequence[Request]) -> dict:
+        reqs = sorted(requests, key=lambda r: r.arrival_s)
+        pending = collections.deque(reqs)
+        queues: Dict[int, collections.deque] = collections.defaultdict(collections.deque)
+        t0 = self.clock()
+        n_queued = 0
+        while pending or n_queued:
+            now = self.clock() - t0
+            while pending and pending[0].arrival_s <= now:
+                r = pending.popleft()
+                if self._bytes(r.session) > self.budget:
+                    self.refused.append(r)
+                    continue
+                queues[r.session].append(r)
+                n_queued += 1
+            ready = sorted((q[0].arrival_s, sid) for sid, q in queues.items() if q)
+            if not ready:
+                if pending:
+                    self.sleep(max(0.0, pending[0].arrival_s - (self.clock() - t0)))
+                continue
+            queued = {sid for _, sid in ready}
+            batch: List[int] = []
+            for _, sid in ready:
+                if len(batch) >= self.max_batch:
+                    break
+                if self.admit(sid, protect=set(batch), queued=queued):
+                    batch.append(sid)
+            if not batch:
+                raise RuntimeError("no queued session fits in the HBM budget with the "
+                                   "resident sessions it cannot park")
+            t_start = self.clock()
+            stats = self.backend.step([self.slots[sid].obj for sid in batch])
+            t_end = self.clock()
+            self.rounds.append(len(batch))
+            for sid, st in zip(batch, stats):
+                r = queues[sid].popleft()
+                n_queued -= 1
+                sl = self.slots[sid]
+                sl.last_used = t_end
+                sl.steps += 1
+                self.completions.append(Completion(
+                    session=sid, arrival_s=r.arrival_s, done_s=t_end - t0,
+                    service_s=t_end - t_start, batch_size=len(batch),
+                    status=int(st.get("status", 0)), iters=int(st.get("iters", 0))))
+        return self.report(self.clock() - t0)
+
+    def report(self, wall_s: float) -> dict:
+        lat = np.array([c.latency_s for c in self.completions]) * 1e3
+        svc = np.array([c.service_s for c in self.completions]) * 1e3
+        pct = lambda a, q: float(np.percentile(a, q)) if a.size else None  # noqa: E731
+        return {
+            "requests_completed": len(self.completions),
+            "requests_refused": len(self.refused),
+            "wall_s": wall_s,
+            "steps_per_s": len(self.completions) / wall_s if wall_s > 0 else None,
+            "latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99),
+                           "mean": float(lat.mean()) if lat.size else None},
+            "service_ms": {"p50": pct(svc, 50), "p99": pct(svc, 99)},
+            "rounds": len(self.rounds),
+            "mean_batch": float(np.mean(self.rounds)) if self.rounds else 0.0,
+            "max_batch": int(max(self.rounds)) if self.rounds else 0,
+            "admitted": self.admitted, "parked": self.parked, "restored": self.restored,
+            "hbm_budget": self.budget, "hbm_peak_used": self.peak_used,
+            "statuses": dict(collections.Counter(c.status for c in self.completions)),
+        }
+
+    def close(self):
+        for sl in self.slots:
+            if sl.obj is not None:
+                self.backend.destroy(sl.obj)
+                sl.obj = None
+                self.used -= sl.nbytes
+
+
+def specs_from_inputs(count: int = 256, seed: int = 5, max_cells: int = 16) -> List[SessionSpec]:
+    """Session mix of the serving workload (sizes log-uniform over 64..32768
+    ions, tolerance class 50/50: 1e-6 mixed or 1e-10 FP64)."""
+    from . import inputs
+    out = []
+    for d in inputs.serving_sessions(count=count, seed=seed, max_cells=max_cells):
+        out.append(SessionSpec(n_cells=d["n_cells"], seed=d["seed"], mixed=d["mixed"],
+                               tol=d["tol"]))
+    return out
+
+
+def poisson_requests(n_requests: int, n_sessions: int, rate_hz: float = 200.0,
+                     seed: int = 5) -> List[Request]:
+    from . import inputs
+    return [Request(r.arrival_s, r.session)
+            for r in inputs.poisson_arrivals(n_requests, n_sessions, rate_hz=rate_hz, seed=seed)]

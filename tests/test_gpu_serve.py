@@ -1,0 +1,54 @@
+"""Served MD steps through the continuous-batching server on the device.
+
+Sessions of uneven size and both precisions are served from a Poisson
+request stream under an HBM budget small enough to force parking and
+restoring. Each session must end exactly where the same number of steps
+taken alone leaves it: batching shares launches but not arithmetic, and the
+checkpoint restores the warm-start history bit for bit.
+"""
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2505_20418_amd import maze
+    maze.lib()
+
+
+def test_served_sessions_equal_alone(gpu):
+    from paper_2505_20418_amd import md, serve
+    specs = [serve.SessionSpec(2, 11, False, 1e-10), serve.SessionSpec(3, 12, True, 1e-6),
+             serve.SessionSpec(4, 13, False, 1e-10), serve.SessionSpec(2, 14, True, 1e-6),
+             serve.SessionSpec(3, 15, False, 1e-10)]
+    be = serve.GpuBackend()
+    sizes = [be.bytes_needed(s) for s in specs]
+    budget = int(sum(sorted(sizes)[-3:]) * 1.01)     # at most ~3 resident at once
+    srv = serve.Server(be, specs, budget, max_batch=4)
+    reqs = serve.poisson_requests(24, len(specs), rate_hz=400.0, seed=3)
+    print(f"case: serve {len(specs)} sessions, {len(reqs)} requests, budget {budget}", flush=True)
+    rep = srv.serve(reqs)
+    assert rep["requests_completed"] == len(reqs)
+    assert rep["parked"] >= 1 and rep["restored"] >= 1, rep
+    assert rep["hbm_peak_used"] <= budget
+    assert set(rep["statuses"]) <= {0}
+    for sid, spec in enumerate(specs):
+        sl = srv.slots[sid]
+        if sl.steps == 0:
+            continue
+        run = sl.obj if sl.obj is not None else be.restore(spec, sl.parked)
+        alone = be.create(spec)
+        for _ in range(sl.steps):
+            alone.step()
+        assert torch.equal(run.pos, alone.pos), sid
+        assert torch.equal(run.vel, alone.vel), sid
+        assert torch.equal(run.scalars, alone.scalars), sid
+        alone.close()
+        if sl.obj is None:
+            run.close()
+    srv.close()

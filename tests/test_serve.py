@@ -1,0 +1,122 @@
+"""Scheduling logic of the continuous-batching server, on the CPU.
+
+A fake backend stands in for the device: it keeps a step counter per
+session and advances a simulated clock by a cost that grows with the batch,
+so admission by budget, parking, continuous batching and the latency
+accounting can be checked exactly without a GPU.
+"""
+import pytest
+
+from paper_2505_20418_amd.serve import Request, Server, SessionSpec
+
+
+class FakeClock:
+    def __init__(self):
+        self.t = 0.0
+
+    def __call__(self):
+        return self.t
+
+    def sleep(self, dt):
+        self.t += max(dt, 1e-9)
+
+
+class FakeBackend:
+    def __init__(self, clock, sizes, step_cost=0.010, per_session=0.002):
+        self.clock = clock
+        self.sizes = sizes
+        self.step_cost = step_cost
+        self.per_session = per_session
+        self.live = {}
+        self.batches = []
+        self.created = 0
+
+    def bytes_needed(self, spec):
+        return self.sizes[spec.seed]
+
+    def create(self, spec):
+        self.created += 1
+        obj = {"sid": spec.seed, "steps": 0}
+        self.live[id(obj)] = obj
+        return obj
+
+    def park(self, obj):
+        del self.live[id(obj)]
+        return {"steps": obj["steps"], "sid": obj["sid"]}
+
+    def restore(self, spec, state):
+        obj = {"sid": state["sid"], "steps": state["steps"]}
+        self.live[id(obj)] = obj
+        return obj
+
+    def step(self, objs):
+        self.batches.append([o["sid"] for o in objs])
+        self.clock.t += self.step_cost + self.per_session * len(objs)
+        for o in objs:
+            o["steps"] += 1
+        return [{"status": 0, "iters": 10} for _ in objs]
+
+    def destroy(self, obj):
+        self.live.pop(id(obj), None)
+
+
+def make(n=4, sizes=None, budget=10**9, max_batch=64):
+    clock = FakeClock()
+    sizes = sizes or {i: 100 for i in range(n)}
+    be = FakeBackend(clock, sizes)
+    specs = [SessionSpec(n_cells=2, seed=i, mixed=False, tol=1e-9) for i in range(n)]
+    return Server(be, specs, budget, max_batch=max_batch, clock=clock, sleep=clock.sleep), be, clock
+
+
+def test_requests_arriving_during_a_round_join_the_next():
+    srv, be, clock = make()
+    reqs = [Request(0.0, 0), Request(0.0, 1), Request(0.005, 2), Request(0.006, 3)]
+    rep = srv.serve(reqs)
+    # round 1 holds what arrived at t=0; the two later arrivals form round 2
+    assert be.batches == [[0, 1], [2, 3]]
+    assert rep["requests_completed"] == 4
+    c = {x.session: x for x in srv.completions}
+    assert c[0].done_s == pytest.approx(0.014)
+    assert c[2].done_s == pytest.approx(0.014 + 0.014)
+    assert c[2].latency_s == pytest.approx(0.028 - 0.005)
+    assert c[0].service_s == pytest.approx(0.014)
+
+
+def test_one_request_per_session_per_round_in_arrival_order():
+    srv, be, clock = make(n=2)
+    reqs = [Request(0.0, 0), Request(0.0, 0), Request(0.0, 1), Request(0.0, 0)]
+    srv.serve(reqs)
+    assert be.batches == [[0, 1], [0], [0]]
+    assert [x.session for x in srv.completions] == [0, 1, 0, 0]
+    assert srv.slots[0].steps == 3 and srv.slots[1].steps == 1
+
+
+def test_budget_parks_least_recently_used_and_restores_state():
+    sizes = {0: 60, 1: 60, 2: 60}
+    srv, be, clock = make(n=3, sizes=sizes, budget=130)
+    reqs = [Request(0.0, 0), Request(0.0, 1), Request(0.1, 2), Request(0.2, 0)]
+    srv.serve(reqs)
+    # two fit; session 2 parks the least recently used idle one, and session 0
+    # comes back with its step count intact
+    assert srv.peak_used <= 130
+    assert srv.parked >= 1 and srv.restored >= 1
+    assert srv.slots[0].steps == 2
+    obj0 = srv.slots[0].obj if srv.slots[0].obj is not None else srv.slots[0].parked
+    assert obj0["steps"] == 2
+
+
+def test_max_batch_and_refusal():
+    sizes = {0: 10, 1: 10, 2: 10, 3: 10**6}
+    srv, be, clock = make(n=4, sizes=sizes, budget=1000, max_batch=2)
+    reqs = [Request(0.0, i) for i in range(4)]
+    rep = srv.serve(reqs)
+    assert rep["requests_refused"] == 1            # session 3 can never fit
+    assert all(len(b) <= 2 for b in be.batches)
+    assert rep["requests_completed"] == 3
+
+
+def test_prefill_stops_at_budget():
+    sizes = {i: 40 for i in range(5)}
+    srv, be, clock = make(n=5, sizes=sizes, budget=100)
+    assert srv.prefill() == 2
+    assert srv.used == 80
