@@ -48,11 +48,11 @@ def stencil_hash() -> str:
     return hashlib.sha256(open(STENCIL_SRC, "rb").read()).hexdigest()[:16]
 
 
-def run_md(system, tol, precision, steps, warmup, record_positions=False):
+def run_md(system, tol, precision, steps, warmup, record_positions=False, order=2):
     import torch
     from paper_2505_20418_amd import maze, md
 
-    run = md.MDRun(system, tol=tol, precision=precision)
+    run = md.MDRun(system, tol=tol, precision=precision, order=order)
     h = run.session.handle
     for _ in range(warmup):
         run.step()
@@ -275,6 +275,7 @@ def main():
     ap.add_argument("--replay", type=int, default=6, help="steps replayed for the error report")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true")
+    ap.add_argument("--no-order4", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-full", action="store_true",
                     help="serve the full 256-session mix (up to 32768 ions) instead of 64")
@@ -355,6 +356,21 @@ def main():
         line["cg_iterations_per_step"]["fp64"] = round(it_fp64, 1)
         line["roofline_fp64"] = r_fp64
         line["mixed_error_vs_fp64"] = errors
+    if not args.no_order4:
+        # the same workload with the cubic B-spline assignment the paper names
+        # (64 points per ion): smoother charge motion, far fewer iterations
+        log("bench: order-4 assignment")
+        o4 = {}
+        for name, prec in (("mixed", maze.MAZE_MIXED), ("fp64", maze.MAZE_FP64)):
+            r = run_md(system, tol, prec, args.steps, args.warmup, order=4)
+            key = "fp32_iters" if prec == maze.MAZE_MIXED else "fp64_iters"
+            o4[name] = {"value": round(r["steps_per_s"], 4), "unit": "MD steps/s",
+                        "cg_iterations_per_step": round(r["prof"][key] / args.steps, 1),
+                        "latency_ms": {"p50": round(float(np.percentile(r["lat_ms"], 50)), 3),
+                                       "p99": round(float(np.percentile(r["lat_ms"], 99)), 3)}}
+        o4["speedup_mixed_vs_fp64"] = round(o4["mixed"]["value"] / o4["fp64"]["value"], 3)
+        line["order4"] = o4
+        log(f"bench: order4 {o4}")
     if not args.no_ensemble:
         log("bench: ensemble of 64 replicas")
         line["ensemble"] = bench_ensemble(max(3, args.steps // 3), 4)
