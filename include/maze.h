@@ -61,6 +61,7 @@ enum {
 enum { MAZE_FP64 = 0, MAZE_MIXED = 1 };
 enum { MAZE_GUESS_ZERO = 0, MAZE_GUESS_STATIC = 1, MAZE_GUESS_TIMEPROP = 2 };
 enum { MAZE_NORM_REL2 = 0, MAZE_NORM_ABSMAX = 1 };
+enum { MAZE_FLAG_MULTIGRID = 1 };
 
 typedef struct {
   int32_t n_ions;         /* > 0 */
@@ -79,7 +80,15 @@ typedef struct {
                              vectors, FP64 dots, norms, projection and an
                              outer refinement on the FP64 residual) */
   int32_t residual_norm;  /* MAZE_NORM_REL2 or MAZE_NORM_ABSMAX */
-  int32_t flags;          /* reserved, must be 0 */
+  int32_t flags;          /* 0, or MAZE_FLAG_MULTIGRID: precondition the
+                             PLCG with a geometric multigrid V-cycle (red-
+                             black Gauss-Seidel, full-weighting restriction,
+                             trilinear prolongation, CG on the coarsest
+                             grid; the multigrid of the Results section)
+                             instead of the Jacobi diagonal. The outer CG is
+                             then FP64 in both precision modes; MAZE_MIXED
+                             runs the V-cycle in FP32. Needs a grid that
+                             halves down to at most 12^3 points. */
   double  coulomb_k;      /* energy/force scale, > 0 */
   void*   stream;         /* hipStream_t or NULL */
 } maze_config;

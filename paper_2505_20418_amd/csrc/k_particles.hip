@@ -436,7 +436,8 @@ __global__ __launch_bounds__(kThreads) void k_finalize(int mode, int count, long
                                                        double tol, double param,
                                                        double coulomb_k, const double* part,
                                                        int pstride, Scalars* sc,
-                                                       double* energy_out, int imax, int norm) {
+                                                       double* energy_out, int imax, int norm,
+                                                       double* hist, int hist_cap) {
   __shared__ double red[8];
   auto slot = [&](int s) { return part + (size_t)s * pstride; };
   if (mode == FIN_QSUM) {
@@ -488,6 +489,51 @@ __global__ __launch_bounds__(kThreads) void k_finalize(int mode, int count, long
       ctl_st(&sc->done, 0);
       ctl_st(&sc->iters, 0);
     }
+  } else if (mode >= FIN_MG_CHECK0) {
+    // multigrid-preconditioned CG; itp[0] counts its iterations
+    if (ctl_ld(&sc->done) != 0 || ctl_ld(&sc->err) != 0) return;
+    if (mode == FIN_MG_RHO) {
+      const double rho = sum_partials(slot(SL_MGRZ), count, red);
+      if (threadIdx.x == 0) {
+        const int it = ctl_ld(&sc->itp[0]);
+        if (!(rho > 0.0) || !isfinite(rho)) {
+          ctl_st(&sc->iters, it);
+          ctl_st(&sc->done, 2);
+          return;
+        }
+        ctl_st(&sc->mg_beta, it == 0 ? 0.0 : rho / ctl_ld(&sc->mg_rho));
+        ctl_st(&sc->mg_rho, rho);
+      }
+    } else if (mode == FIN_MG_MU) {
+      const double mu = sum_partials(slot(SL_MU0), count, red);
+      if (threadIdx.x == 0) {
+        if (!(mu > 0.0) || !isfinite(mu)) {
+          ctl_st(&sc->iters, ctl_ld(&sc->itp[0]));
+          ctl_st(&sc->done, 2);
+          return;
+        }
+        ctl_st(&sc->mg_alpha, ctl_ld(&sc->mg_rho) / mu);
+      }
+    } else {
+      const double gam = sum_partials(slot(SL_RR0), count, red);
+      const double rmax = max_partials(slot(SL_RMAX0), count, red);
+      if (threadIdx.x == 0) {
+        const int it = ctl_ld(&sc->itp[0]) + (mode == FIN_MG_CONV ? 1 : 0);
+        ctl_st(&sc->itp[0], it);
+        if (it < hist_cap) hist[it] = sqrt(gam);
+        const double thr = ctl_ld(&sc->thr);
+        const bool conv = (ctl_ld(&sc->norm) == MAZE_NORM_ABSMAX) ? (rmax <= thr)
+                                                                   : (sqrt(gam) <= thr);
+        if (mode == FIN_MG_CHECK0) ctl_st(&sc->mg_beta, 0.0);
+        if (conv || !isfinite(gam)) {
+          ctl_st(&sc->iters, it);
+          ctl_st(&sc->done, conv ? 1 : 2);
+        } else if (it >= ctl_ld(&sc->max_iter)) {
+          ctl_st(&sc->iters, it);
+          ctl_st(&sc->done, 3);
+        }
+      }
+    }
   }
 }
 
@@ -496,7 +542,7 @@ hipError_t launch_finalize(const DeviceState& d, int mode, int count, double tol
                            int norm, hipStream_t st) {
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), 0, st, mode, count, d.G, tol, param,
                      coulomb_k, (const double*)d.part, d.part_stride, d.sc, energy_out, imax,
-                     norm);
+                     norm, d.hist, d.hist_cap);
   return hipGetLastError();
 }
 

@@ -358,6 +358,82 @@ struct OpRhsPoisson {
 };
 
 // ---------------------------------------------------------------------------
+// Multigrid-preconditioned CG, direction pass: p = z + beta p_old (beta = 0
+// on the first iteration) and <p, A p> with A = -M on the fly. z is the
+// V-cycle output (FP64 or FP32). Staged field: p.
+// ---------------------------------------------------------------------------
+template <typename ZT>
+struct OpMgDir {
+  using T = double;
+  static constexpr int K = 1;
+  static constexpr int NACC = 1;
+  const ZT* z;
+  const double* pold;
+  double* p;
+  double* part;
+  int pstride;
+  int parity;
+  const Scalars* sc;
+  double beta;
+
+  __device__ bool skip() const { return ctl_ld(&sc->done) != 0 || ctl_ld(&sc->err) != 0; }
+  __device__ bool prepare(double*) {
+    beta = ctl_ld(&sc->mg_beta);
+    return true;
+  }
+  __device__ void load(long long g, double v[1]) const {
+    const double zv = (double)z[g];
+    v[0] = (beta == 0.0) ? zv : zv + beta * pold[g];
+  }
+  __device__ void point(long long g, const double* c, const double* xm, const double* xp,
+                        const double* ym, const double* yp, const double* zm, const double* zp,
+                        double* a) const {
+    const double ap = 6.0 * c[0] - nbr_sum(xm[0], xp[0], ym[0], yp[0], zm[0], zp[0]);
+    p[g] = c[0];
+    a[0] += c[0] * ap;
+  }
+  __device__ static bool acc_is_max(int) { return false; }
+  __device__ static int acc_slot(int, int) { return SL_MU0; }
+  __device__ void finish_wg0() const {}
+};
+
+// Multigrid-preconditioned CG, update pass: x += alpha p, r -= alpha A p
+// (A p recomputed from the staged p), ||r||^2 and max |r|.
+struct OpMgUpd {
+  using T = double;
+  static constexpr int K = 1;
+  static constexpr int NACC = 2;
+  const double* p;
+  double* x;
+  double* r;
+  double* part;
+  int pstride;
+  int parity;
+  const Scalars* sc;
+  double alpha;
+
+  __device__ bool skip() const { return ctl_ld(&sc->done) != 0 || ctl_ld(&sc->err) != 0; }
+  __device__ bool prepare(double*) {
+    alpha = ctl_ld(&sc->mg_alpha);
+    return true;
+  }
+  __device__ void load(long long g, double v[1]) const { v[0] = p[g]; }
+  __device__ void point(long long g, const double* c, const double* xm, const double* xp,
+                        const double* ym, const double* yp, const double* zm, const double* zp,
+                        double* a) const {
+    const double ap = 6.0 * c[0] - nbr_sum(xm[0], xp[0], ym[0], yp[0], zm[0], zp[0]);
+    x[g] += alpha * c[0];
+    const double rv = r[g] - alpha * ap;
+    r[g] = rv;
+    a[0] += rv * rv;
+    a[1] = fmax(a[1], fabs(rv));
+  }
+  __device__ static bool acc_is_max(int i) { return i == 1; }
+  __device__ static int acc_slot(int i, int) { return i == 0 ? SL_RR0 : SL_RMAX0; }
+  __device__ void finish_wg0() const {}
+};
+
+// ---------------------------------------------------------------------------
 // FP64 residual M x - s of the current solution: the true residual reported
 // at exit, and in mixed precision the outer refinement step that restores
 // an FP64 residual and hands its FP32 rounding to the next inner solve.
@@ -466,6 +542,22 @@ hipError_t launch_rhs_poisson(const DeviceState& d, const MarchGeom& g, int gues
   }
   OpRhsPoisson<false> op{d.phi_cur, d.phi_prev, d.q, d.sigma, x, d.r, nullptr,
                          d.part, d.part_stride, 0, d.sc, guess, c4, 0.0};
+  return launch_march(op, g, st);
+}
+
+hipError_t launch_mg_dir(const DeviceState& d, const MarchGeom& g, const void* z, bool fp32,
+                         const double* pold, double* pnew, hipStream_t st) {
+  if (fp32) {
+    OpMgDir<float> op{(const float*)z, pold, pnew, d.part, d.part_stride, 0, d.sc, 0.0};
+    return launch_march(op, g, st);
+  }
+  OpMgDir<double> op{(const double*)z, pold, pnew, d.part, d.part_stride, 0, d.sc, 0.0};
+  return launch_march(op, g, st);
+}
+
+hipError_t launch_mg_upd(const DeviceState& d, const MarchGeom& g, const double* p, double* x,
+                         hipStream_t st) {
+  OpMgUpd op{p, x, d.r, d.part, d.part_stride, 0, d.sc, 0.0};
   return launch_march(op, g, st);
 }
 

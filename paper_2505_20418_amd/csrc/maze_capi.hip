@@ -88,8 +88,12 @@ static int validate(const maze_config* c) {
   if (c->precision != MAZE_FP64 && c->precision != MAZE_MIXED) return MAZE_E_INVALID;
   if (c->residual_norm != MAZE_NORM_REL2 && c->residual_norm != MAZE_NORM_ABSMAX)
     return MAZE_E_INVALID;
-  if (c->flags != 0 || !finite_pos(c->coulomb_k)) return MAZE_E_INVALID;
+  if ((c->flags & ~MAZE_FLAG_MULTIGRID) != 0 || !finite_pos(c->coulomb_k)) return MAZE_E_INVALID;
   if (grid_of(c) == 0) return MAZE_E_INVALID;
+  if (c->flags & MAZE_FLAG_MULTIGRID) {
+    int Ns[kMgMaxLevels];
+    if (mg_plan(grid_of(c), Ns, kMgMaxLevels) == 0) return MAZE_E_INVALID;
+  }
   return MAZE_OK;
 }
 
@@ -118,7 +122,7 @@ static int part_stride_for(const DeviceState& d, const MarchGeom& g, const Sweep
 }
 
 struct Layout {
-  size_t off[32];
+  size_t off[64];
   size_t total = 0;
   int n = 0;
   size_t add(size_t bytes) {
@@ -139,7 +143,10 @@ static Layout layout_for(const maze_config* c, int N, int* ntx_out, int* ntiles_
   tmp.G = G;
   tmp.ntiles = ntiles;
   const int stride = part_stride_for(tmp, choose_geom(N), choose_sweep(N));
-  const bool mixed = c->precision == MAZE_MIXED;
+  const bool mg = (c->flags & MAZE_FLAG_MULTIGRID) != 0;
+  // the multigrid-preconditioned CG is FP64 outside the V-cycle; the mixed
+  // mode runs its V-cycle in FP32
+  const bool mixed = c->precision == MAZE_MIXED && !mg;
   const size_t n = (size_t)c->n_ions;
   Layout L;
   const size_t gd = sizeof(double) * (size_t)G, gf = sizeof(float) * (size_t)G;
@@ -168,6 +175,21 @@ static Layout layout_for(const maze_config* c, int N, int* ntx_out, int* ntiles_
   L.add(sizeof(double) * n);              // 22 s_Q
   L.add(sizeof(double) * (n + 1));        // 23 md_epart
   L.add(sizeof(double) * kHistCap);       // 24 residual history
+  if (mg) {
+    int Ns[kMgMaxLevels];
+    const int levels = mg_plan(N, Ns, kMgMaxLevels);
+    const size_t es = (c->precision == MAZE_MIXED) ? sizeof(float) : sizeof(double);
+    const bool f32 = es == sizeof(float);
+    L.add(f32 ? es * (size_t)G : 0);  // 25 z (FP64 uses the second r buffer)
+    L.add(f32 ? es * (size_t)G : 0);  // 26 rounded level-0 right-hand side
+    L.add(es * (size_t)G);            // 27 level-0 residual
+    for (int l = 1; l < levels; ++l) {
+      const size_t gl = (size_t)Ns[l] * Ns[l] * Ns[l];
+      L.add(es * gl);  // x_l
+      L.add(es * gl);  // b_l
+      L.add(es * gl);  // r_l
+    }
+  }
   if (ntx_out) *ntx_out = ntx;
   if (ntiles_out) *ntiles_out = ntiles;
   if (stride_out) *stride_out = stride;
@@ -470,6 +492,50 @@ static int run_cg_batch(std::vector<CgJob>& jobs, bool fp32, bool zero_x, int fi
   }
 }
 
+// Multigrid-preconditioned CG of one session on x (FP64): per iteration a
+// V-cycle z = B r, rho = <r, z>, the direction pass p = z + beta p with
+// <p, A p>, the update pass x += alpha p, r -= alpha A p with ||r||; the
+// device applies the stopping test. Iteration i is queued before the status
+// of iteration i - 1 is waited for.
+static int run_mgcg(maze_session* s, double* x, CgJob& job) {
+  DeviceState& d = s->d;
+  const MarchGeom& g = s->geom;
+  const MgHierarchy& m = d.mg;
+  hipStream_t st = s->stream;
+  HIP_TRY(launch_finalize(d, FIN_MG_CHECK0, g.nwg, 0.0, 0.0, 0.0, nullptr, 0, 0, st));
+  const long long guard = (long long)s->cfg.max_iter + 8;
+  for (long long i = 0;; ++i) {
+    HIP_TRY(launch_mg_vcycle(d, m, d.r, m.z, m.fp32, st));
+    HIP_TRY(launch_mg_dot(d, d.r, m.z, m.fp32, st));
+    HIP_TRY(launch_finalize(d, FIN_MG_RHO, mg_dot_blocks(d.G), 0.0, 0.0, 0.0, nullptr, 0, 0, st));
+    double* pnew = d.p + (size_t)(i & 1) * d.G;
+    const double* pold = d.p + (size_t)((i & 1) ^ 1) * d.G;
+    HIP_TRY(launch_mg_dir(d, g, m.z, m.fp32, pold, pnew, st));
+    HIP_TRY(launch_finalize(d, FIN_MG_MU, g.nwg, 0.0, 0.0, 0.0, nullptr, 0, 0, st));
+    HIP_TRY(launch_mg_upd(d, g, pnew, x, st));
+    HIP_TRY(launch_finalize(d, FIN_MG_CONV, g.nwg, 0.0, 0.0, 0.0, nullptr, 0, 0, st));
+    const int slot = (int)(i & 1);
+    HIP_TRY(hipMemcpyAsync(&s->host_sc[slot], d.sc, sizeof(Scalars), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipEventRecord(s->ev[slot], st));
+    const bool last = i > guard;
+    if (i > 0 || last) {
+      const int ws = last ? slot : (slot ^ 1);
+      HIP_TRY(hipEventSynchronize(s->ev[ws]));
+      const Scalars& h = s->host_sc[ws];
+      if (h.err) {
+        job.err = 1;
+        return MAZE_OK;
+      }
+      if (h.done || last) {
+        job.iters = h.iters;
+        job.code = h.done ? h.done : 3;
+        if (s->trace) return trace_collect(s, h.iters, h.qnorm);
+        return MAZE_OK;
+      }
+    }
+  }
+}
+
 // Resets the binning counters and the error flag after a rejected input.
 static int recover_error(maze_session* s) {
   DeviceState& d = s->d;
@@ -496,13 +562,35 @@ static int solve_multi(std::vector<maze_session*>& ss, std::vector<double*>& xs,
     s->trace_rows.clear();
     s->trace_pass = 0;
   }
+  // multigrid-preconditioned sessions: one solve each
+  std::vector<bool> is_mg(n, false);
+  for (int i = 0; i < n; ++i) {
+    if (ss[i]->d.mg.levels == 0) continue;
+    is_mg[i] = true;
+    maze_session* s = ss[i];
+    CgJob j;
+    j.s = s;
+    j.x = xs[i];
+    j.max_iter = s->cfg.max_iter;
+    const int rc = run_mgcg(s, xs[i], j);
+    if (rc != MAZE_OK) return rc;
+    if (j.err) {
+      rcs[i] = MAZE_E_NONFINITE;
+      continue;
+    }
+    s->iters = j.iters;
+    s->converged = (j.code == 1);
+    HIP_TRY(launch_true_residual(s->d, s->geom, xs[i], s->stream));
+    HIP_TRY(launch_finalize(s->d, FIN_SOLVE_END, s->geom.nwg, 0.0, 0.0, 0.0, nullptr, 0, 0,
+                            s->stream));
+  }
   // FP64 sessions: one CG solve each, batched
   {
     std::vector<CgJob> jobs;
     std::vector<int> idx;
     int fb = 1 << 30;
     for (int i = 0; i < n; ++i)
-      if (ss[i]->cfg.precision != MAZE_MIXED) {
+      if (ss[i]->cfg.precision != MAZE_MIXED && !is_mg[i]) {
         CgJob j;
         j.s = ss[i];
         j.x = xs[i];
@@ -531,7 +619,7 @@ static int solve_multi(std::vector<maze_session*>& ss, std::vector<double*>& xs,
   // Mixed sessions: FP32 inner CG on the correction, FP64 outer residual.
   std::vector<int> act;
   for (int i = 0; i < n; ++i)
-    if (ss[i]->cfg.precision == MAZE_MIXED) act.push_back(i);
+    if (ss[i]->cfg.precision == MAZE_MIXED && !is_mg[i]) act.push_back(i);
   if (act.empty()) return MAZE_OK;
   std::vector<maze_session*> as;
   for (int i : act) as.push_back(ss[i]);
@@ -614,7 +702,7 @@ static int solve_multi(std::vector<maze_session*>& ss, std::vector<double*>& xs,
     act = keep;
   }
   for (int i = 0; i < n; ++i)
-    if (ss[i]->cfg.precision == MAZE_MIXED) ss[i]->iters = total[i];
+    if (ss[i]->cfg.precision == MAZE_MIXED && !is_mg[i]) ss[i]->iters = total[i];
   return MAZE_OK;
 }
 
@@ -659,7 +747,7 @@ static int direct_solve(maze_session* s, int guess, const double* pos, double* x
   const bool mixed = s->cfg.precision == MAZE_MIXED;
   int rc = assign(s, pos);
   if (rc != MAZE_OK) return rc;
-  HIP_TRY(launch_rhs_poisson(d, s->geom, guess, x, mixed, s->stream));
+  HIP_TRY(launch_rhs_poisson(d, s->geom, guess, x, mixed && d.mg.levels == 0, s->stream));
   HIP_TRY(launch_finalize(d, FIN_SOLVE_START, s->geom.nwg, s->cfg.tol, 0.0, 0.0, nullptr,
                           s->cfg.max_iter, s->cfg.residual_norm, s->stream));
   std::vector<maze_session*> one{s};
@@ -687,7 +775,8 @@ static int step_multi(std::vector<maze_session*>& ss, const double* const* pos,
     DeviceState& d = s->d;
     const int rc = assign(s, pos[i]);
     if (rc != MAZE_OK) return rc;
-    HIP_TRY(launch_rhs_maze(d, s->geom, s->cfg.precision == MAZE_MIXED, s->stream));
+    HIP_TRY(launch_rhs_maze(d, s->geom, s->cfg.precision == MAZE_MIXED && d.mg.levels == 0,
+                            s->stream));
     HIP_TRY(launch_finalize(d, FIN_SOLVE_START, s->geom.nwg, s->cfg.tol, 0.0, 0.0, nullptr,
                             s->cfg.max_iter, s->cfg.residual_norm, s->stream));
     ys[i] = d.y;
@@ -805,7 +894,8 @@ int maze_init(const maze_config* cfg, const double* charges_dev, const double* p
   }
   s->base = base;
   auto at = [&](int i) { return (void*)(base + L.off[i]); };
-  const bool mixed = cfg->precision == MAZE_MIXED;
+  const bool mg = (cfg->flags & MAZE_FLAG_MULTIGRID) != 0;
+  const bool mixed = cfg->precision == MAZE_MIXED && !mg;
   d.phi_cur = (double*)at(0);
   d.phi_prev = (double*)at(1);
   d.y = (double*)at(2);
@@ -832,6 +922,25 @@ int maze_init(const maze_config* cfg, const double* charges_dev, const double* p
   d.md_epart = (double*)at(23);
   d.hist = (double*)at(24);
   d.hist_cap = kHistCap;
+  if (mg) {
+    MgHierarchy& m = d.mg;
+    int Ns[kMgMaxLevels];
+    m.levels = mg_plan(d.N, Ns, kMgMaxLevels);
+    m.fp32 = cfg->precision == MAZE_MIXED;
+    for (int l = 0; l < m.levels; ++l) {
+      m.N[l] = Ns[l];
+      m.G[l] = (long long)Ns[l] * Ns[l] * Ns[l];
+      m.c[l] = std::pow(0.25, l);
+    }
+    m.z = m.fp32 ? at(25) : (void*)(d.r + d.G);
+    m.b[0] = m.fp32 ? at(26) : nullptr;
+    m.r[0] = at(27);
+    for (int l = 1; l < m.levels; ++l) {
+      m.x[l] = at(28 + 3 * (l - 1));
+      m.b[l] = at(29 + 3 * (l - 1));
+      m.r[l] = at(30 + 3 * (l - 1));
+    }
+  }
   if (hipHostMalloc((void**)&s->host_sc, 2 * sizeof(Scalars), hipHostMallocDefault) !=
           hipSuccess ||
       hipEventCreateWithFlags(&s->ev[0], hipEventDisableTiming) != hipSuccess ||

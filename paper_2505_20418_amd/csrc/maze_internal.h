@@ -33,6 +33,7 @@ enum PartialSlot : int {
   SL_RW1,
   SL_WW0,          // <A p, A p>, parity 0 / 1
   SL_WW1,
+  SL_MGRZ,         // <r, z> of the multigrid-preconditioned CG
   SL_XSUM,         // sum of the solution vector (y or phi)
   SL_TRR,          // true FP64 residual ||M x - s||^2
   SL_TMAX,         // true FP64 residual max
@@ -65,6 +66,9 @@ struct alignas(64) Scalars {
   int32_t max_iter;
   int32_t norm;        // MAZE_NORM_*
   int32_t pad_i;
+  double mg_rho;       // multigrid-preconditioned CG: <r, z>
+  double mg_alpha;     // rho / <p, A p>
+  double mg_beta;      // rho / rho of the previous iteration (0 first)
   double pad[2];
 };
 
@@ -103,6 +107,24 @@ struct SweepGeom {
 
 SweepGeom make_sweep_geom(int N, int ppt, int cx);
 size_t sweep_lds_bytes(const SweepGeom& g, bool fp32, bool first);
+
+// Multigrid hierarchy of a session (preconditioner of the PLCG solve).
+// Level 0 is the fine grid: its right-hand side is the CG residual and its
+// solution the preconditioned residual z; x / b / r of levels >= 1, the
+// level-0 residual temporary r[0] and, for an FP32 preconditioner, the
+// rounded right-hand side b[0] live in the session allocation.
+constexpr int kMgMaxLevels = 12;
+struct MgHierarchy {
+  int levels = 0;
+  bool fp32 = false;
+  int N[kMgMaxLevels] = {0};
+  long long G[kMgMaxLevels] = {0};
+  double c[kMgMaxLevels] = {0};   // operator scale 4^-l
+  void* x[kMgMaxLevels] = {nullptr};
+  void* b[kMgMaxLevels] = {nullptr};
+  void* r[kMgMaxLevels] = {nullptr};
+  void* z = nullptr;              // preconditioned residual (T)
+};
 
 // Device buffers of one session. All allocated in maze_init.
 struct DeviceState {
@@ -148,6 +170,8 @@ struct DeviceState {
   // residual history of the current CG solve (written by the sweeps)
   double* hist = nullptr;
   int hist_cap = 0;
+  // multigrid preconditioner (levels == 0: Jacobi)
+  MgHierarchy mg;
 };
 
 constexpr int kHistCap = 16384;
@@ -165,6 +189,10 @@ enum FinalizeMode : int {
   FIN_SOLVE_END,     // xbar (from SL_XSUM), true residual
   FIN_ENERGY,        // energy from SL_ENERGY, writes energy_out
   FIN_INNER_START,   // mixed inner solve: thr from `param`, resets counters
+  FIN_MG_CHECK0,     // multigrid CG: stopping test of the first residual
+  FIN_MG_RHO,        // rho = <r, z>, beta (from SL_MGRZ)
+  FIN_MG_MU,         // alpha = rho / <p, A p> (from SL_MU0)
+  FIN_MG_CONV,       // ||r|| (SL_RR0 / SL_RMAX0): count, trace, stopping test
 };
 // imax / norm: iteration cap and norm mode installed by the *_START modes.
 hipError_t launch_finalize(const DeviceState& d, int mode, int count, double tol,
@@ -226,6 +254,19 @@ hipError_t launch_cg_sweep(const DeviceState& d, const SweepGeom& g, int k, int 
 hipError_t launch_batch_poll(Scalars* const* scs, int count, int32_t* out, hipStream_t st);
 hipError_t launch_batch_scalars(Scalars* const* scs, int count, Scalars* out, hipStream_t st);
 
+// Multigrid-preconditioned CG: z = V-cycle(r) (fp32: FP32 hierarchy); the
+// partials of <r, z>; the direction pass p_new = z + beta p_old with
+// <p, A p>; the update pass x += alpha p, r -= alpha A p with ||r||.
+hipError_t launch_mg_vcycle(const DeviceState& d, const MgHierarchy& m, const double* r, void* z,
+                            bool fp32, hipStream_t st);
+hipError_t launch_mg_dot(const DeviceState& d, const double* r, const void* z, bool fp32,
+                         hipStream_t st);
+int mg_dot_blocks(long long G);
+int mg_plan(int N, int* Ns, int max_levels);
+hipError_t launch_mg_dir(const DeviceState& d, const MarchGeom& g, const void* z, bool fp32,
+                         const double* pold, double* pnew, hipStream_t st);
+hipError_t launch_mg_upd(const DeviceState& d, const MarchGeom& g, const double* p, double* x,
+                         hipStream_t st);
 // Mixed precision: x += e (FP64), FP64 residual M x - s, r32 = float(residual),
 // e = 0; partials SL_TRR/SL_TMAX (FP64) and SL_RR0/SL_RMAX0 (of r32).
 hipError_t launch_refine(const DeviceState& d, const MarchGeom& g, double* x,

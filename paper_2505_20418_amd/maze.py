@@ -22,6 +22,7 @@ MAZE_E_INVALID, MAZE_E_NOT_NEUTRAL, MAZE_E_OOM, MAZE_E_DEVICE, MAZE_E_NONFINITE 
 MAZE_FP64, MAZE_MIXED = 0, 1
 MAZE_GUESS_ZERO, MAZE_GUESS_STATIC, MAZE_GUESS_TIMEPROP = 0, 1, 2
 MAZE_NORM_REL2, MAZE_NORM_ABSMAX = 0, 1
+MAZE_FLAG_MULTIGRID = 1
 GRID_PHI, GRID_PHI_PREV, GRID_Y, GRID_Q, GRID_SIGMA = 0, 1, 2, 3, 4
 
 EXPORTED = ("maze_abi_version", "maze_strerror", "maze_device_bytes", "maze_init", "maze_step",
@@ -291,12 +292,12 @@ def maze_trace_read(handle):
 # ---- convenience wrapper -------------------------------------------------------
 def make_config(n_ions, box, grid_spacing, tol=1e-9, order=2, max_iter=100000,
                 precision=MAZE_FP64, residual_norm=MAZE_NORM_REL2, coulomb_k=1.0,
-                stream=None) -> maze_config:
+                stream=None, flags=0) -> maze_config:
     if stream is None:
         stream = torch.cuda.current_stream().cuda_stream
     return maze_config(int(n_ions), int(order), float(box), float(grid_spacing), float(tol),
-                       int(max_iter), int(precision), int(residual_norm), 0, float(coulomb_k),
-                       ctypes.c_void_p(int(stream)))
+                       int(max_iter), int(precision), int(residual_norm), int(flags),
+                       float(coulomb_k), ctypes.c_void_p(int(stream)))
 
 
 class Session:
@@ -306,9 +307,9 @@ class Session:
                  grid_spacing: float, tol: float = 1e-9, order: int = 2,
                  max_iter: int = 100000, precision: int = MAZE_FP64,
                  residual_norm: int = MAZE_NORM_REL2, coulomb_k: float = 1.0,
-                 stream=None):
+                 stream=None, flags: int = 0):
         self.cfg = make_config(charges.numel(), box, grid_spacing, tol, order, max_iter,
-                               precision, residual_norm, coulomb_k, stream)
+                               precision, residual_norm, coulomb_k, stream, flags)
         self.device = charges.device
         self.handle, self.init_status, self.init_stats = maze_init(
             self.cfg, charges.contiguous(), pos0.contiguous())

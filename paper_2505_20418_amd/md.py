@@ -19,7 +19,7 @@ class MDRun:
     def __init__(self, system: inputs.NaClSystem, tol: float = 1e-9,
                  precision: int = maze.MAZE_FP64, order: int = 2, dt: float = 1.0,
                  device: str = "cuda", max_iter: int = 100000, stream=None,
-                 restore: dict = None):
+                 restore: dict = None, flags: int = 0):
         """restore: a dict from save_state(); the run then continues exactly
         where the saved one stopped (particles, forces, observables and the
         MaZe warm-start history), without the priming step."""
@@ -42,7 +42,7 @@ class MDRun:
         self.session = maze.Session(self.charges, self.pos, system.box, system.grid_spacing,
                                     tol=tol, order=order, max_iter=max_iter,
                                     precision=precision, coulomb_k=inputs.COULOMB_K_EV_A,
-                                    stream=stream)
+                                    stream=stream, flags=flags)
         table = (ctypes.c_double * 15)(*inputs.BMH_TABLE.ravel().tolist())
         self.md = maze.maze_md_state(
             n, 0, self.pos.data_ptr(), self.vel.data_ptr(), self.mass.data_ptr(),

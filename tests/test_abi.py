@@ -60,6 +60,15 @@ def test_host_only_entry_points():
     assert L.maze_device_bytes(ctypes.byref(bad)) == 0
     tiny = maze.maze_config(4, 2, 1.0, 0.5, 1e-9, 10, 0, 0, 0, 1.0, None)  # N = 2 < 4
     assert L.maze_device_bytes(ctypes.byref(tiny)) == 0
+    # multigrid: a grid that halves to <= 12^3 is accepted, an odd 101^3 is not;
+    # an unknown flag bit is rejected
+    ok = maze.maze_config(4, 2, 25.6, 0.4, 1e-9, 10, 0, 0, 0, 1.0, None)
+    mg = maze.maze_config(4, 2, 25.6, 0.4, 1e-9, 10, 0, 0, maze.MAZE_FLAG_MULTIGRID, 1.0, None)
+    assert L.maze_device_bytes(ctypes.byref(mg)) > L.maze_device_bytes(ctypes.byref(ok))
+    odd = maze.maze_config(4, 2, 40.4, 0.4, 1e-9, 10, 0, 0, maze.MAZE_FLAG_MULTIGRID, 1.0, None)
+    assert L.maze_device_bytes(ctypes.byref(odd)) == 0
+    badflag = maze.maze_config(4, 2, 25.6, 0.4, 1e-9, 10, 0, 0, 2, 1.0, None)
+    assert L.maze_device_bytes(ctypes.byref(badflag)) == 0
 
 
 def test_struct_layout_matches_c(tmp_path):
