@@ -48,11 +48,11 @@ def stencil_hash() -> str:
     return hashlib.sha256(open(STENCIL_SRC, "rb").read()).hexdigest()[:16]
 
 
-def run_md(system, tol, precision, steps, warmup, record_positions=False, order=2):
+def run_md(system, tol, precision, steps, warmup, record_positions=False, order=2, flags=0):
     import torch
     from paper_2505_20418_amd import maze, md
 
-    run = md.MDRun(system, tol=tol, precision=precision, order=order)
+    run = md.MDRun(system, tol=tol, precision=precision, order=order, flags=flags)
     h = run.session.handle
     for _ in range(warmup):
         run.step()
@@ -276,6 +276,7 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--no-order4", action="store_true")
+    ap.add_argument("--no-multigrid", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-full", action="store_true",
                     help="serve the full 256-session mix (up to 32768 ions) instead of 64")
@@ -371,6 +372,21 @@ def main():
         o4["speedup_mixed_vs_fp64"] = round(o4["mixed"]["value"] / o4["fp64"]["value"], 3)
         line["order4"] = o4
         log(f"bench: order4 {o4}")
+    if not args.no_multigrid:
+        # the same workload with the multigrid-preconditioned PLCG (FP64
+        # outer CG; FP64 or FP32 V-cycle), for both assignment orders
+        log("bench: multigrid preconditioner")
+        mgl = {}
+        for order in (2, 4):
+            for name, prec in (("mixed", maze.MAZE_MIXED), ("fp64", maze.MAZE_FP64)):
+                r = run_md(system, tol, prec, args.steps, args.warmup, order=order,
+                           flags=maze.MAZE_FLAG_MULTIGRID)
+                mgl[f"order{order}_{name}"] = {
+                    "value": round(r["steps_per_s"], 4), "unit": "MD steps/s",
+                    "latency_ms": {"p50": round(float(np.percentile(r["lat_ms"], 50)), 3),
+                                   "p99": round(float(np.percentile(r["lat_ms"], 99)), 3)}}
+        line["multigrid"] = mgl
+        log(f"bench: multigrid {mgl}")
     if not args.no_ensemble:
         log("bench: ensemble of 64 replicas")
         line["ensemble"] = bench_ensemble(max(3, args.steps // 3), 4)
