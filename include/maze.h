@@ -61,7 +61,17 @@ enum {
 enum { MAZE_FP64 = 0, MAZE_MIXED = 1 };
 enum { MAZE_GUESS_ZERO = 0, MAZE_GUESS_STATIC = 1, MAZE_GUESS_TIMEPROP = 2 };
 enum { MAZE_NORM_REL2 = 0, MAZE_NORM_ABSMAX = 1 };
-enum { MAZE_FLAG_MULTIGRID = 1 };
+enum {
+  MAZE_FLAG_MULTIGRID = 1,
+  /* forces by equation "F_Benoit" (-k Q sum grad W phi, the derivative on
+     the assignment weights) instead of equation "F_nostra"; not momentum
+     conserving, for the comparison of force estimators */
+  MAZE_FLAG_WEIGHT_GRADIENT_FORCE = 2,
+  /* accept charges that do not sum to zero: the zero-mode projection then
+     acts as a uniform neutralising background (the single-charge
+     measurements of the two-particle appendix) */
+  MAZE_FLAG_ALLOW_NET_CHARGE = 4
+};
 
 typedef struct {
   int32_t n_ions;         /* > 0 */
@@ -80,7 +90,7 @@ typedef struct {
                              vectors, FP64 dots, norms, projection and an
                              outer refinement on the FP64 residual) */
   int32_t residual_norm;  /* MAZE_NORM_REL2 or MAZE_NORM_ABSMAX */
-  int32_t flags;          /* 0, or MAZE_FLAG_MULTIGRID: precondition the
+  int32_t flags;          /* bitwise OR of MAZE_FLAG_*; MAZE_FLAG_MULTIGRID: precondition the
                              PLCG with a geometric multigrid V-cycle (red-
                              black Gauss-Seidel, full-weighting restriction,
                              trilinear prolongation, CG on the coarsest

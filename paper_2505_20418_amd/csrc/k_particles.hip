@@ -335,9 +335,82 @@ __global__ __launch_bounds__(kThreads) void k_gather(int n, int N, int order, do
   forces[3 * ion + 2] = kq * acc[2];
 }
 
+// ---- alternative force (equation "F_Benoit") --------------------------------
+// F_a = -k Q_a sum_n grad W(r_a - r_n) phi_n: the derivative falls on the
+// assignment weights instead of the potential. It is minus the gradient of
+// the discrete energy of equation "energy_discr" (for the exact field) but
+// does not conserve momentum; kept for the comparison of force estimators.
+__device__ __forceinline__ double bspline3_deriv(double s) {
+#pragma clang fp contract(off)
+  const double a = fabs(s);
+  const double sg = (s < 0.0) ? -1.0 : 1.0;
+  if (a < 1.0) return sg * (-2.0 * a + 1.5 * a * a);
+  if (a < 2.0) {
+    const double t = 2.0 - a;
+    return sg * (-0.5 * t * t);
+  }
+  return 0.0;
+}
+
+__global__ __launch_bounds__(kThreads) void k_gather_wg(int n, int N, int order, double h,
+                                                        double coulomb_k,
+                                                        const int32_t* __restrict__ sorted_idx,
+                                                        const int32_t* __restrict__ s_cell,
+                                                        const double* __restrict__ s_w,
+                                                        const double* __restrict__ s_Q,
+                                                        const double* __restrict__ ion_t,
+                                                        const double* __restrict__ phi,
+                                                        double* __restrict__ forces,
+                                                        const Scalars* sc) {
+#pragma clang fp contract(off)
+  const int s = blockIdx.x * kThreads + threadIdx.x;
+  if (s >= n || ctl_ld(&sc->err)) return;
+  const int ion = sorted_idx[s];
+  const int off = (order == 2) ? 0 : 1;
+  const double* w = s_w + (size_t)3 * s * order;
+  double dw[3][kMaxOrder];
+  int idx[3][kMaxOrder];
+  for (int d = 0; d < 3; ++d) {
+    const double t = ion_t[3 * ion + d];
+    if (order == 2) {
+      dw[d][0] = -1.0 / h;
+      dw[d][1] = 1.0 / h;
+    } else {
+      dw[d][0] = bspline3_deriv(t + 1.0) / h;
+      dw[d][1] = bspline3_deriv(t) / h;
+      dw[d][2] = bspline3_deriv(t - 1.0) / h;
+      dw[d][3] = bspline3_deriv(t - 2.0) / h;
+    }
+    for (int m = 0; m < order; ++m) {
+      int v = s_cell[3 * s + d] - off + m;
+      idx[d][m] = v < 0 ? v + N : (v >= N ? v - N : v);
+    }
+  }
+  const long long NN = (long long)N * N;
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int a = 0; a < order; ++a)
+    for (int b = 0; b < order; ++b)
+      for (int c = 0; c < order; ++c) {
+        const double v = phi[idx[0][a] * NN + (long long)idx[1][b] * N + idx[2][c]];
+        acc[0] += dw[0][a] * w[order + b] * w[2 * order + c] * v;
+        acc[1] += w[a] * dw[1][b] * w[2 * order + c] * v;
+        acc[2] += w[a] * w[order + b] * dw[2][c] * v;
+      }
+  const double kq = -coulomb_k * s_Q[s];
+  forces[3 * ion + 0] = kq * acc[0];
+  forces[3 * ion + 1] = kq * acc[1];
+  forces[3 * ion + 2] = kq * acc[2];
+}
+
 hipError_t launch_gather(const DeviceState& d, const double* phi, double coulomb_k,
                          double* forces, hipStream_t st) {
   const int nb = (d.n_ions + kThreads - 1) / kThreads;
+  if (d.weight_gradient_force) {
+    hipLaunchKernelGGL(k_gather_wg, dim3(nb), dim3(kThreads), 0, st, d.n_ions, d.N, d.order, d.h,
+                       coulomb_k, d.sorted_idx, d.s_cell, d.s_w, d.s_Q, (const double*)d.ion_t,
+                       phi, forces, (const Scalars*)d.sc);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_gather, dim3(nb), dim3(kThreads), 0, st, d.n_ions, d.N, d.order, d.h,
                      coulomb_k, d.sorted_idx, d.s_cell, d.s_w, d.s_Q, phi, forces,
                      (const Scalars*)d.sc);

@@ -88,7 +88,9 @@ static int validate(const maze_config* c) {
   if (c->precision != MAZE_FP64 && c->precision != MAZE_MIXED) return MAZE_E_INVALID;
   if (c->residual_norm != MAZE_NORM_REL2 && c->residual_norm != MAZE_NORM_ABSMAX)
     return MAZE_E_INVALID;
-  if ((c->flags & ~MAZE_FLAG_MULTIGRID) != 0 || !finite_pos(c->coulomb_k)) return MAZE_E_INVALID;
+  const int32_t known = MAZE_FLAG_MULTIGRID | MAZE_FLAG_WEIGHT_GRADIENT_FORCE |
+                        MAZE_FLAG_ALLOW_NET_CHARGE;
+  if ((c->flags & ~known) != 0 || !finite_pos(c->coulomb_k)) return MAZE_E_INVALID;
   if (grid_of(c) == 0) return MAZE_E_INVALID;
   if (c->flags & MAZE_FLAG_MULTIGRID) {
     int Ns[kMgMaxLevels];
@@ -869,7 +871,8 @@ int maze_init(const maze_config* cfg, const double* charges_dev, const double* p
   }
   delete[] hq;
   if (!qfin) return MAZE_E_INVALID;
-  if (std::fabs(qs) > 1e-10 * qa) return MAZE_E_NOT_NEUTRAL;
+  if (!(cfg->flags & MAZE_FLAG_ALLOW_NET_CHARGE) && std::fabs(qs) > 1e-10 * qa)
+    return MAZE_E_NOT_NEUTRAL;
 
   maze_session* s = new (std::nothrow) maze_session();
   if (!s) return MAZE_E_OOM;
@@ -922,6 +925,7 @@ int maze_init(const maze_config* cfg, const double* charges_dev, const double* p
   d.md_epart = (double*)at(23);
   d.hist = (double*)at(24);
   d.hist_cap = kHistCap;
+  d.weight_gradient_force = (cfg->flags & MAZE_FLAG_WEIGHT_GRADIENT_FORCE) ? 1 : 0;
   if (mg) {
     MgHierarchy& m = d.mg;
     int Ns[kMgMaxLevels];

@@ -172,6 +172,8 @@ struct DeviceState {
   int hist_cap = 0;
   // multigrid preconditioner (levels == 0: Jacobi)
   MgHierarchy mg;
+  // force estimator: 0 equation "F_nostra", 1 equation "F_Benoit"
+  int weight_gradient_force = 0;
 };
 
 constexpr int kHistCap = 16384;

@@ -22,7 +22,7 @@ MAZE_E_INVALID, MAZE_E_NOT_NEUTRAL, MAZE_E_OOM, MAZE_E_DEVICE, MAZE_E_NONFINITE 
 MAZE_FP64, MAZE_MIXED = 0, 1
 MAZE_GUESS_ZERO, MAZE_GUESS_STATIC, MAZE_GUESS_TIMEPROP = 0, 1, 2
 MAZE_NORM_REL2, MAZE_NORM_ABSMAX = 0, 1
-MAZE_FLAG_MULTIGRID = 1
+MAZE_FLAG_MULTIGRID, MAZE_FLAG_WEIGHT_GRADIENT_FORCE, MAZE_FLAG_ALLOW_NET_CHARGE = 1, 2, 4
 GRID_PHI, GRID_PHI_PREV, GRID_Y, GRID_Q, GRID_SIGMA = 0, 1, 2, 3, 4
 
 EXPORTED = ("maze_abi_version", "maze_strerror", "maze_device_bytes", "maze_init", "maze_step",

@@ -67,7 +67,7 @@ def test_host_only_entry_points():
     assert L.maze_device_bytes(ctypes.byref(mg)) > L.maze_device_bytes(ctypes.byref(ok))
     odd = maze.maze_config(4, 2, 40.4, 0.4, 1e-9, 10, 0, 0, maze.MAZE_FLAG_MULTIGRID, 1.0, None)
     assert L.maze_device_bytes(ctypes.byref(odd)) == 0
-    badflag = maze.maze_config(4, 2, 25.6, 0.4, 1e-9, 10, 0, 0, 2, 1.0, None)
+    badflag = maze.maze_config(4, 2, 25.6, 0.4, 1e-9, 10, 0, 0, 8, 1.0, None)
     assert L.maze_device_bytes(ctypes.byref(badflag)) == 0
 
 

@@ -205,3 +205,38 @@ def test_far_field_matches_periodic_coulomb(oracle_lib):
     ref = ewald_pair_force(r, box)
     assert np.linalg.norm(F[0] - ref) < 0.02 * np.linalg.norm(ref)
     assert np.dot(F[0], r) < 0  # attraction
+
+
+@pytest.mark.parametrize("order", [2, 4])
+def test_weight_gradient_force_is_energy_gradient(oracle_lib, order):
+    """Equation F_Benoit: with phi the exact discrete Poisson solution,
+    V = (1/2) phi.q = (1/2) q^T G q with G symmetric, so
+    dV/dr_a = phi . dq/dr_a = Q_a sum_n grad W phi_n: the weight-gradient
+    force is minus the gradient of the discrete energy (equation
+    energy_discr). Checked by a centred difference that stays inside one
+    cell, where the weights are polynomials in the position."""
+    from conftest import fft_poisson
+    box, N = 6.0, 12
+    h = box / N
+    pos = np.array([[1.13, 2.27, 3.41], [4.02, 1.61, 0.77], [2.55, 4.48, 5.12],
+                    [0.64, 3.33, 2.09]])
+    Q = np.array([1.0, -1.0, 1.0, -1.0])
+
+    def energy(p):
+        q = oracle_lib.spread(p, Q, box, N, order)
+        phi = fft_poisson(q, h)
+        return oracle_lib.energy(phi, q), phi
+
+    _, phi = energy(pos)
+    Fb = oracle_lib.gather(pos, Q, box, phi, order=order, weight_gradient=True)
+    d = 1e-4
+    for a in range(len(Q)):
+        for c in range(3):
+            pp, pm = pos.copy(), pos.copy()
+            pp[a, c] += d
+            pm[a, c] -= d
+            # both sides in the same cell of every axis
+            assert np.floor(pp[a, c] / h) == np.floor(pm[a, c] / h)
+            g = (energy(pp)[0] - energy(pm)[0]) / (2 * d)
+            tol = 1e-7 if order == 2 else 1e-6
+            assert abs(-g - Fb[a, c]) <= tol * np.abs(Fb).max() + 1e-12, (a, c, -g, Fb[a, c])
