@@ -170,8 +170,13 @@ int maze_solve(maze_session* s, int guess, const double* pos_dev,
  * unconverged session of a precision, and sessions that have converged drop
  * out. Sessions may differ in grid size and precision; they must share the
  * device and the stream of sessions[0]. Per-session semantics and outputs are
- * those of maze_step, and each session's result is bitwise the one it gets
- * stepped alone. pos_dev[i], forces_dev[i] (forces_dev or an entry may be
+ * those of maze_step. Each session has two launch shapes (maze_launch_shape):
+ * a batch whose sessions together need fewer than 256 workgroups in their
+ * throughput shapes is swept in the latency shapes, and each session's
+ * result is then bitwise the one it gets stepped alone; a larger batch is
+ * swept in the throughput shapes, and each result then meets the session's
+ * tolerance but sums in another order (MAZE_BATCH_MODE=latency or
+ * =throughput in the environment forces one mode). pos_dev[i], forces_dev[i] (forces_dev or an entry may be
  * NULL) belong to session i; energies_dev (count doubles, device) and st
  * (count entries, host) may be NULL; st[i].status holds session i's status.
  * A session whose positions are rejected is left unchanged while the others
@@ -208,6 +213,17 @@ int maze_load(maze_session* s, const void* host_buf, size_t bytes);
  * maze_init). */
 int maze_profile_enable(maze_session* s, int on);
 int maze_profile_read(maze_session* s, double* out8);
+
+/* Launch shapes of the session's CG sweep. The latency shape, used alone
+ * and in batches below the fill level, is picked at maze_init by timing the
+ * candidate shapes on the session's own buffers (cached per device, grid
+ * size and precision; MAZE_AUTOTUNE=0 in the environment selects fixed
+ * defaults). The throughput shape, used in batches that fill the device, is
+ * the one with the longest runs and segments that fits (16 x planes, 1024
+ * points). MAZE_SWEEP_SHAPE="ppt:cx" forces both. out8 (HOST, 8 int32):
+ * {points per thread, x planes per workgroup, workgroups, segment length}
+ * of the latency shape, then of the throughput shape. */
+int maze_launch_shape(const maze_session* s, int32_t* out8);
 
 /* Residual trace of the last solve (for convergence studies such as the
  * residual-versus-iteration comparison of Appendix B). When enabled, each

@@ -576,6 +576,26 @@ hipError_t launch_cg_sweep(const DeviceState& d, const SweepGeom& g, int k, int 
   return launch_sweep(L, false, k == 0, st);
 }
 
+// Deterministic, finite, non-smooth fill (used to time sweeps on real work
+// before a session's buffers are cleared for its first solve).
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_fill_pattern(T* x, long long G) {
+  const long long g = (long long)blockIdx.x * kThreads + threadIdx.x;
+  if (g >= G) return;
+  uint32_t h = (uint32_t)(g * 2654435761ull) ^ (uint32_t)(g >> 32);
+  h ^= h >> 15;
+  h *= 2246822519u;
+  h ^= h >> 13;
+  x[g] = (T)((double)(h & 0xffffff) / 16777216.0 - 0.5);
+}
+
+hipError_t launch_fill_pattern(void* x, long long G, bool fp32, hipStream_t st) {
+  const unsigned nb = (unsigned)((G + kThreads - 1) / kThreads);
+  if (fp32) hipLaunchKernelGGL(k_fill_pattern<float>, dim3(nb), dim3(kThreads), 0, st, (float*)x, G);
+  else hipLaunchKernelGGL(k_fill_pattern<double>, dim3(nb), dim3(kThreads), 0, st, (double*)x, G);
+  return hipGetLastError();
+}
+
 hipError_t launch_batch_poll(Scalars* const* scs, int count, int32_t* out, hipStream_t st) {
   hipLaunchKernelGGL(k_batch_poll, dim3((count + kThreads - 1) / kThreads), dim3(kThreads), 0, st,
                      scs, count, out);

@@ -3,6 +3,9 @@
 // device convergence flag, the mixed-precision refinement loop, checkpoints
 // and the MD driver entry points.
 #include <algorithm>
+#include <cstdlib>
+#include <map>
+#include <mutex>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -43,7 +46,8 @@ struct maze_session {
   maze_config cfg{};
   DeviceState d;
   MarchGeom geom{};
-  SweepGeom sweep{};
+  SweepGeom sweep{};     // latency shape: alone and in batches below the fill level
+  SweepGeom sweep_tp{};  // throughput shape: batches that fill the GPU
   hipStream_t stream = nullptr;
   int device = 0;
   Scalars* host_sc = nullptr;   // pinned, 2 slots for pipelined polling
@@ -119,8 +123,33 @@ static SweepGeom choose_sweep(int N) {
   return make_sweep_geom(N, 1, 4);
 }
 
+// Launch shapes the autotuner times: segments of 256, 512 or 1024 points
+// of the (y, z) plane and runs of 4 to 64 x planes. Shapes whose halo slots
+// or LDS do not fit a kernel instantiation are left out.
+static std::vector<SweepGeom> sweep_candidates(int N, bool fp32) {
+  std::vector<SweepGeom> out;
+  const int P = N * N;
+  for (int ppt : {1, 2, 4}) {
+    if (ppt > 1 && kThreads * ppt / 2 >= P) continue;  // segment longer than a plane
+    for (int cx : {4, 8, 16, 32, 64}) {
+      if (cx > N && cx != 4) continue;
+      const SweepGeom g = make_sweep_geom(N, ppt, cx);
+      if (sweep_nh_class(g.nh) == 0) continue;
+      if (sweep_lds_bytes(g, fp32, false) > 159 * 1024) continue;
+      bool dup = false;
+      for (const SweepGeom& o : out) dup |= (o.ppt == g.ppt && o.cx == g.cx);
+      if (!dup) out.push_back(g);
+    }
+  }
+  return out;
+}
+
 static int part_stride_for(const DeviceState& d, const MarchGeom& g, const SweepGeom& w) {
-  return std::max({g.nwg, w.nwg, update_blocks(d.G), d.ntiles, 1});
+  int m = std::max({g.nwg, w.nwg, update_blocks(d.G), d.ntiles, 1});
+  const int N = g.N;
+  for (bool f : {false, true})
+    for (const SweepGeom& c : sweep_candidates(N, f)) m = std::max(m, c.nwg);
+  return m;
 }
 
 struct Layout {
@@ -381,6 +410,25 @@ static int gather_scalars(std::vector<maze_session*>& ss, std::vector<Scalars>& 
   return MAZE_OK;
 }
 
+// A batch whose sessions need at least kThroughputWgs workgroups in their
+// throughput shapes (one per CU) is swept in those shapes; a smaller one in
+// each session's latency shape, so that a session swept in it sums its
+// partials in the same order as when stepped alone. Measured on molten-NaCl
+// batches of 2 to 64 sessions (32^3 to 192^3 grids): below one workgroup
+// per CU the latency shapes are up to 2.6x faster per step, above it the
+// throughput shapes up to 1.8x. MAZE_BATCH_MODE=latency or =throughput in
+// the environment forces one mode.
+constexpr long long kThroughputWgs = 256;
+
+static bool batch_throughput_mode(const std::vector<CgJob>& jobs) {
+  const char* e = std::getenv("MAZE_BATCH_MODE");
+  if (e && std::strcmp(e, "latency") == 0) return false;
+  if (e && std::strcmp(e, "throughput") == 0) return true;
+  long long w = 0;
+  for (const CgJob& j : jobs) w += j.s->sweep_tp.nwg;
+  return w >= kThroughputWgs;
+}
+
 // Batched CG solves: one launch per sweep and template class covers every
 // session; a compact status array is polled.
 static int run_cg_batch(std::vector<CgJob>& jobs, bool fp32, bool zero_x, int first_batch) {
@@ -390,11 +438,13 @@ static int run_cg_batch(std::vector<CgJob>& jobs, bool fp32, bool zero_x, int fi
   int rc = ensure_table(jobs[0].s->device, n, &t);
   if (rc != MAZE_OK) return rc;
   hipStream_t st = jobs[0].s->stream;
+  const bool tp = batch_throughput_mode(jobs);
+  auto shape = [&](int i) -> const SweepGeom& { return tp ? jobs[i].s->sweep_tp : jobs[i].s->sweep; };
   // order the sessions by template class (ppt, nh)
   std::vector<int> order(n);
   for (int i = 0; i < n; ++i) order[i] = i;
   auto cls = [&](int i) {
-    const SweepGeom& g = jobs[i].s->sweep;
+    const SweepGeom& g = shape(i);
     return g.ppt * 16 + sweep_nh_class(g.nh);
   };
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cls(a) < cls(b); });
@@ -409,7 +459,7 @@ static int run_cg_batch(std::vector<CgJob>& jobs, bool fp32, bool zero_x, int fi
   for (int q = 0; q < n; ++q) {
     const int i = order[q];
     maze_session* s = jobs[i].s;
-    const SweepGeom& g = s->sweep;
+    const SweepGeom& g = shape(i);
     if (classes.empty() || cls(order[classes.back().c0]) != cls(i)) {
       if (!classes.empty()) hw[wpos++] = classes.back().nwg;
       classes.push_back({q, q, wpos, 0, g.ppt, sweep_nh_class(g.nh), 0});
@@ -804,6 +854,112 @@ static int step_multi(std::vector<maze_session*>& ss, const double* const* pos,
   return MAZE_OK;
 }
 
+// ---- launch-shape autotuner -------------------------------------------------
+// At session creation, before the buffers are cleared for the first solve,
+// each candidate shape runs the first sweep, 3 warm-up sweeps and 8 timed
+// sweeps on a fixed pattern (thresholds set so that nothing converges); the
+// fastest shape is kept for the session and cached per (device, N,
+// precision), so later sessions of that size reuse it without timing and
+// sessions of equal size share one shape (and one summation order).
+// MAZE_AUTOTUNE=0 in the environment selects the fixed default shapes.
+struct TuneKey {
+  int device, N, fp32;
+  bool operator<(const TuneKey& o) const {
+    return device != o.device ? device < o.device : (N != o.N ? N < o.N : fp32 < o.fp32);
+  }
+};
+static std::map<TuneKey, SweepGeom> g_tuned;
+static std::mutex g_tune_mu;
+
+static bool autotune_enabled() {
+  const char* e = std::getenv("MAZE_AUTOTUNE");
+  return !(e && e[0] == '0');
+}
+
+// MAZE_SWEEP_SHAPE="ppt:cx" forces one launch shape (points per thread 1, 2
+// or 4; x planes per workgroup) for every session that admits it.
+static bool forced_shape(int N, bool fp32, SweepGeom* out) {
+  const char* e = std::getenv("MAZE_SWEEP_SHAPE");
+  int ppt = 0, cx = 0;
+  if (!e || std::sscanf(e, "%d:%d", &ppt, &cx) != 2) return false;
+  if ((ppt != 1 && ppt != 2 && ppt != 4) || cx < 1) return false;
+  const SweepGeom g = make_sweep_geom(N, ppt, cx);
+  if (sweep_nh_class(g.nh) == 0 || sweep_lds_bytes(g, fp32, false) > 159 * 1024) return false;
+  *out = g;
+  return true;
+}
+
+// Throughput shape: the admissible shape with the least re-read traffic per
+// point among runs of 16 x planes and 1024-point segments (then shorter
+// segments and runs). Within a batch that fills the GPU many times over,
+// workgroups are not the limit and the halo re-reads of short runs are.
+static SweepGeom throughput_sweep(int N, bool fp32) {
+  SweepGeom g;
+  if (forced_shape(N, fp32, &g)) return g;
+  const std::vector<SweepGeom> cand = sweep_candidates(N, fp32);
+  for (int ppt : {4, 2, 1})
+    for (int cx : {16, 8, 4})
+      for (const SweepGeom& c : cand)
+        if (c.ppt == ppt && c.cx == std::min(cx, N)) return c;
+  return choose_sweep(N);
+}
+
+static SweepGeom autotune_sweep(maze_session* s) {
+  DeviceState& d = s->d;
+  const bool fp32 = s->cfg.precision == MAZE_MIXED;
+  SweepGeom def = choose_sweep(d.N);
+  if (forced_shape(d.N, fp32, &def)) return def;
+  if (d.mg.levels > 0 || !autotune_enabled()) return def;
+  const TuneKey key{s->device, d.N, fp32 ? 1 : 0};
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tuned.find(key);
+    if (it != g_tuned.end()) return it->second;
+  }
+  const std::vector<SweepGeom> cand = sweep_candidates(d.N, fp32);
+  if (cand.size() <= 1) return def;
+  hipStream_t st = s->stream;
+  void* x = fp32 ? (void*)d.e32 : (void*)d.xsolve;
+  void* r0 = fp32 ? (void*)d.r32 : (void*)d.r;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return def;
+  Scalars sc{};
+  sc.thr = -1.0;  // never converged
+  sc.max_iter = 1 << 30;
+  sc.norm = MAZE_NORM_REL2;
+  SweepGeom best = def;
+  float best_ms = 1e30f;
+  bool ok = true;
+  for (const SweepGeom& g : cand) {
+    ok = ok && hipMemcpyAsync(d.sc, &sc, sizeof(Scalars), hipMemcpyHostToDevice, st) == hipSuccess;
+    ok = ok && launch_fill_pattern(r0, d.G, fp32, st) == hipSuccess;
+    for (int k = 0; k < 4 && ok; ++k)
+      ok = launch_cg_sweep(d, g, k, s->geom.nwg, x, fp32, true, st) == hipSuccess;
+    ok = ok && hipEventRecord(e0, st) == hipSuccess;
+    for (int k = 4; k < 12 && ok; ++k)
+      ok = launch_cg_sweep(d, g, k, s->geom.nwg, x, fp32, true, st) == hipSuccess;
+    ok = ok && hipEventRecord(e1, st) == hipSuccess;
+    Scalars h{};
+    ok = ok && hipMemcpyAsync(&h, d.sc, sizeof(Scalars), hipMemcpyDeviceToHost, st) == hipSuccess;
+    ok = ok && hipStreamSynchronize(st) == hipSuccess;
+    if (!ok) break;
+    float ms = 0.f;
+    if (h.done == 0 && hipEventElapsedTime(&ms, e0, e1) == hipSuccess && ms < best_ms) {
+      best_ms = ms;
+      best = g;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (!ok) {
+    hipGetLastError();
+    return def;
+  }
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tuned[key] = best;
+  return best;
+}
+
 extern "C" {
 
 int maze_abi_version(void) { return MAZE_ABI_VERSION; }
@@ -953,6 +1109,16 @@ int maze_init(const maze_config* cfg, const double* charges_dev, const double* p
     return MAZE_E_DEVICE;
   }
   // zero everything once (not part of any step, so never graph-captured)
+  if (hipMemsetAsync(base, 0, L.total, stream) != hipSuccess ||
+      hipMemcpyAsync(d.Q, charges_dev, sizeof(double) * n, hipMemcpyDeviceToDevice, stream) !=
+          hipSuccess) {
+    maze_destroy(s);
+    return MAZE_E_DEVICE;
+  }
+  // launch shape of the CG sweep (timed on the still-unused buffers), then
+  // clear them again for the first solve
+  s->sweep = autotune_sweep(s);
+  s->sweep_tp = throughput_sweep(s->d.N, s->cfg.precision == MAZE_MIXED);
   if (hipMemsetAsync(base, 0, L.total, stream) != hipSuccess ||
       hipMemcpyAsync(d.Q, charges_dev, sizeof(double) * n, hipMemcpyDeviceToDevice, stream) !=
           hipSuccess) {
@@ -1135,6 +1301,18 @@ int maze_profile_read(maze_session* s, double* out8) {
   for (int i = 0; i < 8; ++i) {
     out8[i] = s->prof_acc[i];
     s->prof_acc[i] = 0.0;
+  }
+  return MAZE_OK;
+}
+
+int maze_launch_shape(const maze_session* s, int32_t* out8) {
+  if (!s || !out8) return MAZE_E_INVALID;
+  const SweepGeom* g[2] = {&s->sweep, &s->sweep_tp};
+  for (int i = 0; i < 2; ++i) {
+    out8[4 * i + 0] = g[i]->ppt;
+    out8[4 * i + 1] = g[i]->cx;
+    out8[4 * i + 2] = g[i]->nwg;
+    out8[4 * i + 3] = g[i]->S;
   }
   return MAZE_OK;
 }

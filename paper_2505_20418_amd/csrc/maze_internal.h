@@ -251,6 +251,8 @@ hipError_t launch_sweep(const SweepLaunch& L, bool fp32, bool first, hipStream_t
 // float* by fp32; zero_x: sweep 0 writes x = 0.
 hipError_t launch_cg_sweep(const DeviceState& d, const SweepGeom& g, int k, int nprev_first,
                            void* x, bool fp32, bool zero_x, hipStream_t st);
+// Fills x (G elements) with a fixed finite pattern.
+hipError_t launch_fill_pattern(void* x, long long G, bool fp32, hipStream_t st);
 // Batch helpers: {done, iters, err} of every session into out[3 * count];
 // copies of every session's scalars into out[count].
 hipError_t launch_batch_poll(Scalars* const* scs, int count, int32_t* out, hipStream_t st);

@@ -29,7 +29,7 @@ EXPORTED = ("maze_abi_version", "maze_strerror", "maze_device_bytes", "maze_init
             "maze_solve", "maze_step_batch", "maze_grid_n", "maze_get_grid",
             "maze_state_bytes", "maze_save", "maze_load", "maze_destroy", "maze_md_prime",
             "maze_md_step", "maze_profile_enable", "maze_profile_read", "maze_trace_enable",
-            "maze_trace_read", "maze_md_step_batch")
+            "maze_trace_read", "maze_md_step_batch", "maze_launch_shape")
 
 
 class maze_config(ctypes.Structure):
@@ -115,6 +115,8 @@ def lib():
         L.maze_profile_enable.argtypes = [vp, ctypes.c_int]
         L.maze_profile_read.restype = ctypes.c_int
         L.maze_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+        L.maze_launch_shape.restype = ctypes.c_int
+        L.maze_launch_shape.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
         L.maze_md_step_batch.restype = ctypes.c_int
         L.maze_md_step_batch.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(vp), i32,
                                          ctypes.POINTER(maze_stats)]
@@ -272,6 +274,15 @@ def maze_profile_read(handle) -> dict:
     v = list(out)
     return dict(fp64_sweep=(int(v[0]), v[1]), fp32_sweep=(int(v[2]), v[3]),
                 fp64_iters=int(v[4]), fp32_iters=int(v[5]))
+
+
+def maze_launch_shape(handle) -> dict:
+    """Latency and throughput launch shapes of the session's CG sweep."""
+    out = (ctypes.c_int32 * 8)()
+    _check(lib().maze_launch_shape(handle, out), "maze_launch_shape")
+    return {k: dict(ppt=out[4 * i], cx=out[4 * i + 1], nwg=out[4 * i + 2],
+                    segment=out[4 * i + 3])
+            for i, k in enumerate(("latency", "throughput"))}
 
 
 def maze_trace_enable(handle, on: bool = True):

@@ -2,10 +2,14 @@
 
 Sessions of uneven size and mixed precision advance together, one launch
 per CG sweep and template class covering all of them. Each session's
-result must be bitwise the one it gets stepped alone (same kernels, same
-geometry, same fixed-order reductions), a rejected member must leave only
-itself unchanged, and a batch member must agree with the oracle.
+result must be bitwise the one it gets stepped alone while the batch stays
+below the throughput fill level (same kernels, same geometry, same
+fixed-order reductions); a batch swept in the throughput shapes must meet
+every tolerance and agree with the step alone within the bound the
+tolerance implies; a rejected member must leave only itself unchanged, and
+a batch member must agree with the oracle.
 """
+import math
 import numpy as np
 import pytest
 
@@ -55,6 +59,8 @@ def test_batch_is_bitwise_alone(maze):
         systems.append(s)
         alone.append(a)
         batch.append(b)
+    # below one workgroup per CU in the throughput shapes: latency mode
+    assert sum(maze.maze_launch_shape(b.handle)["throughput"]["nwg"] for b in batch) < 256
     for k in range(3):
         pos = [dev(s.pos + (k + 1) * s.vel) for s in systems]
         ref = [a.step(p, want_field=True) for a, p in zip(alone, pos)]
@@ -115,4 +121,41 @@ def test_batch_rejected_member_is_unchanged(maze):
     out = sess[1].step(dev(systems[1].pos + systems[1].vel))
     assert out["status"] == maze.MAZE_OK
     for x in sess:
+        x.close()
+
+
+def test_throughput_mode_within_tolerance_of_alone(maze, monkeypatch):
+    """Throughput shapes change the summation order, so the step differs
+    from the step alone by at most the two solves' residuals through the
+    inverse operator: for the periodic 7-point M the smallest nonzero
+    eigenvalue is 2 (1 - cos(2 pi / N)), and each solve leaves
+    ||sigma_p - M y|| <= tol ||q||, so ||phi_a - phi_b|| <= (4 pi / h) *
+    2 tol ||q|| / lambda_min."""
+    print("case: throughput-mode batch of", CASES, flush=True)
+    systems, alone, batch = [], [], []
+    for i, c in enumerate(CASES):
+        s, a = make(maze, c, seed=300 + i)
+        _, b = make(maze, c, seed=300 + i)
+        systems.append(s)
+        alone.append(a)
+        batch.append(b)
+    shapes = [maze.maze_launch_shape(b.handle) for b in batch]
+    assert any(sh["throughput"] != sh["latency"] for sh in shapes), shapes
+    monkeypatch.setenv("MAZE_BATCH_MODE", "throughput")
+    pos = [dev(s.pos + s.vel) for s in systems]
+    ref = [a.step(p, want_field=True) for a, p in zip(alone, pos)]
+    forces = [torch.empty(s.n_ions, 3, dtype=torch.float64, device="cuda") for s in systems]
+    rc, st = maze.maze_step_batch([b.handle for b in batch], pos, forces)
+    assert rc == maze.MAZE_OK
+    for i, (c, r, b) in enumerate(zip(CASES, ref, batch)):
+        n_cells, N, prec, tol = c
+        assert st[i]["status"] == maze.MAZE_OK and st[i]["converged"] == 1, i
+        assert st[i]["rel_residual"] <= tol, i
+        h = systems[i].box / N
+        qn = torch.linalg.norm(b.grid(maze.GRID_Q)).item()
+        lam = 2.0 * (1.0 - math.cos(2.0 * math.pi / N))
+        bound = (4.0 * math.pi / h) * 2.0 * tol * qn / lam
+        d = torch.linalg.norm(b.grid(maze.GRID_PHI) - r["field"]).item()
+        assert d <= bound, (i, d, bound)
+    for x in alone + batch:
         x.close()
