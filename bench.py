@@ -77,8 +77,9 @@ def run_md(system, tol, precision, steps, warmup, record_positions=False, order=
     maze.maze_profile_enable(h, False)
     lat = np.array([evs[k].elapsed_time(evs[k + 1]) for k in range(steps)])
     obs = run.observables()
+    shape = maze.maze_launch_shape(h)["latency"]
     out = dict(steps_per_s=steps / (t1 - t0), wall_s=t1 - t0, lat_ms=lat, prof=prof,
-               obs=obs, grid_n=run.session.N, traj=traj)
+               obs=obs, grid_n=run.session.N, traj=traj, shape=shape)
     run.close()
     return out
 
@@ -109,7 +110,7 @@ def replay_errors(system, traj, tol, n_replay):
                 steps_compared=len(ef))
 
 
-def roofline(prof_key, prof, G, dtype_key):
+def roofline(prof_key, prof, G, dtype_key, shape=None):
     n, ms = prof[prof_key]
     if n == 0:
         return None
@@ -120,12 +121,19 @@ def roofline(prof_key, prof, G, dtype_key):
          "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
          "kernel": f"k_cg_sweep ({dtype_key})", "avg_launch_us": round(avg_s * 1e6, 2),
          "launches_timed": n, "algorithmic_bytes_per_launch": bpl}
+    if shape is not None:
+        # the launch shape the session swept in; a kernel trace of this run
+        # also holds the autotuner's timing sweeps in other shapes, which
+        # this grid size (workgroups x 256 threads) tells apart
+        r["launch_shape"] = {"ppt": shape["ppt"], "cx": shape["cx"], "workgroups": shape["nwg"],
+                             "grid_threads": shape["nwg"] * 256}
     return r
 
 
 def attach_traffic(r, key):
     """HBM bytes per launch from the committed counter summary, if it was
-    taken with the current stencil source."""
+    taken with the current sweep source and in the launch shape this run
+    swept in."""
     if r is None or not os.path.exists(TRAFFIC_FILE):
         return
     try:
@@ -133,6 +141,10 @@ def attach_traffic(r, key):
     except Exception:
         return
     if t.get("stencil_sha") != stencil_hash() or key not in t:
+        return
+    want = t[key].get("launch_shape")
+    have = r.get("launch_shape")
+    if want is None or have is None or (want["ppt"], want["cx"]) != (have["ppt"], have["cx"]):
         return
     r["traffic"] = t[key]["hbm_bytes_per_launch"]
 
@@ -313,9 +325,9 @@ def main():
             errors = replay_errors(system, fp64["traj"], tol, args.replay)
             log(f"bench: mixed vs fp64 errors {errors}")
 
-    r_mixed = roofline("fp32_sweep", mixed["prof"], G, "fp32")
+    r_mixed = roofline("fp32_sweep", mixed["prof"], G, "fp32", mixed["shape"])
     attach_traffic(r_mixed, "fp32_sweep")
-    r_fp64 = roofline("fp64_sweep", fp64["prof"], G, "fp64") if fp64 else None
+    r_fp64 = roofline("fp64_sweep", fp64["prof"], G, "fp64", fp64["shape"]) if fp64 else None
     attach_traffic(r_fp64, "fp64_sweep")
 
     it_mixed = mixed["prof"]["fp32_iters"] / args.steps
