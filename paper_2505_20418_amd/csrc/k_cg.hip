@@ -560,6 +560,8 @@ template SweepArgs<double> make_sweep_args<double>(const DeviceState&, double*, 
 
 hipError_t launch_cg_sweep(const DeviceState& d, const SweepGeom& g, int k, int nprev_first,
                            void* x, bool fp32, bool zero_x, hipStream_t st) {
+  // one partial per workgroup and slot: the shape must fit the buffer's rows
+  if (g.nwg < 1 || g.nwg > d.part_stride) return hipErrorInvalidValue;
   SweepLaunch L{};
   L.batch = false;
   L.g = g;

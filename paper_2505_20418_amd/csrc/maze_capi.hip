@@ -124,31 +124,53 @@ static SweepGeom choose_sweep(int N) {
 }
 
 // Launch shapes the autotuner times: segments of 256, 512 or 1024 points
-// of the (y, z) plane and runs of 4 to 64 x planes. Shapes whose halo slots
-// or LDS do not fit a kernel instantiation are left out.
-static std::vector<SweepGeom> sweep_candidates(int N, bool fp32) {
+// of the (y, z) plane, runs of 4 to 64 x planes, and the runs that make the
+// workgroup count k times the device's CU count (k = 1..8), since a launch
+// whose last round of workgroups only partly fills the CUs leaves them idle
+// for that round. Shapes whose halo slots or LDS do not fit a kernel
+// instantiation are left out; of runs giving the same number of chunks only
+// the most even split is kept.
+static std::vector<SweepGeom> sweep_candidates(int N, bool fp32, int cus) {
   std::vector<SweepGeom> out;
   const int P = N * N;
   for (int ppt : {1, 2, 4}) {
     if (ppt > 1 && kThreads * ppt / 2 >= P) continue;  // segment longer than a plane
-    for (int cx : {4, 8, 16, 32, 64}) {
+    const int nseg = (P + kThreads * ppt - 1) / (kThreads * ppt);
+    std::vector<int> cxs = {4, 8, 16, 32, 64};
+    for (int k = 1; k <= 8 && cus > 0; ++k) {
+      const int nchunk = (k * cus + nseg - 1) / nseg;
+      if (nchunk >= 1 && nchunk <= N) cxs.push_back((N + nchunk - 1) / nchunk);
+    }
+    for (int cx : cxs) {
       if (cx > N && cx != 4) continue;
-      const SweepGeom g = make_sweep_geom(N, ppt, cx);
+      const SweepGeom g0 = make_sweep_geom(N, ppt, cx);
+      const SweepGeom g = make_sweep_geom(N, ppt, (N + g0.nchunk - 1) / g0.nchunk);
       if (sweep_nh_class(g.nh) == 0) continue;
       if (sweep_lds_bytes(g, fp32, false) > 159 * 1024) continue;
       bool dup = false;
-      for (const SweepGeom& o : out) dup |= (o.ppt == g.ppt && o.cx == g.cx);
+      for (const SweepGeom& o : out) dup |= (o.ppt == g.ppt && o.nchunk == g.nchunk);
       if (!dup) out.push_back(g);
     }
   }
   return out;
 }
 
+// CUs of the current device (0 if it cannot be read).
+static int device_cus() {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0;
+  return cus;
+}
+
 static int part_stride_for(const DeviceState& d, const MarchGeom& g, const SweepGeom& w) {
   int m = std::max({g.nwg, w.nwg, update_blocks(d.G), d.ntiles, 1});
   const int N = g.N;
+  // sized for the fixed list; CU-multiple candidates that would not fit are
+  // skipped by the tuner
   for (bool f : {false, true})
-    for (const SweepGeom& c : sweep_candidates(N, f)) m = std::max(m, c.nwg);
+    for (const SweepGeom& c : sweep_candidates(N, f, 0)) m = std::max(m, c.nwg);
   return m;
 }
 
@@ -460,6 +482,7 @@ static int run_cg_batch(std::vector<CgJob>& jobs, bool fp32, bool zero_x, int fi
     const int i = order[q];
     maze_session* s = jobs[i].s;
     const SweepGeom& g = shape(i);
+    if (g.nwg > s->d.part_stride) return MAZE_E_INVALID;
     if (classes.empty() || cls(order[classes.back().c0]) != cls(i)) {
       if (!classes.empty()) hw[wpos++] = classes.back().nwg;
       classes.push_back({q, q, wpos, 0, g.ppt, sweep_nh_class(g.nh), 0});
@@ -877,14 +900,17 @@ static bool autotune_enabled() {
 }
 
 // MAZE_SWEEP_SHAPE="ppt:cx" forces one launch shape (points per thread 1, 2
-// or 4; x planes per workgroup) for every session that admits it.
-static bool forced_shape(int N, bool fp32, SweepGeom* out) {
+// or 4; x planes per workgroup) for every session that admits it: its halo
+// width and LDS must fit a kernel instantiation and its workgroups the rows
+// of the session's partials buffer.
+static bool forced_shape(const DeviceState& d, bool fp32, SweepGeom* out) {
   const char* e = std::getenv("MAZE_SWEEP_SHAPE");
   int ppt = 0, cx = 0;
   if (!e || std::sscanf(e, "%d:%d", &ppt, &cx) != 2) return false;
   if ((ppt != 1 && ppt != 2 && ppt != 4) || cx < 1) return false;
-  const SweepGeom g = make_sweep_geom(N, ppt, cx);
+  const SweepGeom g = make_sweep_geom(d.N, ppt, cx);
   if (sweep_nh_class(g.nh) == 0 || sweep_lds_bytes(g, fp32, false) > 159 * 1024) return false;
+  if (g.nwg > d.part_stride) return false;
   *out = g;
   return true;
 }
@@ -893,14 +919,15 @@ static bool forced_shape(int N, bool fp32, SweepGeom* out) {
 // point among runs of 16 x planes and 1024-point segments (then shorter
 // segments and runs). Within a batch that fills the GPU many times over,
 // workgroups are not the limit and the halo re-reads of short runs are.
-static SweepGeom throughput_sweep(int N, bool fp32) {
+static SweepGeom throughput_sweep(const DeviceState& d, bool fp32) {
+  const int N = d.N;
   SweepGeom g;
-  if (forced_shape(N, fp32, &g)) return g;
-  const std::vector<SweepGeom> cand = sweep_candidates(N, fp32);
+  if (forced_shape(d, fp32, &g)) return g;
+  const std::vector<SweepGeom> cand = sweep_candidates(N, fp32, 0);
   for (int ppt : {4, 2, 1})
     for (int cx : {16, 8, 4})
       for (const SweepGeom& c : cand)
-        if (c.ppt == ppt && c.cx == std::min(cx, N)) return c;
+        if (c.ppt == ppt && c.nchunk == (N + cx - 1) / cx) return c;
   return choose_sweep(N);
 }
 
@@ -908,7 +935,7 @@ static SweepGeom autotune_sweep(maze_session* s) {
   DeviceState& d = s->d;
   const bool fp32 = s->cfg.precision == MAZE_MIXED;
   SweepGeom def = choose_sweep(d.N);
-  if (forced_shape(d.N, fp32, &def)) return def;
+  if (forced_shape(d, fp32, &def)) return def;
   if (d.mg.levels > 0 || !autotune_enabled()) return def;
   const TuneKey key{s->device, d.N, fp32 ? 1 : 0};
   {
@@ -916,7 +943,9 @@ static SweepGeom autotune_sweep(maze_session* s) {
     auto it = g_tuned.find(key);
     if (it != g_tuned.end()) return it->second;
   }
-  const std::vector<SweepGeom> cand = sweep_candidates(d.N, fp32);
+  std::vector<SweepGeom> cand;
+  for (const SweepGeom& g : sweep_candidates(d.N, fp32, device_cus()))
+    if (g.nwg <= d.part_stride) cand.push_back(g);
   if (cand.size() <= 1) return def;
   hipStream_t st = s->stream;
   void* x = fp32 ? (void*)d.e32 : (void*)d.xsolve;
@@ -1118,7 +1147,7 @@ int maze_init(const maze_config* cfg, const double* charges_dev, const double* p
   // launch shape of the CG sweep (timed on the still-unused buffers), then
   // clear them again for the first solve
   s->sweep = autotune_sweep(s);
-  s->sweep_tp = throughput_sweep(s->d.N, s->cfg.precision == MAZE_MIXED);
+  s->sweep_tp = throughput_sweep(s->d, s->cfg.precision == MAZE_MIXED);
   if (hipMemsetAsync(base, 0, L.total, stream) != hipSuccess ||
       hipMemcpyAsync(d.Q, charges_dev, sizeof(double) * n, hipMemcpyDeviceToDevice, stream) !=
           hipSuccess) {
