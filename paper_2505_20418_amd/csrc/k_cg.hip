@@ -123,6 +123,34 @@ __device__ __forceinline__ int wrap_plane(int u, int N) {
   return u < 0 ? u + N : (u >= N ? u - N : u);
 }
 
+// Plane p of a grid as a buffer resource: a scalar descriptor (base of the
+// plane, its size in bytes) that loads and stores address with a 32-bit
+// per-lane byte offset. Every address then takes one VGPR and no per-lane
+// 64-bit arithmetic, and an offset past the plane reads zero instead of
+// touching other memory. The plane index passes through readfirstlane so
+// the base stays scalar.
+template <typename T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const T* g, int p, size_t Ps) {
+  const T* base = g + (size_t)__builtin_amdgcn_readfirstlane(p) * Ps;
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(base), 0, (int)(Ps * sizeof(T)),
+                                           0x00020000);
+}
+template <typename T>
+__device__ __forceinline__ T buf_ld(__amdgpu_buffer_rsrc_t r, uint32_t boff) {
+  if constexpr (sizeof(T) == 4)
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, boff, 0, 0));
+  else
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, boff, 0, 0));
+}
+template <typename T>
+__device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, uint32_t boff, T v) {
+  if constexpr (sizeof(T) == 4)
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, boff, 0, 0);
+  else
+    __builtin_amdgcn_raw_buffer_store_b64(
+        __builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned int, v), r, boff, 0, 0);
+}
+
 // The work of one workgroup of a sweep: logical index L of the session's
 // grid (L = 0 also writes the session's control scalars). Shared by the
 // single-session and the batched kernels, so a session gets bitwise the same
@@ -134,10 +162,12 @@ __device__ __forceinline__ void sweep_wg(const SweepArgs<T>& a, const SweepGeom&
   if (ctl_ld(&sc->done) != 0 || ctl_ld(&sc->err) != 0) return;
   const int tid = threadIdx.x;
   const bool leader = (L == 0) && (tid == 0);
-  const T* r_in = a.r[par];
-  T* r_out = a.r[par ^ 1];
-  const T* p_in = a.p[par];
-  T* p_out = a.p[par ^ 1];
+  // buffers by parity, selected rather than indexed (an indexed copy of the
+  // batched arguments would live in scratch)
+  const T* r_in = par ? a.r[1] : a.r[0];
+  T* r_out = par ? a.r[0] : a.r[1];
+  const T* p_in = par ? a.p[1] : a.p[0];
+  T* p_out = par ? a.p[0] : a.p[1];
   // number of updates done so far in this solve; a per-parity counter, so
   // the leader's write for the next sweep never races with this sweep's reads
   const int it = ctl_ld(&sc->itp[par]);
@@ -236,6 +266,12 @@ __device__ __forceinline__ void sweep_wg(const SweepArgs<T>& a, const SweepGeom&
     if (o < 0) o += P;
     offo[k] = o;
   }
+  // byte offsets within a plane (below P * sizeof(T) <= 2^23)
+  uint32_t bo[NU], boo[NH];
+#pragma unroll
+  for (int i = 0; i < NU; ++i) bo[i] = (uint32_t)off[i] * (uint32_t)sizeof(T);
+#pragma unroll
+  for (int k = 0; k < NH; ++k) boo[k] = (uint32_t)offo[k] * (uint32_t)sizeof(T);
 
   const T c6 = (T)(1.0 / 6.0);
   const size_t Ps = (size_t)P;
@@ -246,24 +282,24 @@ __device__ __forceinline__ void sweep_wg(const SweepArgs<T>& a, const SweepGeom&
 
   // ---- prologue: planes x0-2 .. x0 of p_{k-1}, plane x0-1 of r_{k-1} ------
   {
-    const T* r0 = r_in + (size_t)wrap_plane(x0 - 1, N) * Ps;
+    const auto r0 = plane_rsrc(r_in, wrap_plane(x0 - 1, N), Ps);
 #pragma unroll
-    for (int i = 0; i < NU; ++i) rc[i] = r0[off[i]];
+    for (int i = 0; i < NU; ++i) rc[i] = buf_ld<T>(r0, bo[i]);
     if (!FIRST) {
-      const T* pa = p_in + (size_t)wrap_plane(x0 - 2, N) * Ps;
-      const T* pb = p_in + (size_t)wrap_plane(x0 - 1, N) * Ps;
-      const T* pd = p_in + (size_t)wrap_plane(x0, N) * Ps;
+      const auto pa = plane_rsrc(p_in, wrap_plane(x0 - 2, N), Ps);
+      const auto pb = plane_rsrc(p_in, wrap_plane(x0 - 1, N), Ps);
+      const auto pd = plane_rsrc(p_in, wrap_plane(x0, N), Ps);
       T ob[NH];
 #pragma unroll
       for (int i = 0; i < NU; ++i) {
-        pm[i] = pa[off[i]];
-        pc[i] = pb[off[i]];
-        pn[i] = pd[off[i]];
+        pm[i] = buf_ld<T>(pa, bo[i]);
+        pc[i] = buf_ld<T>(pb, bo[i]);
+        pn[i] = buf_ld<T>(pd, bo[i]);
       }
 #pragma unroll
       for (int k = 0; k < NH; ++k) {
-        ob[k] = pb[offo[k]];
-        pon[k] = pd[offo[k]];
+        ob[k] = buf_ld<T>(pb, boo[k]);
+        pon[k] = buf_ld<T>(pd, boo[k]);
       }
 #pragma unroll
       for (int i = 0; i < NU; ++i)
@@ -293,19 +329,19 @@ __device__ __forceinline__ void sweep_wg(const SweepArgs<T>& a, const SweepGeom&
     // issue the loads of the next step
     T pf[NU], pof[NH], rf[NU], xf[PPT];
     if (more) {
-      const T* rp = r_in + (size_t)wrap_plane(u + 1, N) * Ps;
+      const auto rp = plane_rsrc(r_in, wrap_plane(u + 1, N), Ps);
 #pragma unroll
-      for (int i = 0; i < NU; ++i) rf[i] = rp[off[i]];
+      for (int i = 0; i < NU; ++i) rf[i] = buf_ld<T>(rp, bo[i]);
       if (!FIRST) {
-        const T* pp = p_in + (size_t)wrap_plane(u + 2, N) * Ps;
+        const auto pp = plane_rsrc(p_in, wrap_plane(u + 2, N), Ps);
 #pragma unroll
-        for (int i = 0; i < NU; ++i) pf[i] = pp[off[i]];
+        for (int i = 0; i < NU; ++i) pf[i] = buf_ld<T>(pp, bo[i]);
 #pragma unroll
-        for (int k = 0; k < NH; ++k) pof[k] = pp[offo[k]];
+        for (int k = 0; k < NH; ++k) pof[k] = buf_ld<T>(pp, boo[k]);
         if (own_n) {
-          const T* xp = a.x + (size_t)(u + 1) * Ps;
+          const auto xp = plane_rsrc((const T*)a.x, u + 1, Ps);
 #pragma unroll
-          for (int j = 0; j < PPT; ++j) xf[j] = xp[off[j]];
+          for (int j = 0; j < PPT; ++j) xf[j] = buf_ld<T>(xp, bo[j]);
         }
       }
     }
@@ -334,14 +370,16 @@ __device__ __forceinline__ void sweep_wg(const SweepArgs<T>& a, const SweepGeom&
       }
     }
     if (own_u) {
-      const size_t pb = (size_t)u * Ps;
+      const auto ro = plane_rsrc((const T*)r_out, u, Ps);
+      const auto po = plane_rsrc((const T*)p_out, u, Ps);
+      const auto xo = plane_rsrc((const T*)a.x, u, Ps);
 #pragma unroll
       for (int j = 0; j < PPT; ++j) {
         if (cval[j]) {
-          r_out[pb + off[j]] = rk[j];
-          p_out[pb + off[j]] = pk[j];
-          if (!FIRST) a.x[pb + off[j]] = xc[j] + alpha * pc[j];
-          else if (a.zero_x) a.x[pb + off[j]] = (T)0;
+          buf_st<T>(ro, bo[j], rk[j]);
+          buf_st<T>(po, bo[j], pk[j]);
+          if (!FIRST) buf_st<T>(xo, bo[j], xc[j] + alpha * pc[j]);
+          else if (a.zero_x) buf_st<T>(xo, bo[j], (T)0);
           const double rd = (double)rk[j];
           acc[0] += rd * rd;
           acc[1] = fmax(acc[1], fabs(rd));
