@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define MAZE_ABI_VERSION 1
+#define MAZE_ABI_VERSION 2
 
 typedef struct maze_session maze_session;
 
@@ -269,6 +269,13 @@ typedef struct {
                                  A [eV], B [1/A], s [A], C [eV A^6],
                                  D [eV A^8]: V = A e^{B(s-r)} - C/r^6 - D/r^8,
                                  shifted to zero at the cutoff */
+  /* Langevin dynamics (Results section: canonical equilibration with the
+   * OVRVO integrator). gamma: friction [1/fs], >= 0; 0 selects plain
+   * velocity Verlet and kT, seed are not read. kT: thermostat temperature
+   * k_B T [eV], >= 0. seed: key of the noise (maze_langevin_noise). */
+  double gamma;
+  double kT;
+  uint64_t seed;
 } maze_md_state;
 
 /* Forces at the current positions: runs maze_step on pos (advancing the
@@ -276,8 +283,15 @@ typedef struct {
  * zeroes the work accumulator and fills the scalars. */
 int maze_md_prime(maze_session* s, const maze_md_state* md, maze_stats* st);
 
-/* One velocity-Verlet step: half kick, drift, maze_step + short range at
- * the new positions, work update, half kick, kinetic energy and momentum.
+/* One MD step. With gamma = 0, velocity Verlet: half kick, drift, maze_step
+ * + short range at the new positions, work update, half kick, kinetic
+ * energy and momentum. With gamma > 0, OVRVO: the same step between two
+ * Ornstein-Uhlenbeck half steps v <- a v + sqrt((1 - a^2) kT accel / m) xi,
+ * a = exp(-gamma dt / 2), one before the first half kick (half 0) and one
+ * after the closing half kick (half 1), with xi the deviates
+ * maze_langevin_noise gives for (seed, step, half) and step the session's
+ * step count at entry (the count maze_step advances and maze_save keeps);
+ * kinetic energy and momentum are then taken after the second half step.
  */
 int maze_md_step(maze_session* s, const maze_md_state* md, maze_stats* st);
 
@@ -291,6 +305,59 @@ int maze_md_step(maze_session* s, const maze_md_state* md, maze_stats* st);
  * most severe status. */
 int maze_md_step_batch(maze_session* const* sessions, const maze_md_state* const* mds,
                        int32_t count, maze_stats* st);
+
+/* Standard normal deviates of the Langevin noise. out_dev (DEVICE, n*3
+ * doubles) receives, for ions i = 0..n-1, the deviates that OVRVO half step
+ * `half` (0 or 1) of step `step` draws with key `seed`: Philox4x32-10
+ * (Salmon, Moraes, Dror and Shaw, SC'11) of counter (i, half, step mod 2^32,
+ * step div 2^32) and key (seed mod 2^32, seed div 2^32) gives words x0..x3;
+ * the Box-Muller transform with u1 = (x + 1) 2^-32 and u2 = x' 2^-32 turns
+ * (x0, x1) into the x and y deviates (r cos 2 pi u2, r sin 2 pi u2,
+ * r = sqrt(-2 ln u1)) and (x2, x3) into z (r cos). Asynchronous on
+ * `stream` (hipStream_t; NULL: the null stream). MAZE_E_INVALID for n < 0,
+ * half not 0 or 1, step < 0 or a NULL out_dev with n > 0. */
+int maze_langevin_noise(uint64_t seed, int64_t step, int32_t half, int32_t n, double* out_dev,
+                        void* stream);
+
+/* ---- structural and transport observables (Results section: radial pair
+ * distribution functions, velocity autocorrelation functions and mean
+ * squared displacements of molten NaCl). ---- */
+
+/* Pair-distance histograms for g_IJ(r). For every pair i < j of the n ions
+ * (pos_dev, DEVICE n*3 doubles, any periodic image), dx = x_j - x_i is
+ * wrapped to dx - box rint(dx / box) per axis and r2 = dx^2 + dy^2 + dz^2
+ * is summed in that order without fused multiply-add; the pair adds one to
+ * hist_dev[row * nbins + b], row = s_i + s_j (species_dev, DEVICE n int32:
+ * 0 Na, 1 Cl; rows Na-Na, Na-Cl, Cl-Cl), where edges2_dev[b] <= r2 <
+ * edges2_dev[b + 1] (DEVICE, nbins + 1 ascending squared bin edges). Pairs
+ * outside the edges are not counted. hist_dev (DEVICE, 3 * nbins uint64) is
+ * accumulated, not cleared. 1 <= nbins <= 4096 and box > 0, else
+ * MAZE_E_INVALID. Asynchronous on `stream`. */
+int maze_rdf_accumulate(const double* pos_dev, const int32_t* species_dev, int32_t n, double box,
+                        const double* edges2_dev, int32_t nbins, uint64_t* hist_dev,
+                        void* stream);
+
+/* Time correlations per species over time origins. Samples are numbered
+ * k = 0, 1, ... in call order; sample k stores a copy of (positions,
+ * velocities) as a time origin when k is a multiple of origin_every, and
+ * every stored origin with lag l = k - k_o <= max_lag adds
+ * sum_i v_i(k_o).v_i(k) and sum_i |r_i(k) - r_i(k_o)|^2 over the ions of
+ * each species (positions unwrapped, as the MD driver keeps them) to the
+ * sums of lag l, and one to counts[l]. Each (origin, sample) pair is one
+ * workgroup's fixed-order reduction, so the sums are reproducible.
+ * maze_tcf_create allocates max_lag / origin_every + 1 origin slots of n
+ * ions and the sums on the current device and copies species_dev (DEVICE, n
+ * int32, 0 or 1); sample and read run on `stream`. */
+typedef struct maze_tcf maze_tcf;
+int maze_tcf_create(int32_t n, const int32_t* species_dev, int32_t max_lag, int32_t origin_every,
+                    void* stream, maze_tcf** out);
+/* pos_dev, vel_dev: DEVICE n*3 doubles. Asynchronous. */
+int maze_tcf_sample(maze_tcf* t, const double* pos_dev, const double* vel_dev);
+/* sums_host (HOST, 4 * (max_lag + 1) doubles: rows VACF Na, VACF Cl, MSD
+ * Na, MSD Cl, not normalised) and counts_host (HOST, max_lag + 1 int64,
+ * origins seen at each lag); either may be NULL. Synchronises the stream. */
+int maze_tcf_read(const maze_tcf* t, double* sums_host, int64_t* counts_host);
+void maze_tcf_destroy(maze_tcf* t);
 
 #ifdef __cplusplus
 }

@@ -1,6 +1,7 @@
 // Molecular-dynamics driver kernels around the MaZe step: velocity Verlet
-// for the ions (Section 2) and the Born-Huggins-Mayer short-range term with
-// the electrostatic part removed (Results section). Not part of the
+// for the ions (Section 2), its Langevin extension OVRVO for canonical runs
+// (Results section), and the Born-Huggins-Mayer short-range term with the
+// electrostatic part removed (Results section). Not part of the
 // electrostatic hot path; they make a full device-resident MD step.
 //
 // Scratch layout (md.scratch_dev): [0, 3n) positions before the drift,
@@ -11,16 +12,24 @@
 #include <cmath>
 
 #include "device_util.h"
+#include "philox.h"
 
 namespace maze {
 
 struct MdParams {
   int n;
+  int lgv;             // Langevin half steps on (gamma > 0)
   double dt, accel, cutoff, box, inv_box;
   double tab[15];
+  double ou_a, ou_b2;  // v <- a v + sqrt(b2 / m) xi
+  uint64_t seed;
+  long long step;      // noise counter of this step
 };
 
-static MdParams md_params(const maze_md_state& md, double box) {
+// The Ornstein-Uhlenbeck half step over dt/2: a = exp(-gamma dt / 2) and
+// b2 = (1 - a^2) kT accel, so that sqrt(b2 / m) is the velocity spread
+// [A/fs] that the half step adds for an ion of mass m [amu].
+static MdParams md_params(const maze_md_state& md, double box, long long step = 0) {
   MdParams p;
   p.n = md.n_ions;
   p.dt = md.dt;
@@ -29,6 +38,11 @@ static MdParams md_params(const maze_md_state& md, double box) {
   p.box = box;
   p.inv_box = 1.0 / box;
   for (int i = 0; i < 15; ++i) p.tab[i] = md.bmh_table[i];
+  p.lgv = md.gamma > 0.0 ? 1 : 0;
+  p.ou_a = p.lgv ? std::exp(-md.gamma * md.dt / 2.0) : 1.0;
+  p.ou_b2 = p.lgv ? (1.0 - p.ou_a * p.ou_a) * md.kT * md.accel : 0.0;
+  p.seed = md.seed;
+  p.step = step;
   return p;
 }
 
@@ -200,10 +214,19 @@ __global__ __launch_bounds__(kThreads) void k_md_kick_drift(MdParams p, double* 
   const int i = blockIdx.x * kThreads + threadIdx.x;
   if (i >= p.n) return;
   const double c = 0.5 * p.dt * p.accel / mass[i];
+  double v0[3] = {vel[3 * i], vel[3 * i + 1], vel[3 * i + 2]};
+  if (p.lgv) {
+    // first Ornstein-Uhlenbeck half step (OVRVO)
+    double z[3];
+    langevin_normals(p.seed, p.step, 0, i, z);
+    const double cs = sqrt(p.ou_b2 / mass[i]);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) v0[d] = p.ou_a * v0[d] + cs * z[d];
+  }
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     const int k = 3 * i + d;
-    const double v = vel[k] + c * (f_es[k] + f_sr[k]);
+    const double v = v0[d] + c * (f_es[k] + f_sr[k]);
     vel[k] = v;
     x_old[k] = pos[k];
     f_old[k] = f_es[k];
@@ -232,9 +255,20 @@ __global__ __launch_bounds__(kThreads) void k_md_kick2(MdParams p, const double*
       v[d] = vel[k];
       if (do_kick) {
         v[d] += c * (f_es[k] + f_sr[k]);
-        vel[k] = v[d];
         w += 0.5 * (f_old[k] + f_es[k]) * (pos[k] - x_old[k]);
       }
+    }
+    if (do_kick && p.lgv) {
+      // second Ornstein-Uhlenbeck half step (OVRVO)
+      double z[3];
+      langevin_normals(p.seed, p.step, 1, i, z);
+      const double cs = sqrt(p.ou_b2 / m);
+#pragma unroll
+      for (int d = 0; d < 3; ++d) v[d] = p.ou_a * v[d] + cs * z[d];
+    }
+    if (do_kick) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) vel[3 * i + d] = v[d];
     }
     ke = 0.5 * m * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) / p.accel;
     px = m * v[0];
@@ -275,8 +309,8 @@ __global__ __launch_bounds__(kThreads) void k_md_finish(const double* part, int 
   }
 }
 
-hipError_t launch_md_kick_drift(const maze_md_state& md, hipStream_t st) {
-  MdParams p = md_params(md, 1.0);
+hipError_t launch_md_kick_drift(const maze_md_state& md, long long step, hipStream_t st) {
+  MdParams p = md_params(md, 1.0, step);
   const int n = md.n_ions;
   hipLaunchKernelGGL(k_md_kick_drift, dim3(md_blocks(n)), dim3(kThreads), 0, st, p, md.pos_dev,
                      md.vel_dev, md.mass_dev, (const double*)md.f_es_dev,
@@ -318,8 +352,8 @@ hipError_t launch_md_bmh(const maze_md_state& md, const DeviceState& d, hipStrea
 }
 
 static hipError_t md_finish(const maze_md_state& md, const DeviceState& d, int do_kick,
-                            hipStream_t st) {
-  MdParams p = md_params(md, 1.0);
+                            long long step, hipStream_t st) {
+  MdParams p = md_params(md, 1.0, step);
   const int n = md.n_ions, nb = md_blocks(n);
   double* part = md.scratch_dev + 6 * (size_t)n;
   hipLaunchKernelGGL(k_md_kick2, dim3(nb), dim3(kThreads), 0, st, p, (const double*)md.pos_dev,
@@ -332,11 +366,12 @@ static hipError_t md_finish(const maze_md_state& md, const DeviceState& d, int d
   return hipGetLastError();
 }
 
-hipError_t launch_md_finish(const maze_md_state& md, const DeviceState& d, hipStream_t st) {
-  return md_finish(md, d, 1, st);
+hipError_t launch_md_finish(const maze_md_state& md, const DeviceState& d, long long step,
+                            hipStream_t st) {
+  return md_finish(md, d, 1, step, st);
 }
 hipError_t launch_md_prime(const maze_md_state& md, const DeviceState& d, hipStream_t st) {
-  return md_finish(md, d, 0, st);
+  return md_finish(md, d, 0, 0, st);
 }
 
 }  // namespace maze

@@ -1368,6 +1368,9 @@ static int md_check(const maze_session* s, const maze_md_state* md) {
     return MAZE_E_INVALID;
   if (!(md->dt > 0) || !(md->accel > 0) || !(md->cutoff > 0) || md->cutoff > 0.5 * s->d.box)
     return MAZE_E_INVALID;
+  if (!(md->gamma >= 0) || !std::isfinite(md->gamma) ||
+      (md->gamma > 0 && (!(md->kT >= 0) || !std::isfinite(md->kT))))
+    return MAZE_E_INVALID;
   return MAZE_OK;
 }
 
@@ -1386,11 +1389,12 @@ int maze_md_step(maze_session* s, const maze_md_state* md, maze_stats* st) {
   int rc = md_check(s, md);
   if (rc != MAZE_OK) return rc;
   hipSetDevice(s->device);
-  HIP_TRY(launch_md_kick_drift(*md, s->stream));
+  const long long k = s->step;  // noise counter of the Langevin half steps
+  HIP_TRY(launch_md_kick_drift(*md, k, s->stream));
   rc = maze_step(s, md->pos_dev, nullptr, md->f_es_dev, md->scalars_dev + 6, nullptr);
   if (rc < 0) return rc;
   HIP_TRY(launch_md_bmh(*md, s->d, s->stream));
-  HIP_TRY(launch_md_finish(*md, s->d, s->stream));
+  HIP_TRY(launch_md_finish(*md, s->d, k, s->stream));
   const int rc2 = finish_call(s, st);
   return rc2 < 0 ? rc2 : rc;
 }
@@ -1409,8 +1413,10 @@ int maze_md_step_batch(maze_session* const* sessions, const maze_md_state* const
   hipSetDevice(ss[0]->device);
   std::vector<const double*> pos(count);
   std::vector<double*> forces(count), energies(count);
+  std::vector<long long> steps(count);
   for (int i = 0; i < count; ++i) {
-    HIP_TRY(launch_md_kick_drift(*mds[i], ss[i]->stream));
+    steps[i] = ss[i]->step;
+    HIP_TRY(launch_md_kick_drift(*mds[i], steps[i], ss[i]->stream));
     pos[i] = mds[i]->pos_dev;
     forces[i] = mds[i]->f_es_dev;
     energies[i] = mds[i]->scalars_dev + 6;
@@ -1421,7 +1427,7 @@ int maze_md_step_batch(maze_session* const* sessions, const maze_md_state* const
   for (int i = 0; i < count; ++i) {
     if (rcs[i] != MAZE_OK) continue;
     HIP_TRY(launch_md_bmh(*mds[i], ss[i]->d, ss[i]->stream));
-    HIP_TRY(launch_md_finish(*mds[i], ss[i]->d, ss[i]->stream));
+    HIP_TRY(launch_md_finish(*mds[i], ss[i]->d, steps[i], ss[i]->stream));
   }
   std::vector<Scalars> h;
   if (st) {

@@ -291,9 +291,10 @@ hipError_t launch_add_correction(const DeviceState& d, double* x, hipStream_t st
 int update_blocks(long long G);
 
 // MD driver
-hipError_t launch_md_kick_drift(const maze_md_state& md, hipStream_t st);
+hipError_t launch_md_kick_drift(const maze_md_state& md, long long step, hipStream_t st);
 hipError_t launch_md_bmh(const maze_md_state& md, const DeviceState& d, hipStream_t st);
-hipError_t launch_md_finish(const maze_md_state& md, const DeviceState& d, hipStream_t st);
+hipError_t launch_md_finish(const maze_md_state& md, const DeviceState& d, long long step,
+                            hipStream_t st);
 hipError_t launch_md_prime(const maze_md_state& md, const DeviceState& d, hipStream_t st);
 // Number of short-range energy partials for this cutoff (<= n_ions).
 int md_energy_partials(const DeviceState& d, double cutoff);

@@ -29,7 +29,9 @@ EXPORTED = ("maze_abi_version", "maze_strerror", "maze_device_bytes", "maze_init
             "maze_solve", "maze_step_batch", "maze_grid_n", "maze_get_grid",
             "maze_state_bytes", "maze_save", "maze_load", "maze_destroy", "maze_md_prime",
             "maze_md_step", "maze_profile_enable", "maze_profile_read", "maze_trace_enable",
-            "maze_trace_read", "maze_md_step_batch", "maze_launch_shape")
+            "maze_trace_read", "maze_md_step_batch", "maze_launch_shape", "maze_langevin_noise",
+            "maze_rdf_accumulate", "maze_tcf_create", "maze_tcf_sample", "maze_tcf_read",
+            "maze_tcf_destroy")
 
 
 class maze_config(ctypes.Structure):
@@ -59,7 +61,8 @@ class maze_md_state(ctypes.Structure):
                 ("f_es_dev", ctypes.c_void_p), ("f_sr_dev", ctypes.c_void_p),
                 ("scratch_dev", ctypes.c_void_p), ("scalars_dev", ctypes.c_void_p),
                 ("dt", ctypes.c_double), ("accel", ctypes.c_double),
-                ("cutoff", ctypes.c_double), ("bmh_table", ctypes.c_double * 15)]
+                ("cutoff", ctypes.c_double), ("bmh_table", ctypes.c_double * 15),
+                ("gamma", ctypes.c_double), ("kT", ctypes.c_double), ("seed", ctypes.c_uint64)]
 
 
 class MazeError(RuntimeError):
@@ -125,6 +128,19 @@ def lib():
         L.maze_trace_read.restype = ctypes.c_int
         L.maze_trace_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.c_int,
                                       ctypes.POINTER(ctypes.c_int)]
+        L.maze_langevin_noise.restype = ctypes.c_int
+        L.maze_langevin_noise.argtypes = [ctypes.c_uint64, ctypes.c_int64, i32, i32, vp, vp]
+        L.maze_rdf_accumulate.restype = ctypes.c_int
+        L.maze_rdf_accumulate.argtypes = [vp, vp, i32, ctypes.c_double, vp, i32, vp, vp]
+        L.maze_tcf_create.restype = ctypes.c_int
+        L.maze_tcf_create.argtypes = [i32, vp, i32, i32, vp, ctypes.POINTER(vp)]
+        L.maze_tcf_sample.restype = ctypes.c_int
+        L.maze_tcf_sample.argtypes = [vp, vp, vp]
+        L.maze_tcf_read.restype = ctypes.c_int
+        L.maze_tcf_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
+                                    ctypes.POINTER(ctypes.c_int64)]
+        L.maze_tcf_destroy.restype = None
+        L.maze_tcf_destroy.argtypes = [vp]
         _lib = L
     return _lib
 

@@ -1,9 +1,10 @@
 """Device-resident molecular dynamics around the MaZe step.
 
 Velocity Verlet for the ions with MaZe electrostatics and the Tosi-Fumi
-short-range term, all in the library's HIP kernels (maze_md_prime /
-maze_md_step). This module only allocates the device buffers and reads
-the scalars.
+short-range term, or its Langevin extension OVRVO for canonical runs (the
+Results section's equilibration), all in the library's HIP kernels
+(maze_md_prime / maze_md_step). This module only allocates the device
+buffers and reads the scalars.
 """
 from __future__ import annotations
 
@@ -19,10 +20,13 @@ class MDRun:
     def __init__(self, system: inputs.NaClSystem, tol: float = 1e-9,
                  precision: int = maze.MAZE_FP64, order: int = 2, dt: float = 1.0,
                  device: str = "cuda", max_iter: int = 100000, stream=None,
-                 restore: dict = None, flags: int = 0):
+                 restore: dict = None, flags: int = 0, gamma: float = 0.0,
+                 temperature: float = 0.0, seed: int = 0):
         """restore: a dict from save_state(); the run then continues exactly
         where the saved one stopped (particles, forces, observables and the
-        MaZe warm-start history), without the priming step."""
+        MaZe warm-start history), without the priming step.
+        gamma [1/fs], temperature [K], seed: Langevin (OVRVO) thermostat;
+        gamma = 0 is velocity Verlet."""
         self.system = system
         dev = torch.device(device)
         f64 = dict(dtype=torch.float64, device=dev)
@@ -48,7 +52,8 @@ class MDRun:
             n, 0, self.pos.data_ptr(), self.vel.data_ptr(), self.mass.data_ptr(),
             self.species.data_ptr(), self.f_es.data_ptr(), self.f_sr.data_ptr(),
             self.scratch.data_ptr(), self.scalars.data_ptr(), float(dt),
-            inputs.ACCEL_FACTOR, inputs.BMH_CUTOFF, table)
+            inputs.ACCEL_FACTOR, inputs.BMH_CUTOFF, table, float(gamma),
+            inputs.KB_EV_PER_K * float(temperature), int(seed))
         self.last = None
         if restore is None:
             self.prime_stats = maze.maze_md_prime(self.session.handle, self.md)[1]
@@ -58,6 +63,14 @@ class MDRun:
             self.f_sr.copy_(torch.as_tensor(np.asarray(restore["f_sr"])))
             self.scalars.copy_(torch.as_tensor(np.asarray(restore["scalars"])))
             self.prime_stats = None
+
+    def set_thermostat(self, gamma: float, temperature: float = 0.0, seed: int = None):
+        """Switch the Langevin friction (0: velocity Verlet, e.g. for the
+        microcanonical production after a canonical equilibration)."""
+        self.md.gamma = float(gamma)
+        self.md.kT = inputs.KB_EV_PER_K * float(temperature)
+        if seed is not None:
+            self.md.seed = int(seed)
 
     def step(self, want_stats: bool = False):
         rc, st = maze.maze_md_step(self.session.handle, self.md, want_stats)

@@ -41,7 +41,7 @@ def test_binding_covers_header():
 def test_host_only_entry_points():
     L = ctypes.CDLL(LIB)
     L.maze_abi_version.restype = ctypes.c_int
-    assert L.maze_abi_version() == 1
+    assert L.maze_abi_version() == 2
     L.maze_strerror.restype = ctypes.c_char_p
     assert b"neutral" in L.maze_strerror(-2)
     L.maze_grid_n.restype = ctypes.c_int
@@ -85,6 +85,7 @@ int main(void) {
   F(maze_config, tol); F(maze_config, coulomb_k); F(maze_config, stream);
   F(maze_stats, h); F(maze_stats, energy); F(maze_stats, status);
   F(maze_md_state, scalars_dev); F(maze_md_state, dt); F(maze_md_state, bmh_table);
+  F(maze_md_state, gamma); F(maze_md_state, kT); F(maze_md_state, seed);
   return 0;
 }
 ''')
