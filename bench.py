@@ -48,11 +48,13 @@ def stencil_hash() -> str:
     return hashlib.sha256(open(STENCIL_SRC, "rb").read()).hexdigest()[:16]
 
 
-def run_md(system, tol, precision, steps, warmup, record_positions=False, order=2, flags=0):
+def run_md(system, tol, precision, steps, warmup, record_positions=False, order=2, flags=0,
+           gamma=0.0):
     import torch
     from paper_2505_20418_amd import maze, md
 
-    run = md.MDRun(system, tol=tol, precision=precision, order=order, flags=flags)
+    run = md.MDRun(system, tol=tol, precision=precision, order=order, flags=flags, gamma=gamma,
+                   temperature=system.temperature, seed=7)
     h = run.session.handle
     for _ in range(warmup):
         run.step()
@@ -130,6 +132,21 @@ def roofline(prof_key, prof, G, dtype_key, shape=None):
     return r
 
 
+def attach_ceilings(r, copy_gbps):
+    """The sweep's rate against the measured copy rate, and the counter-
+    measured rate (HBM bytes from the counters over the same launch time)
+    against both ceilings."""
+    if r is None:
+        return
+    r["copy_GBps"] = round(copy_gbps, 1)
+    r["frac_of_copy"] = round(r["achieved"] / copy_gbps, 4)
+    if r.get("traffic"):
+        g = r["traffic"] / (r["avg_launch_us"] * 1e-6) / 1e9
+        r["counter_GBps"] = round(g, 1)
+        r["counter_frac"] = round(g / HBM_PEAK_GBS, 4)
+        r["counter_frac_of_copy"] = round(g / copy_gbps, 4)
+
+
 def attach_traffic(r, key):
     """HBM bytes per launch from the committed counter summary, if it was
     taken with the current sweep source and in the launch shape this run
@@ -179,11 +196,61 @@ def cpu_baseline(system, tol, iters_per_step):
     total = time.perf_counter() - t_start
     per_step = t_other + iters_per_step * t_iter
     return {"value": round(1.0 / per_step, 6), "unit": "MD steps/s", "cores": 1, "kind": "oracle",
+            **host_description(),
             "sample": (f"one oracle MD step at {N}^3 with the solve capped at 0 iterations "
                        f"({t_other:.2f} s) plus {n_cg} oracle PLCG iterations at {N}^3 "
                        f"({t_iter:.3f} s each), extrapolated to {iters_per_step:.1f} "
                        f"iterations per step (GPU FP64 path); {total:.1f} s of CPU work, "
                        f"single-threaded plain C, -O2 -ffp-contract=off")}
+
+
+def copy_bandwidth(gib: float = 2.0, reps: int = 10) -> float:
+    """Device-to-device copy rate (bytes read + written per second, GB/s)
+    of a plain 2 GiB copy: the practical streaming ceiling beside the
+    vendor peak."""
+    import torch
+    n = int(gib * (1 << 30)) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / reps * 1e-3
+    del a, b
+    return 2.0 * n * 8 / t / 1e9
+
+
+def host_description():
+    """CPU model and thread count of the host, and a numpy triad rate
+    (a = b + s c over 3 x 800 MB; 24 bytes per element) as the oracle's own
+    bandwidth roofline."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    n = 100_000_000
+    b = np.ones(n)
+    c = np.ones(n)
+    a = np.empty(n)
+    best = None
+    for _ in range(3):
+        t0 = time.perf_counter()
+        np.multiply(c, 3.0, out=a)
+        np.add(a, b, out=a)
+        dt = time.perf_counter() - t0
+        best = dt if best is None else min(best, dt)
+    # multiply reads c, writes a; add reads a and b, writes a: 40 B/element
+    return {"cpu_model": model, "host_threads": os.cpu_count(),
+            "host_triad_GBps": round(40.0 * n / best / 1e9, 1)}
 
 
 def copy_calibration(gib: float = 2.0, reps: int = 5):
@@ -242,6 +309,51 @@ def bench_ensemble(steps: int, warmup: int, tol: float = 1e-8):
             "batching_speedup": round(t_serial / t_batch, 3)}
 
 
+def bench_observables(system, tol, steps, warmup):
+    """The Results section's canonical dynamics and observables at the
+    headline size: OVRVO MD steps/s (mixed, gamma 1e-3 /fs) beside velocity
+    Verlet, the pair histogram of all 32768 ions (pairs/s), and one VACF /
+    MSD sample over 51 time origins."""
+    import torch
+    from paper_2505_20418_amd import maze, observables
+
+    out = {}
+    r = run_md(system, tol, maze.MAZE_MIXED, steps, warmup, gamma=1e-3)
+    out["ovrvo_mixed_md_steps_per_s"] = round(r["steps_per_s"], 4)
+    dev = torch.device("cuda")
+    pos = torch.tensor(system.pos, dtype=torch.float64, device=dev)
+    vel = torch.tensor(system.vel, dtype=torch.float64, device=dev)
+    species = torch.tensor(system.species, dtype=torch.int32, device=dev)
+    n = system.n_ions
+    h = observables.PairHistogram(species, system.box, 12.0, 240)
+    h.accumulate(pos)
+    reps = 10
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        h.accumulate(pos)
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / reps * 1e-3
+    out["pair_histogram"] = {"ions": n, "pairs": n * (n - 1) // 2, "ms": round(t * 1e3, 3),
+                             "pairs_per_s": round(n * (n - 1) / 2 / t, 1), "bins": 240,
+                             "r_max_A": 12.0}
+    tc = observables.TimeCorrelations(species, 1000, 20)
+    for _ in range(60):
+        tc.sample(pos, vel)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        tc.sample(pos, vel)
+    e1.record()
+    torch.cuda.synchronize()
+    out["time_correlations"] = {"ions": n, "origins": 51, "max_lag_samples": 1000,
+                                "ms_per_sample": round(e0.elapsed_time(e1) / reps, 4)}
+    tc.close()
+    return out
+
+
 def bench_serving(full: bool):
     """Poisson stream (mean 200 requests/s) of MD-step requests over molten-
     NaCl sessions of log-uniform size, half mixed at 1e-6, half FP64 at
@@ -289,6 +401,7 @@ def main():
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--no-order4", action="store_true")
     ap.add_argument("--no-multigrid", action="store_true")
+    ap.add_argument("--no-observables", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-full", action="store_true",
                     help="serve the full 256-session mix (up to 32768 ions) instead of 64")
@@ -329,6 +442,9 @@ def main():
     attach_traffic(r_mixed, "fp32_sweep")
     r_fp64 = roofline("fp64_sweep", fp64["prof"], G, "fp64", fp64["shape"]) if fp64 else None
     attach_traffic(r_fp64, "fp64_sweep")
+    copy_gbps = copy_bandwidth()
+    attach_ceilings(r_mixed, copy_gbps)
+    attach_ceilings(r_fp64, copy_gbps)
 
     it_mixed = mixed["prof"]["fp32_iters"] / args.steps
     it_fp64 = fp64["prof"]["fp64_iters"] / args.steps if fp64 else None
@@ -399,6 +515,10 @@ def main():
                                    "p99": round(float(np.percentile(r["lat_ms"], 99)), 3)}}
         line["multigrid"] = mgl
         log(f"bench: multigrid {mgl}")
+    if not args.no_observables:
+        log("bench: Langevin dynamics and observables")
+        line["observables"] = bench_observables(system, tol, args.steps, args.warmup)
+        log(f"bench: observables {line['observables']}")
     if not args.no_ensemble:
         log("bench: ensemble of 64 replicas")
         line["ensemble"] = bench_ensemble(max(3, args.steps // 3), 4)

@@ -70,7 +70,15 @@ enum {
   /* accept charges that do not sum to zero: the zero-mode projection then
      acts as a uniform neutralising background (the single-charge
      measurements of the two-particle appendix) */
-  MAZE_FLAG_ALLOW_NET_CHARGE = 4
+  MAZE_FLAG_ALLOW_NET_CHARGE = 4,
+  /* issue the CG iterations after the first poll as replays of a captured
+     HIP graph of kPollBatch sweeps (instantiated on first use per
+     precision, parity and solution vector, up to 4 per precision and
+     parity, freed by maze_destroy) instead of kernel by kernel; same
+     kernels and arguments, so results are bitwise those without it. Needs a non-null cfg.stream (MAZE_E_INVALID otherwise);
+     single-session solves only (batched and multigrid solves launch
+     directly); ignored while maze_profile_enable is on. */
+  MAZE_FLAG_GRAPH_CHUNKS = 8
 };
 
 typedef struct {

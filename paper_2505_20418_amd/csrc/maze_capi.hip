@@ -49,6 +49,17 @@ struct maze_session {
   SweepGeom sweep{};     // latency shape: alone and in batches below the fill level
   SweepGeom sweep_tp{};  // throughput shape: batches that fill the GPU
   hipStream_t stream = nullptr;
+  // captured chunks of kPollBatch sweeps, [fp32][parity of the first sweep]
+  // [slot]: a graph holds its kernels' arguments, and the solution vector
+  // differs between solves (y for MaZe steps, the direct-solve buffer, the
+  // field for the cold solve), so each graph is kept with the x it updates
+  struct ChunkGraph {
+    hipGraphExec_t exec = nullptr;
+    void* x = nullptr;
+  };
+  static constexpr int kChunkSlots = 4;
+  ChunkGraph chunk[2][2][kChunkSlots];
+  int chunk_next[2][2] = {{0, 0}, {0, 0}};
   int device = 0;
   Scalars* host_sc = nullptr;   // pinned, 2 slots for pipelined polling
   hipEvent_t ev[2] = {nullptr, nullptr};
@@ -93,8 +104,10 @@ static int validate(const maze_config* c) {
   if (c->residual_norm != MAZE_NORM_REL2 && c->residual_norm != MAZE_NORM_ABSMAX)
     return MAZE_E_INVALID;
   const int32_t known = MAZE_FLAG_MULTIGRID | MAZE_FLAG_WEIGHT_GRADIENT_FORCE |
-                        MAZE_FLAG_ALLOW_NET_CHARGE;
+                        MAZE_FLAG_ALLOW_NET_CHARGE | MAZE_FLAG_GRAPH_CHUNKS;
   if ((c->flags & ~known) != 0 || !finite_pos(c->coulomb_k)) return MAZE_E_INVALID;
+  // the null stream cannot be captured
+  if ((c->flags & MAZE_FLAG_GRAPH_CHUNKS) && c->stream == nullptr) return MAZE_E_INVALID;
   if (grid_of(c) == 0) return MAZE_E_INVALID;
   if (c->flags & MAZE_FLAG_MULTIGRID) {
     int Ns[kMgMaxLevels];
@@ -301,6 +314,32 @@ static long long sweep_guard(int max_iter, int first_batch) {
   return (long long)max_iter + 4LL * kPollBatch + first_batch + 64;
 }
 
+// Captures kPollBatch sweeps starting at parity par0 (never the first sweep
+// of a solve) on the session's stream into a graph. The sweeps' arguments
+// depend only on the session, the precision and the parity, so one graph
+// serves every later chunk of every solve.
+static int chunk_graph(maze_session* s, bool fp32, int par0, void* x, hipGraphExec_t* out) {
+  hipGraph_t g = nullptr;
+  HIP_TRY(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
+  hipError_t e = hipSuccess;
+  for (int b = 0; b < kPollBatch && e == hipSuccess; ++b)
+    e = launch_cg_sweep(s->d, s->sweep, 2 + par0 + b, s->geom.nwg, x, fp32, false, s->stream);
+  const hipError_t e2 = hipStreamEndCapture(s->stream, &g);
+  if (e != hipSuccess || e2 != hipSuccess || !g) {
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipGetLastError();
+    return MAZE_E_DEVICE;
+  }
+  e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    *out = nullptr;
+    (void)hipGetLastError();
+    return MAZE_E_DEVICE;
+  }
+  return MAZE_OK;
+}
+
 static int run_cg(CgJob& job, bool fp32, bool zero_x, int first_batch) {
   maze_session* s = job.s;
   DeviceState& d = s->d;
@@ -310,9 +349,29 @@ static int run_cg(CgJob& job, bool fp32, bool zero_x, int first_batch) {
   int batch = 0, timed = 0;
   bool have_prev = false;
   const bool prof = s->prof;
+  const bool graphs = (s->cfg.flags & MAZE_FLAG_GRAPH_CHUNKS) && !prof;
   for (;;) {
     const int nb = (batch == 0) ? std::max(kPollBatch, first_batch) : kPollBatch;
-    for (int b = 0; b < nb; ++b, ++k) {
+    if (graphs && batch > 0) {
+      const int f = fp32 ? 1 : 0, par = (int)(k & 1);
+      maze_session::ChunkGraph* hit = nullptr;
+      for (auto& c : s->chunk[f][par])
+        if (c.exec && c.x == job.x) hit = &c;
+      if (!hit) {
+        hit = &s->chunk[f][par][s->chunk_next[f][par]];
+        s->chunk_next[f][par] = (s->chunk_next[f][par] + 1) % maze_session::kChunkSlots;
+        if (hit->exec) {
+          (void)hipGraphExecDestroy(hit->exec);
+          hit->exec = nullptr;
+        }
+        const int rc = chunk_graph(s, fp32, par, job.x, &hit->exec);
+        if (rc != MAZE_OK) return rc;
+        hit->x = job.x;
+      }
+      HIP_TRY(hipGraphLaunch(hit->exec, s->stream));
+      k += nb;
+    }
+    for (int b = 0; b < nb && !(graphs && batch > 0); ++b, ++k) {
       const bool timeit = prof && k >= 1 && (k - 1) % kProfStride == 0 && timed < kProfMax;
       if (timeit) HIP_TRY(hipEventRecord(s->pev[2 * timed], s->stream));
       HIP_TRY(launch_cg_sweep(d, w, (int)(k & 0x7fffffff), s->geom.nwg, job.x, fp32, zero_x,
@@ -1021,6 +1080,10 @@ void maze_destroy(maze_session* s) {
   else hipDeviceSynchronize();
   if (s->base) hipFree(s->base);
   if (s->host_sc) hipHostFree(s->host_sc);
+  for (auto& byf : s->chunk)
+    for (auto& bypar : byf)
+      for (auto& c : bypar)
+        if (c.exec) (void)hipGraphExecDestroy(c.exec);
   for (auto& e : s->pev)
     if (e) hipEventDestroy(e);
   for (auto& e : s->ev)

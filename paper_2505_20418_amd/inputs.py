@@ -113,6 +113,26 @@ def molten_nacl(n_cells: int, seed: int, temperature: float = 1200.0,
                       masses=masses, temperature=temperature, seed=seed)
 
 
+def bcc_nacl(cells: int = 5, box: float = 20.64, grid_spacing: float = 0.172,
+             temperature: float = 1550.0, seed: int = 0) -> NaClSystem:
+    """The Results section's molten-salt start: ions on a bcc lattice
+    (cells^3 cubic cells, Na on the corners and Cl on the body centres, so
+    2 cells^3 ions; 250 ions in 20.64 A for cells = 5) with Maxwell-Boltzmann
+    velocities at the target temperature."""
+    c = box / cells
+    i, j, k = np.meshgrid(np.arange(cells), np.arange(cells), np.arange(cells), indexing="ij")
+    corner = np.stack([i.ravel(), j.ravel(), k.ravel()], axis=1).astype(np.float64) * c
+    pos = np.concatenate([corner, corner + 0.5 * c])
+    n = corner.shape[0]
+    species = np.concatenate([np.zeros(n, np.int32), np.ones(n, np.int32)])
+    charges = np.where(species == 0, 1.0, -1.0)
+    masses = np.where(species == 0, MASS_NA, MASS_CL).astype(np.float64)
+    vel = maxwell_boltzmann(masses, temperature, np.random.default_rng(seed))
+    return NaClSystem(n_cells=cells, box=box, grid_spacing=grid_spacing, pos=pos, vel=vel,
+                      charges=charges, species=species, masses=masses,
+                      temperature=temperature, seed=seed)
+
+
 # The five workloads (cubic box, h = a/16 throughout).
 WORKLOADS = {
     # 64 ions, 32^3 grid, FP64, 100 NVE steps at 1200 K, tol 1e-9

@@ -23,6 +23,7 @@ MAZE_FP64, MAZE_MIXED = 0, 1
 MAZE_GUESS_ZERO, MAZE_GUESS_STATIC, MAZE_GUESS_TIMEPROP = 0, 1, 2
 MAZE_NORM_REL2, MAZE_NORM_ABSMAX = 0, 1
 MAZE_FLAG_MULTIGRID, MAZE_FLAG_WEIGHT_GRADIENT_FORCE, MAZE_FLAG_ALLOW_NET_CHARGE = 1, 2, 4
+MAZE_FLAG_GRAPH_CHUNKS = 8
 GRID_PHI, GRID_PHI_PREV, GRID_Y, GRID_Q, GRID_SIGMA = 0, 1, 2, 3, 4
 
 EXPORTED = ("maze_abi_version", "maze_strerror", "maze_device_bytes", "maze_init", "maze_step",

@@ -59,17 +59,20 @@ class PairHistogram:
         return 0.5 * (self.edges[1:] + self.edges[:-1])
 
 
-def g_features(r: np.ndarray, g: np.ndarray, floor: float = 1e-3) -> dict:
-    """Onset (first r with g above `floor`), first maximum (position and
-    height) and the first minimum after it."""
+def g_features(r: np.ndarray, g: np.ndarray, floor: float = 0.01, smooth: int = 5) -> dict:
+    """The quantities of the paper's g(r) table: onset r_cut (first r with g
+    above `floor`), the first maximum (the highest point of a liquid's g,
+    position and height), and the first minimum after it, located on a
+    `smooth`-bin moving average so that counting noise does not stop the
+    descent early."""
     nz = np.nonzero(g > floor)[0]
     if len(nz) == 0:
         return {}
-    k = k0 = int(nz[0])
-    while k + 1 < len(g) and g[k + 1] >= g[k]:
-        k += 1
-    kmax = k
-    while k + 1 < len(g) and g[k + 1] <= g[k]:
+    k0 = int(nz[0])
+    kmax = int(np.argmax(g))
+    gs = np.convolve(g, np.ones(smooth) / smooth, mode="same")
+    k = kmax
+    while k + 1 < len(gs) and gs[k + 1] <= gs[k]:
         k += 1
     return dict(r_cut=float(r[k0]), r_max=float(r[kmax]), g_max=float(g[kmax]),
                 r_min=float(r[k]))

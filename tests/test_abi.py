@@ -67,8 +67,15 @@ def test_host_only_entry_points():
     assert L.maze_device_bytes(ctypes.byref(mg)) > L.maze_device_bytes(ctypes.byref(ok))
     odd = maze.maze_config(4, 2, 40.4, 0.4, 1e-9, 10, 0, 0, maze.MAZE_FLAG_MULTIGRID, 1.0, None)
     assert L.maze_device_bytes(ctypes.byref(odd)) == 0
-    badflag = maze.maze_config(4, 2, 25.6, 0.4, 1e-9, 10, 0, 0, 8, 1.0, None)
+    badflag = maze.maze_config(4, 2, 25.6, 0.4, 1e-9, 10, 0, 0, 16, 1.0, None)
     assert L.maze_device_bytes(ctypes.byref(badflag)) == 0
+    # graph chunks need a stream that can be captured (not the null stream)
+    nostream = maze.maze_config(4, 2, 25.6, 0.4, 1e-9, 10, 0, 0, maze.MAZE_FLAG_GRAPH_CHUNKS,
+                                1.0, None)
+    assert L.maze_device_bytes(ctypes.byref(nostream)) == 0
+    withstream = maze.maze_config(4, 2, 25.6, 0.4, 1e-9, 10, 0, 0, maze.MAZE_FLAG_GRAPH_CHUNKS,
+                                  1.0, ctypes.c_void_p(0x1000))
+    assert L.maze_device_bytes(ctypes.byref(withstream)) > 0
 
 
 def test_struct_layout_matches_c(tmp_path):

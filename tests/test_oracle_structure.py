@@ -69,6 +69,9 @@ def test_rdf_features_of_analytic_curve():
     r = np.linspace(0.05, 8.0, 160)
     g = np.where(r < 2.0, 0.0, 1.0 + 2.5 * np.exp(-(r - 2.6) ** 2 / 0.1)
                  - 0.6 * np.exp(-(r - 4.2) ** 2 / 0.2))
+    # counting noise, including a blip at the onset, must not move them
+    g = g + np.where(r < 2.0, 0.0, 0.02 * np.sin(37.0 * r))
+    g[np.argmin(np.abs(r - 2.1))] += 0.05
     f = structure.rdf_features(r, g)
     step = r[1] - r[0]
     assert abs(f["r_cut"] - 2.0) <= step
