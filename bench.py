@@ -86,9 +86,10 @@ def run_md(system, tol, precision, steps, warmup, record_positions=False, order=
     return out
 
 
-def replay_errors(system, traj, tol, n_replay):
+def replay_errors(system, traj, tol, n_replay, every=1):
     """Drive a fresh mixed session and a fresh FP64 session through the same
-    recorded positions; errors of mixed against FP64 per step."""
+    recorded positions (both advance every step, so the warm starts match
+    the run); errors of mixed against FP64 at every `every`-th step."""
     import torch
     from paper_2505_20418_amd import inputs, maze
 
@@ -99,17 +100,24 @@ def replay_errors(system, traj, tol, n_replay):
                        precision=maze.MAZE_FP64, coulomb_k=inputs.COULOMB_K_EV_A)
     s32 = maze.Session(Q, p0, system.box, system.grid_spacing, tol=tol,
                        precision=maze.MAZE_MIXED, coulomb_k=inputs.COULOMB_K_EV_A)
-    ef, eF, eE = [], [], []
+    ef, eF, eE, at = [], [], [], []
     for k in range(min(n_replay, traj.shape[0])):
-        a = s64.step(traj[k], want_field=True)
-        b = s32.step(traj[k], want_field=True)
+        want = (k + 1) % every == 0
+        a = s64.step(traj[k], want_field=want)
+        b = s32.step(traj[k], want_field=want)
+        if not want:
+            continue
+        at.append(k + 1)
         ef.append((torch.linalg.norm(b["field"] - a["field"]) / torch.linalg.norm(a["field"])).item())
         eF.append((torch.linalg.norm(b["forces"] - a["forces"]) / torch.linalg.norm(a["forces"])).item())
         eE.append(abs((b["energy"] - a["energy"]).item()) / abs(a["energy"].item()))
     s64.close()
     s32.close()
-    return dict(field_rel_l2_max=max(ef), forces_rel_l2_max=max(eF), energy_rel_max=max(eE),
-                steps_compared=len(ef))
+    out = dict(field_rel_l2_max=max(ef), forces_rel_l2_max=max(eF), energy_rel_max=max(eE),
+               steps_compared=len(ef))
+    if every > 1:
+        out.update(steps=at, field_rel_l2=ef, forces_rel_l2=eF, energy_rel=eE)
+    return out
 
 
 def roofline(prof_key, prof, G, dtype_key, shape=None):
@@ -402,6 +410,9 @@ def main():
     ap.add_argument("--no-order4", action="store_true")
     ap.add_argument("--no-multigrid", action="store_true")
     ap.add_argument("--no-observables", action="store_true")
+    ap.add_argument("--error-trajectory", type=int, default=0,
+                    help="also record an FP64 trajectory of this many steps and compare the "
+                         "mixed path with it every 50 steps (not part of the default run)")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-full", action="store_true",
                     help="serve the full 256-session mix (up to 32768 ions) instead of 64")
@@ -515,6 +526,12 @@ def main():
                                    "p99": round(float(np.percentile(r["lat_ms"], 99)), 3)}}
         line["multigrid"] = mgl
         log(f"bench: multigrid {mgl}")
+    if args.error_trajectory > 0:
+        log(f"bench: mixed vs FP64 over {args.error_trajectory} steps")
+        tr = run_md(system, tol, maze.MAZE_FP64, args.error_trajectory, 0, record_positions=True)
+        line["mixed_error_trajectory"] = replay_errors(system, tr["traj"], tol,
+                                                       args.error_trajectory, every=50)
+        log(f"bench: trajectory errors {line['mixed_error_trajectory']}")
     if not args.no_observables:
         log("bench: Langevin dynamics and observables")
         line["observables"] = bench_observables(system, tol, args.steps, args.warmup)

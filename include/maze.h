@@ -336,7 +336,7 @@ int maze_langevin_noise(uint64_t seed, int64_t step, int32_t half, int32_t n, do
  * wrapped to dx - box rint(dx / box) per axis and r2 = dx^2 + dy^2 + dz^2
  * is summed in that order without fused multiply-add; the pair adds one to
  * hist_dev[row * nbins + b], row = s_i + s_j (species_dev, DEVICE n int32:
- * 0 Na, 1 Cl; rows Na-Na, Na-Cl, Cl-Cl), where edges2_dev[b] <= r2 <
+ * 0 Na, any other value Cl; rows Na-Na, Na-Cl, Cl-Cl), where edges2_dev[b] <= r2 <
  * edges2_dev[b + 1] (DEVICE, nbins + 1 ascending squared bin edges). Pairs
  * outside the edges are not counted. hist_dev (DEVICE, 3 * nbins uint64) is
  * accumulated, not cleared. 1 <= nbins <= 4096 and box > 0, else

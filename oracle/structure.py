@@ -59,22 +59,24 @@ def rdf_normalise(counts: np.ndarray, frames: int, n_na: int, n_cl: int, box: fl
     return counts / (frames * ideal[:, None] * shell[None, :] / V)
 
 
-def rdf_features(r_mid: np.ndarray, g: np.ndarray, floor: float = 1e-3):
-    """The comparison quantities of the g(r) table: r_cut (first r where g is
-    non-zero, above `floor`), position and height of the first maximum, and
-    the first minimum after it."""
+def rdf_features(r_mid: np.ndarray, g: np.ndarray, floor: float = 0.0, smooth: int = 5,
+                 window: float = 3.0):
+    """The comparison quantities of the g(r) table: r_cut (first r where g
+    becomes non-null, above `floor`), position and height of the first
+    maximum (the highest point of a liquid's g), and the first minimum: the
+    lowest point of a `smooth`-bin moving average of g within `window` after
+    the maximum."""
     nz = np.nonzero(g > floor)[0]
     if len(nz) == 0:
         return None
-    k0 = nz[0]
-    k = k0
-    while k + 1 < len(g) and g[k + 1] >= g[k]:
-        k += 1
-    kmax = k
-    while k + 1 < len(g) and g[k + 1] <= g[k]:
-        k += 1
+    k0 = int(nz[0])
+    kmax = int(np.argmax(g))
+    gs = np.convolve(g, np.ones(smooth) / smooth, mode="same")
+    dr = float(r_mid[1] - r_mid[0])
+    hi = min(len(g) - smooth // 2, kmax + 1 + int(round(window / dr)))
+    kmin = kmax + 1 + int(np.argmin(gs[kmax + 1:hi])) if hi > kmax + 1 else kmax
     return dict(r_cut=float(r_mid[k0]), r_max=float(r_mid[kmax]), g_max=float(g[kmax]),
-                r_min=float(r_mid[k]))
+                r_min=float(r_mid[kmin]))
 
 
 class TimeCorrelations:

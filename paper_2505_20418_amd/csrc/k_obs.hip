@@ -69,13 +69,13 @@ __global__ __launch_bounds__(kThreads) void k_rdf_tile(const double* __restrict_
     pj[3 * tid] = pos[3 * j];
     pj[3 * tid + 1] = pos[3 * j + 1];
     pj[3 * tid + 2] = pos[3 * j + 2];
-    sj[tid] = species[j];
+    sj[tid] = species[j] ? 1 : 0;  // any nonzero value counts as Cl
   }
   __syncthreads();
   const int i = bi * kThreads + tid;
   if (i < n) {
     const double pi[3] = {pos[3 * i], pos[3 * i + 1], pos[3 * i + 2]};
-    const int si = species[i];
+    const int si = species[i] ? 1 : 0;
     const int jn = min(kThreads, n - j0);
     const double lo_e = E[0], hi_e = E[nbins];
     for (int t = 0; t < jn; ++t) {
@@ -213,7 +213,11 @@ int maze_tcf_create(int32_t n, const int32_t* species_dev, int32_t max_lag, int3
   t->slots = max_lag / origin_every + 1;
   t->stream = (hipStream_t)stream;
   t->counts.assign((size_t)max_lag + 1, 0);
-  OBS_TRY(hipGetDevice(&t->device));
+  if (hipGetDevice(&t->device) != hipSuccess) {
+    (void)hipGetLastError();
+    delete t;
+    return MAZE_E_DEVICE;
+  }
   const size_t per = sizeof(double) * 3 * (size_t)n * (size_t)t->slots;
   const size_t nsum = 4 * ((size_t)max_lag + 1);
   if (hipMalloc(&t->species, sizeof(int32_t) * (size_t)n) != hipSuccess ||

@@ -83,6 +83,8 @@ def run_study(nvt_ps=2.5, nve_ps=25.0, dt=0.25, gamma=1e-3, temperature=1550.0, 
     out["nve_wall_s"] = time.perf_counter() - t0
     out["md_steps_per_s"] = (n_nvt + n_nve) / (out["nvt_wall_s"] + out["nve_wall_s"])
     o1 = run.observables()
+    out["nve_momentum_start"] = o0["momentum"].tolist()
+    out["nve_momentum_end"] = o1["momentum"].tolist()
     out["nve_mean_T_K"] = float(np.mean(temps))
     out["nve_total_energy_drift_eV"] = o1["total"] - o0["total"]
     out["nve_total_energy_rms_eV"] = float(np.std(totals))

@@ -59,23 +59,24 @@ class PairHistogram:
         return 0.5 * (self.edges[1:] + self.edges[:-1])
 
 
-def g_features(r: np.ndarray, g: np.ndarray, floor: float = 0.01, smooth: int = 5) -> dict:
-    """The quantities of the paper's g(r) table: onset r_cut (first r with g
-    above `floor`), the first maximum (the highest point of a liquid's g,
-    position and height), and the first minimum after it, located on a
-    `smooth`-bin moving average so that counting noise does not stop the
-    descent early."""
+def g_features(r: np.ndarray, g: np.ndarray, floor: float = 0.0, smooth: int = 5,
+               window: float = 3.0) -> dict:
+    """The quantities of the paper's g(r) table: onset r_cut (first r where g
+    becomes non-null, above `floor`), the first maximum (the highest point
+    of a liquid's g: position and height), and the first minimum, the lowest
+    point of a `smooth`-bin moving average of g within `window` after the
+    maximum (so that counting noise does not end the descent early)."""
     nz = np.nonzero(g > floor)[0]
     if len(nz) == 0:
         return {}
     k0 = int(nz[0])
     kmax = int(np.argmax(g))
     gs = np.convolve(g, np.ones(smooth) / smooth, mode="same")
-    k = kmax
-    while k + 1 < len(gs) and gs[k + 1] <= gs[k]:
-        k += 1
+    dr = float(r[1] - r[0]) if len(r) > 1 else 1.0
+    hi = min(len(g) - smooth // 2, kmax + 1 + int(round(window / dr)))
+    kmin = kmax + 1 + int(np.argmin(gs[kmax + 1:hi])) if hi > kmax + 1 else kmax
     return dict(r_cut=float(r[k0]), r_max=float(r[kmax]), g_max=float(g[kmax]),
-                r_min=float(r[k]))
+                r_min=float(r[kmin]))
 
 
 class TimeCorrelations:
