@@ -326,8 +326,10 @@ def bench_observables(system, tol, steps, warmup):
     from paper_2505_20418_amd import maze, observables
 
     out = {}
-    r = run_md(system, tol, maze.MAZE_MIXED, steps, warmup, gamma=1e-3)
-    out["ovrvo_mixed_md_steps_per_s"] = round(r["steps_per_s"], 4)
+    for name, g in (("velocity_verlet", 0.0), ("ovrvo", 1e-3)):
+        r = run_md(system, tol, maze.MAZE_MIXED, steps, warmup, gamma=g)
+        out[f"{name}_mixed_md_steps_per_s"] = round(r["steps_per_s"], 4)
+        out[f"{name}_cg_iterations_per_step"] = round(r["prof"]["fp32_iters"] / steps, 1)
     dev = torch.device("cuda")
     pos = torch.tensor(system.pos, dtype=torch.float64, device=dev)
     vel = torch.tensor(system.vel, dtype=torch.float64, device=dev)
