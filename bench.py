@@ -364,7 +364,7 @@ def bench_observables(system, tol, steps, warmup):
     return out
 
 
-def bench_serving(full: bool):
+def bench_serving(full: bool, rate_hz: float = 200.0):
     """Poisson stream (mean 200 requests/s) of MD-step requests over molten-
     NaCl sessions of log-uniform size, half mixed at 1e-6, half FP64 at
     1e-10, admitted by HBM budget and served with continuous batching."""
@@ -379,14 +379,14 @@ def bench_serving(full: bool):
     t0 = time.perf_counter()
     resident = srv.prefill()
     t_prefill = time.perf_counter() - t0
-    reqs = serve.poisson_requests(n_req, n_sess, rate_hz=200.0, seed=5)
+    reqs = serve.poisson_requests(n_req, n_sess, rate_hz=rate_hz, seed=5)
     rep = srv.serve(reqs)
     srv.close()
     rep = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in rep.items()}
     for key in ("latency_ms", "service_ms"):
         rep[key] = {k: (round(v, 3) if v is not None else None) for k, v in rep[key].items()}
     rep.update({"sessions": n_sess, "max_ions": 8 * max_cells ** 3,
-                "max_grid": inputs_grid(max_cells), "arrival_rate_hz": 200.0,
+                "max_grid": inputs_grid(max_cells), "arrival_rate_hz": rate_hz,
                 "prefilled_resident": resident, "prefill_s": round(t_prefill, 2),
                 "mix": "full" if full else "reduced (sessions up to 4096 ions, 128^3)"})
     return rep
@@ -412,6 +412,8 @@ def main():
     ap.add_argument("--no-order4", action="store_true")
     ap.add_argument("--no-multigrid", action="store_true")
     ap.add_argument("--no-observables", action="store_true")
+    ap.add_argument("--serving-rate", type=float, default=200.0,
+                    help="mean Poisson arrival rate of the serving leg [requests/s]")
     ap.add_argument("--error-trajectory", type=int, default=0,
                     help="also record an FP64 trajectory of this many steps and compare the "
                          "mixed path with it every 50 steps (not part of the default run)")
@@ -544,7 +546,7 @@ def main():
         log(f"bench: ensemble {line['ensemble']}")
     if not args.no_serving:
         log("bench: serving")
-        line["serving"] = bench_serving(args.serving_full)
+        line["serving"] = bench_serving(args.serving_full, args.serving_rate)
         log(f"bench: serving {line['serving']}")
     line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)

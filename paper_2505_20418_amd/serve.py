@@ -4,8 +4,14 @@ Requests ask to advance one session by one MD step and arrive over time.
 The scheduler works at step granularity:
 
 * every round it forms a batch from the requests that have arrived: at most
-  one request per session (its oldest), oldest request first, up to
-  ``max_batch`` sessions;
+  one request per session (its oldest), up to ``max_batch`` sessions. With
+  the default ``cost_class`` policy the sessions are grouped by estimated
+  step cost (powers of four of N^4, doubled for FP64) and a round serves
+  one class: the cheapest class with a waiting request, unless a request
+  has waited longer than ``max_wait_s``, whose class then goes first. A
+  batched step lasts as long as its most expensive member, so mixing a
+  32^3 session with a 256^3 one would make the small one wait for the big
+  one. The ``fifo`` policy batches every ready session, oldest first;
 * a session stays resident on the device between its steps, so its MaZe
   warm start (phi^k, phi^{k-1}, y*) and its particles persist;
 * a session that is not resident is admitted when its device bytes fit in
@@ -122,16 +128,35 @@ class _Slot:
     steps: int = 0
 
 
+def step_cost(spec: SessionSpec) -> float:
+    """Relative cost of one MD step of a session: grid points times CG
+    iterations (which grow about as the grid side N), so N^4, doubled for
+    FP64 vectors."""
+    N = 16 * spec.n_cells
+    return float(N) ** 4 * (1.0 if spec.mixed else 2.0)
+
+
+def cost_class(spec: SessionSpec) -> int:
+    """Sessions within a factor of four of estimated cost share a class."""
+    return int(np.floor(np.log(step_cost(spec)) / np.log(4.0)))
+
+
 class Server:
     """Continuous-batching scheduler over a backend (see module docstring)."""
 
     def __init__(self, backend, specs: Sequence[SessionSpec], hbm_budget: int,
                  max_batch: int = 64, clock: Callable[[], float] = time.perf_counter,
-                 sleep: Callable[[float], None] = time.sleep):
+                 sleep: Callable[[float], None] = time.sleep, policy: str = "cost_class",
+                 max_wait_s: float = 0.25):
+        if policy not in ("cost_class", "fifo"):
+            raise ValueError(f"unknown policy {policy}")
         self.backend = backend
         self.slots = [_Slot(spec=s) for s in specs]
         self.budget = int(hbm_budget)
         self.max_batch = int(max_batch)
+        self.policy = policy
+        self.max_wait_s = float(max_wait_s)
+        self.klass = [cost_class(s) for s in specs]
         self.clock = clock
         self.sleep = sleep
         self.used = 0
@@ -223,6 +248,13 @@ class Server:
                     self.sleep(max(0.0, pending[0].arrival_s - (self.clock() - t0)))
                 continue
             queued = {sid for _, sid in ready}
+            if self.policy == "cost_class":
+                oldest_arrival, oldest = ready[0]
+                if now - oldest_arrival > self.max_wait_s:
+                    k = self.klass[oldest]
+                else:
+                    k = min(self.klass[sid] for _, sid in ready)
+                ready = [(a, sid) for a, sid in ready if self.klass[sid] == k]
             batch: List[int] = []
             for _, sid in ready:
                 if len(batch) >= self.max_batch:

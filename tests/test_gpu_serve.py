@@ -29,7 +29,9 @@ def test_served_sessions_equal_alone(gpu):
     be = serve.GpuBackend()
     sizes = [be.bytes_needed(s) for s in specs]
     budget = int(sum(sorted(sizes)[-3:]) * 1.01)     # at most ~3 resident at once
-    srv = serve.Server(be, specs, budget, max_batch=4)
+    # arrival-order batching: with this budget and stream it parks and
+    # restores sessions (the cost-class order is tested below)
+    srv = serve.Server(be, specs, budget, max_batch=4, policy="fifo")
     reqs = serve.poisson_requests(24, len(specs), rate_hz=400.0, seed=3)
     print(f"case: serve {len(specs)} sessions, {len(reqs)} requests, budget {budget}", flush=True)
     rep = srv.serve(reqs)
@@ -51,4 +53,30 @@ def test_served_sessions_equal_alone(gpu):
         alone.close()
         if sl.obj is None:
             run.close()
+    srv.close()
+
+
+def test_cost_class_served_sessions_equal_alone(gpu):
+    """Rounds of one cost class at a time: each session still ends exactly
+    where the same number of steps alone leaves it."""
+    from paper_2505_20418_amd import serve
+    specs = [serve.SessionSpec(2, 21, True, 1e-6), serve.SessionSpec(4, 22, False, 1e-10),
+             serve.SessionSpec(2, 23, False, 1e-10), serve.SessionSpec(3, 24, True, 1e-6)]
+    be = serve.GpuBackend()
+    srv = serve.Server(be, specs, 1 << 34, max_batch=8)
+    reqs = serve.poisson_requests(30, len(specs), rate_hz=500.0, seed=4)
+    print(f"case: cost-class serve {len(specs)} sessions, {len(reqs)} requests", flush=True)
+    rep = srv.serve(reqs)
+    assert rep["requests_completed"] == len(reqs)
+    assert set(rep["statuses"]) <= {0}
+    for sid, spec in enumerate(specs):
+        sl = srv.slots[sid]
+        if sl.steps == 0:
+            continue
+        alone = be.create(spec)
+        for _ in range(sl.steps):
+            alone.step()
+        assert torch.equal(sl.obj.pos, alone.pos), sid
+        assert torch.equal(sl.obj.vel, alone.vel), sid
+        alone.close()
     srv.close()

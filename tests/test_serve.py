@@ -120,3 +120,51 @@ def test_prefill_stops_at_budget():
     srv, be, clock = make(n=5, sizes=sizes, budget=100)
     assert srv.prefill() == 2
     assert srv.used == 80
+
+
+def make_mixed_sizes(policy, max_wait_s=0.25):
+    clock = FakeClock()
+    specs = [SessionSpec(n_cells=2, seed=0, mixed=True, tol=1e-6),
+             SessionSpec(n_cells=16, seed=1, mixed=False, tol=1e-10),
+             SessionSpec(n_cells=2, seed=2, mixed=True, tol=1e-6)]
+    sizes = {0: 10, 1: 10, 2: 10}
+
+    class CostBackend(FakeBackend):
+        """A round lasts as long as its most expensive member."""
+        def step(self, objs):
+            self.batches.append([o["sid"] for o in objs])
+            self.clock.t += max(0.001 if o["sid"] != 1 else 0.060 for o in objs)
+            for o in objs:
+                o["steps"] += 1
+            return [{"status": 0, "iters": 10} for _ in objs]
+
+    be = CostBackend(clock, sizes)
+    srv = Server(be, specs, 10 ** 9, clock=clock, sleep=clock.sleep, policy=policy,
+                 max_wait_s=max_wait_s)
+    return srv, be
+
+
+def test_cost_classes_keep_small_sessions_off_big_rounds():
+    srv, be = make_mixed_sizes("cost_class")
+    srv.serve([Request(0.0, 0), Request(0.0, 1), Request(0.0, 2)])
+    # the two 32^3 sessions go first, in their own round; the 256^3 one after
+    assert be.batches == [[0, 2], [1]]
+    c = {x.session: x for x in srv.completions}
+    assert c[0].latency_s == pytest.approx(0.001) and c[2].latency_s == pytest.approx(0.001)
+    assert c[1].latency_s == pytest.approx(0.061)
+    # the fifo policy puts all three in one 60 ms round
+    srv2, be2 = make_mixed_sizes("fifo")
+    srv2.serve([Request(0.0, 0), Request(0.0, 1), Request(0.0, 2)])
+    assert be2.batches == [[0, 1, 2]]
+    assert all(x.latency_s == pytest.approx(0.060) for x in srv2.completions)
+
+
+def test_cost_classes_do_not_starve_the_expensive_class():
+    """A steady stream of small requests would always win the cheapest-class
+    rule; once the big request has waited max_wait_s its class goes next."""
+    srv, be = make_mixed_sizes("cost_class", max_wait_s=0.01)
+    reqs = [Request(0.0, 1)] + [Request(0.0005 * k, 0 if k % 2 else 2) for k in range(60)]
+    srv.serve(reqs)
+    big = [x for x in srv.completions if x.session == 1][0]
+    assert big.latency_s <= 0.01 + 0.002 + 0.060 + 1e-9
+    assert srv.report(1.0)["requests_completed"] == len(reqs)
