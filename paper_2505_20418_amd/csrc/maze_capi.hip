@@ -137,7 +137,8 @@ static SweepGeom choose_sweep(int N) {
 }
 
 // Launch shapes the autotuner times: segments of 256, 512 or 1024 points
-// of the (y, z) plane, runs of 4 to 64 x planes, and the runs that make the
+// of the (y, z) plane, runs of 4 to 64 x planes (1 and 2 as well on grids up
+// to 96^3), and the runs that make the
 // workgroup count k times the device's CU count (k = 1..8), since a launch
 // whose last round of workgroups only partly fills the CUs leaves them idle
 // for that round. Shapes whose halo slots or LDS do not fit a kernel
@@ -150,6 +151,12 @@ static std::vector<SweepGeom> sweep_candidates(int N, bool fp32, int cus) {
     if (ppt > 1 && kThreads * ppt / 2 >= P) continue;  // segment longer than a plane
     const int nseg = (P + kThreads * ppt - 1) / (kThreads * ppt);
     std::vector<int> cxs = {4, 8, 16, 32, 64};
+    // small grids are bound by the latency of a workgroup's serial plane
+    // steps (run + 2), not by bandwidth: shorter runs, more workgroups
+    if (N <= 96) {
+      cxs.push_back(1);
+      cxs.push_back(2);
+    }
     for (int k = 1; k <= 8 && cus > 0; ++k) {
       const int nchunk = (k * cus + nseg - 1) / nseg;
       if (nchunk >= 1 && nchunk <= N) cxs.push_back((N + nchunk - 1) / nchunk);
