@@ -72,7 +72,8 @@ def test_requests_arriving_during_a_round_join_the_next():
     srv, be, clock = make()
     reqs = [Request(0.0, 0), Request(0.0, 1), Request(0.005, 2), Request(0.006, 3)]
     rep = srv.serve(reqs)
-    # round 1 holds what arrived at t=0; the two later arrivals form round 2
+    # the first scheduling round holds what arrived at t=0; the two later
+    # arrivals form the second
     assert be.batches == [[0, 1], [2, 3]]
     assert rep["requests_completed"] == 4
     c = {x.session: x for x in srv.completions}
