@@ -1,0 +1,67 @@
+"""The largest grid the library accepts: 1024^3 (2^30 points, 8 GiB per FP64
+vector, about 82 GB of session state) with 2,097,152 ions.
+
+Every index past 2^31 bytes and every launch of a million workgroups is
+exercised. The solve is capped at a few iterations (a converged 1024^3
+solve takes thousands), so the checks are those that hold for any field
+the step returns:
+* the assigned charge grid equals the oracle's assignment (full grid) and
+  sums to zero;
+* the forces on sampled ions equal the oracle's interpolation of the
+  GPU's own field;
+* the electrostatic energy equals 1/2 k sum(phi q) of that field;
+* the field has zero mean and the reported residual is finite.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+from paper_2505_20418_amd import inputs  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def maze():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2505_20418_amd import maze as m
+    m.lib()
+    return m
+
+
+def test_max_grid_1024(maze, monkeypatch):
+    s = inputs.molten_nacl(64, seed=64)
+    assert s.n_ions == 2 ** 21
+    monkeypatch.setenv("MAZE_AUTOTUNE", "0")
+    print(f"case: max grid 1024^3, {s.n_ions} ions", flush=True)
+    Q = torch.tensor(s.charges, dtype=torch.float64, device="cuda")
+    g = maze.Session(Q, torch.tensor(s.pos, dtype=torch.float64, device="cuda"), s.box,
+                     s.grid_spacing, tol=1e-12, max_iter=24, coulomb_k=inputs.COULOMB_K_EV_A)
+    assert g.N == 1024
+    p = s.pos + s.vel
+    out = g.step(torch.tensor(p, dtype=torch.float64, device="cuda"), want_field=True)
+    st = out["stats"]
+    print(f"step status {out['status']} iters {st['iters']} rel_residual {st['rel_residual']:.3e}",
+          flush=True)
+    assert out["status"] == maze.MAZE_NOT_CONVERGED and 0 < st["iters"] <= 24
+    assert np.isfinite(st["rel_residual"]) and 0 < st["rel_residual"] < 1
+    q_gpu = g.grid(maze.GRID_Q).cpu().numpy()
+    q_ref = oracle.spread(p, s.charges, s.box, 1024)
+    assert np.abs(q_gpu - q_ref).max() <= 1e-13
+    assert abs(q_gpu.sum()) <= 1e-9
+    del q_gpu
+    phi = out["field"].cpu().numpy()
+    del out["field"]
+    torch.cuda.empty_cache()
+    assert abs(phi.mean()) <= 1e-13 * np.abs(phi).max()
+    rng = np.random.default_rng(0)
+    idx = rng.choice(s.n_ions, 20000, replace=False)
+    F_ref = oracle.gather(p[idx], s.charges[idx], s.box, phi, coulomb_k=inputs.COULOMB_K_EV_A)
+    F = out["forces"].cpu().numpy()[idx]
+    assert np.linalg.norm(F - F_ref) <= 1e-13 * np.linalg.norm(F_ref)
+    e_ref = oracle.energy(phi, q_ref, inputs.COULOMB_K_EV_A)
+    assert abs(out["energy"].item() - e_ref) <= 1e-11 * abs(e_ref)
+    g.close()
