@@ -107,3 +107,29 @@ int main(void) {
         if "." in key:
             t, m = key.split(".")
             assert getattr(getattr(maze, t), m).offset == int(val), key
+
+
+@needs_lib
+def test_empty_and_degenerate_inputs_on_host():
+    """Cases the entry points settle before any device work: no ions is
+    refused at admission; zero or one ion gives no pairs to histogram and no
+    noise to draw; malformed observable arguments are refused."""
+    from paper_2505_20418_amd import maze
+    L = maze.lib()
+    empty = maze.maze_config(0, 2, 25.6, 0.4, 1e-9, 10, 0, 0, 0, 1.0, None)
+    assert L.maze_device_bytes(ctypes.byref(empty)) == 0
+    dummy = ctypes.c_void_p(0x1000)  # never dereferenced on these paths
+    assert L.maze_rdf_accumulate(None, None, 0, 10.0, dummy, 10, dummy, None) == maze.MAZE_OK
+    assert L.maze_rdf_accumulate(dummy, dummy, 1, 10.0, dummy, 10, dummy, None) == maze.MAZE_OK
+    assert L.maze_rdf_accumulate(dummy, dummy, 5, 10.0, dummy, 0, dummy, None) == maze.MAZE_E_INVALID
+    assert L.maze_rdf_accumulate(dummy, dummy, 5, 10.0, dummy, 5000, dummy, None) == maze.MAZE_E_INVALID
+    assert L.maze_rdf_accumulate(dummy, dummy, 5, -1.0, dummy, 10, dummy, None) == maze.MAZE_E_INVALID
+    assert L.maze_langevin_noise(1, 0, 0, 0, None, None) == maze.MAZE_OK
+    assert L.maze_langevin_noise(1, 0, 2, 4, dummy, None) == maze.MAZE_E_INVALID
+    assert L.maze_langevin_noise(1, -1, 0, 4, dummy, None) == maze.MAZE_E_INVALID
+    h = ctypes.c_void_p()
+    assert L.maze_tcf_create(0, dummy, 10, 1, None, ctypes.byref(h)) == maze.MAZE_E_INVALID
+    assert L.maze_tcf_create(4, dummy, 10, 0, None, ctypes.byref(h)) == maze.MAZE_E_INVALID
+    assert not h.value
+    assert L.maze_tcf_sample(None, dummy, dummy) == maze.MAZE_E_INVALID
+    L.maze_tcf_destroy(None)
