@@ -27,36 +27,59 @@ namespace maze {
 
 __device__ __forceinline__ int wrapi(int v, int N) { return v < 0 ? v + N : (v >= N ? v - N : v); }
 
+template <typename T> struct Pair;
+template <> struct Pair<float> { using type = float2; };
+template <> struct Pair<double> { using type = double2; };
+
 // Red-black Gauss-Seidel half-sweep: points with (i + j + k) % 2 == color
 // get x = (b / c + sum of neighbours) / 6. zero: x starts at zero, so the
 // red points take b / (6 c) and the black points are cleared.
+// Each thread takes two z-neighbours (k even, k + 1; N is even on every
+// smoothed level), one of each colour: it updates the one of `color` and
+// stores the pair whole, the other point with the value it read. Every
+// thread does one update and every store covers whole cache lines; the
+// point of the other colour is not changed by this half-sweep, so writing
+// it back is harmless to the threads that read it as a neighbour.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_mg_smooth(T* __restrict__ x,
                                                         const T* __restrict__ b, int N,
                                                         T inv_c, int color, int zero,
                                                         const Scalars* sc) {
+  using T2 = typename Pair<T>::type;
   if (ctl_ld(&sc->done) != 0) return;
-  const long long G = (long long)N * N * N;
-  const long long g = (long long)blockIdx.x * kThreads + threadIdx.x;
-  if (g >= G) return;
-  const int k = (int)(g % N);
-  const int j = (int)((g / N) % N);
-  const int i = (int)(g / ((long long)N * N));
-  const bool mine = ((i + j + k) & 1) == color;
+  const long long G2 = (long long)N * N * N / 2;
+  const long long m = (long long)blockIdx.x * kThreads + threadIdx.x;
+  if (m >= G2) return;
+  const long long g0 = 2 * m;
+  const int k0 = (int)(g0 % N);
+  const int j = (int)((g0 / N) % N);
+  const int i = (int)(g0 / ((long long)N * N));
+  const int d = (((i + j + k0) & 1) == color) ? 0 : 1;  // the point of `color`
   const T s6 = (T)(1.0 / 6.0);
+  const T2 bp = *reinterpret_cast<const T2*>(b + g0);
   if (zero) {
-    x[g] = mine ? b[g] * inv_c * s6 : (T)0;
+    T2 o;
+    o.x = (d == 0) ? bp.x * inv_c * s6 : (T)0;
+    o.y = (d == 1) ? bp.y * inv_c * s6 : (T)0;
+    *reinterpret_cast<T2*>(x + g0) = o;
     return;
   }
-  if (!mine) return;
+  T2 xp = *reinterpret_cast<const T2*>(x + g0);
+  const int k = k0 + d;
   const long long NN = (long long)N * N;
   const long long bi = (long long)i * NN, bj = (long long)j * N;
+  const T zm = (d == 0) ? x[bi + bj + wrapi(k0 - 1, N)] : xp.x;
+  const T zp = (d == 0) ? xp.y : x[bi + bj + wrapi(k0 + 2, N)];
   const T nb = (x[(long long)wrapi(i - 1, N) * NN + bj + k] +
                 x[(long long)wrapi(i + 1, N) * NN + bj + k]) +
                (x[bi + (long long)wrapi(j - 1, N) * N + k] +
                 x[bi + (long long)wrapi(j + 1, N) * N + k]) +
-               (x[bi + bj + wrapi(k - 1, N)] + x[bi + bj + wrapi(k + 1, N)]);
-  x[g] = (b[g] * inv_c + nb) * s6;
+               (zm + zp);
+  const T bk = (d == 0) ? bp.x : bp.y;
+  const T v = (bk * inv_c + nb) * s6;
+  if (d == 0) xp.x = v;
+  else xp.y = v;
+  *reinterpret_cast<T2*>(x + g0) = xp;
 }
 
 // r = b - c (6 x - sum of neighbours)
@@ -260,9 +283,9 @@ static hipError_t vcycle_t(const DeviceState& d, const MgHierarchy& m, const dou
   for (int l = 0; l + 1 < L; ++l) {
     const int N = m.N[l];
     const double c = m.c[l];
-    hipLaunchKernelGGL(k_mg_smooth<T>, dim3(nblk(m.G[l])), dim3(kThreads), 0, st, xl(l), bl(l),
+    hipLaunchKernelGGL(k_mg_smooth<T>, dim3(nblk(m.G[l] / 2)), dim3(kThreads), 0, st, xl(l), bl(l),
                        N, (T)(1.0 / c), 0, 1, sc);
-    hipLaunchKernelGGL(k_mg_smooth<T>, dim3(nblk(m.G[l])), dim3(kThreads), 0, st, xl(l), bl(l),
+    hipLaunchKernelGGL(k_mg_smooth<T>, dim3(nblk(m.G[l] / 2)), dim3(kThreads), 0, st, xl(l), bl(l),
                        N, (T)(1.0 / c), 1, 0, sc);
     hipLaunchKernelGGL(k_mg_residual<T>, dim3(nblk(m.G[l])), dim3(kThreads), 0, st,
                        (const T*)xl(l), bl(l), R[l], N, (T)c, sc);
@@ -277,9 +300,9 @@ static hipError_t vcycle_t(const DeviceState& d, const MgHierarchy& m, const dou
     const double c = m.c[l];
     hipLaunchKernelGGL(k_mg_prolong<T>, dim3(nblk(m.G[l])), dim3(kThreads), 0, st, xl(l),
                        (const T*)xl(l + 1), N, sc);
-    hipLaunchKernelGGL(k_mg_smooth<T>, dim3(nblk(m.G[l])), dim3(kThreads), 0, st, xl(l), bl(l),
+    hipLaunchKernelGGL(k_mg_smooth<T>, dim3(nblk(m.G[l] / 2)), dim3(kThreads), 0, st, xl(l), bl(l),
                        N, (T)(1.0 / c), 1, 0, sc);
-    hipLaunchKernelGGL(k_mg_smooth<T>, dim3(nblk(m.G[l])), dim3(kThreads), 0, st, xl(l), bl(l),
+    hipLaunchKernelGGL(k_mg_smooth<T>, dim3(nblk(m.G[l] / 2)), dim3(kThreads), 0, st, xl(l), bl(l),
                        N, (T)(1.0 / c), 0, 0, sc);
   }
   return hipGetLastError();
