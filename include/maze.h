@@ -78,7 +78,18 @@ enum {
      kernels and arguments, so results are bitwise those without it. Needs a non-null cfg.stream (MAZE_E_INVALID otherwise);
      single-session solves only (batched and multigrid solves launch
      directly); ignored while maze_profile_enable is on. */
-  MAZE_FLAG_GRAPH_CHUNKS = 8
+  MAZE_FLAG_GRAPH_CHUNKS = 8,
+  /* run the Jacobi PLCG two iterations per pass pair: the s-step CG (s = 2)
+     of Chronopoulos and Gear, whose iterates equal those of the PLCG of
+     Appendix B in exact arithmetic. A basis kernel forms
+     [p, Bp, B^2 p, r/6, B r/6] (B = A/6 - I) and its 15 Gram sums; an
+     update kernel applies two iterations' coefficients. 32 bytes per point
+     per two iterations in FP32 (64 in FP64), against 48 (96). The test on
+     the residual after the first of the two iterations uses its Gram form;
+     with MAZE_NORM_ABSMAX the test runs every two iterations. Not with
+     MAZE_FLAG_MULTIGRID (MAZE_E_INVALID). A batch holding such a session
+     solves its sessions one after another. */
+  MAZE_FLAG_SSTEP = 16
 };
 
 typedef struct {
@@ -217,6 +228,9 @@ int maze_load(maze_session* s, const void* host_buf, size_t bytes);
  * memory):
  *   {FP64 sweeps timed, their total ms, FP32 sweeps timed, their total ms,
  *    FP64 CG iterations, FP32 CG iterations, 0, 0}
+ * With MAZE_FLAG_SSTEP the timed unit is one outer step of two iterations
+ * (basis and update kernel), and the last two entries hold the total ms of
+ * the update kernels of the timed FP64 and FP32 outer steps.
  * and resets them. Enabling creates the events (the only allocation outside
  * maze_init). */
 int maze_profile_enable(maze_session* s, int on);

@@ -534,6 +534,7 @@ __global__ __launch_bounds__(kThreads) void k_finalize(int mode, int count, long
       ctl_st(&sc->true_max, tmx);
       ctl_st(&sc->itp[0], 0);
       ctl_st(&sc->itp[1], 0);
+      ctl_st(&sc->pend, 0);
       ctl_st(&sc->done, 0);
       ctl_st(&sc->iters, 0);
     }
@@ -559,6 +560,7 @@ __global__ __launch_bounds__(kThreads) void k_finalize(int mode, int count, long
       ctl_st(&sc->max_iter, imax);
       ctl_st(&sc->itp[0], 0);
       ctl_st(&sc->itp[1], 0);
+      ctl_st(&sc->pend, 0);
       ctl_st(&sc->done, 0);
       ctl_st(&sc->iters, 0);
     }

@@ -1,0 +1,571 @@
+// Two-iteration (s = 2) form of the Jacobi PLCG solve of M y = sigma_p
+// (Appendix B; equation "SHAKEy") and of the direct Poisson solve (equation
+// "linearproblem"): the s-step conjugate gradient of Chronopoulos and Gear
+// (1989) in the basis form of Hoemmen (2010) and Carson (2015).
+//
+// With A = -M and the preconditioner diag(A) = 6 I, PCG takes the iterates
+// of plain CG on Ahat = A / 6 = I + B, B = -(sum of the six neighbours) / 6,
+// with residual rhat = r / 6. Every eigenvalue of Ahat lies in [0, 2], so B
+// maps into [-1, 1] and the basis below stays well scaled. Two CG
+// iterations starting from (x, r, p) stay in the span of
+//
+//   Y = [p, B p, B^2 p, rhat, B rhat]
+//
+// and, writing a vector of that span as Y v, Ahat (Y v) = Y (v + S v) for
+// every v with v_2 = v_4 = 0, where S shifts (v0, v1, v3) into (v1, v2, v4).
+// One outer step therefore needs the Gram matrix Y^T Y (15 sums) and no
+// other grid-wide reduction:
+//
+//   basis kernel:  Y at every point from r and p (B^2 p needs p two points
+//                  away), the 15 Gram sums and max |r| per workgroup;
+//   update kernel: the sums, then two CG iterations on 5-vectors (alpha,
+//                  beta from v^T G w), then x += Y cx, r = 6 Y cr, p = Y cp
+//                  at every point, with Y recomputed from the same r and p.
+//
+// In exact arithmetic the iterates are those of the one-iteration sweep
+// and of Hestenes-Stiefel PCG. Per point the pair reads r and p (basis) and
+// x, r, p (update) and writes x, r and p: 32 bytes per two iterations in
+// FP32 and 64 in FP64, against 48 and 96 for two single-iteration sweeps.
+//
+// Stopping: the residual norm at the start of an outer step is the direct
+// one (rhat^T rhat and max |r| from the basis kernel); after the first
+// inner iteration it is the Gram form v^T G v. A solve that converges, or
+// reaches its iteration cap, after one inner iteration applies that one
+// and leaves a pending code that the next basis kernel turns into `done`.
+// With the max-norm test only the direct values exist, so the test runs
+// every two iterations.
+//
+// Layout and marching are those of the fused sweep: a workgroup owns a
+// segment of S = 256*PPT points of the (y, z) plane and a run of x planes
+// and walks them in x order. Stage U at plane u forms B p on the segment
+// plus one row each side from p staged in LDS with two rows each side;
+// stage W at plane u-1 forms B^2 p and B rhat on the segment and either
+// accumulates the Gram sums or writes the updated vectors. r and p are
+// double-buffered by outer-step parity; x is updated in place.
+#include "device_util.h"
+
+namespace maze {
+
+namespace {
+
+constexpr int kNs = 16;  // Gram sums (15) and max |r|
+
+// Gram index of the pair (a, b), a <= b, of the five basis vectors.
+__host__ __device__ constexpr int gidx(int a, int b) {
+  return a * 5 - a * (a - 1) / 2 + (b - a);
+}
+
+__device__ __forceinline__ int wrap_pl(int u, int N) {
+  return u < 0 ? u + N : (u >= N ? u - N : u);
+}
+
+// Plane p of a grid as a buffer resource (32-bit per-lane byte offsets,
+// reads past the plane return zero); the plane index is made uniform.
+template <typename T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t pl_rsrc(const T* g, int p, size_t Ps) {
+  const T* base = g + (size_t)__builtin_amdgcn_readfirstlane(p) * Ps;
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(base), 0, (int)(Ps * sizeof(T)),
+                                           0x00020000);
+}
+template <typename T>
+__device__ __forceinline__ T ld(__amdgpu_buffer_rsrc_t r, uint32_t boff) {
+  if constexpr (sizeof(T) == 4)
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, boff, 0, 0));
+  else
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, boff, 0, 0));
+}
+template <typename T>
+__device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, uint32_t boff, T v) {
+  if constexpr (sizeof(T) == 4)
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, boff, 0, 0);
+  else
+    __builtin_amdgcn_raw_buffer_store_b64(
+        __builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned int, v), r, boff, 0, 0);
+}
+
+// kNs per-thread values (the last a max) reduced over the workgroup in a
+// fixed order; every thread receives the results. sm: kNs * 4 doubles.
+__device__ __forceinline__ void block_reduce_ns(double v[kNs], double* sm) {
+#pragma unroll
+  for (int i = 0; i < kNs; ++i) v[i] = (i == kNs - 1) ? wave_max(v[i]) : wave_sum(v[i]);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int i = 0; i < kNs; ++i) sm[i * (kThreads / 64) + w] = v[i];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < kNs; ++i) {
+    double s = sm[i * (kThreads / 64)];
+#pragma unroll
+    for (int k = 1; k < kThreads / 64; ++k)
+      s = (i == kNs - 1) ? fmax(s, sm[i * (kThreads / 64) + k]) : s + sm[i * (kThreads / 64) + k];
+    v[i] = s;
+  }
+}
+
+// v^T G w for 5-vectors, G symmetric from its 15 upper entries.
+__device__ __forceinline__ double gform(const double* g, const double* v, const double* w) {
+  double s = 0.0;
+#pragma unroll
+  for (int a = 0; a < 5; ++a)
+#pragma unroll
+    for (int b = 0; b < 5; ++b) s += v[a] * g[a <= b ? gidx(a, b) : gidx(b, a)] * w[b];
+  return s;
+}
+
+// Ahat v = v + S v for v_2 = v_4 = 0.
+__device__ __forceinline__ void ahat(const double* v, double* o) {
+  o[0] = v[0];
+  o[1] = v[1] + v[0];
+  o[2] = v[1];
+  o[3] = v[3];
+  o[4] = v[3];
+}
+
+}  // namespace
+
+// The work of one workgroup (logical index L) of a basis (UPDATE = false)
+// or update (UPDATE = true) kernel of outer step parity `par`. FIRST: the
+// first outer step of a solve, p = r / 6 (p is not read).
+template <typename T, bool FIRST, bool UPDATE, int PPT, int NH>
+__device__ __forceinline__ void sstep_wg(const SweepArgs<T>& a, const SweepGeom& g, int par,
+                                         int L, unsigned char* smem_raw, double* red) {
+  Scalars* sc = a.sc;
+  if (ctl_ld(&sc->done) != 0 || ctl_ld(&sc->err) != 0) return;
+  const int tid = threadIdx.x;
+  const bool leader = (L == 0) && (tid == 0);
+  const T* r_in = par ? a.r[1] : a.r[0];
+  T* r_out = par ? a.r[0] : a.r[1];
+  const T* p_in = FIRST ? r_in : (par ? a.p[1] : a.p[0]);
+  T* p_out = par ? a.p[0] : a.p[1];
+  const T sp = FIRST ? (T)(1.0 / 6.0) : (T)1;  // p = sp * (value read)
+
+  // ---- basis kernel: a pending stop left by the update before -------------
+  if (!UPDATE && !FIRST) {
+    const int pend = ctl_ld(&sc->pend);
+    if (pend != 0) {
+      if (leader) {
+        ctl_st(&sc->iters, ctl_ld(&sc->itp[par]));
+        ctl_st(&sc->done, pend);
+      }
+      return;
+    }
+  }
+
+  // ---- update kernel: two CG iterations on the coordinates -----------------
+  T cx[5], cr[5], cp[5];
+  if (UPDATE) {
+    double v[kNs];
+#pragma unroll
+    for (int i = 0; i < kNs; ++i) v[i] = 0.0;
+    for (int i = tid; i < a.nprev_sweep; i += kThreads) {
+#pragma unroll
+      for (int c = 0; c < kNs - 1; ++c) v[c] += a.part[(size_t)(SL_SG0 + c) * a.pstride + i];
+      v[kNs - 1] = fmax(v[kNs - 1], a.part[(size_t)SL_SGMAX * a.pstride + i]);
+    }
+    block_reduce_ns(v, red);
+    const double* G = v;
+    const int it = ctl_ld(&sc->itp[par]);
+    const double thr = ctl_ld(&sc->thr);
+    const bool absmax = ctl_ld(&sc->norm) == MAZE_NORM_ABSMAX;
+    const int imax = ctl_ld(&sc->max_iter);
+    bool finite = true;
+#pragma unroll
+    for (int c = 0; c < kNs; ++c) finite = finite && isfinite(G[c]);
+    const double rr0 = G[gidx(3, 3)];
+    const double rn0 = 6.0 * sqrt(fmax(rr0, 0.0));
+    if (leader && it < a.hist_cap) a.hist[it] = rn0;
+    const bool conv0 = absmax ? (G[kNs - 1] <= thr) : (rn0 <= thr);
+    int code = 0;
+    if (conv0) code = 1;
+    else if (!finite) code = 2;
+    else if (it >= imax) code = 3;
+    double xv[5] = {0, 0, 0, 0, 0}, rv[5] = {0, 0, 0, 1, 0}, pv[5] = {1, 0, 0, 0, 0};
+    double ap[5];
+    if (code == 0) {
+      ahat(pv, ap);
+      const double mu = gform(G, pv, ap);
+      if (!(mu > 0.0) || !isfinite(mu)) code = 2;
+      else {
+        const double al = rr0 / mu;
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+          xv[c] += al * pv[c];
+          rv[c] -= al * ap[c];
+        }
+      }
+    }
+    int pend = 0, nsteps = 1;
+    if (code != 0) {
+      // no update in this outer step. A first step that starts x from zero
+      // still has to write x = 0: it runs with zero coefficients for x (r
+      // and p copied) and leaves the stop pending, so that no workgroup of
+      // this launch skips its points on seeing `done`.
+      if (!(FIRST && a.zero_x)) {
+        if (leader) {
+          ctl_st(&sc->iters, it);
+          ctl_st(&sc->done, code);
+        }
+        return;
+      }
+#pragma unroll
+      for (int c = 0; c < 5; ++c) xv[c] = rv[c] = pv[c] = 0.0;
+      rv[3] = 1.0;
+      pv[0] = 1.0;
+      pend = code;
+      nsteps = 0;
+    }
+    // first inner iteration done (unless stopped above)
+    const double rr1 = fmax(gform(G, rv, rv), 0.0);
+    const double rn1 = 6.0 * sqrt(rr1);
+    if (pend == 0 && leader && it + 1 < a.hist_cap) a.hist[it + 1] = rn1;
+    if (pend == 0) {
+      if (!absmax && rn1 <= thr) pend = 1;
+      else if (it + 1 >= imax) pend = 3;
+    }
+    if (nsteps == 1) {
+      const double b1 = rr1 / rr0;
+#pragma unroll
+      for (int c = 0; c < 5; ++c) pv[c] = rv[c] + b1 * pv[c];
+    }
+    if (pend == 0) {
+      ahat(pv, ap);
+      const double mu = gform(G, pv, ap);
+      if (!(mu > 0.0) || !isfinite(mu)) pend = 2;
+      else {
+        const double al = rr1 / mu;
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+          xv[c] += al * pv[c];
+          rv[c] -= al * ap[c];
+        }
+        nsteps = 2;
+        const double rr2 = fmax(gform(G, rv, rv), 0.0);
+        const double b2 = rr2 / rr1;
+#pragma unroll
+        for (int c = 0; c < 5; ++c) pv[c] = rv[c] + b2 * pv[c];
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+      cx[c] = (T)xv[c];
+      cr[c] = (T)(6.0 * rv[c]);
+      cp[c] = (T)pv[c];
+    }
+    if (leader) {
+      ctl_st(&sc->itp[par ^ 1], it + nsteps);
+      if (pend != 0) ctl_st(&sc->pend, pend);
+    }
+  }
+
+  // ---- geometry of this workgroup -------------------------------------------
+  const int N = g.N, P = g.P, S = g.S;
+  const int seg = L % g.nseg, chunk = L / g.nseg;
+  const int s0 = seg * S;
+  const int x0 = chunk * g.cx, x1 = min(N, x0 + g.cx);
+  const int E1 = S + 4 * N, E2 = S + 2 * N;
+  T* P1 = reinterpret_cast<T*>(smem_raw);  // [2][E1] p of plane u (two rows each side)
+  T* Q2 = P1 + 2 * E1;                     // [2][E2] B p of plane u-1 / u
+  T* R2 = Q2 + 2 * E2;                     // [2][E2] r of plane u-1 / u
+  constexpr int NU = PPT + NH;             // stage-U slots: segment, then inner halo
+
+  int e1[NU], e1zm[NU], e1zp[NU], e2[NU];
+  bool uval[NU];
+  int e2zm[PPT], e2zp[PPT];
+  bool cval[PPT];
+  int e1o[NH];
+  bool oval[NH];
+  uint32_t bo[NU], boo[NH];
+#pragma unroll
+  for (int i = 0; i < NU; ++i) {
+    int f, ee2;
+    if (i < PPT) {
+      const int loc = tid + i * kThreads;
+      f = s0 + loc;
+      ee2 = N + loc;
+      uval[i] = true;
+      cval[i] = f < P;
+    } else {
+      const int h = tid + (i - PPT) * kThreads;
+      uval[i] = h < 2 * N;
+      const int hh = uval[i] ? h : 0;
+      ee2 = (hh < N) ? hh : S + hh;
+      f = s0 - N + ee2;
+    }
+    int o = f % P;
+    if (o < 0) o += P;
+    bo[i] = (uint32_t)o * (uint32_t)sizeof(T);
+    e2[i] = ee2;
+    e1[i] = ee2 + N;
+    const int z = o % N;
+    e1zm[i] = (z == 0) ? e1[i] + N - 1 : e1[i] - 1;
+    e1zp[i] = (z == N - 1) ? e1[i] - N + 1 : e1[i] + 1;
+    if (i < PPT) {
+      e2zm[i] = (z == 0) ? ee2 + N - 1 : ee2 - 1;
+      e2zp[i] = (z == N - 1) ? ee2 - N + 1 : ee2 + 1;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NH; ++k) {
+    const int h = tid + k * kThreads;
+    oval[k] = h < 2 * N;
+    const int hh = oval[k] ? h : 0;
+    e1o[k] = (hh < N) ? hh : S + 2 * N + hh;
+    int o = (s0 - 2 * N + e1o[k]) % P;
+    if (o < 0) o += P;
+    boo[k] = (uint32_t)o * (uint32_t)sizeof(T);
+  }
+
+  const T c6 = (T)(1.0 / 6.0);
+  const T c36 = (T)(1.0 / 36.0);
+  const size_t Ps = (size_t)P;
+  T pm[NU], pc[NU], pn[NU], pon[NH];  // p: planes u-1, u, u+1; outer halo of u+1
+  T rc[NU];                           // r at plane u
+  T rm1[PPT], rm2[PPT];               // r at planes u-1, u-2 (segment)
+  T bm[PPT], bc[PPT];                 // B p at planes u-2, u-1 (segment)
+  T xc[PPT];                          // x at plane u-1 (update)
+  double acc[kNs];
+#pragma unroll
+  for (int i = 0; i < kNs; ++i) acc[i] = 0.0;
+
+  // ---- prologue: planes x0-2 .. x0 of p, plane x0-1 of r --------------------
+  {
+    const auto r0 = pl_rsrc(r_in, wrap_pl(x0 - 1, N), Ps);
+    const auto pa = pl_rsrc(p_in, wrap_pl(x0 - 2, N), Ps);
+    const auto pb = pl_rsrc(p_in, wrap_pl(x0 - 1, N), Ps);
+    const auto pd = pl_rsrc(p_in, wrap_pl(x0, N), Ps);
+    T ob[NH];
+#pragma unroll
+    for (int i = 0; i < NU; ++i) {
+      rc[i] = ld<T>(r0, bo[i]);
+      pm[i] = sp * ld<T>(pa, bo[i]);
+      pc[i] = sp * ld<T>(pb, bo[i]);
+      pn[i] = sp * ld<T>(pd, bo[i]);
+    }
+#pragma unroll
+    for (int k = 0; k < NH; ++k) {
+      ob[k] = sp * ld<T>(pb, boo[k]);
+      pon[k] = sp * ld<T>(pd, boo[k]);
+    }
+#pragma unroll
+    for (int i = 0; i < NU; ++i)
+      if (uval[i]) P1[e1[i]] = pc[i];
+#pragma unroll
+    for (int k = 0; k < NH; ++k)
+      if (oval[k]) P1[e1o[k]] = ob[k];
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) rm1[j] = rm2[j] = bm[j] = bc[j] = xc[j] = (T)0;
+  }
+  __syncthreads();
+  __builtin_amdgcn_s_waitcnt(0);
+
+  const int nsteps = x1 - x0 + 2;  // stage U on planes x0-1 .. x1
+  for (int t = 0; t < nsteps; ++t) {
+    const int u = x0 - 1 + t;
+    const bool more = t + 1 < nsteps;
+    const bool own_u = (u >= x0) && (u < x1);
+    // issue the loads of the next step
+    T pf[NU], pof[NH], rf[NU], xf[PPT];
+    if (more) {
+      const auto rp = pl_rsrc(r_in, wrap_pl(u + 1, N), Ps);
+      const auto pp = pl_rsrc(p_in, wrap_pl(u + 2, N), Ps);
+#pragma unroll
+      for (int i = 0; i < NU; ++i) {
+        rf[i] = ld<T>(rp, bo[i]);
+        pf[i] = sp * ld<T>(pp, bo[i]);
+      }
+#pragma unroll
+      for (int k = 0; k < NH; ++k) pof[k] = sp * ld<T>(pp, boo[k]);
+      if (UPDATE && !a.zero_x && own_u) {
+        const auto xp = pl_rsrc((const T*)a.x, u, Ps);
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) xf[j] = ld<T>(xp, bo[j]);
+      }
+    }
+
+    // stage U at plane u: B p (segment + inner halo), r staged
+    const int tb = t & 1;
+    T* P1b = P1 + tb * E1;
+    T* Q2w = Q2 + tb * E2;
+    T* R2w = R2 + tb * E2;
+    T bk[PPT];
+#pragma unroll
+    for (int i = 0; i < NU; ++i) {
+      const T bp = -c6 * (((pm[i] + pn[i]) + (P1b[e1[i] - N] + P1b[e1[i] + N])) +
+                          (P1b[e1zm[i]] + P1b[e1zp[i]]));
+      if (uval[i]) {
+        Q2w[e2[i]] = bp;
+        R2w[e2[i]] = rc[i];
+      }
+      if (i < PPT) bk[i] = bp;
+    }
+
+    // stage W at plane u-1: B^2 p and B rhat on the segment
+    if (t >= 2) {
+      const T* Q2r = Q2 + (tb ^ 1) * E2;
+      const T* R2r = R2 + (tb ^ 1) * E2;
+      // plane u-1 lies in [x0, x1) here
+      const auto xo = pl_rsrc((const T*)a.x, u - 1, Ps);
+      const auto ro = pl_rsrc((const T*)r_out, u - 1, Ps);
+      const auto po = pl_rsrc((const T*)p_out, u - 1, Ps);
+#pragma unroll
+      for (int j = 0; j < PPT; ++j) {
+        const T y0 = pm[j];
+        const T y1 = bc[j];
+        const T y2 = -c6 * (((bm[j] + bk[j]) + (Q2r[e2[j] - N] + Q2r[e2[j] + N])) +
+                            (Q2r[e2zm[j]] + Q2r[e2zp[j]]));
+        const T y3 = c6 * rm1[j];
+        const T y4 = -c36 * (((rm2[j] + rc[j]) + (R2r[e2[j] - N] + R2r[e2[j] + N])) +
+                             (R2r[e2zm[j]] + R2r[e2zp[j]]));
+        if (!UPDATE) {
+          if (cval[j]) {
+            const double yd[5] = {(double)y0, (double)y1, (double)y2, (double)y3, (double)y4};
+#pragma unroll
+            for (int aa = 0; aa < 5; ++aa)
+#pragma unroll
+              for (int b = aa; b < 5; ++b) acc[gidx(aa, b)] += yd[aa] * yd[b];
+            acc[kNs - 1] = fmax(acc[kNs - 1], fabs((double)rm1[j]));
+          }
+        } else if (cval[j]) {
+          const T xn = xc[j] + ((cx[0] * y0 + cx[1] * y1) + (cx[2] * y2 + cx[3] * y3) + cx[4] * y4);
+          const T rn = (cr[0] * y0 + cr[1] * y1) + (cr[2] * y2 + cr[3] * y3) + cr[4] * y4;
+          const T pnw = (cp[0] * y0 + cp[1] * y1) + (cp[2] * y2 + cp[3] * y3) + cp[4] * y4;
+          st<T>(xo, bo[j], xn);
+          st<T>(ro, bo[j], rn);
+          st<T>(po, bo[j], pnw);
+        }
+      }
+    }
+
+    // stage p of plane u+1 for the next step
+    if (more) {
+      T* P1n = P1 + (tb ^ 1) * E1;
+#pragma unroll
+      for (int i = 0; i < NU; ++i)
+        if (uval[i]) P1n[e1[i]] = pn[i];
+#pragma unroll
+      for (int k = 0; k < NH; ++k)
+        if (oval[k]) P1n[e1o[k]] = pon[k];
+    }
+    __syncthreads();
+
+    // rotate
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+      bm[j] = bc[j];
+      bc[j] = bk[j];
+      rm2[j] = rm1[j];
+      rm1[j] = rc[j];
+    }
+    if (more) {
+#pragma unroll
+      for (int i = 0; i < NU; ++i) {
+        rc[i] = rf[i];
+        pm[i] = pc[i];
+        pc[i] = pn[i];
+        pn[i] = pf[i];
+      }
+#pragma unroll
+      for (int k = 0; k < NH; ++k) pon[k] = pof[k];
+      if (UPDATE) {
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) xc[j] = (a.zero_x || !own_u) ? (T)0 : xf[j];
+      }
+    }
+  }
+
+  if (!UPDATE) {
+    block_reduce_ns(acc, red);
+    if (tid == 0) {
+#pragma unroll
+      for (int c = 0; c < kNs - 1; ++c) a.part[(size_t)(SL_SG0 + c) * a.pstride + L] = acc[c];
+      a.part[(size_t)SL_SGMAX * a.pstride + L] = acc[kNs - 1];
+    }
+  }
+}
+
+template <typename T, bool FIRST, bool UPDATE, int PPT, int NH>
+__global__ __launch_bounds__(kThreads) void k_sstep(SweepArgs<T> a, SweepGeom g, int par) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ double red[kNs * (kThreads / 64)];
+  sstep_wg<T, FIRST, UPDATE, PPT, NH>(a, g, par, xcd_remap(blockIdx.x, g.nwg), smem_raw, red);
+}
+
+size_t sstep_lds_bytes(const SweepGeom& g, bool fp32) {
+  const size_t es = fp32 ? sizeof(float) : sizeof(double);
+  const size_t e1 = (size_t)g.S + 4 * (size_t)g.N, e2 = (size_t)g.S + 2 * (size_t)g.N;
+  return es * 2 * (e1 + 2 * e2);
+}
+
+namespace {
+
+template <typename T, bool FIRST, bool UPDATE, int PPT, int NH>
+hipError_t sstep_launch(const SweepArgs<T>& a, const SweepGeom& g, int par, hipStream_t st) {
+  static bool raised = false;
+  const size_t lds = sstep_lds_bytes(g, sizeof(T) == 4);
+  if (lds > 160 * 1024 - 1024) return hipErrorInvalidValue;
+  if (lds > 65536 && !raised) {
+    const hipError_t e =
+        hipFuncSetAttribute((const void*)k_sstep<T, FIRST, UPDATE, PPT, NH>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 1024);
+    if (e != hipSuccess) return e;
+    raised = true;
+  }
+  hipLaunchKernelGGL((k_sstep<T, FIRST, UPDATE, PPT, NH>), dim3(g.nwg), dim3(kThreads), lds, st,
+                     a, g, par);
+  return hipGetLastError();
+}
+
+template <typename T, bool FIRST, bool UPDATE, int PPT>
+hipError_t sstep_nh(const SweepArgs<T>& a, const SweepGeom& g, int par, hipStream_t st) {
+  switch (sweep_nh_class(g.nh)) {
+    case 1: return sstep_launch<T, FIRST, UPDATE, PPT, 1>(a, g, par, st);
+    case 2: return sstep_launch<T, FIRST, UPDATE, PPT, 2>(a, g, par, st);
+    case 4: return sstep_launch<T, FIRST, UPDATE, PPT, 4>(a, g, par, st);
+    case 8: return sstep_launch<T, FIRST, UPDATE, PPT, 8>(a, g, par, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename T, bool FIRST, bool UPDATE>
+hipError_t sstep_ppt(const SweepArgs<T>& a, const SweepGeom& g, int par, hipStream_t st) {
+  switch (g.ppt) {
+    case 1: return sstep_nh<T, FIRST, UPDATE, 1>(a, g, par, st);
+    case 2: return sstep_nh<T, FIRST, UPDATE, 2>(a, g, par, st);
+    case 4: return sstep_nh<T, FIRST, UPDATE, 4>(a, g, par, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename T>
+hipError_t sstep_half(const SweepArgs<T>& a, const SweepGeom& g, int o, bool update,
+                      hipStream_t st) {
+  const int par = o & 1;
+  if (o == 0)
+    return update ? sstep_ppt<T, true, true>(a, g, par, st) : sstep_ppt<T, true, false>(a, g, par, st);
+  return update ? sstep_ppt<T, false, true>(a, g, par, st) : sstep_ppt<T, false, false>(a, g, par, st);
+}
+
+}  // namespace
+
+hipError_t launch_sstep_half(const DeviceState& d, const SweepGeom& g, int o, void* x, bool fp32,
+                             bool zero_x, bool update, hipStream_t st) {
+  // one partial per workgroup and slot: the shape must fit the buffer's rows
+  if (g.nwg < 1 || g.nwg > d.part_stride || o < 0) return hipErrorInvalidValue;
+  const bool zx = zero_x && o == 0;
+  if (fp32) return sstep_half<float>(make_sweep_args<float>(d, (float*)x, 0, g.nwg, zx), g, o,
+                                     update, st);
+  return sstep_half<double>(make_sweep_args<double>(d, (double*)x, 0, g.nwg, zx), g, o, update,
+                            st);
+}
+
+hipError_t launch_sstep_outer(const DeviceState& d, const SweepGeom& g, int o, void* x,
+                              bool fp32, bool zero_x, hipStream_t st) {
+  const hipError_t e = launch_sstep_half(d, g, o, x, fp32, zero_x, false, st);
+  if (e != hipSuccess) return e;
+  return launch_sstep_half(d, g, o, x, fp32, zero_x, true, st);
+}
+
+}  // namespace maze

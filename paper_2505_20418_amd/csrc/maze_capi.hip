@@ -104,8 +104,9 @@ static int validate(const maze_config* c) {
   if (c->residual_norm != MAZE_NORM_REL2 && c->residual_norm != MAZE_NORM_ABSMAX)
     return MAZE_E_INVALID;
   const int32_t known = MAZE_FLAG_MULTIGRID | MAZE_FLAG_WEIGHT_GRADIENT_FORCE |
-                        MAZE_FLAG_ALLOW_NET_CHARGE | MAZE_FLAG_GRAPH_CHUNKS;
+                        MAZE_FLAG_ALLOW_NET_CHARGE | MAZE_FLAG_GRAPH_CHUNKS | MAZE_FLAG_SSTEP;
   if ((c->flags & ~known) != 0 || !finite_pos(c->coulomb_k)) return MAZE_E_INVALID;
+  if ((c->flags & MAZE_FLAG_SSTEP) && (c->flags & MAZE_FLAG_MULTIGRID)) return MAZE_E_INVALID;
   // the null stream cannot be captured
   if ((c->flags & MAZE_FLAG_GRAPH_CHUNKS) && c->stream == nullptr) return MAZE_E_INVALID;
   if (grid_of(c) == 0) return MAZE_E_INVALID;
@@ -234,7 +235,7 @@ static Layout layout_for(const maze_config* c, int N, int* ntx_out, int* ntiles_
   L.add(mixed ? 2 * gf : 0); // 8 r32 (two buffers)
   L.add(mixed ? 2 * gf : 0); // 9 p32 (two buffers)
   L.add(mixed ? gf : 0);     // 10 e32
-  L.add(sizeof(double) * (size_t)SL_COUNT * stride);  // 11 partials
+  L.add(sizeof(double) * (size_t)SL_COUNT * stride);  // partial-sum table
   L.add(sizeof(Scalars));    // 12 scalars
   L.add(sizeof(double) * n); // 13 Q
   L.add(sizeof(int32_t) * ntiles);        // 14 tile_count
@@ -277,16 +278,20 @@ static Layout layout_for(const maze_config* c, int N, int* ntx_out, int* ntiles_
 // test and the iteration cap itself (sweep k stops when k - 1 updates reach
 // max_iter), so the host only counts sweeps as a guard.
 // ---------------------------------------------------------------------------
-static void prof_collect(maze_session* s, int timed, int iters, bool fp32) {
+// units: sweeps (or two-iteration outer steps) that did work in the solve.
+static void prof_collect(maze_session* s, int timed, int units, int iters, bool fp32,
+                         bool sstep) {
   double* acc = s->prof_acc + (fp32 ? 2 : 0);
   for (int j = 0; j < timed; ++j) {
-    // sample j timed sweep k = 1 + j * kProfStride; sweeps past `iters`
+    // sample j timed unit k = 1 + j * kProfStride; units past `units`
     // returned without work and are not counted
-    if (1 + j * kProfStride > iters) break;
-    float ms = 0.f;
-    if (hipEventElapsedTime(&ms, s->pev[2 * j], s->pev[2 * j + 1]) == hipSuccess) {
+    if (1 + j * kProfStride > units) break;
+    float ms = 0.f, mu = 0.f;
+    if (hipEventElapsedTime(&ms, s->pev[3 * j], s->pev[3 * j + 2]) == hipSuccess &&
+        (!sstep || hipEventElapsedTime(&mu, s->pev[3 * j + 1], s->pev[3 * j + 2]) == hipSuccess)) {
       acc[0] += 1;
       acc[1] += ms;
+      s->prof_acc[fp32 ? 7 : 6] += mu;
     }
   }
   s->prof_acc[fp32 ? 5 : 4] += iters;
@@ -325,12 +330,23 @@ static long long sweep_guard(int max_iter, int first_batch) {
 // of a solve) on the session's stream into a graph. The sweeps' arguments
 // depend only on the session, the precision and the parity, so one graph
 // serves every later chunk of every solve.
+static bool sstep_of(const maze_session* s) { return (s->cfg.flags & MAZE_FLAG_SSTEP) != 0; }
+// CG units queued between polls: sweeps, or two-iteration outer steps.
+static int poll_units(const maze_session* s) { return sstep_of(s) ? kPollBatch / 2 : kPollBatch; }
+
+// Unit k of a solve: sweep k, or outer step k of the two-iteration form.
+static hipError_t launch_unit(maze_session* s, long long k, void* x, bool fp32, bool zero_x) {
+  const int kk = (int)(k & 0x7fffffff);
+  if (sstep_of(s)) return launch_sstep_outer(s->d, s->sweep, kk, x, fp32, zero_x, s->stream);
+  return launch_cg_sweep(s->d, s->sweep, kk, s->geom.nwg, x, fp32, zero_x, s->stream);
+}
+
 static int chunk_graph(maze_session* s, bool fp32, int par0, void* x, hipGraphExec_t* out) {
   hipGraph_t g = nullptr;
   HIP_TRY(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
   hipError_t e = hipSuccess;
-  for (int b = 0; b < kPollBatch && e == hipSuccess; ++b)
-    e = launch_cg_sweep(s->d, s->sweep, 2 + par0 + b, s->geom.nwg, x, fp32, false, s->stream);
+  for (int b = 0; b < poll_units(s) && e == hipSuccess; ++b)
+    e = launch_unit(s, 2 + par0 + b, x, fp32, false);
   const hipError_t e2 = hipStreamEndCapture(s->stream, &g);
   if (e != hipSuccess || e2 != hipSuccess || !g) {
     if (g) (void)hipGraphDestroy(g);
@@ -352,13 +368,17 @@ static int run_cg(CgJob& job, bool fp32, bool zero_x, int first_batch) {
   DeviceState& d = s->d;
   const SweepGeom& w = s->sweep;
   const long long guard = sweep_guard(job.max_iter, first_batch);
+  const bool ss = sstep_of(s);
+  const int per = poll_units(s);
+  // first_batch counts iterations; a two-iteration unit covers two
+  const int first_units = ss ? first_batch / 2 : first_batch;
   long long k = 0;
   int batch = 0, timed = 0;
   bool have_prev = false;
   const bool prof = s->prof;
   const bool graphs = (s->cfg.flags & MAZE_FLAG_GRAPH_CHUNKS) && !prof;
   for (;;) {
-    const int nb = (batch == 0) ? std::max(kPollBatch, first_batch) : kPollBatch;
+    const int nb = (batch == 0) ? std::max(per, first_units) : per;
     if (graphs && batch > 0) {
       const int f = fp32 ? 1 : 0, par = (int)(k & 1);
       maze_session::ChunkGraph* hit = nullptr;
@@ -380,11 +400,19 @@ static int run_cg(CgJob& job, bool fp32, bool zero_x, int first_batch) {
     }
     for (int b = 0; b < nb && !(graphs && batch > 0); ++b, ++k) {
       const bool timeit = prof && k >= 1 && (k - 1) % kProfStride == 0 && timed < kProfMax;
-      if (timeit) HIP_TRY(hipEventRecord(s->pev[2 * timed], s->stream));
-      HIP_TRY(launch_cg_sweep(d, w, (int)(k & 0x7fffffff), s->geom.nwg, job.x, fp32, zero_x,
-                              s->stream));
+      if (timeit) HIP_TRY(hipEventRecord(s->pev[3 * timed], s->stream));
+      if (ss && timeit) {
+        // basis and update kernels timed apart
+        const SweepGeom& g = w;
+        const int kk = (int)(k & 0x7fffffff);
+        HIP_TRY(launch_sstep_half(d, g, kk, job.x, fp32, zero_x, false, s->stream));
+        HIP_TRY(hipEventRecord(s->pev[3 * timed + 1], s->stream));
+        HIP_TRY(launch_sstep_half(d, g, kk, job.x, fp32, zero_x, true, s->stream));
+      } else {
+        HIP_TRY(launch_unit(s, k, job.x, fp32, zero_x));
+      }
       if (timeit) {
-        HIP_TRY(hipEventRecord(s->pev[2 * timed + 1], s->stream));
+        HIP_TRY(hipEventRecord(s->pev[3 * timed + 2], s->stream));
         ++timed;
       }
     }
@@ -404,7 +432,7 @@ static int run_cg(CgJob& job, bool fp32, bool zero_x, int first_batch) {
       if (h.done || last) {
         job.iters = h.iters;
         job.code = h.done ? h.done : 3;
-        if (prof) prof_collect(s, timed, h.iters, fp32);
+        if (prof) prof_collect(s, timed, ss ? (h.iters + 1) / 2 : h.iters, h.iters, fp32, ss);
         if (s->trace) return trace_collect(s, h.iters, h.qnorm);
         return MAZE_OK;
       }
@@ -522,6 +550,16 @@ static bool batch_throughput_mode(const std::vector<CgJob>& jobs) {
 static int run_cg_batch(std::vector<CgJob>& jobs, bool fp32, bool zero_x, int first_batch) {
   const int n = (int)jobs.size();
   if (n == 1) return run_cg(jobs[0], fp32, zero_x, first_batch);
+  // the two-iteration form has no batched kernels: such a batch is solved
+  // one session after another
+  for (const CgJob& j : jobs)
+    if (sstep_of(j.s)) {
+      for (CgJob& q : jobs) {
+        const int rc = run_cg(q, fp32, zero_x, first_batch);
+        if (rc != MAZE_OK) return rc;
+      }
+      return MAZE_OK;
+    }
   BatchTable* t = nullptr;
   int rc = ensure_table(jobs[0].s->device, n, &t);
   if (rc != MAZE_OK) return rc;
@@ -1386,7 +1424,7 @@ int maze_profile_enable(maze_session* s, int on) {
   if (!s) return MAZE_E_INVALID;
   hipSetDevice(s->device);
   if (on && s->pev.empty()) {
-    s->pev.assign(2 * kProfMax, nullptr);
+    s->pev.assign(3 * kProfMax, nullptr);
     for (auto& e : s->pev)
       if (hipEventCreate(&e) != hipSuccess) return MAZE_E_DEVICE;
   }

@@ -39,6 +39,8 @@ enum PartialSlot : int {
   SL_TMAX,         // true FP64 residual max
   SL_ENERGY,       // phi . (q - qbar)
   SL_PHISUM,       // sum of phi^{k+1}
+  SL_SG0,          // two-iteration CG: the 15 Gram sums of its basis
+  SL_SGMAX = SL_SG0 + 15,  // two-iteration CG: max |r|
   SL_COUNT
 };
 
@@ -65,7 +67,8 @@ struct alignas(64) Scalars {
   double energy;       // (1/2) k phi . q
   int32_t max_iter;
   int32_t norm;        // MAZE_NORM_*
-  int32_t pad_i;
+  int32_t pend;        // two-iteration CG: stop code left by an update that
+                       // ended the solve, turned into done by the next kernel
   double mg_rho;       // multigrid-preconditioned CG: <r, z>
   double mg_alpha;     // rho / <p, A p>
   double mg_beta;      // rho / rho of the previous iteration (0 first)
@@ -251,6 +254,15 @@ hipError_t launch_sweep(const SweepLaunch& L, bool fp32, bool first, hipStream_t
 // float* by fp32; zero_x: sweep 0 writes x = 0.
 hipError_t launch_cg_sweep(const DeviceState& d, const SweepGeom& g, int k, int nprev_first,
                            void* x, bool fp32, bool zero_x, hipStream_t st);
+// Outer step o of a two-iteration (s = 2) CG solve: its basis kernel and
+// its update kernel (o = 0: p_0 = r_0 / 6; zero_x then writes x from zero).
+// Same vectors, partial table and scalars as the sweeps above.
+hipError_t launch_sstep_outer(const DeviceState& d, const SweepGeom& g, int o, void* x,
+                              bool fp32, bool zero_x, hipStream_t st);
+// One of the two kernels of outer step o (update = false: the basis kernel).
+hipError_t launch_sstep_half(const DeviceState& d, const SweepGeom& g, int o, void* x, bool fp32,
+                             bool zero_x, bool update, hipStream_t st);
+size_t sstep_lds_bytes(const SweepGeom& g, bool fp32);
 // Fills x (G elements) with a fixed finite pattern.
 hipError_t launch_fill_pattern(void* x, long long G, bool fp32, hipStream_t st);
 // Batch helpers: {done, iters, err} of every session into out[3 * count];

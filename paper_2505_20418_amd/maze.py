@@ -24,6 +24,7 @@ MAZE_GUESS_ZERO, MAZE_GUESS_STATIC, MAZE_GUESS_TIMEPROP = 0, 1, 2
 MAZE_NORM_REL2, MAZE_NORM_ABSMAX = 0, 1
 MAZE_FLAG_MULTIGRID, MAZE_FLAG_WEIGHT_GRADIENT_FORCE, MAZE_FLAG_ALLOW_NET_CHARGE = 1, 2, 4
 MAZE_FLAG_GRAPH_CHUNKS = 8
+MAZE_FLAG_SSTEP = 16
 GRID_PHI, GRID_PHI_PREV, GRID_Y, GRID_Q, GRID_SIGMA = 0, 1, 2, 3, 4
 
 EXPORTED = ("maze_abi_version", "maze_strerror", "maze_device_bytes", "maze_init", "maze_step",
@@ -289,8 +290,11 @@ def maze_profile_read(handle) -> dict:
     out = (ctypes.c_double * 8)()
     _check(lib().maze_profile_read(handle, out), "maze_profile_read")
     v = list(out)
+    # with MAZE_FLAG_SSTEP a timed unit is a two-iteration outer step, and
+    # *_update_ms is the time of its update kernels
     return dict(fp64_sweep=(int(v[0]), v[1]), fp32_sweep=(int(v[2]), v[3]),
-                fp64_iters=int(v[4]), fp32_iters=int(v[5]))
+                fp64_iters=int(v[4]), fp32_iters=int(v[5]), fp64_update_ms=v[6],
+                fp32_update_ms=v[7])
 
 
 def maze_launch_shape(handle) -> dict:

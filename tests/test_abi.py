@@ -67,8 +67,14 @@ def test_host_only_entry_points():
     assert L.maze_device_bytes(ctypes.byref(mg)) > L.maze_device_bytes(ctypes.byref(ok))
     odd = maze.maze_config(4, 2, 40.4, 0.4, 1e-9, 10, 0, 0, maze.MAZE_FLAG_MULTIGRID, 1.0, None)
     assert L.maze_device_bytes(ctypes.byref(odd)) == 0
-    badflag = maze.maze_config(4, 2, 25.6, 0.4, 1e-9, 10, 0, 0, 16, 1.0, None)
+    badflag = maze.maze_config(4, 2, 25.6, 0.4, 1e-9, 10, 0, 0, 32, 1.0, None)
     assert L.maze_device_bytes(ctypes.byref(badflag)) == 0
+    # the two-iteration CG is accepted alone, not with the multigrid preconditioner
+    ss = maze.maze_config(4, 2, 25.6, 0.4, 1e-9, 10, 0, 0, maze.MAZE_FLAG_SSTEP, 1.0, None)
+    assert L.maze_device_bytes(ctypes.byref(ss)) == L.maze_device_bytes(ctypes.byref(ok))
+    ssmg = maze.maze_config(4, 2, 25.6, 0.4, 1e-9, 10, 0, 0,
+                            maze.MAZE_FLAG_SSTEP | maze.MAZE_FLAG_MULTIGRID, 1.0, None)
+    assert L.maze_device_bytes(ctypes.byref(ssmg)) == 0
     # graph chunks need a stream that can be captured (not the null stream)
     nostream = maze.maze_config(4, 2, 25.6, 0.4, 1e-9, 10, 0, 0, maze.MAZE_FLAG_GRAPH_CHUNKS,
                                 1.0, None)
