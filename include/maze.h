@@ -82,7 +82,7 @@ enum {
   /* run the Jacobi PLCG two iterations per pass pair: the s-step CG (s = 2)
      of Chronopoulos and Gear, whose iterates equal those of the PLCG of
      Appendix B in exact arithmetic. A basis kernel forms
-     [p, Bp, B^2 p, r/6, B r/6] (B = A/6 - I) and its 15 Gram sums; an
+     [p, Bp, B^2 p, r/6, B r/6] (B = A/6 - I) and its Gram sums; an
      update kernel applies two iterations' coefficients. 32 bytes per point
      per two iterations in FP32 (64 in FP64), against 48 (96). The test on
      the residual after the first of the two iterations uses its Gram form;

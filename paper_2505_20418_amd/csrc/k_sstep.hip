@@ -13,11 +13,12 @@
 //
 // and, writing a vector of that span as Y v, Ahat (Y v) = Y (v + S v) for
 // every v with v_2 = v_4 = 0, where S shifts (v0, v1, v3) into (v1, v2, v4).
-// One outer step therefore needs the Gram matrix Y^T Y (15 sums) and no
-// other grid-wide reduction:
+// One outer step therefore needs the Gram matrix Y^T Y and no other
+// grid-wide reduction:
 //
 //   basis kernel:  Y at every point from r and p (B^2 p needs p two points
-//                  away), the 15 Gram sums and max |r| per workgroup;
+//                  away), the Gram sums (as 12 moments) and max |r| per
+//                  workgroup;
 //   update kernel: the sums, then two CG iterations on 5-vectors (alpha,
 //                  beta from v^T G w), then x += Y cx, r = 6 Y cr, p = Y cp
 //                  at every point, with Y recomputed from the same r and p.
@@ -48,11 +49,22 @@ namespace maze {
 
 namespace {
 
-constexpr int kNs = 16;  // Gram sums (15) and max |r|
+// B is symmetric, so <B^a u, B^b v> depends on a + b only: the 15 Gram
+// entries of Y come from 12 moments, <p, B^k p> (k = 0..4), <p, B^k rhat>
+// (k = 0..3) and <rhat, B^k rhat> (k = 0..2), each summed as the product of
+// two basis vectors whose powers add up to k.
+constexpr int kNm = 12;       // moments
+constexpr int kNs = kNm + 1;  // and max |r|
 
 // Gram index of the pair (a, b), a <= b, of the five basis vectors.
 __host__ __device__ constexpr int gidx(int a, int b) {
   return a * 5 - a * (a - 1) / 2 + (b - a);
+}
+
+// Moment holding the Gram entry (a, b), a <= b: p-block indices 0..2,
+// rhat-block 3..4.
+__host__ __device__ constexpr int gmom(int a, int b) {
+  return b <= 2 ? a + b : (a <= 2 ? 5 + a + (b - 3) : 9 + (a - 3) + (b - 3));
 }
 
 __device__ __forceinline__ int wrap_pl(int u, int N) {
@@ -162,22 +174,26 @@ __device__ __forceinline__ void sstep_wg(const SweepArgs<T>& a, const SweepGeom&
     for (int i = 0; i < kNs; ++i) v[i] = 0.0;
     for (int i = tid; i < a.nprev_sweep; i += kThreads) {
 #pragma unroll
-      for (int c = 0; c < kNs - 1; ++c) v[c] += a.part[(size_t)(SL_SG0 + c) * a.pstride + i];
-      v[kNs - 1] = fmax(v[kNs - 1], a.part[(size_t)SL_SGMAX * a.pstride + i]);
+      for (int c = 0; c < kNm; ++c) v[c] += a.part[(size_t)(SL_SG0 + c) * a.pstride + i];
+      v[kNm] = fmax(v[kNm], a.part[(size_t)SL_SGMAX * a.pstride + i]);
     }
     block_reduce_ns(v, red);
-    const double* G = v;
+    double G[15];
+#pragma unroll
+    for (int aa = 0; aa < 5; ++aa)
+#pragma unroll
+      for (int b = aa; b < 5; ++b) G[gidx(aa, b)] = v[gmom(aa, b)];
     const int it = ctl_ld(&sc->itp[par]);
     const double thr = ctl_ld(&sc->thr);
     const bool absmax = ctl_ld(&sc->norm) == MAZE_NORM_ABSMAX;
     const int imax = ctl_ld(&sc->max_iter);
     bool finite = true;
 #pragma unroll
-    for (int c = 0; c < kNs; ++c) finite = finite && isfinite(G[c]);
+    for (int c = 0; c < kNs; ++c) finite = finite && isfinite(v[c]);
     const double rr0 = G[gidx(3, 3)];
     const double rn0 = 6.0 * sqrt(fmax(rr0, 0.0));
     if (leader && it < a.hist_cap) a.hist[it] = rn0;
-    const bool conv0 = absmax ? (G[kNs - 1] <= thr) : (rn0 <= thr);
+    const bool conv0 = absmax ? (v[kNm] <= thr) : (rn0 <= thr);
     int code = 0;
     if (conv0) code = 1;
     else if (!finite) code = 2;
@@ -362,6 +378,9 @@ __device__ __forceinline__ void sstep_wg(const SweepArgs<T>& a, const SweepGeom&
   __builtin_amdgcn_s_waitcnt(0);
 
   const int nsteps = x1 - x0 + 2;  // stage U on planes x0-1 .. x1
+  // unrolled six times (both LDS parities, all three positions of the plane
+  // windows), so the windows rotate by renaming instead of register moves
+#pragma unroll 6
   for (int t = 0; t < nsteps; ++t) {
     const int u = x0 - 1 + t;
     const bool more = t + 1 < nsteps;
@@ -421,12 +440,20 @@ __device__ __forceinline__ void sstep_wg(const SweepArgs<T>& a, const SweepGeom&
                              (R2r[e2zm[j]] + R2r[e2zp[j]]));
         if (!UPDATE) {
           if (cval[j]) {
-            const double yd[5] = {(double)y0, (double)y1, (double)y2, (double)y3, (double)y4};
-#pragma unroll
-            for (int aa = 0; aa < 5; ++aa)
-#pragma unroll
-              for (int b = aa; b < 5; ++b) acc[gidx(aa, b)] += yd[aa] * yd[b];
-            acc[kNs - 1] = fmax(acc[kNs - 1], fabs((double)rm1[j]));
+            const double d0 = y0, d1 = y1, d2 = y2, d3 = y3, d4 = y4;
+            acc[0] += d0 * d0;
+            acc[1] += d0 * d1;
+            acc[2] += d1 * d1;
+            acc[3] += d1 * d2;
+            acc[4] += d2 * d2;
+            acc[5] += d0 * d3;
+            acc[6] += d0 * d4;
+            acc[7] += d1 * d4;
+            acc[8] += d2 * d4;
+            acc[9] += d3 * d3;
+            acc[10] += d3 * d4;
+            acc[11] += d4 * d4;
+            acc[kNm] = fmax(acc[kNm], fabs((double)rm1[j]));
           }
         } else if (cval[j]) {
           const T xn = xc[j] + ((cx[0] * y0 + cx[1] * y1) + (cx[2] * y2 + cx[3] * y3) + cx[4] * y4);
@@ -480,8 +507,8 @@ __device__ __forceinline__ void sstep_wg(const SweepArgs<T>& a, const SweepGeom&
     block_reduce_ns(acc, red);
     if (tid == 0) {
 #pragma unroll
-      for (int c = 0; c < kNs - 1; ++c) a.part[(size_t)(SL_SG0 + c) * a.pstride + L] = acc[c];
-      a.part[(size_t)SL_SGMAX * a.pstride + L] = acc[kNs - 1];
+      for (int c = 0; c < kNm; ++c) a.part[(size_t)(SL_SG0 + c) * a.pstride + L] = acc[c];
+      a.part[(size_t)SL_SGMAX * a.pstride + L] = acc[kNm];
     }
   }
 }

@@ -39,8 +39,8 @@ enum PartialSlot : int {
   SL_TMAX,         // true FP64 residual max
   SL_ENERGY,       // phi . (q - qbar)
   SL_PHISUM,       // sum of phi^{k+1}
-  SL_SG0,          // two-iteration CG: the 15 Gram sums of its basis
-  SL_SGMAX = SL_SG0 + 15,  // two-iteration CG: max |r|
+  SL_SG0,          // two-iteration CG: the 12 Gram moments of its basis
+  SL_SGMAX = SL_SG0 + 12,  // two-iteration CG: max |r|
   SL_COUNT
 };
 
