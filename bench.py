@@ -11,11 +11,17 @@ refinement) is the headline value; the FP64 path runs side by side, and the
 mixed path's field, force and energy error against FP64 is reported on a
 replay of the FP64 trajectory.
 
-Prints ONE JSON line. `roofline` describes the dominant kernel, the fused
-CG sweep of the mixed path's FP32 inner solves (the FP64 sweep is in
-`roofline_fp64`), timed with HIP events that the library records around
-sampled sweeps on the stream they run on. `cpu_baseline` times the plain
-FP64 CPU oracle on a bounded sample of the same workload.
+The PLCG runs in its two-iteration (s-step, s = 2) form by default
+(`--cg sstep`): a basis kernel and an update kernel per two iterations.
+`--cg sweep` runs the one-iteration fused sweep instead; the default run
+also times that form on the same workload (`one_iteration_sweep`).
+
+Prints ONE JSON line. `roofline` describes the dominant kernel, the update
+kernel of the two-iteration CG in the mixed path's FP32 inner solves (the
+FP64 one is in `roofline_fp64`; each carries its basis kernel under
+`basis_kernel`), timed with HIP events that the library records around
+sampled outer steps on the stream they run on. `cpu_baseline` times the
+plain FP64 CPU oracle on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -33,19 +39,26 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_cg_sweep_nacl32768_g256.json")
-STENCIL_SRC = os.path.join(ROOT, "paper_2505_20418_amd", "csrc", "k_cg.hip")
-# algorithmic HBM bytes per grid point of one fused CG sweep: reads x, r, p
-# and writes x, r, p once (FP64: 8 B each, FP32: 4 B each)
+CSRC = os.path.join(ROOT, "paper_2505_20418_amd", "csrc")
+# committed counter summaries: HBM bytes per launch, with the hash of the
+# kernel source they were taken with
+TRAFFIC = {"sweep": (os.path.join(ROOT, "profiles", "traffic_cg_sweep_nacl32768_g256.json"),
+                     os.path.join(CSRC, "k_cg.hip")),
+           "sstep": (os.path.join(ROOT, "profiles", "traffic_sstep_nacl32768_g256.json"),
+                     os.path.join(CSRC, "k_sstep.hip"))}
+# algorithmic HBM bytes per grid point of one fused CG sweep, and of the
+# update kernel of the two-iteration form: read x, r, p and write x, r, p
+# once (FP64: 8 B each, FP32: 4 B each); the basis kernel reads r and p
 SWEEP_BYTES = {"fp64": 48, "fp32": 24}
+BASIS_BYTES = {"fp64": 16, "fp32": 8}
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def stencil_hash() -> str:
-    return hashlib.sha256(open(STENCIL_SRC, "rb").read()).hexdigest()[:16]
+def source_hash(path) -> str:
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
 
 
 def run_md(system, tol, precision, steps, warmup, record_positions=False, order=2, flags=0,
@@ -86,7 +99,7 @@ def run_md(system, tol, precision, steps, warmup, record_positions=False, order=
     return out
 
 
-def replay_errors(system, traj, tol, n_replay, every=1):
+def replay_errors(system, traj, tol, n_replay, every=1, flags=0):
     """Drive a fresh mixed session and a fresh FP64 session through the same
     recorded positions (both advance every step, so the warm starts match
     the run); errors of mixed against FP64 at every `every`-th step."""
@@ -97,9 +110,9 @@ def replay_errors(system, traj, tol, n_replay, every=1):
     Q = torch.tensor(system.charges, dtype=torch.float64, device=dev)
     p0 = torch.tensor(system.pos, dtype=torch.float64, device=dev)
     s64 = maze.Session(Q, p0, system.box, system.grid_spacing, tol=tol,
-                       precision=maze.MAZE_FP64, coulomb_k=inputs.COULOMB_K_EV_A)
+                       precision=maze.MAZE_FP64, coulomb_k=inputs.COULOMB_K_EV_A, flags=flags)
     s32 = maze.Session(Q, p0, system.box, system.grid_spacing, tol=tol,
-                       precision=maze.MAZE_MIXED, coulomb_k=inputs.COULOMB_K_EV_A)
+                       precision=maze.MAZE_MIXED, coulomb_k=inputs.COULOMB_K_EV_A, flags=flags)
     ef, eF, eE, at = [], [], [], []
     for k in range(min(n_replay, traj.shape[0])):
         want = (k + 1) % every == 0
@@ -120,17 +133,32 @@ def replay_errors(system, traj, tol, n_replay, every=1):
     return out
 
 
-def roofline(prof_key, prof, G, dtype_key, shape=None):
+def roofline(prof_key, prof, G, dtype_key, shape=None, sstep=False):
+    """Roofline of the dominant CG kernel from the library's event timings:
+    the fused sweep, or (sstep) the update kernel of the two-iteration form
+    with its basis kernel alongside."""
     n, ms = prof[prof_key]
     if n == 0:
         return None
-    avg_s = ms / n / 1e3
+    upd_ms = prof[f"{dtype_key}_update_ms"] if sstep else ms
+    avg_s = upd_ms / n / 1e3
     bpl = SWEEP_BYTES[dtype_key] * G
     achieved = bpl / avg_s / 1e9
+    kernel = f"k_sstep update ({dtype_key})" if sstep else f"k_cg_sweep ({dtype_key})"
     r = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
          "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-         "kernel": f"k_cg_sweep ({dtype_key})", "avg_launch_us": round(avg_s * 1e6, 2),
+         "kernel": kernel, "avg_launch_us": round(avg_s * 1e6, 2),
          "launches_timed": n, "algorithmic_bytes_per_launch": bpl}
+    if sstep:
+        b_s = (ms - upd_ms) / n / 1e3
+        bb = BASIS_BYTES[dtype_key] * G
+        r["basis_kernel"] = {"kernel": f"k_sstep basis ({dtype_key})",
+                             "avg_launch_us": round(b_s * 1e6, 2),
+                             "algorithmic_bytes_per_launch": bb,
+                             "achieved": round(bb / b_s / 1e9, 1),
+                             "frac": round(bb / b_s / 1e9 / HBM_PEAK_GBS, 4), "traffic": None}
+        r["outer_step_us"] = round(ms / n * 1e3, 2)
+        r["iterations_per_outer_step"] = 2
     if shape is not None:
         # the launch shape the session swept in; a kernel trace of this run
         # also holds the autotuner's timing sweeps in other shapes, which
@@ -155,23 +183,29 @@ def attach_ceilings(r, copy_gbps):
         r["counter_frac_of_copy"] = round(g / copy_gbps, 4)
 
 
-def attach_traffic(r, key):
+def attach_traffic(r, key, form="sweep"):
     """HBM bytes per launch from the committed counter summary, if it was
-    taken with the current sweep source and in the launch shape this run
-    swept in."""
-    if r is None or not os.path.exists(TRAFFIC_FILE):
+    taken with the current kernel source and in the launch shape this run
+    swept in (for the two-iteration form: key_update and key_basis)."""
+    path, src = TRAFFIC[form]
+    if r is None or not os.path.exists(path):
         return
     try:
-        t = json.load(open(TRAFFIC_FILE))
+        t = json.load(open(path))
     except Exception:
         return
-    if t.get("stencil_sha") != stencil_hash() or key not in t:
+    if t.get("stencil_sha") != source_hash(src):
         return
-    want = t[key].get("launch_shape")
     have = r.get("launch_shape")
-    if want is None or have is None or (want["ppt"], want["cx"]) != (have["ppt"], have["cx"]):
-        return
-    r["traffic"] = t[key]["hbm_bytes_per_launch"]
+    targets = [(r, key)] if form == "sweep" else [(r, f"{key}_update"),
+                                                  (r.get("basis_kernel"), f"{key}_basis")]
+    for obj, k in targets:
+        if obj is None or k not in t:
+            continue
+        want = t[k].get("launch_shape")
+        if want is None or have is None or (want["ppt"], want["cx"]) != (have["ppt"], have["cx"]):
+            continue
+        obj["traffic"] = t[k]["hbm_bytes_per_launch"]
 
 
 def cpu_baseline(system, tol, iters_per_step):
@@ -317,7 +351,7 @@ def bench_ensemble(steps: int, warmup: int, tol: float = 1e-8):
             "batching_speedup": round(t_serial / t_batch, 3)}
 
 
-def bench_observables(system, tol, steps, warmup):
+def bench_observables(system, tol, steps, warmup, flags=0):
     """The Results section's canonical dynamics and observables at the
     headline size: OVRVO MD steps/s (mixed, gamma 1e-3 /fs) beside velocity
     Verlet, the pair histogram of all 32768 ions (pairs/s), and one VACF /
@@ -327,7 +361,7 @@ def bench_observables(system, tol, steps, warmup):
 
     out = {}
     for name, g in (("velocity_verlet", 0.0), ("ovrvo", 1e-3)):
-        r = run_md(system, tol, maze.MAZE_MIXED, steps, warmup, gamma=g)
+        r = run_md(system, tol, maze.MAZE_MIXED, steps, warmup, gamma=g, flags=flags)
         out[f"{name}_mixed_md_steps_per_s"] = round(r["steps_per_s"], 4)
         out[f"{name}_cg_iterations_per_step"] = round(r["prof"]["fp32_iters"] / steps, 1)
     dev = torch.device("cuda")
@@ -403,6 +437,11 @@ def main():
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="nacl32768_g256")
+    ap.add_argument("--cg", choices=("sstep", "sweep"), default="sstep",
+                    help="PLCG form of the headline: two-iteration (s-step) or one-iteration "
+                         "fused sweep")
+    ap.add_argument("--no-sweep-compare", action="store_true",
+                    help="skip timing the one-iteration sweep beside the two-iteration form")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mixed-only", action="store_true",
                     help="skip the FP64 side-by-side run (for profiling)")
@@ -439,27 +478,37 @@ def main():
     tol = wl["tol"]
     G = (inputs.GRID_PER_CELL * wl["n_cells"]) ** 3
 
+    ss = args.cg == "sstep"
+    cg_flags = maze.MAZE_FLAG_SSTEP if ss else 0
     log(f"bench: {args.workload} ions={system.n_ions} grid={inputs.GRID_PER_CELL * wl['n_cells']}^3 "
-        f"tol={tol} mixed: warmup {args.warmup}, {args.steps} timed steps")
-    mixed = run_md(system, tol, maze.MAZE_MIXED, args.steps, args.warmup)
+        f"tol={tol} cg={args.cg} mixed: warmup {args.warmup}, {args.steps} timed steps")
+    mixed = run_md(system, tol, maze.MAZE_MIXED, args.steps, args.warmup, flags=cg_flags)
     log(f"bench: mixed {mixed['steps_per_s']:.3f} steps/s")
     fp64 = None
     errors = None
     if not args.mixed_only:
         fp64 = run_md(system, tol, maze.MAZE_FP64, args.steps, args.warmup,
-                      record_positions=True)
+                      record_positions=True, flags=cg_flags)
         log(f"bench: fp64 {fp64['steps_per_s']:.3f} steps/s")
         if args.replay > 0:
-            errors = replay_errors(system, fp64["traj"], tol, args.replay)
+            errors = replay_errors(system, fp64["traj"], tol, args.replay, flags=cg_flags)
             log(f"bench: mixed vs fp64 errors {errors}")
 
-    r_mixed = roofline("fp32_sweep", mixed["prof"], G, "fp32", mixed["shape"])
-    attach_traffic(r_mixed, "fp32_sweep")
-    r_fp64 = roofline("fp64_sweep", fp64["prof"], G, "fp64", fp64["shape"]) if fp64 else None
-    attach_traffic(r_fp64, "fp64_sweep")
+    r_mixed = roofline("fp32_sweep", mixed["prof"], G, "fp32", mixed["shape"], sstep=ss)
+    r_fp64 = (roofline("fp64_sweep", fp64["prof"], G, "fp64", fp64["shape"], sstep=ss)
+              if fp64 else None)
+    if ss:
+        attach_traffic(r_mixed, "fp32", "sstep")
+        attach_traffic(r_fp64, "fp64", "sstep")
+    else:
+        attach_traffic(r_mixed, "fp32_sweep")
+        attach_traffic(r_fp64, "fp64_sweep")
     copy_gbps = copy_bandwidth()
     attach_ceilings(r_mixed, copy_gbps)
     attach_ceilings(r_fp64, copy_gbps)
+    if ss:
+        attach_ceilings(r_mixed and r_mixed.get("basis_kernel"), copy_gbps)
+        attach_ceilings(r_fp64 and r_fp64.get("basis_kernel"), copy_gbps)
 
     it_mixed = mixed["prof"]["fp32_iters"] / args.steps
     it_fp64 = fp64["prof"]["fp64_iters"] / args.steps if fp64 else None
@@ -486,7 +535,9 @@ def main():
                    "grid": inputs.GRID_PER_CELL * wl["n_cells"], "box_A": system.box,
                    "tol_rel_residual": tol, "dt_fs": 1.0, "temperature_K": system.temperature,
                    "assignment_order": 2, "precision": "mixed (fp32 stencil/vectors, fp64 dots "
-                   "and refinement)", "parallelism": "single GPU"},
+                   "and refinement)", "cg_form": ("two-iteration s-step PLCG (s=2)" if ss else
+                                                 "one-iteration fused PLCG sweep"),
+                   "parallelism": "single GPU"},
         "latency_ms": {"p50": round(float(np.percentile(mixed["lat_ms"], 50)), 3),
                        "p99": round(float(np.percentile(mixed["lat_ms"], 99)), 3)},
         "cg_iterations_per_step": {"mixed_fp32_inner": round(it_mixed, 1)},
@@ -500,13 +551,33 @@ def main():
         line["cg_iterations_per_step"]["fp64"] = round(it_fp64, 1)
         line["roofline_fp64"] = r_fp64
         line["mixed_error_vs_fp64"] = errors
+    if ss and not args.no_sweep_compare:
+        # the same workload with the one-iteration fused sweep
+        log("bench: one-iteration sweep")
+        one = {}
+        for name, prec, key, dk in (("mixed", maze.MAZE_MIXED, "fp32_sweep", "fp32"),
+                                    ("fp64", maze.MAZE_FP64, "fp64_sweep", "fp64")):
+            if name == "fp64" and args.mixed_only:
+                continue
+            r = run_md(system, tol, prec, args.steps, args.warmup)
+            rl = roofline(key, r["prof"], G, dk, r["shape"])
+            attach_traffic(rl, key)
+            attach_ceilings(rl, copy_gbps)
+            one[name] = {"value": round(r["steps_per_s"], 4), "unit": "MD steps/s",
+                         "cg_iterations_per_step": round(r["prof"][f"{dk}_iters"] / args.steps, 1),
+                         "latency_ms": {"p50": round(float(np.percentile(r["lat_ms"], 50)), 3),
+                                        "p99": round(float(np.percentile(r["lat_ms"], 99)), 3)},
+                         "roofline": rl}
+        line["one_iteration_sweep"] = one
+        line["speedup_two_iteration_vs_sweep"] = round(value / one["mixed"]["value"], 3)
+        log(f"bench: one-iteration sweep {one}")
     if not args.no_order4:
         # the same workload with the cubic B-spline assignment the paper names
         # (64 points per ion): smoother charge motion, far fewer iterations
         log("bench: order-4 assignment")
         o4 = {}
         for name, prec in (("mixed", maze.MAZE_MIXED), ("fp64", maze.MAZE_FP64)):
-            r = run_md(system, tol, prec, args.steps, args.warmup, order=4)
+            r = run_md(system, tol, prec, args.steps, args.warmup, order=4, flags=cg_flags)
             key = "fp32_iters" if prec == maze.MAZE_MIXED else "fp64_iters"
             o4[name] = {"value": round(r["steps_per_s"], 4), "unit": "MD steps/s",
                         "cg_iterations_per_step": round(r["prof"][key] / args.steps, 1),
@@ -532,13 +603,15 @@ def main():
         log(f"bench: multigrid {mgl}")
     if args.error_trajectory > 0:
         log(f"bench: mixed vs FP64 over {args.error_trajectory} steps")
-        tr = run_md(system, tol, maze.MAZE_FP64, args.error_trajectory, 0, record_positions=True)
+        tr = run_md(system, tol, maze.MAZE_FP64, args.error_trajectory, 0, record_positions=True,
+                    flags=cg_flags)
         line["mixed_error_trajectory"] = replay_errors(system, tr["traj"], tol,
-                                                       args.error_trajectory, every=50)
+                                                       args.error_trajectory, every=50,
+                                                       flags=cg_flags)
         log(f"bench: trajectory errors {line['mixed_error_trajectory']}")
     if not args.no_observables:
         log("bench: Langevin dynamics and observables")
-        line["observables"] = bench_observables(system, tol, args.steps, args.warmup)
+        line["observables"] = bench_observables(system, tol, args.steps, args.warmup, cg_flags)
         log(f"bench: observables {line['observables']}")
     if not args.no_ensemble:
         log("bench: ensemble of 64 replicas")
