@@ -89,36 +89,60 @@ __global__ __launch_bounds__(kThreads) void k_bin_ions(const double* __restrict_
 
 // Exclusive scan of the tile counts (one workgroup; each thread scans a
 // contiguous chunk), cursor = start, counts reset to zero for the next step.
-__global__ __launch_bounds__(kThreads) void k_bin_scan(int32_t* tile_count, int32_t* tile_start,
-                                                       int32_t* tile_cursor, int ntiles,
-                                                       const Scalars* sc) {
-  __shared__ int32_t sums[kThreads];
+// Exclusive scan of the tile counts into tile starts (and cursors), which
+// also clears the counts for the next binning. One workgroup of 1024
+// threads walks the tiles in chunks of 4096: each thread takes four
+// consecutive counts, a wavefront scan and the 16 wavefront totals give its
+// offset, and a carry runs across chunks. Integer sums, so any order gives
+// the same starts.
+constexpr int kScanThreads = 1024;
+__global__ __launch_bounds__(kScanThreads) void k_bin_scan(int32_t* tile_count,
+                                                           int32_t* tile_start,
+                                                           int32_t* tile_cursor, int ntiles,
+                                                           const Scalars* sc) {
+  constexpr int W = kScanThreads / 64;
+  __shared__ int32_t wsum[W];
   if (ctl_ld(&sc->err)) return;
-  const int tid = threadIdx.x;
-  const int per = (ntiles + kThreads - 1) / kThreads;
-  const int b = tid * per, e = min(ntiles, b + per);
-  int32_t s = 0;
-  for (int i = b; i < e; ++i) s += tile_count[i];
-  sums[tid] = s;
-  __syncthreads();
-  if (tid == 0) {
-    int32_t run = 0;
-    for (int k = 0; k < kThreads; ++k) {
-      const int32_t v = sums[k];
-      sums[k] = run;
-      run += v;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  int32_t carry = 0;
+  for (int c0 = 0; c0 < ntiles; c0 += 4 * kScanThreads) {
+    int32_t v[4];
+    int32_t own = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int i = c0 + 4 * tid + k;
+      v[k] = (i < ntiles) ? tile_count[i] : 0;
+      own += v[k];
     }
-    tile_start[ntiles] = run;
+    int32_t x = own;  // inclusive scan over the wavefront
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int32_t y = __shfl_up(x, off, 64);
+      if (lane >= off) x += y;
+    }
+    if (lane == 63) wsum[w] = x;
+    __syncthreads();
+    int32_t before = 0, total = 0;
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+      before += (k < w) ? wsum[k] : 0;
+      total += wsum[k];
+    }
+    int32_t run = carry + before + (x - own);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int i = c0 + 4 * tid + k;
+      if (i < ntiles) {
+        tile_start[i] = run;
+        tile_cursor[i] = run;
+        tile_count[i] = 0;
+      }
+      run += v[k];
+    }
+    carry += total;
+    __syncthreads();  // wsum is rewritten by the next chunk
   }
-  __syncthreads();
-  int32_t run = sums[tid];
-  for (int i = b; i < e; ++i) {
-    const int32_t v = tile_count[i];
-    tile_start[i] = run;
-    tile_cursor[i] = run;
-    tile_count[i] = 0;
-    run += v;
-  }
+  if (tid == 0) tile_start[ntiles] = carry;
 }
 
 __global__ __launch_bounds__(kThreads) void k_bin_scatter(int n, int ntx, const int32_t* ion_cell,
@@ -169,7 +193,7 @@ hipError_t launch_bin(const DeviceState& d, const double* pos, hipStream_t st) {
   const int nb = (d.n_ions + kThreads - 1) / kThreads;
   hipLaunchKernelGGL(k_bin_ions, dim3(nb), dim3(kThreads), 0, st, pos, d.n_ions, d.box, d.h,
                      d.N, d.ntx, d.ion_cell, d.ion_t, d.tile_count, d.sc);
-  hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(kThreads), 0, st, d.tile_count, d.tile_start,
+  hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(kScanThreads), 0, st, d.tile_count, d.tile_start,
                      d.tile_cursor, d.ntiles, (const Scalars*)d.sc);
   hipLaunchKernelGGL(k_bin_scatter, dim3(nb), dim3(kThreads), 0, st, d.n_ions, d.ntx,
                      d.ion_cell, d.tile_cursor, d.sorted_idx, (const Scalars*)d.sc);
@@ -207,6 +231,13 @@ __device__ __forceinline__ int candidate_tiles(int T, int ntx, int order, int* o
   return n;
 }
 
+// One workgroup per tile of kTile^3 grid points, two points per thread.
+// The ions of the candidate tiles are read cooperatively into LDS in
+// batches, in the canonical order (candidate tiles in (x, y, z) order, ions
+// in tile order), and every thread then sums their weights at its points
+// in that order: the result is independent of scheduling, and the global
+// loads of a batch are issued together instead of one ion after another.
+constexpr int kSpreadBatch = 128;
 __global__ __launch_bounds__(kThreads) void k_spread(int N, int ntx, int order,
                                                      const int32_t* __restrict__ tile_start,
                                                      const int32_t* __restrict__ s_cell,
@@ -216,6 +247,10 @@ __global__ __launch_bounds__(kThreads) void k_spread(int N, int ntx, int order,
                                                      const Scalars* sc) {
 #pragma clang fp contract(off)
   __shared__ double red[8];
+  __shared__ int32_t cstart[27], cpre[28];
+  __shared__ double lQ[kSpreadBatch];
+  __shared__ int32_t lcell[kSpreadBatch * 3];
+  __shared__ double lw[kSpreadBatch * 3 * kMaxOrder];
   if (ctl_ld(&sc->err)) return;
   const int T = blockIdx.x;
   const int TX = T / (ntx * ntx), TY = (T / ntx) % ntx, TZ = T % ntx;
@@ -223,44 +258,67 @@ __global__ __launch_bounds__(kThreads) void k_spread(int N, int ntx, int order,
   const int nx = candidate_tiles(TX, ntx, order, cx);
   const int ny = candidate_tiles(TY, ntx, order, cy);
   const int nz = candidate_tiles(TZ, ntx, order, cz);
+  const int ncand = nx * ny * nz;
   const int off = (order == 2) ? 0 : 1;
+  const int tid = threadIdx.x;
+  if (tid < ncand) {
+    const int a = tid / (ny * nz), b = (tid / nz) % ny, c = tid % nz;
+    const int ct = (cx[a] * ntx + cy[b]) * ntx + cz[c];
+    cstart[tid] = tile_start[ct];
+    cpre[tid + 1] = tile_start[ct + 1] - tile_start[ct];
+  }
+  __syncthreads();
+  if (tid == 0) {
+    cpre[0] = 0;
+    for (int t = 0; t < ncand; ++t) cpre[t + 1] += cpre[t];
+  }
+  __syncthreads();
+  const int total = cpre[ncand];
 
   int gp[2][3];
   bool valid[2];
   double acc[2] = {0.0, 0.0};
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
-    const int pt = threadIdx.x + j * kThreads;
+    const int pt = tid + j * kThreads;
     gp[j][0] = TX * kTile + (pt >> 6);
     gp[j][1] = TY * kTile + ((pt >> 3) & 7);
     gp[j][2] = TZ * kTile + (pt & 7);
     valid[j] = gp[j][0] < N && gp[j][1] < N && gp[j][2] < N;
   }
-  for (int a = 0; a < nx; ++a)
-    for (int b = 0; b < ny; ++b)
-      for (int c = 0; c < nz; ++c) {
-        const int ct = (cx[a] * ntx + cy[b]) * ntx + cz[c];
-        const int sb = tile_start[ct], se = tile_start[ct + 1];
-        for (int s = sb; s < se; ++s) {
-          const double Qs = s_Q[s];
-          const int bx = s_cell[3 * s] - off, by = s_cell[3 * s + 1] - off,
-                    bz = s_cell[3 * s + 2] - off;
-          const double* w = s_w + (size_t)3 * s * order;
+  for (int base = 0; base < total; base += kSpreadBatch) {
+    const int m = min(kSpreadBatch, total - base);
+    if (tid < m) {
+      const int k = base + tid;
+      int t = 0;
+      while (cpre[t + 1] <= k) ++t;
+      const int s = cstart[t] + (k - cpre[t]);
+      lQ[tid] = s_Q[s];
 #pragma unroll
-          for (int j = 0; j < 2; ++j) {
-            int dx = gp[j][0] - bx, dy = gp[j][1] - by, dz = gp[j][2] - bz;
-            dx = (dx < 0) ? dx + N : (dx >= N ? dx - N : dx);
-            dy = (dy < 0) ? dy + N : (dy >= N ? dy - N : dy);
-            dz = (dz < 0) ? dz + N : (dz >= N ? dz - N : dz);
-            if (dx < order && dy < order && dz < order) {
-              double v = Qs * w[dx];
-              v = v * w[order + dy];
-              v = v * w[2 * order + dz];
-              acc[j] += v;
-            }
-          }
+      for (int d = 0; d < 3; ++d) lcell[3 * tid + d] = s_cell[3 * s + d];
+      for (int e = 0; e < 3 * order; ++e) lw[tid * 3 * kMaxOrder + e] = s_w[(size_t)3 * s * order + e];
+    }
+    __syncthreads();
+    for (int i = 0; i < m; ++i) {
+      const double Qs = lQ[i];
+      const int bx = lcell[3 * i] - off, by = lcell[3 * i + 1] - off, bz = lcell[3 * i + 2] - off;
+      const double* w = lw + i * 3 * kMaxOrder;
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        int dx = gp[j][0] - bx, dy = gp[j][1] - by, dz = gp[j][2] - bz;
+        dx = (dx < 0) ? dx + N : (dx >= N ? dx - N : dx);
+        dy = (dy < 0) ? dy + N : (dy >= N ? dy - N : dy);
+        dz = (dz < 0) ? dz + N : (dz >= N ? dz - N : dz);
+        if (dx < order && dy < order && dz < order) {
+          double v = Qs * w[dx];
+          v = v * w[order + dy];
+          v = v * w[2 * order + dz];
+          acc[j] += v;
         }
       }
+    }
+    __syncthreads();  // the batch buffers are refilled next
+  }
   double local = 0.0;
 #pragma unroll
   for (int j = 0; j < 2; ++j)
@@ -269,7 +327,7 @@ __global__ __launch_bounds__(kThreads) void k_spread(int N, int ntx, int order,
       local += acc[j];
     }
   const double tot = block_sum(local, red);
-  if (threadIdx.x == 0) part[T] = tot;
+  if (tid == 0) part[T] = tot;
 }
 
 hipError_t launch_spread(const DeviceState& d, hipStream_t st) {
