@@ -93,6 +93,7 @@ def run_md(system, tol, precision, steps, warmup, record_positions=False, order=
     lat = np.array([evs[k].elapsed_time(evs[k + 1]) for k in range(steps)])
     obs = run.observables()
     shape = maze.maze_launch_shape(h)["latency"]
+    shape["basis"] = maze.maze_basis_shape(h)
     out = dict(steps_per_s=steps / (t1 - t0), wall_s=t1 - t0, lat_ms=lat, prof=prof,
                obs=obs, grid_n=run.session.N, traj=traj, shape=shape)
     run.close()
@@ -159,6 +160,11 @@ def roofline(prof_key, prof, G, dtype_key, shape=None, sstep=False):
                              "frac": round(bb / b_s / 1e9 / HBM_PEAK_GBS, 4), "traffic": None}
         r["outer_step_us"] = round(ms / n * 1e3, 2)
         r["iterations_per_outer_step"] = 2
+        if shape is not None and "basis" in shape:
+            bs = shape["basis"]
+            r["basis_kernel"]["launch_shape"] = {
+                "threads": bs["threads"], "ppt": bs["ppt"], "cx": bs["cx"],
+                "workgroups": bs["nwg"], "grid_threads": bs["nwg"] * bs["threads"]}
     if shape is not None:
         # the launch shape the session swept in; a kernel trace of this run
         # also holds the autotuner's timing sweeps in other shapes, which
@@ -196,14 +202,17 @@ def attach_traffic(r, key, form="sweep"):
         return
     if t.get("stencil_sha") != source_hash(src):
         return
-    have = r.get("launch_shape")
     targets = [(r, key)] if form == "sweep" else [(r, f"{key}_update"),
                                                   (r.get("basis_kernel"), f"{key}_basis")]
     for obj, k in targets:
         if obj is None or k not in t:
             continue
         want = t[k].get("launch_shape")
-        if want is None or have is None or (want["ppt"], want["cx"]) != (have["ppt"], have["cx"]):
+        have = obj.get("launch_shape", r.get("launch_shape"))
+        if want is None or have is None:
+            continue
+        shape_key = lambda x: (x.get("threads", 256), x["ppt"], x["cx"])  # noqa: E731
+        if shape_key(want) != shape_key(have):
             continue
         obj["traffic"] = t[k]["hbm_bytes_per_launch"]
 

@@ -247,6 +247,16 @@ int maze_profile_read(maze_session* s, double* out8);
  * of the latency shape, then of the throughput shape. */
 int maze_launch_shape(const maze_session* s, int32_t* out8);
 
+/* Launch shape of the basis kernel of the two-iteration CG
+ * (MAZE_FLAG_SSTEP): picked at maze_init by timing the session's latency
+ * shape and 1024-thread shapes (longer segments, less halo work) on the
+ * session's own buffers, cached per device, grid size and precision;
+ * MAZE_BASIS_SHAPE="threads:ppt:cx" forces one, MAZE_AUTOTUNE=0 keeps the
+ * latency shape. Without the flag it is the latency shape. out4 (HOST,
+ * 4 int32): {threads per workgroup, points per thread, x planes per
+ * workgroup, workgroups}. */
+int maze_basis_shape(const maze_session* s, int32_t* out4);
+
 /* Residual trace of the last solve (for convergence studies such as the
  * residual-versus-iteration comparison of Appendix B). When enabled, each
  * solve records, per CG iteration k, the norm of the recursive residual

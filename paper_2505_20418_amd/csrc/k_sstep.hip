@@ -95,24 +95,26 @@ __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, uint32_t boff, T v)
         __builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned int, v), r, boff, 0, 0);
 }
 
-// kNs per-thread values (the last a max) reduced over the workgroup in a
-// fixed order; every thread receives the results. sm: kNs * 4 doubles.
+// kNs per-thread values (the last a max) reduced over the NT threads of the
+// workgroup in a fixed order; every thread receives the results.
+// sm: kNs * NT / 64 doubles.
+template <int NT>
 __device__ __forceinline__ void block_reduce_ns(double v[kNs], double* sm) {
+  constexpr int WV = NT / 64;
 #pragma unroll
   for (int i = 0; i < kNs; ++i) v[i] = (i == kNs - 1) ? wave_max(v[i]) : wave_sum(v[i]);
   const int w = threadIdx.x >> 6;
   __syncthreads();
   if ((threadIdx.x & 63) == 0) {
 #pragma unroll
-    for (int i = 0; i < kNs; ++i) sm[i * (kThreads / 64) + w] = v[i];
+    for (int i = 0; i < kNs; ++i) sm[i * WV + w] = v[i];
   }
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < kNs; ++i) {
-    double s = sm[i * (kThreads / 64)];
+    double s = sm[i * WV];
 #pragma unroll
-    for (int k = 1; k < kThreads / 64; ++k)
-      s = (i == kNs - 1) ? fmax(s, sm[i * (kThreads / 64) + k]) : s + sm[i * (kThreads / 64) + k];
+    for (int k = 1; k < WV; ++k) s = (i == kNs - 1) ? fmax(s, sm[i * WV + k]) : s + sm[i * WV + k];
     v[i] = s;
   }
 }
@@ -141,7 +143,7 @@ __device__ __forceinline__ void ahat(const double* v, double* o) {
 // The work of one workgroup (logical index L) of a basis (UPDATE = false)
 // or update (UPDATE = true) kernel of outer step parity `par`. FIRST: the
 // first outer step of a solve, p = r / 6 (p is not read).
-template <typename T, bool FIRST, bool UPDATE, int PPT, int NH>
+template <typename T, bool FIRST, bool UPDATE, int PPT, int NH, int NT>
 __device__ __forceinline__ void sstep_wg(const SweepArgs<T>& a, const SweepGeom& g, int par,
                                          int L, unsigned char* smem_raw, double* red) {
   Scalars* sc = a.sc;
@@ -172,12 +174,12 @@ __device__ __forceinline__ void sstep_wg(const SweepArgs<T>& a, const SweepGeom&
     double v[kNs];
 #pragma unroll
     for (int i = 0; i < kNs; ++i) v[i] = 0.0;
-    for (int i = tid; i < a.nprev_sweep; i += kThreads) {
+    for (int i = tid; i < a.nprev_sweep; i += NT) {
 #pragma unroll
       for (int c = 0; c < kNm; ++c) v[c] += a.part[(size_t)(SL_SG0 + c) * a.pstride + i];
       v[kNm] = fmax(v[kNm], a.part[(size_t)SL_SGMAX * a.pstride + i]);
     }
-    block_reduce_ns(v, red);
+    block_reduce_ns<NT>(v, red);
     double G[15];
 #pragma unroll
     for (int aa = 0; aa < 5; ++aa)
@@ -298,13 +300,13 @@ __device__ __forceinline__ void sstep_wg(const SweepArgs<T>& a, const SweepGeom&
   for (int i = 0; i < NU; ++i) {
     int f, ee2;
     if (i < PPT) {
-      const int loc = tid + i * kThreads;
+      const int loc = tid + i * NT;
       f = s0 + loc;
       ee2 = N + loc;
       uval[i] = true;
       cval[i] = f < P;
     } else {
-      const int h = tid + (i - PPT) * kThreads;
+      const int h = tid + (i - PPT) * NT;
       uval[i] = h < 2 * N;
       const int hh = uval[i] ? h : 0;
       ee2 = (hh < N) ? hh : S + hh;
@@ -325,7 +327,7 @@ __device__ __forceinline__ void sstep_wg(const SweepArgs<T>& a, const SweepGeom&
   }
 #pragma unroll
   for (int k = 0; k < NH; ++k) {
-    const int h = tid + k * kThreads;
+    const int h = tid + k * NT;
     oval[k] = h < 2 * N;
     const int hh = oval[k] ? h : 0;
     e1o[k] = (hh < N) ? hh : S + 2 * N + hh;
@@ -504,7 +506,7 @@ __device__ __forceinline__ void sstep_wg(const SweepArgs<T>& a, const SweepGeom&
   }
 
   if (!UPDATE) {
-    block_reduce_ns(acc, red);
+    block_reduce_ns<NT>(acc, red);
     if (tid == 0) {
 #pragma unroll
       for (int c = 0; c < kNm; ++c) a.part[(size_t)(SL_SG0 + c) * a.pstride + L] = acc[c];
@@ -513,11 +515,27 @@ __device__ __forceinline__ void sstep_wg(const SweepArgs<T>& a, const SweepGeom&
   }
 }
 
-template <typename T, bool FIRST, bool UPDATE, int PPT, int NH>
-__global__ __launch_bounds__(kThreads) void k_sstep(SweepArgs<T> a, SweepGeom g, int par) {
+template <typename T, bool FIRST, bool UPDATE, int PPT, int NH, int NT>
+__global__ __launch_bounds__(NT) void k_sstep(SweepArgs<T> a, SweepGeom g, int par) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  __shared__ double red[kNs * (kThreads / 64)];
-  sstep_wg<T, FIRST, UPDATE, PPT, NH>(a, g, par, xcd_remap(blockIdx.x, g.nwg), smem_raw, red);
+  __shared__ double red[kNs * (NT / 64)];
+  sstep_wg<T, FIRST, UPDATE, PPT, NH, NT>(a, g, par, xcd_remap(blockIdx.x, g.nwg), smem_raw, red);
+}
+
+// Geometry of a two-iteration kernel with nt threads per workgroup
+// (segments of nt * ppt points, nh halo slots per thread for one row).
+SweepGeom make_sstep_geom(int N, int ppt, int cx, int nt) {
+  SweepGeom g;
+  g.N = N;
+  g.P = N * N;
+  g.ppt = ppt;
+  g.S = nt * ppt;
+  g.nseg = (g.P + g.S - 1) / g.S;
+  g.cx = cx < 1 ? 1 : (cx > N ? N : cx);
+  g.nchunk = (N + g.cx - 1) / g.cx;
+  g.nwg = g.nseg * g.nchunk;
+  g.nh = (2 * N + nt - 1) / nt;
+  return g;
 }
 
 size_t sstep_lds_bytes(const SweepGeom& g, bool fp32) {
@@ -528,42 +546,70 @@ size_t sstep_lds_bytes(const SweepGeom& g, bool fp32) {
 
 namespace {
 
-template <typename T, bool FIRST, bool UPDATE, int PPT, int NH>
+template <typename T, bool FIRST, bool UPDATE, int PPT, int NH, int NT>
 hipError_t sstep_launch(const SweepArgs<T>& a, const SweepGeom& g, int par, hipStream_t st) {
-  static bool raised = false;
+  static size_t allowed = 0;  // dynamic LDS the kernel is known to accept
   const size_t lds = sstep_lds_bytes(g, sizeof(T) == 4);
-  if (lds > 160 * 1024 - 1024) return hipErrorInvalidValue;
-  if (lds > 65536 && !raised) {
-    const hipError_t e =
-        hipFuncSetAttribute((const void*)k_sstep<T, FIRST, UPDATE, PPT, NH>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 1024);
-    if (e != hipSuccess) return e;
-    raised = true;
+  if (lds > 160 * 1024 - 2048) return hipErrorInvalidValue;
+  if (lds > 65536 && lds > allowed) {
+    // raise the kernel's limit only where it is below what this launch
+    // needs (the runtime refuses the request for some workgroup sizes whose
+    // limit is already the whole LDS)
+    const void* fn = (const void*)k_sstep<T, FIRST, UPDATE, PPT, NH, NT>;
+    hipFuncAttributes fa{};
+    if (hipFuncGetAttributes(&fa, fn) == hipSuccess && (size_t)fa.maxDynamicSharedSizeBytes >= lds) {
+      allowed = (size_t)fa.maxDynamicSharedSizeBytes;
+    } else {
+      const hipError_t e =
+          hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 2048);
+      if (e != hipSuccess) return e;
+      allowed = 160 * 1024 - 2048;
+    }
   }
-  hipLaunchKernelGGL((k_sstep<T, FIRST, UPDATE, PPT, NH>), dim3(g.nwg), dim3(kThreads), lds, st,
+  hipLaunchKernelGGL((k_sstep<T, FIRST, UPDATE, PPT, NH, NT>), dim3(g.nwg), dim3(NT), lds, st,
                      a, g, par);
   return hipGetLastError();
 }
 
-template <typename T, bool FIRST, bool UPDATE, int PPT>
+template <typename T, bool FIRST, bool UPDATE, int PPT, int NT>
 hipError_t sstep_nh(const SweepArgs<T>& a, const SweepGeom& g, int par, hipStream_t st) {
   switch (sweep_nh_class(g.nh)) {
-    case 1: return sstep_launch<T, FIRST, UPDATE, PPT, 1>(a, g, par, st);
-    case 2: return sstep_launch<T, FIRST, UPDATE, PPT, 2>(a, g, par, st);
-    case 4: return sstep_launch<T, FIRST, UPDATE, PPT, 4>(a, g, par, st);
-    case 8: return sstep_launch<T, FIRST, UPDATE, PPT, 8>(a, g, par, st);
+    case 1: return sstep_launch<T, FIRST, UPDATE, PPT, 1, NT>(a, g, par, st);
+    case 2: return sstep_launch<T, FIRST, UPDATE, PPT, 2, NT>(a, g, par, st);
+    case 4:
+      if constexpr (NT == kThreads) return sstep_launch<T, FIRST, UPDATE, PPT, 4, NT>(a, g, par, st);
+      return hipErrorInvalidValue;
+    case 8:
+      if constexpr (NT == kThreads) return sstep_launch<T, FIRST, UPDATE, PPT, 8, NT>(a, g, par, st);
+      return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
   }
 }
 
+// Workgroups of kThreads for every kernel; the basis kernel also comes in
+// 1024-thread workgroups (longer segments, less halo work per point).
 template <typename T, bool FIRST, bool UPDATE>
 hipError_t sstep_ppt(const SweepArgs<T>& a, const SweepGeom& g, int par, hipStream_t st) {
-  switch (g.ppt) {
-    case 1: return sstep_nh<T, FIRST, UPDATE, 1>(a, g, par, st);
-    case 2: return sstep_nh<T, FIRST, UPDATE, 2>(a, g, par, st);
-    case 4: return sstep_nh<T, FIRST, UPDATE, 4>(a, g, par, st);
-    default: return hipErrorInvalidValue;
+  const int nt = g.S / g.ppt;
+  if (nt == kThreads) {
+    switch (g.ppt) {
+      case 1: return sstep_nh<T, FIRST, UPDATE, 1, kThreads>(a, g, par, st);
+      case 2: return sstep_nh<T, FIRST, UPDATE, 2, kThreads>(a, g, par, st);
+      case 4: return sstep_nh<T, FIRST, UPDATE, 4, kThreads>(a, g, par, st);
+      default: return hipErrorInvalidValue;
+    }
   }
+  if constexpr (!UPDATE) {
+    if (nt == 1024) {
+      switch (g.ppt) {
+        case 1: return sstep_nh<T, FIRST, UPDATE, 1, 1024>(a, g, par, st);
+        case 2: return sstep_nh<T, FIRST, UPDATE, 2, 1024>(a, g, par, st);
+        case 4: return sstep_nh<T, FIRST, UPDATE, 4, 1024>(a, g, par, st);
+        default: return hipErrorInvalidValue;
+      }
+    }
+  }
+  return hipErrorInvalidValue;
 }
 
 template <typename T>
@@ -577,22 +623,38 @@ hipError_t sstep_half(const SweepArgs<T>& a, const SweepGeom& g, int o, bool upd
 
 }  // namespace
 
-hipError_t launch_sstep_half(const DeviceState& d, const SweepGeom& g, int o, void* x, bool fp32,
-                             bool zero_x, bool update, hipStream_t st) {
-  // one partial per workgroup and slot: the shape must fit the buffer's rows
-  if (g.nwg < 1 || g.nwg > d.part_stride || o < 0) return hipErrorInvalidValue;
+hipError_t launch_sstep_half(const DeviceState& d, const SweepGeom& gb, const SweepGeom& gu, int o,
+                             void* x, bool fp32, bool zero_x, bool update, hipStream_t st) {
+  // one partial per workgroup and slot: the basis shape must fit the
+  // buffer's rows (the update reads one row per basis workgroup)
+  if (gb.nwg < 1 || gb.nwg > d.part_stride || gu.nwg < 1 || o < 0) return hipErrorInvalidValue;
   const bool zx = zero_x && o == 0;
-  if (fp32) return sstep_half<float>(make_sweep_args<float>(d, (float*)x, 0, g.nwg, zx), g, o,
+  const SweepGeom& g = update ? gu : gb;
+  if (fp32) return sstep_half<float>(make_sweep_args<float>(d, (float*)x, 0, gb.nwg, zx), g, o,
                                      update, st);
-  return sstep_half<double>(make_sweep_args<double>(d, (double*)x, 0, g.nwg, zx), g, o, update,
+  return sstep_half<double>(make_sweep_args<double>(d, (double*)x, 0, gb.nwg, zx), g, o, update,
                             st);
 }
 
-hipError_t launch_sstep_outer(const DeviceState& d, const SweepGeom& g, int o, void* x,
-                              bool fp32, bool zero_x, hipStream_t st) {
-  const hipError_t e = launch_sstep_half(d, g, o, x, fp32, zero_x, false, st);
+hipError_t launch_sstep_outer(const DeviceState& d, const SweepGeom& gb, const SweepGeom& gu, int o,
+                              void* x, bool fp32, bool zero_x, hipStream_t st) {
+  const hipError_t e = launch_sstep_half(d, gb, gu, o, x, fp32, zero_x, false, st);
   if (e != hipSuccess) return e;
-  return launch_sstep_half(d, g, o, x, fp32, zero_x, true, st);
+  return launch_sstep_half(d, gb, gu, o, x, fp32, zero_x, true, st);
+}
+
+// Basis-kernel shapes that compile without register spills: 256 threads in
+// every class; 1024 threads for FP32 up to 4 points per thread with one
+// halo slot (2 points with two), and for FP64 up to 2 points with one halo
+// slot (1 point with two).
+bool sstep_basis_shape_ok(const SweepGeom& g, bool fp32) {
+  const int nt = g.S / g.ppt;
+  const int nh = sweep_nh_class(g.nh);
+  if (nh == 0 || sstep_lds_bytes(g, fp32) > 160 * 1024 - 2048) return false;
+  if (nt == kThreads) return g.ppt == 1 || g.ppt == 2 || g.ppt == 4;
+  if (nt != 1024 || nh > 2) return false;
+  if (fp32) return g.ppt == 1 || g.ppt == 2 || (g.ppt == 4 && nh == 1);
+  return g.ppt == 1 || (g.ppt == 2 && nh == 1);
 }
 
 }  // namespace maze

@@ -48,6 +48,7 @@ struct maze_session {
   MarchGeom geom{};
   SweepGeom sweep{};     // latency shape: alone and in batches below the fill level
   SweepGeom sweep_tp{};  // throughput shape: batches that fill the GPU
+  SweepGeom sbasis{};    // basis kernel of the two-iteration CG (own shape)
   hipStream_t stream = nullptr;
   // captured chunks of kPollBatch sweeps, [fp32][parity of the first sweep]
   // [slot]: a graph holds its kernels' arguments, and the solution vector
@@ -337,7 +338,8 @@ static int poll_units(const maze_session* s) { return sstep_of(s) ? kPollBatch /
 // Unit k of a solve: sweep k, or outer step k of the two-iteration form.
 static hipError_t launch_unit(maze_session* s, long long k, void* x, bool fp32, bool zero_x) {
   const int kk = (int)(k & 0x7fffffff);
-  if (sstep_of(s)) return launch_sstep_outer(s->d, s->sweep, kk, x, fp32, zero_x, s->stream);
+  if (sstep_of(s))
+    return launch_sstep_outer(s->d, s->sbasis, s->sweep, kk, x, fp32, zero_x, s->stream);
   return launch_cg_sweep(s->d, s->sweep, kk, s->geom.nwg, x, fp32, zero_x, s->stream);
 }
 
@@ -403,11 +405,10 @@ static int run_cg(CgJob& job, bool fp32, bool zero_x, int first_batch) {
       if (timeit) HIP_TRY(hipEventRecord(s->pev[3 * timed], s->stream));
       if (ss && timeit) {
         // basis and update kernels timed apart
-        const SweepGeom& g = w;
         const int kk = (int)(k & 0x7fffffff);
-        HIP_TRY(launch_sstep_half(d, g, kk, job.x, fp32, zero_x, false, s->stream));
+        HIP_TRY(launch_sstep_half(d, s->sbasis, w, kk, job.x, fp32, zero_x, false, s->stream));
         HIP_TRY(hipEventRecord(s->pev[3 * timed + 1], s->stream));
-        HIP_TRY(launch_sstep_half(d, g, kk, job.x, fp32, zero_x, true, s->stream));
+        HIP_TRY(launch_sstep_half(d, s->sbasis, w, kk, job.x, fp32, zero_x, true, s->stream));
       } else {
         HIP_TRY(launch_unit(s, k, job.x, fp32, zero_x));
       }
@@ -1093,6 +1094,95 @@ static SweepGeom autotune_sweep(maze_session* s) {
   return best;
 }
 
+// Shape of the basis kernel of the two-iteration CG. It only reads r and p
+// and is bound by its per-plane steps rather than by HBM, so it prefers
+// fewer, larger workgroups than the update kernel (1024 threads, segments of
+// 2048 or 4096 points: less halo work per point). Candidates are the
+// session's latency shape and the spill-free 1024-thread shapes; each runs
+// 3 warm-up and 8 timed launches on a fill pattern of the session's r and p
+// (the basis kernel writes only its partials), and the fastest is cached per
+// (device, N, precision). MAZE_BASIS_SHAPE="threads:ppt:cx" forces one;
+// MAZE_AUTOTUNE=0 keeps the latency shape.
+static std::map<TuneKey, SweepGeom> g_tuned_basis;
+
+static bool forced_basis(const DeviceState& d, bool fp32, SweepGeom* out) {
+  const char* e = std::getenv("MAZE_BASIS_SHAPE");
+  int nt = 0, ppt = 0, cx = 0;
+  if (!e || std::sscanf(e, "%d:%d:%d", &nt, &ppt, &cx) != 3) return false;
+  if ((nt != kThreads && nt != 1024) || (ppt != 1 && ppt != 2 && ppt != 4) || cx < 1) return false;
+  const SweepGeom g = make_sstep_geom(d.N, ppt, cx, nt);
+  if (!sstep_basis_shape_ok(g, fp32) || g.nwg > d.part_stride) return false;
+  *out = g;
+  return true;
+}
+
+static SweepGeom autotune_basis(maze_session* s) {
+  DeviceState& d = s->d;
+  const bool fp32 = s->cfg.precision == MAZE_MIXED;
+  SweepGeom def = s->sweep;
+  if (forced_basis(d, fp32, &def)) return def;
+  if (!autotune_enabled()) return def;
+  const TuneKey key{s->device, d.N, fp32 ? 1 : 0};
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tuned_basis.find(key);
+    if (it != g_tuned_basis.end()) return it->second;
+  }
+  std::vector<SweepGeom> cand{def};
+  const long long P = (long long)d.N * d.N;
+  for (int ppt : {1, 2, 4}) {
+    if (1024LL * ppt > P) continue;  // segments longer than a plane
+    int last = -1;
+    for (int cx : {8, 12, 16, 24, 32, 48, 64}) {
+      const SweepGeom g = make_sstep_geom(d.N, ppt, cx, 1024);
+      if (g.nchunk == last || !sstep_basis_shape_ok(g, fp32) || g.nwg > d.part_stride) continue;
+      last = g.nchunk;
+      cand.push_back(g);
+    }
+  }
+  if (cand.size() <= 1) return def;
+  hipStream_t st = s->stream;
+  void* r0 = fp32 ? (void*)d.r32 : (void*)d.r;
+  void* p0 = fp32 ? (void*)d.p32 : (void*)d.p;
+  void* x = fp32 ? (void*)d.e32 : (void*)d.xsolve;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return def;
+  Scalars sc{};
+  sc.thr = -1.0;
+  sc.max_iter = 1 << 30;
+  sc.norm = MAZE_NORM_REL2;
+  bool ok = hipMemcpyAsync(d.sc, &sc, sizeof(Scalars), hipMemcpyHostToDevice, st) == hipSuccess &&
+            launch_fill_pattern(r0, d.G, fp32, st) == hipSuccess &&
+            launch_fill_pattern(p0, d.G, fp32, st) == hipSuccess;
+  SweepGeom best = def;
+  float best_ms = 1e30f;
+  for (const SweepGeom& g : cand) {
+    // outer step 2: parity 0, not the first (reads r[0] and p[0])
+    for (int k = 0; k < 3 && ok; ++k)
+      ok = launch_sstep_half(d, g, s->sweep, 2, x, fp32, false, false, st) == hipSuccess;
+    ok = ok && hipEventRecord(e0, st) == hipSuccess;
+    for (int k = 0; k < 8 && ok; ++k)
+      ok = launch_sstep_half(d, g, s->sweep, 2, x, fp32, false, false, st) == hipSuccess;
+    ok = ok && hipEventRecord(e1, st) == hipSuccess;
+    ok = ok && hipStreamSynchronize(st) == hipSuccess;
+    if (!ok) break;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, e0, e1) == hipSuccess && ms < best_ms) {
+      best_ms = ms;
+      best = g;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (!ok) {
+    hipGetLastError();
+    return def;
+  }
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tuned_basis[key] = best;
+  return best;
+}
+
 extern "C" {
 
 int maze_abi_version(void) { return MAZE_ABI_VERSION; }
@@ -1256,6 +1346,7 @@ int maze_init(const maze_config* cfg, const double* charges_dev, const double* p
   // clear them again for the first solve
   s->sweep = autotune_sweep(s);
   s->sweep_tp = throughput_sweep(s->d, s->cfg.precision == MAZE_MIXED);
+  s->sbasis = sstep_of(s) ? autotune_basis(s) : s->sweep;
   if (hipMemsetAsync(base, 0, L.total, stream) != hipSuccess ||
       hipMemcpyAsync(d.Q, charges_dev, sizeof(double) * n, hipMemcpyDeviceToDevice, stream) !=
           hipSuccess) {
@@ -1451,6 +1542,15 @@ int maze_launch_shape(const maze_session* s, int32_t* out8) {
     out8[4 * i + 2] = g[i]->nwg;
     out8[4 * i + 3] = g[i]->S;
   }
+  return MAZE_OK;
+}
+
+int maze_basis_shape(const maze_session* s, int32_t* out4) {
+  if (!s || !out4) return MAZE_E_INVALID;
+  out4[0] = s->sbasis.S / s->sbasis.ppt;
+  out4[1] = s->sbasis.ppt;
+  out4[2] = s->sbasis.cx;
+  out4[3] = s->sbasis.nwg;
   return MAZE_OK;
 }
 

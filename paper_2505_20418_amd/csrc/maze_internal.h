@@ -257,12 +257,19 @@ hipError_t launch_cg_sweep(const DeviceState& d, const SweepGeom& g, int k, int 
 // Outer step o of a two-iteration (s = 2) CG solve: its basis kernel and
 // its update kernel (o = 0: p_0 = r_0 / 6; zero_x then writes x from zero).
 // Same vectors, partial table and scalars as the sweeps above.
-hipError_t launch_sstep_outer(const DeviceState& d, const SweepGeom& g, int o, void* x,
-                              bool fp32, bool zero_x, hipStream_t st);
+// gb: shape of the basis kernel (256 or 1024 threads per workgroup), gu:
+// shape of the update kernel (256 threads).
+hipError_t launch_sstep_outer(const DeviceState& d, const SweepGeom& gb, const SweepGeom& gu, int o,
+                              void* x, bool fp32, bool zero_x, hipStream_t st);
 // One of the two kernels of outer step o (update = false: the basis kernel).
-hipError_t launch_sstep_half(const DeviceState& d, const SweepGeom& g, int o, void* x, bool fp32,
-                             bool zero_x, bool update, hipStream_t st);
+hipError_t launch_sstep_half(const DeviceState& d, const SweepGeom& gb, const SweepGeom& gu, int o,
+                             void* x, bool fp32, bool zero_x, bool update, hipStream_t st);
+// Whether a basis-kernel shape has an instantiation that fits (LDS, halo
+// class) and runs without register spills.
+bool sstep_basis_shape_ok(const SweepGeom& g, bool fp32);
 size_t sstep_lds_bytes(const SweepGeom& g, bool fp32);
+// Geometry of a two-iteration kernel with nt threads per workgroup.
+SweepGeom make_sstep_geom(int N, int ppt, int cx, int nt);
 // Fills x (G elements) with a fixed finite pattern.
 hipError_t launch_fill_pattern(void* x, long long G, bool fp32, hipStream_t st);
 // Batch helpers: {done, iters, err} of every session into out[3 * count];

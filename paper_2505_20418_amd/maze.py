@@ -31,7 +31,8 @@ EXPORTED = ("maze_abi_version", "maze_strerror", "maze_device_bytes", "maze_init
             "maze_solve", "maze_step_batch", "maze_grid_n", "maze_get_grid",
             "maze_state_bytes", "maze_save", "maze_load", "maze_destroy", "maze_md_prime",
             "maze_md_step", "maze_profile_enable", "maze_profile_read", "maze_trace_enable",
-            "maze_trace_read", "maze_md_step_batch", "maze_launch_shape", "maze_langevin_noise",
+            "maze_trace_read", "maze_md_step_batch", "maze_launch_shape", "maze_basis_shape",
+            "maze_langevin_noise",
             "maze_rdf_accumulate", "maze_tcf_create", "maze_tcf_sample", "maze_tcf_read",
             "maze_tcf_destroy")
 
@@ -122,6 +123,8 @@ def lib():
         L.maze_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
         L.maze_launch_shape.restype = ctypes.c_int
         L.maze_launch_shape.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
+        L.maze_basis_shape.restype = ctypes.c_int
+        L.maze_basis_shape.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
         L.maze_md_step_batch.restype = ctypes.c_int
         L.maze_md_step_batch.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(vp), i32,
                                          ctypes.POINTER(maze_stats)]
@@ -304,6 +307,13 @@ def maze_launch_shape(handle) -> dict:
     return {k: dict(ppt=out[4 * i], cx=out[4 * i + 1], nwg=out[4 * i + 2],
                     segment=out[4 * i + 3])
             for i, k in enumerate(("latency", "throughput"))}
+
+
+def maze_basis_shape(handle) -> dict:
+    """Launch shape of the basis kernel of the two-iteration CG."""
+    out = (ctypes.c_int32 * 4)()
+    _check(lib().maze_basis_shape(handle, out), "maze_basis_shape")
+    return dict(threads=out[0], ppt=out[1], cx=out[2], nwg=out[3])
 
 
 def maze_trace_enable(handle, on: bool = True):

@@ -16,8 +16,10 @@ def prof(n, total_ms, update_ms, key="fp32"):
 
 def test_sstep_roofline_splits_basis_and_update():
     r = bench.roofline("fp32_sweep", prof(10, 1.5, 0.9), G, "fp32",
-                       {"ppt": 4, "cx": 22, "nwg": 768}, sstep=True)
+                       {"ppt": 4, "cx": 22, "nwg": 768,
+                        "basis": {"threads": 1024, "ppt": 4, "cx": 16, "nwg": 256}}, sstep=True)
     assert r["kernel"].startswith("k_sstep update")
+    assert r["basis_kernel"]["launch_shape"]["grid_threads"] == 256 * 1024
     assert r["avg_launch_us"] == pytest.approx(90.0)
     assert r["achieved"] == pytest.approx(24 * G / 90e-6 / 1e9, rel=1e-3)
     b = r["basis_kernel"]
@@ -39,21 +41,26 @@ def test_traffic_needs_matching_source_and_shape(tmp_path, monkeypatch):
     src.write_text("kernel source")
     t = {"stencil_sha": bench.source_hash(str(src)),
          "fp32_update": {"hbm_bytes_per_launch": 111, "launch_shape": {"ppt": 4, "cx": 22}},
-         "fp32_basis": {"hbm_bytes_per_launch": 22, "launch_shape": {"ppt": 4, "cx": 22}}}
+         "fp32_basis": {"hbm_bytes_per_launch": 22,
+                        "launch_shape": {"threads": 1024, "ppt": 4, "cx": 16}}}
     f = tmp_path / "traffic.json"
     f.write_text(json.dumps(t))
     monkeypatch.setitem(bench.TRAFFIC, "sstep", (str(f), str(src)))
 
-    def fresh(cx):
+    def fresh(cx, basis_threads=1024):
         r = bench.roofline("fp32_sweep", prof(10, 1.5, 0.9), G, "fp32",
-                           {"ppt": 4, "cx": cx, "nwg": 768}, sstep=True)
+                           {"ppt": 4, "cx": cx, "nwg": 768,
+                            "basis": {"threads": basis_threads, "ppt": 4, "cx": 16, "nwg": 256}},
+                           sstep=True)
         bench.attach_traffic(r, "fp32", "sstep")
         return r
 
     r = fresh(22)
     assert r["traffic"] == 111 and r["basis_kernel"]["traffic"] == 22
-    r = fresh(32)  # another launch shape: not the one the counters saw
-    assert r["traffic"] is None and r["basis_kernel"]["traffic"] is None
+    r = fresh(32)  # another update shape: not the one the counters saw
+    assert r["traffic"] is None and r["basis_kernel"]["traffic"] == 22
+    r = fresh(22, basis_threads=256)  # another basis shape
+    assert r["traffic"] == 111 and r["basis_kernel"]["traffic"] is None
     src.write_text("changed kernel source")  # counters taken with other code
     r = fresh(22)
     assert r["traffic"] is None and r["basis_kernel"]["traffic"] is None

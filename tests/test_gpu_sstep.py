@@ -287,3 +287,44 @@ def test_sstep_profile_counts_outer_steps(maze):
     assert 1 <= n <= (out["stats"]["iters"] + 1) // 2
     assert 0 < pr["fp32_update_ms"] < ms
     g.close()
+
+
+@pytest.mark.parametrize("N,shape,precision", [(100, "1024:2:8", 0), (64, "1024:4:16", 1),
+                                               (36, "1024:1:8", 0), (100, "1024:1:32", 1),
+                                               (64, "1024:2:64", 1)])
+def test_sstep_basis_shapes(maze, monkeypatch, N, shape, precision):
+    """Forced 1024-thread basis shapes (a segment that is a whole plane, a
+    ragged last segment, one x run): the same field as the oracle."""
+    monkeypatch.setenv("MAZE_BASIS_SHAPE", shape)
+    box = 0.4 * N
+    pos, Q, vel = random_system(3 * N, box, seed=N + precision)
+    print(f"case: sstep basis shape {shape} N={N} precision {precision}", flush=True)
+    tol = 1e-12 if precision == 0 else 1e-9
+    g = maze.Session(dev(Q), dev(pos), box, 0.4, tol=tol, precision=precision,
+                     flags=maze.MAZE_FLAG_SSTEP)
+    nt, ppt, cx = (int(v) for v in shape.split(":"))
+    bs = maze.maze_basis_shape(g.handle)
+    assert (bs["threads"], bs["ppt"], bs["cx"]) == (nt, ppt, cx)
+    o = oracle.Session(Q, pos, box, 0.4, tol=1e-13)
+    p = pos + vel
+    out = g.step(dev(p), want_field=True)
+    ref = o.step(p)
+    assert out["status"] == 0
+    bound = FIELD_TOL if precision == 0 else kappa(N) * out["stats"]["rel_residual"] * 1.01 + 1e-12
+    assert rel(out["field"], ref["field"]) <= bound
+    g.close()
+
+
+def test_sstep_tuned_basis_shape_is_cached(maze):
+    s = inputs.molten_nacl(8, seed=4)
+    print("case: sstep tuned basis shape 128^3", flush=True)
+    kw = dict(tol=1e-8, precision=maze.MAZE_MIXED, flags=maze.MAZE_FLAG_SSTEP)
+    a = maze.Session(dev(s.charges), dev(s.pos), s.box, s.grid_spacing, **kw)
+    b = maze.Session(dev(s.charges), dev(s.pos), s.box, s.grid_spacing, **kw)
+    sa, sb = maze.maze_basis_shape(a.handle), maze.maze_basis_shape(b.handle)
+    print("basis shape", sa, flush=True)
+    assert sa == sb and sa["threads"] in (256, 1024) and sa["nwg"] >= 1
+    ra, rb = a.step(dev(s.pos + s.vel)), b.step(dev(s.pos + s.vel))
+    assert ra["status"] == 0 and torch.equal(ra["forces"], rb["forces"])
+    a.close()
+    b.close()
