@@ -317,7 +317,7 @@ def copy_calibration(gib: float = 2.0, reps: int = 5):
                       "launches": reps}))
 
 
-def bench_ensemble(steps: int, warmup: int, tol: float = 1e-8):
+def bench_ensemble(steps: int, warmup: int, tol: float = 1e-8, flags: int = 0):
     """64 molten-NaCl replicas of uneven size (2..6 cells per side, 32^3 to
     96^3 grids, 1100-1400 K), mixed precision, advanced together with one
     batched MD step per round; the same replicas stepped one by one for
@@ -327,7 +327,7 @@ def bench_ensemble(steps: int, warmup: int, tol: float = 1e-8):
 
     reps = inputs.ensemble_replicas(64, master_seed=4)
     runs = [md.MDRun(inputs.molten_nacl(r.n_cells, seed=r.seed, temperature=r.temperature),
-                     tol=tol, precision=maze.MAZE_MIXED) for r in reps]
+                     tol=tol, precision=maze.MAZE_MIXED, flags=flags) for r in reps]
     for _ in range(warmup):
         md.step_many(runs, want_stats=False)
     torch.cuda.synchronize()
@@ -352,6 +352,7 @@ def bench_ensemble(steps: int, warmup: int, tol: float = 1e-8):
     lat_ms = np.array(lat) * 1e3
     return {"replicas": len(reps), "ions_total": ions, "grid_points_total": pts,
             "tol_rel_residual": tol, "precision": "mixed", "steps": steps,
+            "cg_form": "two-iteration" if flags & maze.MAZE_FLAG_SSTEP else "one-iteration",
             "replica_steps_per_s": round(len(reps) * steps / t_batch, 1),
             "ensemble_steps_per_s": round(steps / t_batch, 3),
             "step_ms": {"p50": round(float(np.percentile(lat_ms, 50)), 3),
@@ -624,7 +625,7 @@ def main():
         log(f"bench: observables {line['observables']}")
     if not args.no_ensemble:
         log("bench: ensemble of 64 replicas")
-        line["ensemble"] = bench_ensemble(max(3, args.steps // 3), 4)
+        line["ensemble"] = bench_ensemble(max(3, args.steps // 3), 4, flags=cg_flags)
         log(f"bench: ensemble {line['ensemble']}")
     if not args.no_serving:
         log("bench: serving")

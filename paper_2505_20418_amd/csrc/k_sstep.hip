@@ -399,7 +399,7 @@ __device__ __forceinline__ void sstep_wg(const SweepArgs<T>& a, const SweepGeom&
       }
 #pragma unroll
       for (int k = 0; k < NH; ++k) pof[k] = sp * ld<T>(pp, boo[k]);
-      if (UPDATE && !a.zero_x && own_u) {
+      if (UPDATE && !(FIRST && a.zero_x) && own_u) {
         const auto xp = pl_rsrc((const T*)a.x, u, Ps);
 #pragma unroll
         for (int j = 0; j < PPT; ++j) xf[j] = ld<T>(xp, bo[j]);
@@ -500,7 +500,7 @@ __device__ __forceinline__ void sstep_wg(const SweepArgs<T>& a, const SweepGeom&
       for (int k = 0; k < NH; ++k) pon[k] = pof[k];
       if (UPDATE) {
 #pragma unroll
-        for (int j = 0; j < PPT; ++j) xc[j] = (a.zero_x || !own_u) ? (T)0 : xf[j];
+        for (int j = 0; j < PPT; ++j) xc[j] = ((FIRST && a.zero_x) || !own_u) ? (T)0 : xf[j];
       }
     }
   }
@@ -520,6 +520,29 @@ __global__ __launch_bounds__(NT) void k_sstep(SweepArgs<T> a, SweepGeom g, int p
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ double red[kNs * (NT / 64)];
   sstep_wg<T, FIRST, UPDATE, PPT, NH, NT>(a, g, par, xcd_remap(blockIdx.x, g.nwg), smem_raw, red);
+}
+
+// Batched form: the workgroups of `count` sessions in one launch; session i
+// owns workgroups [wg_begin[i], wg_begin[i+1]) and runs the same
+// per-workgroup code as alone (logical index = block - wg_begin[i]), so a
+// session's result does not depend on its batch.
+template <typename T, bool FIRST, bool UPDATE, int PPT, int NH, int NT>
+__global__ __launch_bounds__(NT) void k_sstep_batch(const SweepArgs<T>* __restrict__ args,
+                                                    const SweepGeom* __restrict__ geoms,
+                                                    const int* __restrict__ wg_begin, int count,
+                                                    int par) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ double red[kNs * (NT / 64)];
+  const int b = blockIdx.x;
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (wg_begin[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  const SweepArgs<T> a = args[lo];
+  const SweepGeom g = geoms[lo];
+  sstep_wg<T, FIRST, UPDATE, PPT, NH, NT>(a, g, par, b - wg_begin[lo], smem_raw, red);
 }
 
 // Geometry of a two-iteration kernel with nt threads per workgroup
@@ -546,41 +569,71 @@ size_t sstep_lds_bytes(const SweepGeom& g, bool fp32) {
 
 namespace {
 
-template <typename T, bool FIRST, bool UPDATE, int PPT, int NH, int NT>
-hipError_t sstep_launch(const SweepArgs<T>& a, const SweepGeom& g, int par, hipStream_t st) {
-  static size_t allowed = 0;  // dynamic LDS the kernel is known to accept
-  const size_t lds = sstep_lds_bytes(g, sizeof(T) == 4);
+// Dynamic LDS the kernel fn accepts, raised once where it is below lds (the
+// runtime refuses the request for some workgroup sizes whose limit is
+// already the whole LDS, so the limit is queried first).
+hipError_t ensure_lds(const void* fn, size_t lds, size_t* allowed) {
   if (lds > 160 * 1024 - 2048) return hipErrorInvalidValue;
-  if (lds > 65536 && lds > allowed) {
-    // raise the kernel's limit only where it is below what this launch
-    // needs (the runtime refuses the request for some workgroup sizes whose
-    // limit is already the whole LDS)
-    const void* fn = (const void*)k_sstep<T, FIRST, UPDATE, PPT, NH, NT>;
-    hipFuncAttributes fa{};
-    if (hipFuncGetAttributes(&fa, fn) == hipSuccess && (size_t)fa.maxDynamicSharedSizeBytes >= lds) {
-      allowed = (size_t)fa.maxDynamicSharedSizeBytes;
-    } else {
-      const hipError_t e =
-          hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 2048);
-      if (e != hipSuccess) return e;
-      allowed = 160 * 1024 - 2048;
-    }
+  if (lds <= 65536 || lds <= *allowed) return hipSuccess;
+  hipFuncAttributes fa{};
+  if (hipFuncGetAttributes(&fa, fn) == hipSuccess && (size_t)fa.maxDynamicSharedSizeBytes >= lds) {
+    *allowed = (size_t)fa.maxDynamicSharedSizeBytes;
+    return hipSuccess;
   }
-  hipLaunchKernelGGL((k_sstep<T, FIRST, UPDATE, PPT, NH, NT>), dim3(g.nwg), dim3(NT), lds, st,
-                     a, g, par);
-  return hipGetLastError();
+  const hipError_t e =
+      hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 2048);
+  if (e == hipSuccess) *allowed = 160 * 1024 - 2048;
+  return e;
 }
 
-template <typename T, bool FIRST, bool UPDATE, int PPT, int NT>
-hipError_t sstep_nh(const SweepArgs<T>& a, const SweepGeom& g, int par, hipStream_t st) {
-  switch (sweep_nh_class(g.nh)) {
-    case 1: return sstep_launch<T, FIRST, UPDATE, PPT, 1, NT>(a, g, par, st);
-    case 2: return sstep_launch<T, FIRST, UPDATE, PPT, 2, NT>(a, g, par, st);
+// One session: args and geometry on the host.
+template <typename T, bool FIRST, bool UPDATE>
+struct SingleLaunch {
+  const SweepArgs<T>& a;
+  const SweepGeom& g;
+  int par;
+  hipStream_t st;
+  template <int PPT, int NH, int NT>
+  hipError_t run() const {
+    static size_t allowed = 0;
+    const size_t lds = sstep_lds_bytes(g, sizeof(T) == 4);
+    const hipError_t e = ensure_lds((const void*)k_sstep<T, FIRST, UPDATE, PPT, NH, NT>, lds,
+                                    &allowed);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_sstep<T, FIRST, UPDATE, PPT, NH, NT>), dim3(g.nwg), dim3(NT), lds, st,
+                       a, g, par);
+    return hipGetLastError();
+  }
+};
+
+// A batch of sessions of one template class (device arrays in L).
+template <typename T, bool FIRST, bool UPDATE>
+struct BatchLaunch {
+  const SweepLaunch& L;
+  hipStream_t st;
+  template <int PPT, int NH, int NT>
+  hipError_t run() const {
+    static size_t allowed = 0;
+    const hipError_t e = ensure_lds((const void*)k_sstep_batch<T, FIRST, UPDATE, PPT, NH, NT>,
+                                    L.lds, &allowed);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_sstep_batch<T, FIRST, UPDATE, PPT, NH, NT>), dim3(L.nwg_total),
+                       dim3(NT), L.lds, st, static_cast<const SweepArgs<T>*>(L.args), L.geoms,
+                       L.wg_begin, L.count, L.par);
+    return hipGetLastError();
+  }
+};
+
+template <bool UPDATE, int PPT, int NT, class F>
+hipError_t sstep_nh(int nh, const F& f) {
+  switch (nh) {
+    case 1: return f.template run<PPT, 1, NT>();
+    case 2: return f.template run<PPT, 2, NT>();
     case 4:
-      if constexpr (NT == kThreads) return sstep_launch<T, FIRST, UPDATE, PPT, 4, NT>(a, g, par, st);
+      if constexpr (NT == kThreads) return f.template run<PPT, 4, NT>();
       return hipErrorInvalidValue;
     case 8:
-      if constexpr (NT == kThreads) return sstep_launch<T, FIRST, UPDATE, PPT, 8, NT>(a, g, par, st);
+      if constexpr (NT == kThreads) return f.template run<PPT, 8, NT>();
       return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
   }
@@ -588,28 +641,39 @@ hipError_t sstep_nh(const SweepArgs<T>& a, const SweepGeom& g, int par, hipStrea
 
 // Workgroups of kThreads for every kernel; the basis kernel also comes in
 // 1024-thread workgroups (longer segments, less halo work per point).
-template <typename T, bool FIRST, bool UPDATE>
-hipError_t sstep_ppt(const SweepArgs<T>& a, const SweepGeom& g, int par, hipStream_t st) {
-  const int nt = g.S / g.ppt;
+template <bool UPDATE, class F>
+hipError_t sstep_dispatch(int nt, int ppt, int nh, const F& f) {
   if (nt == kThreads) {
-    switch (g.ppt) {
-      case 1: return sstep_nh<T, FIRST, UPDATE, 1, kThreads>(a, g, par, st);
-      case 2: return sstep_nh<T, FIRST, UPDATE, 2, kThreads>(a, g, par, st);
-      case 4: return sstep_nh<T, FIRST, UPDATE, 4, kThreads>(a, g, par, st);
+    switch (ppt) {
+      case 1: return sstep_nh<UPDATE, 1, kThreads>(nh, f);
+      case 2: return sstep_nh<UPDATE, 2, kThreads>(nh, f);
+      case 4: return sstep_nh<UPDATE, 4, kThreads>(nh, f);
       default: return hipErrorInvalidValue;
     }
   }
   if constexpr (!UPDATE) {
     if (nt == 1024) {
-      switch (g.ppt) {
-        case 1: return sstep_nh<T, FIRST, UPDATE, 1, 1024>(a, g, par, st);
-        case 2: return sstep_nh<T, FIRST, UPDATE, 2, 1024>(a, g, par, st);
-        case 4: return sstep_nh<T, FIRST, UPDATE, 4, 1024>(a, g, par, st);
+      switch (ppt) {
+        case 1: return sstep_nh<UPDATE, 1, 1024>(nh, f);
+        case 2: return sstep_nh<UPDATE, 2, 1024>(nh, f);
+        case 4: return sstep_nh<UPDATE, 4, 1024>(nh, f);
         default: return hipErrorInvalidValue;
       }
     }
   }
   return hipErrorInvalidValue;
+}
+
+template <typename T, bool FIRST, bool UPDATE>
+hipError_t sstep_ppt(const SweepArgs<T>& a, const SweepGeom& g, int par, hipStream_t st) {
+  const SingleLaunch<T, FIRST, UPDATE> f{a, g, par, st};
+  return sstep_dispatch<UPDATE>(g.S / g.ppt, g.ppt, sweep_nh_class(g.nh), f);
+}
+
+template <typename T, bool FIRST, bool UPDATE>
+hipError_t sstep_batch_ppt(const SweepLaunch& L, int nt, hipStream_t st) {
+  const BatchLaunch<T, FIRST, UPDATE> f{L, st};
+  return sstep_dispatch<UPDATE>(nt, L.ppt, L.nh, f);
 }
 
 template <typename T>
@@ -641,6 +705,21 @@ hipError_t launch_sstep_outer(const DeviceState& d, const SweepGeom& gb, const S
   const hipError_t e = launch_sstep_half(d, gb, gu, o, x, fp32, zero_x, false, st);
   if (e != hipSuccess) return e;
   return launch_sstep_half(d, gb, gu, o, x, fp32, zero_x, true, st);
+}
+
+hipError_t launch_sstep_batch(const SweepLaunch& L, int nt, bool fp32, bool first, bool update,
+                              hipStream_t st) {
+  if (L.count < 1 || L.nwg_total < 1) return hipErrorInvalidValue;
+  if (fp32) {
+    if (first) return update ? sstep_batch_ppt<float, true, true>(L, nt, st)
+                             : sstep_batch_ppt<float, true, false>(L, nt, st);
+    return update ? sstep_batch_ppt<float, false, true>(L, nt, st)
+                  : sstep_batch_ppt<float, false, false>(L, nt, st);
+  }
+  if (first) return update ? sstep_batch_ppt<double, true, true>(L, nt, st)
+                           : sstep_batch_ppt<double, true, false>(L, nt, st);
+  return update ? sstep_batch_ppt<double, false, true>(L, nt, st)
+                : sstep_batch_ppt<double, false, false>(L, nt, st);
 }
 
 // Basis-kernel shapes that compile without register spills: 256 threads in

@@ -453,7 +453,9 @@ struct BatchTable {
   char* dev = nullptr;
   char* host = nullptr;
   hipEvent_t ev[2] = {nullptr, nullptr};
+  // o_geom2 / o_wgb2: the update kernels' shapes of a two-iteration batch
   size_t o_args = 0, o_geom = 0, o_wgb = 0, o_scs = 0, o_poll = 0, o_sco = 0, bytes = 0;
+  size_t o_geom2 = 0, o_wgb2 = 0;
 };
 static BatchTable g_tables[64];
 
@@ -471,6 +473,8 @@ static int ensure_table(int device, int count, BatchTable** out) {
     n.o_args = o; o = align256(o + sizeof(SweepArgs<double>) * cap);
     n.o_geom = o; o = align256(o + sizeof(SweepGeom) * cap);
     n.o_wgb = o;  o = align256(o + sizeof(int) * (2 * cap + 16));
+    n.o_geom2 = o; o = align256(o + sizeof(SweepGeom) * cap);
+    n.o_wgb2 = o; o = align256(o + sizeof(int) * (2 * cap + 16));
     n.o_scs = o;  o = align256(o + sizeof(Scalars*) * cap);
     n.o_poll = o; o = align256(o + sizeof(int32_t) * 6 * cap);
     n.o_sco = o;  o = align256(o + sizeof(Scalars) * cap);
@@ -546,21 +550,84 @@ static bool batch_throughput_mode(const std::vector<CgJob>& jobs) {
   return w >= kThroughputWgs;
 }
 
+// The polling loop of a batched solve: queues `per` units (first call:
+// at least first_units) through launch(k), then copies every session's
+// status to pinned memory and waits for the copy of the group before, so
+// the device always has a group queued; returns once every session is done
+// (or the guard is reached), with iterations and codes in the jobs.
+template <class F>
+static int batch_loop(std::vector<CgJob>& jobs, const std::vector<int>& order, BatchTable* t,
+                      hipStream_t st, long long guard, int per, int first_units, F launch) {
+  const int n = (int)jobs.size();
+  char* H = t->host;
+  int32_t* poll_h = (int32_t*)(H + t->o_poll);
+  int32_t* poll_d = (int32_t*)(t->dev + t->o_poll);
+  long long k = 0;
+  int batch = 0;
+  bool have_prev = false;
+  for (;;) {
+    const int nb = (batch == 0) ? std::max(per, first_units) : per;
+    for (int b = 0; b < nb; ++b, ++k) HIP_TRY(launch(k));
+    const bool last = k > guard;
+    const int slot = batch & 1;
+    HIP_TRY(launch_batch_poll((Scalars* const*)(t->dev + t->o_scs), n, poll_d + 3 * n * slot, st));
+    HIP_TRY(hipMemcpyAsync(poll_h + 3 * n * slot, poll_d + 3 * n * slot, sizeof(int32_t) * 3 * n,
+                           hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipEventRecord(t->ev[slot], st));
+    if (have_prev || last) {
+      const int ws = last ? slot : (slot ^ 1);
+      HIP_TRY(hipEventSynchronize(t->ev[ws]));
+      const int32_t* p = poll_h + 3 * n * ws;
+      bool all = true;
+      for (int q = 0; q < n; ++q) all &= (p[3 * q] != 0 || p[3 * q + 2] != 0);
+      if (all || last) {
+        for (int q = 0; q < n; ++q) {
+          CgJob& j = jobs[order[q]];
+          j.err = p[3 * q + 2] != 0;
+          j.iters = p[3 * q + 1];
+          j.code = p[3 * q] ? p[3 * q] : 3;
+        }
+        for (CgJob& j : jobs) {
+          if (!j.err && j.s->trace) {
+            std::vector<maze_session*> one{j.s};
+            std::vector<Scalars> h;
+            int rc = gather_scalars(one, h);
+            if (rc != MAZE_OK) return rc;
+            rc = trace_collect(j.s, j.iters, h[0].qnorm);
+            if (rc != MAZE_OK) return rc;
+          }
+        }
+        return MAZE_OK;
+      }
+    }
+    have_prev = true;
+    ++batch;
+  }
+}
+
+static int run_sstep_batch(std::vector<CgJob>& jobs, bool fp32, bool zero_x, int first_batch);
+
 // Batched CG solves: one launch per sweep and template class covers every
 // session; a compact status array is polled.
 static int run_cg_batch(std::vector<CgJob>& jobs, bool fp32, bool zero_x, int first_batch) {
   const int n = (int)jobs.size();
   if (n == 1) return run_cg(jobs[0], fp32, zero_x, first_batch);
-  // the two-iteration form has no batched kernels: such a batch is solved
-  // one session after another
-  for (const CgJob& j : jobs)
-    if (sstep_of(j.s)) {
-      for (CgJob& q : jobs) {
-        const int rc = run_cg(q, fp32, zero_x, first_batch);
-        if (rc != MAZE_OK) return rc;
-      }
+  // two-iteration sessions run in batches of their own
+  {
+    std::vector<CgJob> ss, one;
+    for (const CgJob& j : jobs) (sstep_of(j.s) ? ss : one).push_back(j);
+    if (!ss.empty()) {
+      int rc = MAZE_OK;
+      if (one.empty()) return run_sstep_batch(jobs, fp32, zero_x, first_batch);
+      rc = run_cg_batch(one, fp32, zero_x, first_batch);
+      if (rc != MAZE_OK) return rc;
+      rc = run_cg_batch(ss, fp32, zero_x, first_batch);
+      if (rc != MAZE_OK) return rc;
+      size_t a = 0, b = 0;  // results back into the caller's order
+      for (CgJob& j : jobs) j = sstep_of(j.s) ? ss[b++] : one[a++];
       return MAZE_OK;
     }
+  }
   BatchTable* t = nullptr;
   int rc = ensure_table(jobs[0].s->device, n, &t);
   if (rc != MAZE_OK) return rc;
@@ -612,64 +679,127 @@ static int run_cg_batch(std::vector<CgJob>& jobs, bool fp32, bool zero_x, int fi
   for (const Cls& c : classes)
     if (c.nh == 0 || c.lds > 160 * 1024 - 1024) return MAZE_E_INVALID;
   HIP_TRY(hipMemcpyAsync(t->dev, H, t->o_poll, hipMemcpyHostToDevice, st));
-  int32_t* poll_h = (int32_t*)(H + t->o_poll);
-  int32_t* poll_d = (int32_t*)(t->dev + t->o_poll);
-  long long k = 0;
-  int batch = 0;
-  bool have_prev = false;
-  for (;;) {
-    const int nb = (batch == 0) ? std::max(kPollBatch, first_batch) : kPollBatch;
-    for (int b = 0; b < nb; ++b, ++k) {
-      for (const Cls& c : classes) {
+  return batch_loop(jobs, order, t, st, guard, kPollBatch, first_batch, [&](long long k) {
+    for (const Cls& c : classes) {
+      SweepLaunch L{};
+      L.batch = true;
+      L.par = (int)(k & 1);
+      L.ppt = c.ppt;
+      L.nh = c.nh;
+      L.args = t->dev + t->o_args + (size_t)c.c0 * sizeof(SweepArgs<double>);
+      L.geoms = (const SweepGeom*)(t->dev + t->o_geom) + c.c0;
+      L.wg_begin = (const int*)(t->dev + t->o_wgb) + c.wgb0;
+      L.count = c.c1 - c.c0;
+      L.nwg_total = c.nwg;
+      L.lds = c.lds;
+      const hipError_t e = launch_sweep(L, fp32, k == 0, st);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  });
+}
+
+// Batched two-iteration solves. The sessions are ordered by the template
+// class of their basis kernel, then of their update kernel; each kernel
+// runs one launch per run of equal class. In latency mode the shapes are
+// the sessions' own (basis and latency shapes), so a session's result is
+// bitwise the one it gets alone; in throughput mode both kernels take the
+// throughput shape.
+static int run_sstep_batch(std::vector<CgJob>& jobs, bool fp32, bool zero_x, int first_batch) {
+  const int n = (int)jobs.size();
+  BatchTable* t = nullptr;
+  int rc = ensure_table(jobs[0].s->device, n, &t);
+  if (rc != MAZE_OK) return rc;
+  hipStream_t st = jobs[0].s->stream;
+  const bool tp = batch_throughput_mode(jobs);
+  auto gb = [&](int i) -> const SweepGeom& { return tp ? jobs[i].s->sweep_tp : jobs[i].s->sbasis; };
+  auto gu = [&](int i) -> const SweepGeom& { return tp ? jobs[i].s->sweep_tp : jobs[i].s->sweep; };
+  auto cls = [](const SweepGeom& g) {
+    return ((g.S / g.ppt) * 8 + g.ppt) * 16 + sweep_nh_class(g.nh);
+  };
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    const int ca = cls(gb(a)), cb = cls(gb(b));
+    return ca != cb ? ca < cb : cls(gu(a)) < cls(gu(b));
+  });
+  struct Grp { int c0, c1, wgb0, nwg, nt, ppt, nh; size_t lds; };
+  std::vector<Grp> gbs, gus;
+  char* H = t->host;
+  SweepGeom* hg = (SweepGeom*)(H + t->o_geom);
+  SweepGeom* hg2 = (SweepGeom*)(H + t->o_geom2);
+  int* hw = (int*)(H + t->o_wgb);
+  int* hw2 = (int*)(H + t->o_wgb2);
+  Scalars** hs = (Scalars**)(H + t->o_scs);
+  int wpos = 0, wpos2 = 0;
+  long long guard = 0;
+  for (int q = 0; q < n; ++q) {
+    const int i = order[q];
+    maze_session* s = jobs[i].s;
+    const SweepGeom& b = gb(i);
+    const SweepGeom& u = gu(i);
+    if (b.nwg > s->d.part_stride || u.nwg > s->d.part_stride) return MAZE_E_INVALID;
+    if (!sstep_basis_shape_ok(b, fp32) || sweep_nh_class(u.nh) == 0) return MAZE_E_INVALID;
+    const int cb = cls(b), cu = cls(u);
+    if (gbs.empty() || cls(hg[gbs.back().c0]) != cb) {
+      if (!gbs.empty()) hw[wpos++] = gbs.back().nwg;
+      gbs.push_back({q, q, wpos, 0, b.S / b.ppt, b.ppt, sweep_nh_class(b.nh), 0});
+    }
+    if (gus.empty() || cls(hg2[gus.back().c0]) != cu) {
+      if (!gus.empty()) hw2[wpos2++] = gus.back().nwg;
+      gus.push_back({q, q, wpos2, 0, kThreads, u.ppt, sweep_nh_class(u.nh), 0});
+    }
+    hg[q] = b;
+    hg2[q] = u;
+    Grp& B = gbs.back();
+    hw[wpos++] = B.nwg;
+    B.nwg += b.nwg;
+    B.c1 = q + 1;
+    B.lds = std::max(B.lds, sstep_lds_bytes(b, fp32));
+    Grp& U = gus.back();
+    hw2[wpos2++] = U.nwg;
+    U.nwg += u.nwg;
+    U.c1 = q + 1;
+    U.lds = std::max(U.lds, sstep_lds_bytes(u, fp32));
+    hs[q] = s->d.sc;
+    // the update kernel reads one partial per basis workgroup
+    if (fp32) {
+      ((SweepArgs<float>*)(H + t->o_args))[q] =
+          make_sweep_args<float>(s->d, (float*)jobs[i].x, 0, b.nwg, zero_x);
+    } else {
+      ((SweepArgs<double>*)(H + t->o_args))[q] =
+          make_sweep_args<double>(s->d, (double*)jobs[i].x, 0, b.nwg, zero_x);
+    }
+    guard = std::max(guard, sweep_guard(jobs[i].max_iter, first_batch));
+  }
+  // at most one start per session and one total per run: 2n + 1 entries
+  hw[wpos++] = gbs.back().nwg;
+  hw2[wpos2++] = gus.back().nwg;
+  for (const std::vector<Grp>* gs : {&gbs, &gus})
+    for (const Grp& g : *gs)
+      if (g.nh == 0 || g.lds > 160 * 1024 - 2048) return MAZE_E_INVALID;
+  HIP_TRY(hipMemcpyAsync(t->dev, H, t->o_poll, hipMemcpyHostToDevice, st));
+  return batch_loop(jobs, order, t, st, guard, kPollBatch / 2, first_batch / 2, [&](long long k) {
+    for (int half = 0; half < 2; ++half) {
+      const bool update = half == 1;
+      for (const Grp& g : update ? gus : gbs) {
         SweepLaunch L{};
         L.batch = true;
         L.par = (int)(k & 1);
-        L.ppt = c.ppt;
-        L.nh = c.nh;
-        L.args = t->dev + t->o_args + (size_t)c.c0 * sizeof(SweepArgs<double>);
-        L.geoms = (const SweepGeom*)(t->dev + t->o_geom) + c.c0;
-        L.wg_begin = (const int*)(t->dev + t->o_wgb) + c.wgb0;
-        L.count = c.c1 - c.c0;
-        L.nwg_total = c.nwg;
-        L.lds = c.lds;
-        HIP_TRY(launch_sweep(L, fp32, k == 0, st));
+        L.ppt = g.ppt;
+        L.nh = g.nh;
+        L.args = t->dev + t->o_args + (size_t)g.c0 * sizeof(SweepArgs<double>);
+        L.geoms = (const SweepGeom*)(t->dev + (update ? t->o_geom2 : t->o_geom)) + g.c0;
+        L.wg_begin = (const int*)(t->dev + (update ? t->o_wgb2 : t->o_wgb)) + g.wgb0;
+        L.count = g.c1 - g.c0;
+        L.nwg_total = g.nwg;
+        L.lds = g.lds;
+        const hipError_t e = launch_sstep_batch(L, g.nt, fp32, k == 0, update, st);
+        if (e != hipSuccess) return e;
       }
     }
-    const bool last = k > guard;
-    const int slot = batch & 1;
-    HIP_TRY(launch_batch_poll((Scalars* const*)(t->dev + t->o_scs), n, poll_d + 3 * n * slot, st));
-    HIP_TRY(hipMemcpyAsync(poll_h + 3 * n * slot, poll_d + 3 * n * slot, sizeof(int32_t) * 3 * n,
-                           hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipEventRecord(t->ev[slot], st));
-    if (have_prev || last) {
-      const int ws = last ? slot : (slot ^ 1);
-      HIP_TRY(hipEventSynchronize(t->ev[ws]));
-      const int32_t* p = poll_h + 3 * n * ws;
-      bool all = true;
-      for (int q = 0; q < n; ++q) all &= (p[3 * q] != 0 || p[3 * q + 2] != 0);
-      if (all || last) {
-        for (int q = 0; q < n; ++q) {
-          CgJob& j = jobs[order[q]];
-          j.err = p[3 * q + 2] != 0;
-          j.iters = p[3 * q + 1];
-          j.code = p[3 * q] ? p[3 * q] : 3;
-        }
-        for (CgJob& j : jobs) {
-          if (!j.err && j.s->trace) {
-            std::vector<maze_session*> one{j.s};
-            std::vector<Scalars> h;
-            rc = gather_scalars(one, h);
-            if (rc != MAZE_OK) return rc;
-            rc = trace_collect(j.s, j.iters, h[0].qnorm);
-            if (rc != MAZE_OK) return rc;
-          }
-        }
-        return MAZE_OK;
-      }
-    }
-    have_prev = true;
-    ++batch;
-  }
+    return hipSuccess;
+  });
 }
 
 // Multigrid-preconditioned CG of one session on x (FP64): per iteration a

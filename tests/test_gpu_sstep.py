@@ -245,21 +245,33 @@ def test_sstep_graph_chunks_bitwise(maze):
         b.close()
 
 
-def test_sstep_batch_is_bitwise_alone(maze):
-    """A batch holding two-iteration sessions solves them one by one: each
-    ends bitwise where the same step alone leaves it."""
-    cases = [(2, 32, 0, 1e-10), (3, 48, 1, 1e-8)]
-    print("case: sstep batch", cases, flush=True)
+BATCH_CASES = [(2, 32, 0, 1e-10), (3, 48, 1, 1e-8), (4, 64, 0, 1e-9), (2, 20, 1, 1e-7),
+               (5, 76, 1, 1e-8), (3, 36, 0, 1e-11), (4, 64, 1, 1e-8)]
+
+
+def _batch_sessions(maze, seed0):
     systems, alone, batch = [], [], []
-    for i, (n_cells, N, prec, tol) in enumerate(cases):
-        s = inputs.molten_nacl(n_cells, seed=40 + i)
+    for i, (n_cells, N, prec, tol) in enumerate(BATCH_CASES):
+        s = inputs.molten_nacl(n_cells, seed=seed0 + i)
         s.grid_spacing = s.box / N
         kw = dict(tol=tol, precision=prec, coulomb_k=inputs.COULOMB_K_EV_A,
                   flags=maze.MAZE_FLAG_SSTEP)
         systems.append(s)
         alone.append(maze.Session(dev(s.charges), dev(s.pos), s.box, s.grid_spacing, **kw))
         batch.append(maze.Session(dev(s.charges), dev(s.pos), s.box, s.grid_spacing, **kw))
-    for k in range(2):
+    return systems, alone, batch
+
+
+def test_sstep_batch_is_bitwise_alone(maze):
+    """Batches of two-iteration sessions (uneven grids, both precisions,
+    basis kernels of 256 and 1024 threads) run batched kernels; below the
+    fill level each session ends bitwise where the same step alone leaves
+    it."""
+    print("case: sstep batch", BATCH_CASES, flush=True)
+    systems, alone, batch = _batch_sessions(maze, 40)
+    assert sum(maze.maze_launch_shape(b.handle)["throughput"]["nwg"] for b in batch) < 256
+    print("basis shapes", [maze.maze_basis_shape(b.handle)["threads"] for b in batch], flush=True)
+    for k in range(3):
         pos = [dev(s.pos + (k + 1) * s.vel) for s in systems]
         ref = [a.step(p, want_field=True) for a, p in zip(alone, pos)]
         forces = [torch.empty(s.n_ions, 3, dtype=torch.float64, device="cuda") for s in systems]
@@ -267,8 +279,34 @@ def test_sstep_batch_is_bitwise_alone(maze):
         assert rc == maze.MAZE_OK
         for i, (r, b) in enumerate(zip(ref, batch)):
             assert st[i]["iters"] == r["stats"]["iters"], i
+            assert st[i]["refinements"] == r["stats"]["refinements"], i
             assert torch.equal(forces[i], r["forces"]), i
             assert torch.equal(b.grid(maze.GRID_PHI), r["field"]), i
+    for x in alone + batch:
+        x.close()
+
+
+def test_sstep_batch_throughput_mode(maze, monkeypatch):
+    """Forced throughput mode (both kernels in the throughput shape, another
+    summation order): every session meets its tolerance, and the field
+    differs from the step alone by at most the two solves' residuals through
+    the inverse operator, (4 pi / h) 2 tol ||q|| / lambda_min with
+    lambda_min = 2 (1 - cos(2 pi / N))."""
+    monkeypatch.setenv("MAZE_BATCH_MODE", "throughput")
+    print("case: sstep batch throughput mode", flush=True)
+    systems, alone, batch = _batch_sessions(maze, 60)
+    pos = [dev(s.pos + s.vel) for s in systems]
+    ref = [a.step(p, want_field=True) for a, p in zip(alone, pos)]
+    rc, st = maze.maze_step_batch([b.handle for b in batch], pos)
+    assert rc == maze.MAZE_OK
+    for i, (r, b) in enumerate(zip(ref, batch)):
+        n_cells, N, prec, tol = BATCH_CASES[i]
+        assert st[i]["status"] == maze.MAZE_OK and st[i]["rel_residual"] <= tol, i
+        h = systems[i].box / N
+        qn = torch.linalg.norm(b.grid(maze.GRID_Q)).item()
+        bound = (4 * math.pi / h) * 2 * tol * qn / (2 * (1 - math.cos(2 * math.pi / N)))
+        d = torch.linalg.norm(b.grid(maze.GRID_PHI) - r["field"]).item()
+        assert d <= bound, (i, d, bound)
     for x in alone + batch:
         x.close()
 
