@@ -408,7 +408,7 @@ def bench_observables(system, tol, steps, warmup, flags=0):
     return out
 
 
-def bench_serving(full: bool, rate_hz: float = 200.0):
+def bench_serving(full: bool, rate_hz: float = 200.0, flags: int = 0):
     """Poisson stream (mean 200 requests/s) of MD-step requests over molten-
     NaCl sessions of log-uniform size, half mixed at 1e-6, half FP64 at
     1e-10, admitted by HBM budget and served with continuous batching."""
@@ -419,7 +419,7 @@ def bench_serving(full: bool, rate_hz: float = 200.0):
     else:
         n_sess, max_cells, n_req, budget = 64, 8, 400, 16 << 30
     specs = serve.specs_from_inputs(count=n_sess, seed=5, max_cells=max_cells)
-    srv = serve.Server(serve.GpuBackend(), specs, budget, max_batch=64)
+    srv = serve.Server(serve.GpuBackend(flags=flags), specs, budget, max_batch=64)
     t0 = time.perf_counter()
     resident = srv.prefill()
     t_prefill = time.perf_counter() - t0
@@ -432,7 +432,8 @@ def bench_serving(full: bool, rate_hz: float = 200.0):
     rep.update({"sessions": n_sess, "max_ions": 8 * max_cells ** 3,
                 "max_grid": inputs_grid(max_cells), "arrival_rate_hz": rate_hz,
                 "prefilled_resident": resident, "prefill_s": round(t_prefill, 2),
-                "mix": "full" if full else "reduced (sessions up to 4096 ions, 128^3)"})
+                "mix": "full" if full else "reduced (sessions up to 4096 ions, 128^3)",
+                "cg_form": "two-iteration" if flags else "one-iteration"})
     return rep
 
 
@@ -629,7 +630,7 @@ def main():
         log(f"bench: ensemble {line['ensemble']}")
     if not args.no_serving:
         log("bench: serving")
-        line["serving"] = bench_serving(args.serving_full, args.serving_rate)
+        line["serving"] = bench_serving(args.serving_full, args.serving_rate, flags=cg_flags)
         log(f"bench: serving {line['serving']}")
     line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)

@@ -87,8 +87,9 @@ enum {
      per two iterations in FP32 (64 in FP64), against 48 (96). The test on
      the residual after the first of the two iterations uses its Gram form;
      with MAZE_NORM_ABSMAX the test runs every two iterations. Not with
-     MAZE_FLAG_MULTIGRID (MAZE_E_INVALID). A batch holding such a session
-     solves its sessions one after another. */
+     MAZE_FLAG_MULTIGRID (MAZE_E_INVALID). Batches run batched forms of both
+     kernels; sessions without the flag in the same batch are solved as a
+     batch of their own. */
   MAZE_FLAG_SSTEP = 16
 };
 

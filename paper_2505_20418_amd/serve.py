@@ -70,12 +70,14 @@ class Completion:
 
 
 class GpuBackend:
-    """Sessions as device-resident MD runs of the library."""
+    """Sessions as device-resident MD runs of the library (flags: MAZE_FLAG_*
+    for every session, e.g. MAZE_FLAG_SSTEP for the two-iteration CG)."""
 
-    def __init__(self, device: str = "cuda", dt: float = 1.0):
+    def __init__(self, device: str = "cuda", dt: float = 1.0, flags: int = 0):
         from . import inputs, maze, md  # noqa: F401  (fails loudly without the library)
         self.device = device
         self.dt = dt
+        self.flags = flags
         maze.lib()
 
     def _system(self, spec: SessionSpec):
@@ -86,7 +88,7 @@ class GpuBackend:
         from . import inputs, maze
         s = self._system(spec)
         cfg = maze.maze_config(s.n_ions, 2, s.box, s.grid_spacing, spec.tol, 100000,
-                               maze.MAZE_MIXED if spec.mixed else maze.MAZE_FP64, 0, 0,
+                               maze.MAZE_MIXED if spec.mixed else maze.MAZE_FP64, 0, self.flags,
                                inputs.COULOMB_K_EV_A, None)
         n = s.n_ions
         particles = 8 * (3 * 5 + 2) * n + 8 * (6 * n + 8 * ((n + 255) // 256) + 8) + 4 * n
@@ -96,7 +98,7 @@ class GpuBackend:
         from . import maze, md
         return md.MDRun(self._system(spec), tol=spec.tol,
                         precision=maze.MAZE_MIXED if spec.mixed else maze.MAZE_FP64,
-                        dt=self.dt, device=self.device)
+                        dt=self.dt, device=self.device, flags=self.flags)
 
     def park(self, run) -> dict:
         state = run.save_state()
@@ -107,7 +109,7 @@ class GpuBackend:
         from . import maze, md
         return md.MDRun(self._system(spec), tol=spec.tol,
                         precision=maze.MAZE_MIXED if spec.mixed else maze.MAZE_FP64,
-                        dt=self.dt, device=self.device, restore=state)
+                        dt=self.dt, device=self.device, restore=state, flags=self.flags)
 
     def step(self, runs: Sequence) -> List[dict]:
         from . import md
