@@ -473,8 +473,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(the multi-GPU layout is described, not built).", file=sys.stderr)
+        print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} is not supported "
+              "(slab decomposition across GPUs is designed, not implemented).", file=sys.stderr)
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration()
