@@ -241,6 +241,36 @@ __global__ __launch_bounds__(kThreads) void k_mg_round(const double* __restrict_
   if (g < G) b[g] = (float)r[g];
 }
 
+// Level 0 of an FP32 V-cycle: the FP64 residual rounded into b, and the
+// first (zero-start, red) half-sweep of the pre-smoother in the same pass:
+// x = b / (6 c) on red points, 0 on black, with the float arithmetic of
+// k_mg_smooth, so the result is bitwise that of the two passes. One z-pair
+// (k even, k + 1) per thread, as in k_mg_smooth; N is even.
+__global__ __launch_bounds__(kThreads) void k_mg_round_zero(const double* __restrict__ r,
+                                                            float* __restrict__ b,
+                                                            float* __restrict__ x, int N,
+                                                            float inv_c, const Scalars* sc) {
+  if (ctl_ld(&sc->done) != 0) return;
+  const long long G2 = (long long)N * N * N / 2;
+  const long long m = (long long)blockIdx.x * kThreads + threadIdx.x;
+  if (m >= G2) return;
+  const long long g0 = 2 * m;
+  const int k0 = (int)(g0 % N);
+  const int j = (int)((g0 / N) % N);
+  const int i = (int)(g0 / ((long long)N * N));
+  const int d = ((i + j + k0) & 1) == 0 ? 0 : 1;  // the red point of the pair
+  const double2 rp = *reinterpret_cast<const double2*>(r + g0);
+  float2 bp;
+  bp.x = (float)rp.x;
+  bp.y = (float)rp.y;
+  *reinterpret_cast<float2*>(b + g0) = bp;
+  const float s6 = (float)(1.0 / 6.0);
+  float2 o;
+  o.x = (d == 0) ? bp.x * inv_c * s6 : 0.0f;
+  o.y = (d == 1) ? bp.y * inv_c * s6 : 0.0f;
+  *reinterpret_cast<float2*>(x + g0) = o;
+}
+
 // <r, z> per workgroup into the partial slot SL_MGRZ.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_mg_dot(const double* __restrict__ r,
@@ -269,22 +299,31 @@ static hipError_t vcycle_t(const DeviceState& d, const MgHierarchy& m, const dou
   T* const* B = reinterpret_cast<T* const*>(m.b);
   T* const* R = reinterpret_cast<T* const*>(m.r);
   const T* b0;
+  T* x0 = reinterpret_cast<T*>(z);
+  // an FP32 hierarchy rounds the level-0 residual in the pass that starts
+  // its pre-smoother (when level 0 is smoothed at all)
+  const bool fused0 = sizeof(T) == sizeof(float) && L > 1;
   if (sizeof(T) == sizeof(double)) {
     b0 = reinterpret_cast<const T*>(r);
+  } else if (fused0) {
+    hipLaunchKernelGGL(k_mg_round_zero, dim3(nblk(m.G[0] / 2)), dim3(kThreads), 0, st, r,
+                       reinterpret_cast<float*>(B[0]), reinterpret_cast<float*>(x0), m.N[0],
+                       (float)(1.0 / m.c[0]), (const Scalars*)d.sc);
+    b0 = B[0];
   } else {
     hipLaunchKernelGGL(k_mg_round, dim3(nblk(m.G[0])), dim3(kThreads), 0, st, r,
                        reinterpret_cast<float*>(B[0]), m.G[0], (const Scalars*)d.sc);
     b0 = B[0];
   }
-  T* x0 = reinterpret_cast<T*>(z);
   auto xl = [&](int l) { return l == 0 ? x0 : X[l]; };
   auto bl = [&](int l) { return l == 0 ? b0 : (const T*)B[l]; };
   const Scalars* sc = d.sc;
   for (int l = 0; l + 1 < L; ++l) {
     const int N = m.N[l];
     const double c = m.c[l];
-    hipLaunchKernelGGL(k_mg_smooth<T>, dim3(nblk(m.G[l] / 2)), dim3(kThreads), 0, st, xl(l), bl(l),
-                       N, (T)(1.0 / c), 0, 1, sc);
+    if (!(l == 0 && fused0))
+      hipLaunchKernelGGL(k_mg_smooth<T>, dim3(nblk(m.G[l] / 2)), dim3(kThreads), 0, st, xl(l),
+                         bl(l), N, (T)(1.0 / c), 0, 1, sc);
     hipLaunchKernelGGL(k_mg_smooth<T>, dim3(nblk(m.G[l] / 2)), dim3(kThreads), 0, st, xl(l), bl(l),
                        N, (T)(1.0 / c), 1, 0, sc);
     hipLaunchKernelGGL(k_mg_residual<T>, dim3(nblk(m.G[l])), dim3(kThreads), 0, st,
