@@ -36,9 +36,10 @@
 // With the max-norm test only the direct values exist, so the test runs
 // every two iterations.
 //
-// Layout and marching are those of the fused sweep: a workgroup owns a
-// segment of S = 256*PPT points of the (y, z) plane and a run of x planes
-// and walks them in x order. Stage U at plane u forms B p on the segment
+// Layout and marching are those of the fused sweep: a workgroup of NT
+// threads (256; the basis kernel also 1024) owns a segment of S = NT*PPT
+// points of the (y, z) plane and a run of x planes and walks them in x
+// order. Stage U at plane u forms B p on the segment
 // plus one row each side from p staged in LDS with two rows each side;
 // stage W at plane u-1 forms B^2 p and B rhat on the segment and either
 // accumulates the Gram sums or writes the updated vectors. r and p are
