@@ -1476,6 +1476,26 @@ int maze_init(const maze_config* cfg, const double* charges_dev, const double* p
   // clear them again for the first solve
   s->sweep = autotune_sweep(s);
   s->sweep_tp = throughput_sweep(s->d, s->cfg.precision == MAZE_MIXED);
+  if (sstep_of(s)) {
+    // the two-iteration kernels stage one more array in LDS than the sweep:
+    // on the largest grids keep the x run and shorten the segments until
+    // they fit
+    const bool f32 = s->cfg.precision == MAZE_MIXED;
+    for (SweepGeom* g : {&s->sweep, &s->sweep_tp}) {
+      if (sstep_basis_shape_ok(*g, f32)) continue;
+      for (int ppt : {2, 1}) {
+        const SweepGeom h = make_sweep_geom(d.N, ppt, g->cx);
+        if (h.ppt < g->ppt && sstep_basis_shape_ok(h, f32) && h.nwg <= d.part_stride) {
+          *g = h;
+          break;
+        }
+      }
+      if (!sstep_basis_shape_ok(*g, f32)) {
+        maze_destroy(s);
+        return MAZE_E_INVALID;
+      }
+    }
+  }
   s->sbasis = sstep_of(s) ? autotune_basis(s) : s->sweep;
   if (hipMemsetAsync(base, 0, L.total, stream) != hipSuccess ||
       hipMemcpyAsync(d.Q, charges_dev, sizeof(double) * n, hipMemcpyDeviceToDevice, stream) !=
