@@ -36,14 +36,17 @@
 // With the max-norm test only the direct values exist, so the test runs
 // every two iterations.
 //
-// Layout and marching are those of the fused sweep: a workgroup of NT
-// threads (256; the basis kernel also 1024) owns a segment of S = NT*PPT
-// points of the (y, z) plane and a run of x planes and walks them in x
-// order. Stage U at plane u forms B p on the segment
-// plus one row each side from p staged in LDS with two rows each side;
-// stage W at plane u-1 forms B^2 p and B rhat on the segment and either
-// accumulates the Gram sums or writes the updated vectors. r and p are
-// double-buffered by outer-step parity; x is updated in place.
+// Layout and marching follow the fused sweep: a workgroup of NT threads
+// (256; the basis kernel also 1024) owns a segment of S = NT*PPT points of
+// the (y, z) plane and a run of x planes and walks them in x order, upward
+// in even runs and downward in odd ones. Stage U at plane u forms B p on
+// the segment plus one row each side from p staged in LDS with two rows
+// each side; stage W at the plane before u forms B^2 p and B rhat on the
+// segment and either accumulates the Gram sums or writes the updated
+// vectors. r and p are double-buffered by outer-step parity; x is updated
+// in place.
+#include <algorithm>
+
 #include "device_util.h"
 
 namespace maze {
@@ -146,7 +149,11 @@ __device__ __forceinline__ void ahat(const double* v, double* o) {
 // first outer step of a solve, p = r / 6 (p is not read).
 template <typename T, bool FIRST, bool UPDATE, int PPT, int NH, int NT>
 __device__ __forceinline__ void sstep_wg(const SweepArgs<T>& a, const SweepGeom& g, int par,
-                                         int L, unsigned char* smem_raw, double* red) {
+                                         int L, unsigned char* smem_raw) {
+  // the workgroup reductions use the start of the dynamic LDS (before the
+  // march in the update kernel, after it in the basis kernel), so a
+  // workgroup needs no LDS beyond its plane buffers
+  double* red = reinterpret_cast<double*>(smem_raw);
   Scalars* sc = a.sc;
   if (ctl_ld(&sc->done) != 0 || ctl_ld(&sc->err) != 0) return;
   const int tid = threadIdx.x;
@@ -181,6 +188,7 @@ __device__ __forceinline__ void sstep_wg(const SweepArgs<T>& a, const SweepGeom&
       v[kNm] = fmax(v[kNm], a.part[(size_t)SL_SGMAX * a.pstride + i]);
     }
     block_reduce_ns<NT>(v, red);
+    __syncthreads();  // red is reused for the planes below
     double G[15];
 #pragma unroll
     for (int aa = 0; aa < 5; ++aa)
@@ -280,10 +288,17 @@ __device__ __forceinline__ void sstep_wg(const SweepArgs<T>& a, const SweepGeom&
   }
 
   // ---- geometry of this workgroup -------------------------------------------
+  // Logical indices run over the chunks of one segment first, so the
+  // workgroups that one XCD receives (a contiguous range) hold whole columns
+  // of x-neighbouring chunks. Odd chunks march down in x: two neighbouring
+  // chunks then start, or end, on the same four planes at the same time,
+  // and the second reader of a halo plane finds it in that XCD's L2.
   const int N = g.N, P = g.P, S = g.S;
-  const int seg = L % g.nseg, chunk = L / g.nseg;
+  const int chunk = L % g.nchunk, seg = L / g.nchunk;
   const int s0 = seg * S;
   const int x0 = chunk * g.cx, x1 = min(N, x0 + g.cx);
+  const int dir = (chunk & 1) ? -1 : 1;
+  const int ub = (chunk & 1) ? x1 : x0 - 1;  // plane of stage U at the first step
   const int E1 = S + 4 * N, E2 = S + 2 * N;
   T* P1 = reinterpret_cast<T*>(smem_raw);  // [2][E1] p of plane u (two rows each side)
   T* Q2 = P1 + 2 * E1;                     // [2][E2] B p of plane u-1 / u
@@ -340,6 +355,7 @@ __device__ __forceinline__ void sstep_wg(const SweepArgs<T>& a, const SweepGeom&
   const T c6 = (T)(1.0 / 6.0);
   const T c36 = (T)(1.0 / 36.0);
   const size_t Ps = (size_t)P;
+  // planes named for an upward march (u-1 is the plane before u)
   T pm[NU], pc[NU], pn[NU], pon[NH];  // p: planes u-1, u, u+1; outer halo of u+1
   T rc[NU];                           // r at plane u
   T rm1[PPT], rm2[PPT];               // r at planes u-1, u-2 (segment)
@@ -355,12 +371,12 @@ __device__ __forceinline__ void sstep_wg(const SweepArgs<T>& a, const SweepGeom&
 #pragma unroll
   for (int i = 0; i < kNs; ++i) acc[i] = (T)0;
 
-  // ---- prologue: planes x0-2 .. x0 of p, plane x0-1 of r --------------------
+  // ---- prologue: planes ub-dir .. ub+dir of p, plane ub of r -----------------
   {
-    const auto r0 = pl_rsrc(r_in, wrap_pl(x0 - 1, N), Ps);
-    const auto pa = pl_rsrc(p_in, wrap_pl(x0 - 2, N), Ps);
-    const auto pb = pl_rsrc(p_in, wrap_pl(x0 - 1, N), Ps);
-    const auto pd = pl_rsrc(p_in, wrap_pl(x0, N), Ps);
+    const auto r0 = pl_rsrc(r_in, wrap_pl(ub, N), Ps);
+    const auto pa = pl_rsrc(p_in, wrap_pl(ub - dir, N), Ps);
+    const auto pb = pl_rsrc(p_in, wrap_pl(ub, N), Ps);
+    const auto pd = pl_rsrc(p_in, wrap_pl(ub + dir, N), Ps);
     T ob[NH];
 #pragma unroll
     for (int i = 0; i < NU; ++i) {
@@ -386,19 +402,19 @@ __device__ __forceinline__ void sstep_wg(const SweepArgs<T>& a, const SweepGeom&
   __syncthreads();
   __builtin_amdgcn_s_waitcnt(0);
 
-  const int nsteps = x1 - x0 + 2;  // stage U on planes x0-1 .. x1
+  const int nsteps = x1 - x0 + 2;  // stage U on planes x0-1 .. x1, in march order
   // unrolled six times (both LDS parities, all three positions of the plane
   // windows), so the windows rotate by renaming instead of register moves
 #pragma unroll 6
   for (int t = 0; t < nsteps; ++t) {
-    const int u = x0 - 1 + t;
+    const int u = ub + dir * t;
     const bool more = t + 1 < nsteps;
     const bool own_u = (u >= x0) && (u < x1);
     // issue the loads of the next step
     T pf[NU], pof[NH], rf[NU], xf[PPT];
     if (more) {
-      const auto rp = pl_rsrc(r_in, wrap_pl(u + 1, N), Ps);
-      const auto pp = pl_rsrc(p_in, wrap_pl(u + 2, N), Ps);
+      const auto rp = pl_rsrc(r_in, wrap_pl(u + dir, N), Ps);
+      const auto pp = pl_rsrc(p_in, wrap_pl(u + 2 * dir, N), Ps);
 #pragma unroll
       for (int i = 0; i < NU; ++i) {
         rf[i] = ld<T>(rp, bo[i]);
@@ -430,14 +446,14 @@ __device__ __forceinline__ void sstep_wg(const SweepArgs<T>& a, const SweepGeom&
       if (i < PPT) bk[i] = bp;
     }
 
-    // stage W at plane u-1: B^2 p and B rhat on the segment
+    // stage W at plane u-dir: B^2 p and B rhat on the segment
     if (t >= 2) {
       const T* Q2r = Q2 + (tb ^ 1) * E2;
       const T* R2r = R2 + (tb ^ 1) * E2;
-      // plane u-1 lies in [x0, x1) here
-      const auto xo = pl_rsrc((const T*)a.x, u - 1, Ps);
-      const auto ro = pl_rsrc((const T*)r_out, u - 1, Ps);
-      const auto po = pl_rsrc((const T*)p_out, u - 1, Ps);
+      // plane u-dir lies in [x0, x1) here
+      const auto xo = pl_rsrc((const T*)a.x, u - dir, Ps);
+      const auto ro = pl_rsrc((const T*)r_out, u - dir, Ps);
+      const auto po = pl_rsrc((const T*)p_out, u - dir, Ps);
 #pragma unroll
       for (int j = 0; j < PPT; ++j) {
         const T y0 = pm[j];
@@ -475,7 +491,7 @@ __device__ __forceinline__ void sstep_wg(const SweepArgs<T>& a, const SweepGeom&
       }
     }
 
-    // stage p of plane u+1 for the next step
+    // stage p of plane u+dir for the next step
     if (more) {
       T* P1n = P1 + (tb ^ 1) * E1;
 #pragma unroll
@@ -528,8 +544,7 @@ __device__ __forceinline__ void sstep_wg(const SweepArgs<T>& a, const SweepGeom&
 template <typename T, bool FIRST, bool UPDATE, int PPT, int NH, int NT>
 __global__ __launch_bounds__(NT) void k_sstep(SweepArgs<T> a, SweepGeom g, int par) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  __shared__ double red[kNs * (NT / 64)];
-  sstep_wg<T, FIRST, UPDATE, PPT, NH, NT>(a, g, par, xcd_remap(blockIdx.x, g.nwg), smem_raw, red);
+  sstep_wg<T, FIRST, UPDATE, PPT, NH, NT>(a, g, par, xcd_remap(blockIdx.x, g.nwg), smem_raw);
 }
 
 // Batched form: the workgroups of `count` sessions in one launch; session i
@@ -542,7 +557,6 @@ __global__ __launch_bounds__(NT) void k_sstep_batch(const SweepArgs<T>* __restri
                                                     const int* __restrict__ wg_begin, int count,
                                                     int par) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  __shared__ double red[kNs * (NT / 64)];
   const int b = blockIdx.x;
   int lo = 0, hi = count - 1;
   while (lo < hi) {
@@ -552,7 +566,7 @@ __global__ __launch_bounds__(NT) void k_sstep_batch(const SweepArgs<T>* __restri
   }
   const SweepArgs<T> a = args[lo];
   const SweepGeom g = geoms[lo];
-  sstep_wg<T, FIRST, UPDATE, PPT, NH, NT>(a, g, par, b - wg_begin[lo], smem_raw, red);
+  sstep_wg<T, FIRST, UPDATE, PPT, NH, NT>(a, g, par, b - wg_begin[lo], smem_raw);
 }
 
 // Geometry of a two-iteration kernel with nt threads per workgroup
@@ -574,7 +588,8 @@ SweepGeom make_sstep_geom(int N, int ppt, int cx, int nt) {
 size_t sstep_lds_bytes(const SweepGeom& g, bool fp32) {
   const size_t es = fp32 ? sizeof(float) : sizeof(double);
   const size_t e1 = (size_t)g.S + 4 * (size_t)g.N, e2 = (size_t)g.S + 2 * (size_t)g.N;
-  return es * 2 * (e1 + 2 * e2);
+  const size_t red = sizeof(double) * kNs * (size_t)(g.S / g.ppt / 64);
+  return std::max(es * 2 * (e1 + 2 * e2), red);
 }
 
 namespace {
