@@ -301,8 +301,10 @@ __device__ __forceinline__ void sstep_wg(const SweepArgs<T>& a, const SweepGeom&
   const int ub = (chunk & 1) ? x1 : x0 - 1;  // plane of stage U at the first step
   const int E1 = S + 4 * N, E2 = S + 2 * N;
   T* P1 = reinterpret_cast<T*>(smem_raw);  // [2][E1] p of plane u (two rows each side)
-  T* Q2 = P1 + 2 * E1;                     // [2][E2] B p of plane u-1 / u
-  T* R2 = Q2 + 2 * E2;                     // [2][E2] r of plane u-1 / u
+  // [2][E2] (B p, r) pairs of plane u-1 / u: stage W reads both at each
+  // neighbour with one LDS access
+  using T2 = T __attribute__((ext_vector_type(2)));
+  T2* QR = reinterpret_cast<T2*>(P1 + 2 * E1);
   constexpr int NU = PPT + NH;             // stage-U slots: segment, then inner halo
 
   int e1[NU], e1zm[NU], e1zp[NU], e2[NU];
@@ -432,24 +434,24 @@ __device__ __forceinline__ void sstep_wg(const SweepArgs<T>& a, const SweepGeom&
     // stage U at plane u: B p (segment + inner halo), r staged
     const int tb = t & 1;
     T* P1b = P1 + tb * E1;
-    T* Q2w = Q2 + tb * E2;
-    T* R2w = R2 + tb * E2;
+    T2* QRw = QR + tb * E2;
     T bk[PPT];
 #pragma unroll
     for (int i = 0; i < NU; ++i) {
       const T bp = -c6 * (((pm[i] + pn[i]) + (P1b[e1[i] - N] + P1b[e1[i] + N])) +
                           (P1b[e1zm[i]] + P1b[e1zp[i]]));
       if (uval[i]) {
-        Q2w[e2[i]] = bp;
-        R2w[e2[i]] = rc[i];
+        T2 w;
+        w.x = bp;
+        w.y = rc[i];
+        QRw[e2[i]] = w;
       }
       if (i < PPT) bk[i] = bp;
     }
 
     // stage W at plane u-dir: B^2 p and B rhat on the segment
     if (t >= 2) {
-      const T* Q2r = Q2 + (tb ^ 1) * E2;
-      const T* R2r = R2 + (tb ^ 1) * E2;
+      const T2* QRr = QR + (tb ^ 1) * E2;
       // plane u-dir lies in [x0, x1) here
       const auto xo = pl_rsrc((const T*)a.x, u - dir, Ps);
       const auto ro = pl_rsrc((const T*)r_out, u - dir, Ps);
@@ -458,11 +460,11 @@ __device__ __forceinline__ void sstep_wg(const SweepArgs<T>& a, const SweepGeom&
       for (int j = 0; j < PPT; ++j) {
         const T y0 = pm[j];
         const T y1 = bc[j];
-        const T y2 = -c6 * (((bm[j] + bk[j]) + (Q2r[e2[j] - N] + Q2r[e2[j] + N])) +
-                            (Q2r[e2zm[j]] + Q2r[e2zp[j]]));
+        const T2 ym = QRr[e2[j] - N], yp = QRr[e2[j] + N];
+        const T2 zm = QRr[e2zm[j]], zp = QRr[e2zp[j]];
+        const T y2 = -c6 * (((bm[j] + bk[j]) + (ym.x + yp.x)) + (zm.x + zp.x));
         const T y3 = c6 * rm1[j];
-        const T y4 = -c36 * (((rm2[j] + rc[j]) + (R2r[e2[j] - N] + R2r[e2[j] + N])) +
-                             (R2r[e2zm[j]] + R2r[e2zp[j]]));
+        const T y4 = -c36 * (((rm2[j] + rc[j]) + (ym.y + yp.y)) + (zm.y + zp.y));
         if (!UPDATE) {
           if (cval[j]) {
             const T d0 = y0, d1 = y1, d2 = y2, d3 = y3, d4 = y4;
