@@ -405,9 +405,9 @@ __device__ __forceinline__ void sstep_wg(const SweepArgs<T>& a, const SweepGeom&
   __builtin_amdgcn_s_waitcnt(0);
 
   const int nsteps = x1 - x0 + 2;  // stage U on planes x0-1 .. x1, in march order
-  // unrolled six times (both LDS parities, all three positions of the plane
-  // windows), so the windows rotate by renaming instead of register moves
-#pragma unroll 6
+  // The compiler does not unroll a loop with a barrier and a run-time trip
+  // count, so the plane windows rotate by register moves (about 20 per
+  // step); the kernels are not bound by their vector ALU work.
   for (int t = 0; t < nsteps; ++t) {
     const int u = ub + dir * t;
     const bool more = t + 1 < nsteps;
