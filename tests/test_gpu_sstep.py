@@ -353,6 +353,45 @@ def test_sstep_basis_shapes(maze, monkeypatch, N, shape, precision):
     g.close()
 
 
+@pytest.mark.parametrize("N,update,basis,precision", [(36, "1:5", "256:1:7", 0),
+                                                      (40, "2:6", "1024:1:3", 0),
+                                                      (33, "1:4", "256:2:11", 1)])
+def test_sstep_march_directions(maze, monkeypatch, N, update, basis, precision):
+    """x runs alternate between upward and downward marches. Forced shapes
+    give odd and even run counts and a last run of a single plane at either
+    end of that alternation (N=36: the update's last run, the 8th, and the
+    basis kernel's 6th each hold one plane and march down; N=40: the basis
+    kernel's 14th run holds one plane; N=33: nine update runs, the last of
+    one plane marching up, and three basis runs with a ragged segment)."""
+    monkeypatch.setenv("MAZE_SWEEP_SHAPE", update)
+    monkeypatch.setenv("MAZE_BASIS_SHAPE", basis)
+    box = 0.4 * N
+    pos, Q, vel = random_system(2 * N, box, seed=3 * N + precision)
+    print(f"case: sstep march directions N={N} update {update} basis {basis} "
+          f"precision {precision}", flush=True)
+    tol = 1e-12 if precision == 0 else 1e-9
+    g = maze.Session(dev(Q), dev(pos), box, 0.4, tol=tol, precision=precision,
+                     flags=maze.MAZE_FLAG_SSTEP)
+    ppt, cx = (int(v) for v in update.split(":"))
+    ls = maze.maze_launch_shape(g.handle)["latency"]
+    assert (ls["ppt"], ls["cx"]) == (ppt, cx)
+    nt, bppt, bcx = (int(v) for v in basis.split(":"))
+    bs = maze.maze_basis_shape(g.handle)
+    assert (bs["threads"], bs["ppt"], bs["cx"]) == (nt, bppt, bcx)
+    o = oracle.Session(Q, pos, box, 0.4, tol=1e-13)
+    for k in range(2):
+        p = pos + (k + 1) * vel
+        out = g.step(dev(p), want_field=True)
+        ref = o.step(p)
+        assert out["status"] == 0
+        bound = FIELD_TOL if precision == 0 else \
+            kappa(N) * out["stats"]["rel_residual"] * 1.01 + 1e-12
+        assert rel(out["field"], ref["field"]) <= bound
+        if precision == 0:
+            assert rel(out["forces"], ref["forces"]) <= FORCE_TOL
+    g.close()
+
+
 def test_sstep_tuned_basis_shape_is_cached(maze):
     s = inputs.molten_nacl(8, seed=4)
     print("case: sstep tuned basis shape 128^3", flush=True)
