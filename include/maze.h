@@ -223,17 +223,18 @@ int maze_save(const maze_session* s, void* host_buf, size_t bytes);
 int maze_load(maze_session* s, const void* host_buf, size_t bytes);
 
 /* Sweep timing for measurement. When enabled, the runtime brackets every
- * fourth CG sweep of each solve (at most 512 per solve) with a pair of HIP
- * events on the session stream, and keeps the durations of the sampled
+ * sixteenth CG sweep of each solve (at most 512 per solve) with a pair of
+ * HIP events on the session stream, and keeps the durations of the sampled
  * sweeps that did work. maze_profile_read copies 8 doubles into out8 (HOST
- * memory):
+ * memory) and resets them:
  *   {FP64 sweeps timed, their total ms, FP32 sweeps timed, their total ms,
  *    FP64 CG iterations, FP32 CG iterations, 0, 0}
  * With MAZE_FLAG_SSTEP the timed unit is one outer step of two iterations
- * (basis and update kernel), and the last two entries hold the total ms of
- * the update kernels of the timed FP64 and FP32 outer steps.
- * and resets them. Enabling creates the events (the only allocation outside
- * maze_init). */
+ * (basis and update kernel, with a third event between them), and the last
+ * two entries hold the total ms of the update kernels of the timed FP64 and
+ * FP32 outer steps. Enabling creates the events (the only allocation
+ * outside maze_init). Sampling adds event records to the stream: about 0.5%
+ * of a 256^3 step. */
 int maze_profile_enable(maze_session* s, int on);
 int maze_profile_read(maze_session* s, double* out8);
 

@@ -30,7 +30,7 @@ constexpr double kInnerReduction = 1e-7;
 constexpr double kInnerMargin = 0.95;
 constexpr uint64_t kMagic = 0x4d415a4531534553ull;  // "MAZE1SES"
 constexpr int kProfMax = 512;          // sweeps timed per solve
-constexpr int kProfStride = 4;         // every kProfStride-th sweep is timed
+constexpr int kProfStride = 16;        // every kProfStride-th sweep is timed
 
 struct SaveHeader {
   uint64_t magic;
