@@ -279,14 +279,17 @@ static Layout layout_for(const maze_config* c, int N, int* ntx_out, int* ntiles_
 // test and the iteration cap itself (sweep k stops when k - 1 updates reach
 // max_iter), so the host only counts sweeps as a guard.
 // ---------------------------------------------------------------------------
-// units: sweeps (or two-iteration outer steps) that did work in the solve.
-static void prof_collect(maze_session* s, int timed, int units, int iters, bool fp32,
+// last: index of the last unit that did work in the solve. Sweep k applies
+// iteration k, so a solve of n iterations ends with sweep n; outer step k of
+// the two-iteration form applies iterations 2k+1 and 2k+2, so it ends with
+// outer step (n + 1) / 2 - 1.
+static void prof_collect(maze_session* s, int timed, int last, int iters, bool fp32,
                          bool sstep) {
   double* acc = s->prof_acc + (fp32 ? 2 : 0);
   for (int j = 0; j < timed; ++j) {
-    // sample j timed unit k = 1 + j * kProfStride; units past `units`
+    // sample j timed unit k = 1 + j * kProfStride; units past `last`
     // returned without work and are not counted
-    if (1 + j * kProfStride > units) break;
+    if (1 + j * kProfStride > last) break;
     float ms = 0.f, mu = 0.f;
     if (hipEventElapsedTime(&ms, s->pev[3 * j], s->pev[3 * j + 2]) == hipSuccess &&
         (!sstep || hipEventElapsedTime(&mu, s->pev[3 * j + 1], s->pev[3 * j + 2]) == hipSuccess)) {
@@ -433,7 +436,7 @@ static int run_cg(CgJob& job, bool fp32, bool zero_x, int first_batch) {
       if (h.done || last) {
         job.iters = h.iters;
         job.code = h.done ? h.done : 3;
-        if (prof) prof_collect(s, timed, ss ? (h.iters + 1) / 2 : h.iters, h.iters, fp32, ss);
+        if (prof) prof_collect(s, timed, ss ? (h.iters + 1) / 2 - 1 : h.iters, h.iters, fp32, ss);
         if (s->trace) return trace_collect(s, h.iters, h.qnorm);
         return MAZE_OK;
       }

@@ -318,12 +318,24 @@ def test_sstep_profile_counts_outer_steps(maze):
     g = maze.Session(dev(s.charges), dev(s.pos), s.box, s.grid_spacing, tol=1e-9,
                      precision=maze.MAZE_MIXED, flags=maze.MAZE_FLAG_SSTEP)
     maze.maze_profile_enable(g.handle, True)
+    maze.maze_trace_enable(g.handle, True)
     out = g.step(dev(s.pos + s.vel))
     pr = maze.maze_profile_read(g.handle)
     n, ms = pr["fp32_sweep"]
     assert pr["fp32_iters"] == out["stats"]["iters"]
     assert 1 <= n <= (out["stats"]["iters"] + 1) // 2
     assert 0 < pr["fp32_update_ms"] < ms
+    # exactly the sampled outer steps k = 1, 17, 33, ... that did work: a
+    # pass of n iterations works in outer steps 0 .. (n + 1) // 2 - 1 (a
+    # refinement pass of two iterations has no sampled step that worked)
+    rows = maze.maze_trace_read(g.handle)
+    iters = {}
+    for p, t, _ in rows:
+        if t >= 0:
+            iters[p] = max(iters.get(p, 0), t)
+    assert len(iters) >= 1
+    want = sum(len(range(1, (k + 1) // 2, 16)) for k in iters.values())
+    assert n == want, (n, iters)
     g.close()
 
 
