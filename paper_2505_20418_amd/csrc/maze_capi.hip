@@ -1668,9 +1668,12 @@ int maze_profile_enable(maze_session* s, int on) {
   if (!s) return MAZE_E_INVALID;
   hipSetDevice(s->device);
   if (on && s->pev.empty()) {
+    // timing only: without the system-scope fence at each record, which
+    // writes back and invalidates caches between the kernels it brackets
     s->pev.assign(3 * kProfMax, nullptr);
     for (auto& e : s->pev)
-      if (hipEventCreate(&e) != hipSuccess) return MAZE_E_DEVICE;
+      if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess)
+        return MAZE_E_DEVICE;
   }
   s->prof = on != 0;
   for (double& v : s->prof_acc) v = 0.0;
