@@ -146,8 +146,12 @@ __device__ __forceinline__ void ahat(const double* v, double* o) {
 
 // The work of one workgroup (logical index L) of a basis (UPDATE = false)
 // or update (UPDATE = true) kernel of outer step parity `par`. FIRST: the
-// first outer step of a solve, p = r / 6 (p is not read).
-template <typename T, bool FIRST, bool UPDATE, int PPT, int NH, int NT>
+// first outer step of a solve, p = r / 6 (p is not read). ROWS (only where
+// N divides NT): each group of N threads owns PPT consecutive rows of the
+// segment, a z column per thread, so the y neighbours of a point in an
+// inner row are the thread's own values of the rows above and below
+// instead of LDS reads.
+template <typename T, bool FIRST, bool UPDATE, int PPT, int NH, int NT, bool ROWS>
 __device__ __forceinline__ void sstep_wg(const SweepArgs<T>& a, const SweepGeom& g, int par,
                                          int L, unsigned char* smem_raw) {
   // the workgroup reductions use the start of the dynamic LDS (before the
@@ -314,11 +318,12 @@ __device__ __forceinline__ void sstep_wg(const SweepArgs<T>& a, const SweepGeom&
   int e1o[NH];
   bool oval[NH];
   uint32_t bo[NU], boo[NH];
+  const int grp = ROWS ? tid / N : 0, zcol = tid - grp * N;
 #pragma unroll
   for (int i = 0; i < NU; ++i) {
     int f, ee2;
     if (i < PPT) {
-      const int loc = tid + i * NT;
+      const int loc = ROWS ? (grp * PPT + i) * N + zcol : tid + i * NT;
       f = s0 + loc;
       ee2 = N + loc;
       uval[i] = true;
@@ -438,8 +443,10 @@ __device__ __forceinline__ void sstep_wg(const SweepArgs<T>& a, const SweepGeom&
     T bk[PPT];
 #pragma unroll
     for (int i = 0; i < NU; ++i) {
-      const T bp = -c6 * (((pm[i] + pn[i]) + (P1b[e1[i] - N] + P1b[e1[i] + N])) +
-                          (P1b[e1zm[i]] + P1b[e1zp[i]]));
+      const bool own_m = ROWS && i > 0 && i < PPT, own_p = ROWS && i + 1 < PPT;
+      const T ym = own_m ? pc[own_m ? i - 1 : 0] : P1b[e1[i] - N];
+      const T yp = own_p ? pc[own_p ? i + 1 : 0] : P1b[e1[i] + N];
+      const T bp = -c6 * (((pm[i] + pn[i]) + (ym + yp)) + (P1b[e1zm[i]] + P1b[e1zp[i]]));
       if (uval[i]) {
         T2 w;
         w.x = bp;
@@ -460,7 +467,19 @@ __device__ __forceinline__ void sstep_wg(const SweepArgs<T>& a, const SweepGeom&
       for (int j = 0; j < PPT; ++j) {
         const T y0 = pm[j];
         const T y1 = bc[j];
-        const T2 ym = QRr[e2[j] - N], yp = QRr[e2[j] + N];
+        T2 ym, yp;
+        if (ROWS && j > 0) {
+          ym.x = bc[j > 0 ? j - 1 : 0];
+          ym.y = rm1[j > 0 ? j - 1 : 0];
+        } else {
+          ym = QRr[e2[j] - N];
+        }
+        if (ROWS && j + 1 < PPT) {
+          yp.x = bc[j + 1 < PPT ? j + 1 : 0];
+          yp.y = rm1[j + 1 < PPT ? j + 1 : 0];
+        } else {
+          yp = QRr[e2[j] + N];
+        }
         const T2 zm = QRr[e2zm[j]], zp = QRr[e2zp[j]];
         const T y2 = -c6 * (((bm[j] + bk[j]) + (ym.x + yp.x)) + (zm.x + zp.x));
         const T y3 = c6 * rm1[j];
@@ -543,17 +562,18 @@ __device__ __forceinline__ void sstep_wg(const SweepArgs<T>& a, const SweepGeom&
   }
 }
 
-template <typename T, bool FIRST, bool UPDATE, int PPT, int NH, int NT>
+template <typename T, bool FIRST, bool UPDATE, int PPT, int NH, int NT, bool ROWS>
 __global__ __launch_bounds__(NT) void k_sstep(SweepArgs<T> a, SweepGeom g, int par) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  sstep_wg<T, FIRST, UPDATE, PPT, NH, NT>(a, g, par, xcd_remap(blockIdx.x, g.nwg), smem_raw);
+  sstep_wg<T, FIRST, UPDATE, PPT, NH, NT, ROWS>(a, g, par, xcd_remap(blockIdx.x, g.nwg),
+                                               smem_raw);
 }
 
 // Batched form: the workgroups of `count` sessions in one launch; session i
 // owns workgroups [wg_begin[i], wg_begin[i+1]) and runs the same
 // per-workgroup code as alone (logical index = block - wg_begin[i]), so a
 // session's result does not depend on its batch.
-template <typename T, bool FIRST, bool UPDATE, int PPT, int NH, int NT>
+template <typename T, bool FIRST, bool UPDATE, int PPT, int NH, int NT, bool ROWS>
 __global__ __launch_bounds__(NT) void k_sstep_batch(const SweepArgs<T>* __restrict__ args,
                                                     const SweepGeom* __restrict__ geoms,
                                                     const int* __restrict__ wg_begin, int count,
@@ -568,7 +588,7 @@ __global__ __launch_bounds__(NT) void k_sstep_batch(const SweepArgs<T>* __restri
   }
   const SweepArgs<T> a = args[lo];
   const SweepGeom g = geoms[lo];
-  sstep_wg<T, FIRST, UPDATE, PPT, NH, NT>(a, g, par, b - wg_begin[lo], smem_raw);
+  sstep_wg<T, FIRST, UPDATE, PPT, NH, NT, ROWS>(a, g, par, b - wg_begin[lo], smem_raw);
 }
 
 // Geometry of a two-iteration kernel with nt threads per workgroup
@@ -586,6 +606,8 @@ SweepGeom make_sstep_geom(int N, int ppt, int cx, int nt) {
   g.nh = (2 * N + nt - 1) / nt;
   return g;
 }
+
+bool sstep_rows(const SweepGeom& g) { return (g.S / g.ppt) % g.N == 0; }
 
 size_t sstep_lds_bytes(const SweepGeom& g, bool fp32) {
   const size_t es = fp32 ? sizeof(float) : sizeof(double);
@@ -620,15 +642,15 @@ struct SingleLaunch {
   const SweepGeom& g;
   int par;
   hipStream_t st;
-  template <int PPT, int NH, int NT>
+  template <int PPT, int NH, int NT, bool ROWS>
   hipError_t run() const {
     static size_t allowed = 0;
     const size_t lds = sstep_lds_bytes(g, sizeof(T) == 4);
-    const hipError_t e = ensure_lds((const void*)k_sstep<T, FIRST, UPDATE, PPT, NH, NT>, lds,
-                                    &allowed);
+    const hipError_t e = ensure_lds(
+        (const void*)k_sstep<T, FIRST, UPDATE, PPT, NH, NT, ROWS>, lds, &allowed);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_sstep<T, FIRST, UPDATE, PPT, NH, NT>), dim3(g.nwg), dim3(NT), lds, st,
-                       a, g, par);
+    hipLaunchKernelGGL((k_sstep<T, FIRST, UPDATE, PPT, NH, NT, ROWS>), dim3(g.nwg), dim3(NT),
+                       lds, st, a, g, par);
     return hipGetLastError();
   }
 };
@@ -638,29 +660,34 @@ template <typename T, bool FIRST, bool UPDATE>
 struct BatchLaunch {
   const SweepLaunch& L;
   hipStream_t st;
-  template <int PPT, int NH, int NT>
+  template <int PPT, int NH, int NT, bool ROWS>
   hipError_t run() const {
     static size_t allowed = 0;
-    const hipError_t e = ensure_lds((const void*)k_sstep_batch<T, FIRST, UPDATE, PPT, NH, NT>,
-                                    L.lds, &allowed);
+    const hipError_t e = ensure_lds(
+        (const void*)k_sstep_batch<T, FIRST, UPDATE, PPT, NH, NT, ROWS>, L.lds, &allowed);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_sstep_batch<T, FIRST, UPDATE, PPT, NH, NT>), dim3(L.nwg_total),
+    hipLaunchKernelGGL((k_sstep_batch<T, FIRST, UPDATE, PPT, NH, NT, ROWS>), dim3(L.nwg_total),
                        dim3(NT), L.lds, st, static_cast<const SweepArgs<T>*>(L.args), L.geoms,
                        L.wg_begin, L.count, L.par);
     return hipGetLastError();
   }
 };
 
+// rows: the row-owning layout (N divides NT, so at most two halo slots)
 template <bool UPDATE, int PPT, int NT, class F>
-hipError_t sstep_nh(int nh, const F& f) {
+hipError_t sstep_nh(int nh, bool rows, const F& f) {
   switch (nh) {
-    case 1: return f.template run<PPT, 1, NT>();
-    case 2: return f.template run<PPT, 2, NT>();
+    case 1:
+      return rows ? f.template run<PPT, 1, NT, true>() : f.template run<PPT, 1, NT, false>();
+    case 2:
+      return rows ? f.template run<PPT, 2, NT, true>() : f.template run<PPT, 2, NT, false>();
     case 4:
-      if constexpr (NT == kThreads) return f.template run<PPT, 4, NT>();
+      if constexpr (NT == kThreads)
+        if (!rows) return f.template run<PPT, 4, NT, false>();
       return hipErrorInvalidValue;
     case 8:
-      if constexpr (NT == kThreads) return f.template run<PPT, 8, NT>();
+      if constexpr (NT == kThreads)
+        if (!rows) return f.template run<PPT, 8, NT, false>();
       return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
   }
@@ -669,21 +696,21 @@ hipError_t sstep_nh(int nh, const F& f) {
 // Workgroups of kThreads for every kernel; the basis kernel also comes in
 // 1024-thread workgroups (longer segments, less halo work per point).
 template <bool UPDATE, class F>
-hipError_t sstep_dispatch(int nt, int ppt, int nh, const F& f) {
+hipError_t sstep_dispatch(int nt, int ppt, int nh, bool rows, const F& f) {
   if (nt == kThreads) {
     switch (ppt) {
-      case 1: return sstep_nh<UPDATE, 1, kThreads>(nh, f);
-      case 2: return sstep_nh<UPDATE, 2, kThreads>(nh, f);
-      case 4: return sstep_nh<UPDATE, 4, kThreads>(nh, f);
+      case 1: return sstep_nh<UPDATE, 1, kThreads>(nh, rows, f);
+      case 2: return sstep_nh<UPDATE, 2, kThreads>(nh, rows, f);
+      case 4: return sstep_nh<UPDATE, 4, kThreads>(nh, rows, f);
       default: return hipErrorInvalidValue;
     }
   }
   if constexpr (!UPDATE) {
     if (nt == 1024) {
       switch (ppt) {
-        case 1: return sstep_nh<UPDATE, 1, 1024>(nh, f);
-        case 2: return sstep_nh<UPDATE, 2, 1024>(nh, f);
-        case 4: return sstep_nh<UPDATE, 4, 1024>(nh, f);
+        case 1: return sstep_nh<UPDATE, 1, 1024>(nh, rows, f);
+        case 2: return sstep_nh<UPDATE, 2, 1024>(nh, rows, f);
+        case 4: return sstep_nh<UPDATE, 4, 1024>(nh, rows, f);
         default: return hipErrorInvalidValue;
       }
     }
@@ -694,13 +721,13 @@ hipError_t sstep_dispatch(int nt, int ppt, int nh, const F& f) {
 template <typename T, bool FIRST, bool UPDATE>
 hipError_t sstep_ppt(const SweepArgs<T>& a, const SweepGeom& g, int par, hipStream_t st) {
   const SingleLaunch<T, FIRST, UPDATE> f{a, g, par, st};
-  return sstep_dispatch<UPDATE>(g.S / g.ppt, g.ppt, sweep_nh_class(g.nh), f);
+  return sstep_dispatch<UPDATE>(g.S / g.ppt, g.ppt, sweep_nh_class(g.nh), sstep_rows(g), f);
 }
 
 template <typename T, bool FIRST, bool UPDATE>
-hipError_t sstep_batch_ppt(const SweepLaunch& L, int nt, hipStream_t st) {
+hipError_t sstep_batch_ppt(const SweepLaunch& L, int nt, bool rows, hipStream_t st) {
   const BatchLaunch<T, FIRST, UPDATE> f{L, st};
-  return sstep_dispatch<UPDATE>(nt, L.ppt, L.nh, f);
+  return sstep_dispatch<UPDATE>(nt, L.ppt, L.nh, rows, f);
 }
 
 template <typename T>
@@ -734,19 +761,19 @@ hipError_t launch_sstep_outer(const DeviceState& d, const SweepGeom& gb, const S
   return launch_sstep_half(d, gb, gu, o, x, fp32, zero_x, true, st);
 }
 
-hipError_t launch_sstep_batch(const SweepLaunch& L, int nt, bool fp32, bool first, bool update,
-                              hipStream_t st) {
+hipError_t launch_sstep_batch(const SweepLaunch& L, int nt, bool rows, bool fp32, bool first,
+                              bool update, hipStream_t st) {
   if (L.count < 1 || L.nwg_total < 1) return hipErrorInvalidValue;
   if (fp32) {
-    if (first) return update ? sstep_batch_ppt<float, true, true>(L, nt, st)
-                             : sstep_batch_ppt<float, true, false>(L, nt, st);
-    return update ? sstep_batch_ppt<float, false, true>(L, nt, st)
-                  : sstep_batch_ppt<float, false, false>(L, nt, st);
+    if (first) return update ? sstep_batch_ppt<float, true, true>(L, nt, rows, st)
+                             : sstep_batch_ppt<float, true, false>(L, nt, rows, st);
+    return update ? sstep_batch_ppt<float, false, true>(L, nt, rows, st)
+                  : sstep_batch_ppt<float, false, false>(L, nt, rows, st);
   }
-  if (first) return update ? sstep_batch_ppt<double, true, true>(L, nt, st)
-                           : sstep_batch_ppt<double, true, false>(L, nt, st);
-  return update ? sstep_batch_ppt<double, false, true>(L, nt, st)
-                : sstep_batch_ppt<double, false, false>(L, nt, st);
+  if (first) return update ? sstep_batch_ppt<double, true, true>(L, nt, rows, st)
+                           : sstep_batch_ppt<double, true, false>(L, nt, rows, st);
+  return update ? sstep_batch_ppt<double, false, true>(L, nt, rows, st)
+                : sstep_batch_ppt<double, false, false>(L, nt, rows, st);
 }
 
 // Basis-kernel shapes that compile without register spills: 256 threads in

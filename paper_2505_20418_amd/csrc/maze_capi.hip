@@ -718,7 +718,7 @@ static int run_sstep_batch(std::vector<CgJob>& jobs, bool fp32, bool zero_x, int
   auto gb = [&](int i) -> const SweepGeom& { return tp ? jobs[i].s->sweep_tp : jobs[i].s->sbasis; };
   auto gu = [&](int i) -> const SweepGeom& { return tp ? jobs[i].s->sweep_tp : jobs[i].s->sweep; };
   auto cls = [](const SweepGeom& g) {
-    return ((g.S / g.ppt) * 8 + g.ppt) * 16 + sweep_nh_class(g.nh);
+    return (((g.S / g.ppt) * 8 + g.ppt) * 16 + sweep_nh_class(g.nh)) * 2 + (sstep_rows(g) ? 1 : 0);
   };
   std::vector<int> order(n);
   for (int i = 0; i < n; ++i) order[i] = i;
@@ -726,7 +726,7 @@ static int run_sstep_batch(std::vector<CgJob>& jobs, bool fp32, bool zero_x, int
     const int ca = cls(gb(a)), cb = cls(gb(b));
     return ca != cb ? ca < cb : cls(gu(a)) < cls(gu(b));
   });
-  struct Grp { int c0, c1, wgb0, nwg, nt, ppt, nh; size_t lds; };
+  struct Grp { int c0, c1, wgb0, nwg, nt, ppt, nh; bool rows; size_t lds; };
   std::vector<Grp> gbs, gus;
   char* H = t->host;
   SweepGeom* hg = (SweepGeom*)(H + t->o_geom);
@@ -746,11 +746,11 @@ static int run_sstep_batch(std::vector<CgJob>& jobs, bool fp32, bool zero_x, int
     const int cb = cls(b), cu = cls(u);
     if (gbs.empty() || cls(hg[gbs.back().c0]) != cb) {
       if (!gbs.empty()) hw[wpos++] = gbs.back().nwg;
-      gbs.push_back({q, q, wpos, 0, b.S / b.ppt, b.ppt, sweep_nh_class(b.nh), 0});
+      gbs.push_back({q, q, wpos, 0, b.S / b.ppt, b.ppt, sweep_nh_class(b.nh), sstep_rows(b), 0});
     }
     if (gus.empty() || cls(hg2[gus.back().c0]) != cu) {
       if (!gus.empty()) hw2[wpos2++] = gus.back().nwg;
-      gus.push_back({q, q, wpos2, 0, kThreads, u.ppt, sweep_nh_class(u.nh), 0});
+      gus.push_back({q, q, wpos2, 0, kThreads, u.ppt, sweep_nh_class(u.nh), sstep_rows(u), 0});
     }
     hg[q] = b;
     hg2[q] = u;
@@ -797,7 +797,7 @@ static int run_sstep_batch(std::vector<CgJob>& jobs, bool fp32, bool zero_x, int
         L.count = g.c1 - g.c0;
         L.nwg_total = g.nwg;
         L.lds = g.lds;
-        const hipError_t e = launch_sstep_batch(L, g.nt, fp32, k == 0, update, st);
+        const hipError_t e = launch_sstep_batch(L, g.nt, g.rows, fp32, k == 0, update, st);
         if (e != hipSuccess) return e;
       }
     }

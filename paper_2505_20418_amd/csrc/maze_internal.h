@@ -265,11 +265,15 @@ hipError_t launch_sstep_outer(const DeviceState& d, const SweepGeom& gb, const S
 hipError_t launch_sstep_half(const DeviceState& d, const SweepGeom& gb, const SweepGeom& gu, int o,
                              void* x, bool fp32, bool zero_x, bool update, hipStream_t st);
 // One batched launch of the basis (update = false) or update kernels of a
-// class of sessions (L.batch arrays on the device; L.ppt, L.nh the class,
-// nt its threads per workgroup; the update kernel reads one partial per
-// basis workgroup of its session, nprev_sweep of its arguments).
-hipError_t launch_sstep_batch(const SweepLaunch& L, int nt, bool fp32, bool first, bool update,
-                              hipStream_t st);
+// class of sessions (L.batch arrays on the device; L.ppt, L.nh and rows the
+// class, nt its threads per workgroup; the update kernel reads one partial
+// per basis workgroup of its session, nprev_sweep of its arguments).
+hipError_t launch_sstep_batch(const SweepLaunch& L, int nt, bool rows, bool fp32, bool first,
+                              bool update, hipStream_t st);
+// Whether a two-iteration shape runs in the row-owning layout: its
+// workgroup size is a multiple of N, so each thread owns a z column of
+// consecutive rows of the segment.
+bool sstep_rows(const SweepGeom& g);
 // Whether a basis-kernel shape has an instantiation that fits (LDS, halo
 // class) and runs without register spills.
 bool sstep_basis_shape_ok(const SweepGeom& g, bool fp32);
