@@ -717,8 +717,14 @@ static int run_sstep_batch(std::vector<CgJob>& jobs, bool fp32, bool zero_x, int
   const bool tp = batch_throughput_mode(jobs);
   auto gb = [&](int i) -> const SweepGeom& { return tp ? jobs[i].s->sweep_tp : jobs[i].s->sbasis; };
   auto gu = [&](int i) -> const SweepGeom& { return tp ? jobs[i].s->sweep_tp : jobs[i].s->sweep; };
-  auto cls = [](const SweepGeom& g) {
-    return (((g.S / g.ppt) * 8 + g.ppt) * 16 + sweep_nh_class(g.nh)) * 2 + (sstep_rows(g) ? 1 : 0);
+  // The row-owning layout changes which points a thread's Gram sums cover,
+  // so a latency-mode batch keeps each session's own layout (its results
+  // are bitwise those it gets alone) and a throughput-mode batch, whose
+  // partials are summed in another order anyway, runs every member in the
+  // flat layout: fewer classes, fewer launches.
+  auto rows = [tp](const SweepGeom& g) { return !tp && sstep_rows(g); };
+  auto cls = [&rows](const SweepGeom& g) {
+    return (((g.S / g.ppt) * 8 + g.ppt) * 16 + sweep_nh_class(g.nh)) * 2 + (rows(g) ? 1 : 0);
   };
   std::vector<int> order(n);
   for (int i = 0; i < n; ++i) order[i] = i;
@@ -746,11 +752,11 @@ static int run_sstep_batch(std::vector<CgJob>& jobs, bool fp32, bool zero_x, int
     const int cb = cls(b), cu = cls(u);
     if (gbs.empty() || cls(hg[gbs.back().c0]) != cb) {
       if (!gbs.empty()) hw[wpos++] = gbs.back().nwg;
-      gbs.push_back({q, q, wpos, 0, b.S / b.ppt, b.ppt, sweep_nh_class(b.nh), sstep_rows(b), 0});
+      gbs.push_back({q, q, wpos, 0, b.S / b.ppt, b.ppt, sweep_nh_class(b.nh), rows(b), 0});
     }
     if (gus.empty() || cls(hg2[gus.back().c0]) != cu) {
       if (!gus.empty()) hw2[wpos2++] = gus.back().nwg;
-      gus.push_back({q, q, wpos2, 0, kThreads, u.ppt, sweep_nh_class(u.nh), sstep_rows(u), 0});
+      gus.push_back({q, q, wpos2, 0, kThreads, u.ppt, sweep_nh_class(u.nh), rows(u), 0});
     }
     hg[q] = b;
     hg2[q] = u;
