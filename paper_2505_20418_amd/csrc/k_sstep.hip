@@ -38,8 +38,9 @@
 //
 // Layout and marching follow the fused sweep: a workgroup of NT threads
 // (256; the basis kernel also 1024) owns a segment of S = NT*PPT points of
-// the (y, z) plane and a run of x planes and walks them in x order, upward
-// in even runs and downward in odd ones. Stage U at plane u forms B p on
+// the (y, z) plane (thread t holding points t + i*NT, or, where N divides
+// NT, a z column of PPT consecutive rows) and a run of x planes and walks
+// them in x order, upward in even runs and downward in odd ones. Stage U at plane u forms B p on
 // the segment plus one row each side from p staged in LDS with two rows
 // each side; stage W at the plane before u forms B^2 p and B rhat on the
 // segment and either accumulates the Gram sums or writes the updated
@@ -295,8 +296,9 @@ __device__ __forceinline__ void sstep_wg(const SweepArgs<T>& a, const SweepGeom&
   // Logical indices run over the chunks of one segment first, so the
   // workgroups that one XCD receives (a contiguous range) hold whole columns
   // of x-neighbouring chunks. Odd chunks march down in x: two neighbouring
-  // chunks then start, or end, on the same four planes at the same time,
-  // and the second reader of a halo plane finds it in that XCD's L2.
+  // chunks then start, or end, on the same four planes at the same time.
+  // (Measured faster than one direction and segment-major order, by 4% in
+  // FP64, although the L2 fetch counters did not fall.)
   const int N = g.N, P = g.P, S = g.S;
   const int chunk = L % g.nchunk, seg = L / g.nchunk;
   const int s0 = seg * S;
