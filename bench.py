@@ -168,9 +168,10 @@ def roofline(prof_key, prof, G, dtype_key, shape=None, sstep=False):
     if shape is not None:
         # the launch shape the session swept in; a kernel trace of this run
         # also holds the autotuner's timing sweeps in other shapes, which
-        # this grid size (workgroups x 256 threads) tells apart
-        r["launch_shape"] = {"ppt": shape["ppt"], "cx": shape["cx"], "workgroups": shape["nwg"],
-                             "grid_threads": shape["nwg"] * 256}
+        # this grid size (workgroups x threads) tells apart
+        threads = shape["segment"] // shape["ppt"] if "segment" in shape else 256
+        r["launch_shape"] = {"threads": threads, "ppt": shape["ppt"], "cx": shape["cx"],
+                             "workgroups": shape["nwg"], "grid_threads": shape["nwg"] * threads}
     return r
 
 

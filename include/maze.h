@@ -244,9 +244,14 @@ int maze_profile_read(maze_session* s, double* out8);
  * size and precision; MAZE_AUTOTUNE=0 in the environment selects fixed
  * defaults). The throughput shape, used in batches that fill the device, is
  * the one with the longest runs and segments that fits (16 x planes, 1024
- * points). MAZE_SWEEP_SHAPE="ppt:cx" forces both. out8 (HOST, 8 int32):
- * {points per thread, x planes per workgroup, workgroups, segment length}
- * of the latency shape, then of the throughput shape. */
+ * points). MAZE_SWEEP_SHAPE="ppt:cx" forces both. With MAZE_FLAG_SSTEP the
+ * latency shape is that of the update kernel: the sweep shape or a
+ * 512-thread shape, whichever the session times faster at maze_init
+ * (cached like the others; MAZE_UPDATE_SHAPE="threads:ppt:cx" forces one,
+ * and a forced MAZE_SWEEP_SHAPE or MAZE_AUTOTUNE=0 keeps the sweep shape).
+ * out8 (HOST, 8 int32): {points per thread, x planes per workgroup,
+ * workgroups, segment length} of the latency shape, then of the throughput
+ * shape; threads per workgroup = segment length / points per thread. */
 int maze_launch_shape(const maze_session* s, int32_t* out8);
 
 /* Launch shape of the basis kernel of the two-iteration CG

@@ -695,8 +695,9 @@ hipError_t sstep_nh(int nh, bool rows, const F& f) {
   }
 }
 
-// Workgroups of kThreads for every kernel; the basis kernel also comes in
-// 1024-thread workgroups (longer segments, less halo work per point).
+// Workgroups of kThreads for every kernel; the update kernel also comes in
+// 512-thread and the basis kernel in 1024-thread workgroups (longer
+// segments, less halo work per point).
 template <bool UPDATE, class F>
 hipError_t sstep_dispatch(int nt, int ppt, int nh, bool rows, const F& f) {
   if (nt == kThreads) {
@@ -705,6 +706,15 @@ hipError_t sstep_dispatch(int nt, int ppt, int nh, bool rows, const F& f) {
       case 2: return sstep_nh<UPDATE, 2, kThreads>(nh, rows, f);
       case 4: return sstep_nh<UPDATE, 4, kThreads>(nh, rows, f);
       default: return hipErrorInvalidValue;
+    }
+  }
+  if constexpr (UPDATE) {
+    if (nt == 512) {
+      switch (ppt) {
+        case 2: return sstep_nh<UPDATE, 2, 512>(nh, rows, f);
+        case 4: return sstep_nh<UPDATE, 4, 512>(nh, rows, f);
+        default: return hipErrorInvalidValue;
+      }
     }
   }
   if constexpr (!UPDATE) {
@@ -776,6 +786,16 @@ hipError_t launch_sstep_batch(const SweepLaunch& L, int nt, bool rows, bool fp32
                            : sstep_batch_ppt<double, true, false>(L, nt, rows, st);
   return update ? sstep_batch_ppt<double, false, true>(L, nt, rows, st)
                 : sstep_batch_ppt<double, false, false>(L, nt, rows, st);
+}
+
+// Update-kernel shapes with an instantiation: 256 threads in every class;
+// 512 threads with 2 or 4 points per thread and at most two halo slots.
+bool sstep_update_shape_ok(const SweepGeom& g, bool fp32) {
+  const int nt = g.S / g.ppt;
+  const int nh = sweep_nh_class(g.nh);
+  if (nh == 0 || sstep_lds_bytes(g, fp32) > 160 * 1024 - 2048) return false;
+  if (nt == kThreads) return g.ppt == 1 || g.ppt == 2 || g.ppt == 4;
+  return nt == 512 && nh <= 2 && (g.ppt == 2 || g.ppt == 4);
 }
 
 // Basis-kernel shapes that compile without register spills: 256 threads in

@@ -748,7 +748,7 @@ static int run_sstep_batch(std::vector<CgJob>& jobs, bool fp32, bool zero_x, int
     const SweepGeom& b = gb(i);
     const SweepGeom& u = gu(i);
     if (b.nwg > s->d.part_stride || u.nwg > s->d.part_stride) return MAZE_E_INVALID;
-    if (!sstep_basis_shape_ok(b, fp32) || sweep_nh_class(u.nh) == 0) return MAZE_E_INVALID;
+    if (!sstep_basis_shape_ok(b, fp32) || !sstep_update_shape_ok(u, fp32)) return MAZE_E_INVALID;
     const int cb = cls(b), cu = cls(u);
     if (gbs.empty() || cls(hg[gbs.back().c0]) != cb) {
       if (!gbs.empty()) hw[wpos++] = gbs.back().nwg;
@@ -756,7 +756,7 @@ static int run_sstep_batch(std::vector<CgJob>& jobs, bool fp32, bool zero_x, int
     }
     if (gus.empty() || cls(hg2[gus.back().c0]) != cu) {
       if (!gus.empty()) hw2[wpos2++] = gus.back().nwg;
-      gus.push_back({q, q, wpos2, 0, kThreads, u.ppt, sweep_nh_class(u.nh), rows(u), 0});
+      gus.push_back({q, q, wpos2, 0, u.S / u.ppt, u.ppt, sweep_nh_class(u.nh), rows(u), 0});
     }
     hg[q] = b;
     hg2[q] = u;
@@ -1322,6 +1322,101 @@ static SweepGeom autotune_basis(maze_session* s) {
   return best;
 }
 
+// Shape of the update kernel of the two-iteration CG: the session's
+// latency sweep shape (256 threads) or a 512-thread shape (segments of 1024
+// or 2048 points: half the halo rows per point, at fewer waves per CU).
+// Each candidate runs 2 warm-up and 6 timed launches after one basis launch
+// on a fill of the session's r and p (the update reads only the partials
+// of that launch, so every launch does the same work); the fastest is
+// cached per (device, N, precision). MAZE_UPDATE_SHAPE="threads:ppt:cx"
+// forces one; MAZE_AUTOTUNE=0 or a forced MAZE_SWEEP_SHAPE keeps the sweep
+// shape.
+static std::map<TuneKey, SweepGeom> g_tuned_update;
+
+static bool forced_update(const DeviceState& d, bool fp32, SweepGeom* out) {
+  const char* e = std::getenv("MAZE_UPDATE_SHAPE");
+  int nt = 0, ppt = 0, cx = 0;
+  if (!e || std::sscanf(e, "%d:%d:%d", &nt, &ppt, &cx) != 3) return false;
+  if ((nt != kThreads && nt != 512) || (ppt != 1 && ppt != 2 && ppt != 4) || cx < 1) return false;
+  const SweepGeom g = make_sstep_geom(d.N, ppt, cx, nt);
+  if (!sstep_update_shape_ok(g, fp32) || g.nwg > d.part_stride) return false;
+  *out = g;
+  return true;
+}
+
+static SweepGeom autotune_update(maze_session* s) {
+  DeviceState& d = s->d;
+  const bool fp32 = s->cfg.precision == MAZE_MIXED;
+  SweepGeom def = s->sweep;
+  if (forced_update(d, fp32, &def)) return def;
+  // a forced sweep shape (MAZE_SWEEP_SHAPE) is the update shape as well
+  SweepGeom fs;
+  if (!autotune_enabled() || forced_shape(d, fp32, &fs)) return def;
+  const TuneKey key{s->device, d.N, fp32 ? 1 : 0};
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tuned_update.find(key);
+    if (it != g_tuned_update.end()) return it->second;
+  }
+  std::vector<SweepGeom> cand{def};
+  const long long P = (long long)d.N * d.N;
+  for (int ppt : {2, 4}) {
+    if (512LL * ppt > P) continue;  // segments longer than a plane
+    int last = -1;
+    for (int cx : {8, 12, 16, 24, 32, 48, 64}) {
+      const SweepGeom g = make_sstep_geom(d.N, ppt, cx, 512);
+      if (g.nchunk == last || !sstep_update_shape_ok(g, fp32) || g.nwg > d.part_stride) continue;
+      last = g.nchunk;
+      cand.push_back(g);
+    }
+  }
+  if (cand.size() <= 1) return def;
+  hipStream_t st = s->stream;
+  void* r0 = fp32 ? (void*)d.r32 : (void*)d.r;
+  void* p0 = fp32 ? (void*)d.p32 : (void*)d.p;
+  void* x = fp32 ? (void*)d.e32 : (void*)d.xsolve;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return def;
+  Scalars sc{};
+  sc.thr = -1.0;  // never converged
+  sc.max_iter = 1 << 30;
+  sc.norm = MAZE_NORM_REL2;
+  // outer step 2: parity 0, not the first (reads r[0], p[0] and x)
+  bool ok = hipMemcpyAsync(d.sc, &sc, sizeof(Scalars), hipMemcpyHostToDevice, st) == hipSuccess &&
+            launch_fill_pattern(r0, d.G, fp32, st) == hipSuccess &&
+            launch_fill_pattern(p0, d.G, fp32, st) == hipSuccess &&
+            launch_sstep_half(d, s->sbasis, def, 2, x, fp32, false, false, st) == hipSuccess;
+  SweepGeom best = def;
+  float best_ms = 1e30f;
+  for (const SweepGeom& g : cand) {
+    for (int k = 0; k < 2 && ok; ++k)
+      ok = launch_sstep_half(d, s->sbasis, g, 2, x, fp32, false, true, st) == hipSuccess;
+    ok = ok && hipEventRecord(e0, st) == hipSuccess;
+    for (int k = 0; k < 6 && ok; ++k)
+      ok = launch_sstep_half(d, s->sbasis, g, 2, x, fp32, false, true, st) == hipSuccess;
+    ok = ok && hipEventRecord(e1, st) == hipSuccess;
+    Scalars h{};
+    ok = ok && hipMemcpyAsync(&h, d.sc, sizeof(Scalars), hipMemcpyDeviceToHost, st) == hipSuccess;
+    ok = ok && hipStreamSynchronize(st) == hipSuccess;
+    if (!ok) break;
+    float ms = 0.f;
+    if (h.done == 0 && h.err == 0 && hipEventElapsedTime(&ms, e0, e1) == hipSuccess &&
+        ms < best_ms) {
+      best_ms = ms;
+      best = g;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (!ok) {
+    hipGetLastError();
+    return def;
+  }
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tuned_update[key] = best;
+  return best;
+}
+
 extern "C" {
 
 int maze_abi_version(void) { return MAZE_ABI_VERSION; }
@@ -1506,6 +1601,7 @@ int maze_init(const maze_config* cfg, const double* charges_dev, const double* p
     }
   }
   s->sbasis = sstep_of(s) ? autotune_basis(s) : s->sweep;
+  if (sstep_of(s)) s->sweep = autotune_update(s);
   if (hipMemsetAsync(base, 0, L.total, stream) != hipSuccess ||
       hipMemcpyAsync(d.Q, charges_dev, sizeof(double) * n, hipMemcpyDeviceToDevice, stream) !=
           hipSuccess) {

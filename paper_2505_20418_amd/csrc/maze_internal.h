@@ -277,6 +277,8 @@ bool sstep_rows(const SweepGeom& g);
 // Whether a basis-kernel shape has an instantiation that fits (LDS, halo
 // class) and runs without register spills.
 bool sstep_basis_shape_ok(const SweepGeom& g, bool fp32);
+// The same for an update-kernel shape (256 or 512 threads).
+bool sstep_update_shape_ok(const SweepGeom& g, bool fp32);
 size_t sstep_lds_bytes(const SweepGeom& g, bool fp32);
 // Geometry of a two-iteration kernel with nt threads per workgroup.
 SweepGeom make_sstep_geom(int N, int ppt, int cx, int nt);

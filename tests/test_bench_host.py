@@ -29,6 +29,14 @@ def test_sstep_roofline_splits_basis_and_update():
     assert r["launch_shape"]["grid_threads"] == 768 * 256
 
 
+def test_sstep_roofline_512_thread_update_shape():
+    r = bench.roofline("fp32_sweep", prof(10, 1.5, 0.9), G, "fp32",
+                       {"ppt": 4, "cx": 32, "nwg": 256, "segment": 2048,
+                        "basis": {"threads": 1024, "ppt": 4, "cx": 16, "nwg": 256}}, sstep=True)
+    assert r["launch_shape"]["threads"] == 512
+    assert r["launch_shape"]["grid_threads"] == 256 * 512
+
+
 def test_sweep_roofline_unchanged():
     r = bench.roofline("fp64_sweep", {"fp64_sweep": (4, 0.8)}, G, "fp64")
     assert r["avg_launch_us"] == pytest.approx(200.0)

@@ -404,6 +404,56 @@ def test_sstep_march_directions(maze, monkeypatch, N, update, basis, precision):
     g.close()
 
 
+@pytest.mark.parametrize("N,update,precision", [(64, "512:4:8", 1), (64, "512:2:16", 0),
+                                               (100, "512:2:16", 0), (36, "512:2:5", 1),
+                                               (256, "512:4:32", 0)])
+def test_sstep_update_shapes_512(maze, monkeypatch, N, update, precision):
+    """Forced 512-thread update shapes (row-owning layout where N divides
+    512, flat where it does not, a ragged last run, a segment of more than
+    half a plane, and the full-size shape): the same field as the oracle,
+    or at 256^3 a converged step that matches the 256-thread shape."""
+    monkeypatch.setenv("MAZE_UPDATE_SHAPE", update)
+    nt, ppt, cx = (int(v) for v in update.split(":"))
+    print(f"case: sstep update shape {update} N={N} precision {precision}", flush=True)
+    if N == 256:
+        s = inputs.molten_nacl(16, seed=3)
+        kw = dict(tol=1e-8, precision=precision, coulomb_k=inputs.COULOMB_K_EV_A,
+                  flags=maze.MAZE_FLAG_SSTEP)
+        g = maze.Session(dev(s.charges), dev(s.pos), s.box, s.grid_spacing, **kw)
+        ls = maze.maze_launch_shape(g.handle)["latency"]
+        assert (ls["segment"] // ls["ppt"], ls["ppt"], ls["cx"]) == (nt, ppt, cx)
+        monkeypatch.setenv("MAZE_UPDATE_SHAPE", "256:4:64")
+        h = maze.Session(dev(s.charges), dev(s.pos), s.box, s.grid_spacing, **kw)
+        p = dev(s.pos + s.vel)
+        a, b = g.step(p, want_field=True), h.step(p, want_field=True)
+        assert a["status"] == 0 and b["status"] == 0
+        # the same iterates up to the rounding order of the Gram sums
+        assert abs(a["stats"]["iters"] - b["stats"]["iters"]) <= 2
+        assert rel(a["field"], b["field"].cpu().numpy()) <= 1e-6
+        g.close()
+        h.close()
+        return
+    box = 0.4 * N
+    pos, Q, vel = random_system(2 * N, box, seed=7 * N + precision)
+    tol = 1e-12 if precision == 0 else 1e-9
+    g = maze.Session(dev(Q), dev(pos), box, 0.4, tol=tol, precision=precision,
+                     flags=maze.MAZE_FLAG_SSTEP)
+    ls = maze.maze_launch_shape(g.handle)["latency"]
+    assert (ls["segment"] // ls["ppt"], ls["ppt"], ls["cx"]) == (nt, ppt, cx)
+    o = oracle.Session(Q, pos, box, 0.4, tol=1e-13)
+    for k in range(2):
+        p = pos + (k + 1) * vel
+        out = g.step(dev(p), want_field=True)
+        ref = o.step(p)
+        assert out["status"] == 0
+        bound = FIELD_TOL if precision == 0 else \
+            kappa(N) * out["stats"]["rel_residual"] * 1.01 + 1e-12
+        assert rel(out["field"], ref["field"]) <= bound
+        if precision == 0:
+            assert rel(out["forces"], ref["forces"]) <= FORCE_TOL
+    g.close()
+
+
 def test_sstep_tuned_basis_shape_is_cached(maze):
     s = inputs.molten_nacl(8, seed=4)
     print("case: sstep tuned basis shape 128^3", flush=True)
