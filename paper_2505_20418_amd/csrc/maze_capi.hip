@@ -330,13 +330,24 @@ static long long sweep_guard(int max_iter, int first_batch) {
   return (long long)max_iter + 4LL * kPollBatch + first_batch + 64;
 }
 
-// Captures kPollBatch sweeps starting at parity par0 (never the first sweep
+// Captures one poll group of units starting at parity par0 (never the first sweep
 // of a solve) on the session's stream into a graph. The sweeps' arguments
 // depend only on the session, the precision and the parity, so one graph
 // serves every later chunk of every solve.
 static bool sstep_of(const maze_session* s) { return (s->cfg.flags & MAZE_FLAG_SSTEP) != 0; }
 // CG units queued between polls: sweeps, or two-iteration outer steps.
-static int poll_units(const maze_session* s) { return sstep_of(s) ? kPollBatch / 2 : kPollBatch; }
+// Enough for about 100 us of device work (a unit moves 24-64 B per point at
+// some 5 TB/s, plus about 10 us of launch and reduction latency), so the
+// device stays busy through the host's poll; no more, because the units
+// queued after convergence run for nothing (at 256^3 a group of four outer
+// steps left about eight such launches per solve).
+static int poll_units(const maze_session* s, bool fp32) {
+  const bool ss = sstep_of(s);
+  const double bytes = (ss ? 32.0 : 24.0) * (fp32 ? 1.0 : 2.0);
+  const double unit_us = (double)s->d.G * bytes / 5.0e6 + 10.0;
+  const int cap = ss ? kPollBatch / 2 : kPollBatch;
+  return std::max(1, std::min(cap, (int)std::ceil(100.0 / unit_us)));
+}
 
 // Unit k of a solve: sweep k, or outer step k of the two-iteration form.
 static hipError_t launch_unit(maze_session* s, long long k, void* x, bool fp32, bool zero_x) {
@@ -350,7 +361,7 @@ static int chunk_graph(maze_session* s, bool fp32, int par0, void* x, hipGraphEx
   hipGraph_t g = nullptr;
   HIP_TRY(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
   hipError_t e = hipSuccess;
-  for (int b = 0; b < poll_units(s) && e == hipSuccess; ++b)
+  for (int b = 0; b < poll_units(s, fp32) && e == hipSuccess; ++b)
     e = launch_unit(s, 2 + par0 + b, x, fp32, false);
   const hipError_t e2 = hipStreamEndCapture(s->stream, &g);
   if (e != hipSuccess || e2 != hipSuccess || !g) {
@@ -374,7 +385,7 @@ static int run_cg(CgJob& job, bool fp32, bool zero_x, int first_batch) {
   const SweepGeom& w = s->sweep;
   const long long guard = sweep_guard(job.max_iter, first_batch);
   const bool ss = sstep_of(s);
-  const int per = poll_units(s);
+  const int per = poll_units(s, fp32);
   // first_batch counts iterations; a two-iteration unit covers two
   const int first_units = ss ? first_batch / 2 : first_batch;
   long long k = 0;
