@@ -695,9 +695,9 @@ hipError_t sstep_nh(int nh, bool rows, const F& f) {
   }
 }
 
-// Workgroups of kThreads for every kernel; the update kernel also comes in
-// 512-thread and the basis kernel in 1024-thread workgroups (longer
-// segments, less halo work per point).
+// Workgroups of kThreads for every kernel; both also come in 512-thread and
+// the basis kernel in 1024-thread workgroups (longer segments, less halo
+// work per point).
 template <bool UPDATE, class F>
 hipError_t sstep_dispatch(int nt, int ppt, int nh, bool rows, const F& f) {
   if (nt == kThreads) {
@@ -708,13 +708,11 @@ hipError_t sstep_dispatch(int nt, int ppt, int nh, bool rows, const F& f) {
       default: return hipErrorInvalidValue;
     }
   }
-  if constexpr (UPDATE) {
-    if (nt == 512) {
-      switch (ppt) {
-        case 2: return sstep_nh<UPDATE, 2, 512>(nh, rows, f);
-        case 4: return sstep_nh<UPDATE, 4, 512>(nh, rows, f);
-        default: return hipErrorInvalidValue;
-      }
+  if (nt == 512) {
+    switch (ppt) {
+      case 2: return sstep_nh<UPDATE, 2, 512>(nh, rows, f);
+      case 4: return sstep_nh<UPDATE, 4, 512>(nh, rows, f);
+      default: return hipErrorInvalidValue;
     }
   }
   if constexpr (!UPDATE) {
@@ -799,14 +797,16 @@ bool sstep_update_shape_ok(const SweepGeom& g, bool fp32) {
 }
 
 // Basis-kernel shapes that compile without register spills: 256 threads in
-// every class; 1024 threads for FP32 up to 4 points per thread with one
-// halo slot (2 points with two), and for FP64 up to 2 points with one halo
-// slot (1 point with two).
+// every class; 512 threads with 2 or 4 points per thread (FP32) or 2 (FP64)
+// and at most two halo slots; 1024 threads for FP32 up to 4 points per
+// thread with one halo slot (2 points with two), and for FP64 up to 2
+// points with one halo slot (1 point with two).
 bool sstep_basis_shape_ok(const SweepGeom& g, bool fp32) {
   const int nt = g.S / g.ppt;
   const int nh = sweep_nh_class(g.nh);
   if (nh == 0 || sstep_lds_bytes(g, fp32) > 160 * 1024 - 2048) return false;
   if (nt == kThreads) return g.ppt == 1 || g.ppt == 2 || g.ppt == 4;
+  if (nt == 512) return nh <= 2 && (g.ppt == 2 || (fp32 && g.ppt == 4));
   if (nt != 1024 || nh > 2) return false;
   if (fp32) return g.ppt == 1 || g.ppt == 2 || (g.ppt == 4 && nh == 1);
   return g.ppt == 1 || (g.ppt == 2 && nh == 1);

@@ -1246,50 +1246,43 @@ static SweepGeom autotune_sweep(maze_session* s) {
 
 // Shape of the basis kernel of the two-iteration CG. It only reads r and p
 // and is bound by its per-plane steps rather than by HBM, so it prefers
-// fewer, larger workgroups than the update kernel (1024 threads, segments of
-// 2048 or 4096 points: less halo work per point). Candidates are the
-// session's latency shape and the spill-free 1024-thread shapes; each runs
-// 3 warm-up and 8 timed launches on a fill pattern of the session's r and p
-// (the basis kernel writes only its partials), and the fastest is cached per
-// (device, N, precision). MAZE_BASIS_SHAPE="threads:ppt:cx" forces one;
-// MAZE_AUTOTUNE=0 keeps the latency shape.
-static std::map<TuneKey, SweepGeom> g_tuned_basis;
+// larger workgroups (512 or 1024 threads, segments of 1024 to 4096 points:
+// less halo work per point). Candidates are the session's latency shape
+// and the spill-free 512- and 1024-thread shapes; each runs 2 warm-up and
+// 6 timed outer steps (basis and update kernel) on a fill pattern of the
+// session's r and p. MAZE_BASIS_SHAPE="threads:ppt:cx" forces one.
 
 static bool forced_basis(const DeviceState& d, bool fp32, SweepGeom* out) {
   const char* e = std::getenv("MAZE_BASIS_SHAPE");
   int nt = 0, ppt = 0, cx = 0;
   if (!e || std::sscanf(e, "%d:%d:%d", &nt, &ppt, &cx) != 3) return false;
-  if ((nt != kThreads && nt != 1024) || (ppt != 1 && ppt != 2 && ppt != 4) || cx < 1) return false;
+  if ((nt != kThreads && nt != 512 && nt != 1024) || (ppt != 1 && ppt != 2 && ppt != 4) || cx < 1)
+    return false;
   const SweepGeom g = make_sstep_geom(d.N, ppt, cx, nt);
   if (!sstep_basis_shape_ok(g, fp32) || g.nwg > d.part_stride) return false;
   *out = g;
   return true;
 }
 
-static SweepGeom autotune_basis(maze_session* s) {
+// Times the basis candidates with the update kernel in shape `upd`.
+static SweepGeom tune_basis(maze_session* s, const SweepGeom& upd) {
   DeviceState& d = s->d;
   const bool fp32 = s->cfg.precision == MAZE_MIXED;
-  SweepGeom def = s->sweep;
-  if (forced_basis(d, fp32, &def)) return def;
-  if (!autotune_enabled()) return def;
-  const TuneKey key{s->device, d.N, fp32 ? 1 : 0};
-  {
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    auto it = g_tuned_basis.find(key);
-    if (it != g_tuned_basis.end()) return it->second;
-  }
+  const SweepGeom def = s->sweep;
   std::vector<SweepGeom> cand{def};
   const long long P = (long long)d.N * d.N;
-  for (int ppt : {1, 2, 4}) {
-    if (1024LL * ppt > P) continue;  // segments longer than a plane
-    int last = -1;
-    for (int cx : {8, 12, 16, 24, 32, 48, 64}) {
-      const SweepGeom g = make_sstep_geom(d.N, ppt, cx, 1024);
-      if (g.nchunk == last || !sstep_basis_shape_ok(g, fp32) || g.nwg > d.part_stride) continue;
-      last = g.nchunk;
-      cand.push_back(g);
+  for (int nt : {512, 1024})
+    for (int ppt : {1, 2, 4}) {
+      if ((long long)nt * ppt > P) continue;  // segments longer than a plane
+      int last = -1;
+      for (int cx : {8, 12, 16, 24, 32, 48, 64}) {
+        const SweepGeom g = make_sstep_geom(d.N, ppt, cx, nt);
+        if (g.nchunk == last || !sstep_basis_shape_ok(g, fp32) || g.nwg > d.part_stride)
+          continue;
+        last = g.nchunk;
+        cand.push_back(g);
+      }
     }
-  }
   if (cand.size() <= 1) return def;
   hipStream_t st = s->stream;
   void* r0 = fp32 ? (void*)d.r32 : (void*)d.r;
@@ -1307,17 +1300,22 @@ static SweepGeom autotune_basis(maze_session* s) {
   SweepGeom best = def;
   float best_ms = 1e30f;
   for (const SweepGeom& g : cand) {
-    // outer step 2: parity 0, not the first (reads r[0] and p[0])
-    for (int k = 0; k < 3 && ok; ++k)
-      ok = launch_sstep_half(d, g, s->sweep, 2, x, fp32, false, false, st) == hipSuccess;
+    // outer step 2 (parity 0, not the first: reads r[0], p[0], x; the
+    // update writes r[1], p[1] and x), whole outer steps: a basis kernel
+    // timed alone, on data it has just read, ranks the shapes differently
+    for (int k = 0; k < 2 && ok; ++k)
+      ok = launch_sstep_outer(d, g, upd, 2, x, fp32, false, st) == hipSuccess;
     ok = ok && hipEventRecord(e0, st) == hipSuccess;
-    for (int k = 0; k < 8 && ok; ++k)
-      ok = launch_sstep_half(d, g, s->sweep, 2, x, fp32, false, false, st) == hipSuccess;
+    for (int k = 0; k < 6 && ok; ++k)
+      ok = launch_sstep_outer(d, g, upd, 2, x, fp32, false, st) == hipSuccess;
     ok = ok && hipEventRecord(e1, st) == hipSuccess;
+    Scalars h{};
+    ok = ok && hipMemcpyAsync(&h, d.sc, sizeof(Scalars), hipMemcpyDeviceToHost, st) == hipSuccess;
     ok = ok && hipStreamSynchronize(st) == hipSuccess;
     if (!ok) break;
     float ms = 0.f;
-    if (hipEventElapsedTime(&ms, e0, e1) == hipSuccess && ms < best_ms) {
+    if (h.done == 0 && h.err == 0 && hipEventElapsedTime(&ms, e0, e1) == hipSuccess &&
+        ms < best_ms) {
       best_ms = ms;
       best = g;
     }
@@ -1328,21 +1326,16 @@ static SweepGeom autotune_basis(maze_session* s) {
     hipGetLastError();
     return def;
   }
-  std::lock_guard<std::mutex> lk(g_tune_mu);
-  g_tuned_basis[key] = best;
   return best;
 }
 
 // Shape of the update kernel of the two-iteration CG: the session's
 // latency sweep shape (256 threads) or a 512-thread shape (segments of 1024
 // or 2048 points: half the halo rows per point, at fewer waves per CU).
-// Each candidate runs 2 warm-up and 6 timed launches after one basis launch
-// on a fill of the session's r and p (the update reads only the partials
-// of that launch, so every launch does the same work); the fastest is
-// cached per (device, N, precision). MAZE_UPDATE_SHAPE="threads:ppt:cx"
-// forces one; MAZE_AUTOTUNE=0 or a forced MAZE_SWEEP_SHAPE keeps the sweep
-// shape.
-static std::map<TuneKey, SweepGeom> g_tuned_update;
+// Each candidate runs 2 warm-up and 6 timed outer steps (basis kernel,
+// then the update kernel in that shape) on a fill of the session's r and
+// p. MAZE_UPDATE_SHAPE="threads:ppt:cx" forces one; a forced
+// MAZE_SWEEP_SHAPE keeps the sweep shape.
 
 static bool forced_update(const DeviceState& d, bool fp32, SweepGeom* out) {
   const char* e = std::getenv("MAZE_UPDATE_SHAPE");
@@ -1355,20 +1348,11 @@ static bool forced_update(const DeviceState& d, bool fp32, SweepGeom* out) {
   return true;
 }
 
-static SweepGeom autotune_update(maze_session* s) {
+// Times the update candidates with the basis kernel in shape `basis`.
+static SweepGeom tune_update(maze_session* s, const SweepGeom& basis) {
   DeviceState& d = s->d;
   const bool fp32 = s->cfg.precision == MAZE_MIXED;
-  SweepGeom def = s->sweep;
-  if (forced_update(d, fp32, &def)) return def;
-  // a forced sweep shape (MAZE_SWEEP_SHAPE) is the update shape as well
-  SweepGeom fs;
-  if (!autotune_enabled() || forced_shape(d, fp32, &fs)) return def;
-  const TuneKey key{s->device, d.N, fp32 ? 1 : 0};
-  {
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    auto it = g_tuned_update.find(key);
-    if (it != g_tuned_update.end()) return it->second;
-  }
+  const SweepGeom def = s->sweep;
   std::vector<SweepGeom> cand{def};
   const long long P = (long long)d.N * d.N;
   for (int ppt : {2, 4}) {
@@ -1395,16 +1379,15 @@ static SweepGeom autotune_update(maze_session* s) {
   // outer step 2: parity 0, not the first (reads r[0], p[0] and x)
   bool ok = hipMemcpyAsync(d.sc, &sc, sizeof(Scalars), hipMemcpyHostToDevice, st) == hipSuccess &&
             launch_fill_pattern(r0, d.G, fp32, st) == hipSuccess &&
-            launch_fill_pattern(p0, d.G, fp32, st) == hipSuccess &&
-            launch_sstep_half(d, s->sbasis, def, 2, x, fp32, false, false, st) == hipSuccess;
+            launch_fill_pattern(p0, d.G, fp32, st) == hipSuccess;
   SweepGeom best = def;
   float best_ms = 1e30f;
   for (const SweepGeom& g : cand) {
     for (int k = 0; k < 2 && ok; ++k)
-      ok = launch_sstep_half(d, s->sbasis, g, 2, x, fp32, false, true, st) == hipSuccess;
+      ok = launch_sstep_outer(d, basis, g, 2, x, fp32, false, st) == hipSuccess;
     ok = ok && hipEventRecord(e0, st) == hipSuccess;
     for (int k = 0; k < 6 && ok; ++k)
-      ok = launch_sstep_half(d, s->sbasis, g, 2, x, fp32, false, true, st) == hipSuccess;
+      ok = launch_sstep_outer(d, basis, g, 2, x, fp32, false, st) == hipSuccess;
     ok = ok && hipEventRecord(e1, st) == hipSuccess;
     Scalars h{};
     ok = ok && hipMemcpyAsync(&h, d.sc, sizeof(Scalars), hipMemcpyDeviceToHost, st) == hipSuccess;
@@ -1423,9 +1406,52 @@ static SweepGeom autotune_update(maze_session* s) {
     hipGetLastError();
     return def;
   }
-  std::lock_guard<std::mutex> lk(g_tune_mu);
-  g_tuned_update[key] = best;
   return best;
+}
+
+// Basis and update shapes of a two-iteration session. Each kernel's best
+// shape depends on the other's (the basis kernel reads what the update
+// kernel has just written), so the update shape is timed with the latency
+// basis, the basis shape with that update, and the update shape again with
+// the chosen basis. The pair is cached per (device, N, precision); a forced
+// shape is kept and the other tuned around it; MAZE_AUTOTUNE=0 keeps the
+// latency shape for both.
+struct SstepShapes {
+  SweepGeom basis, update;
+};
+static std::map<TuneKey, SstepShapes> g_tuned_sstep;
+
+static void autotune_sstep(maze_session* s) {
+  DeviceState& d = s->d;
+  const bool fp32 = s->cfg.precision == MAZE_MIXED;
+  SweepGeom b = s->sweep, u = s->sweep, fs;
+  const bool fb = forced_basis(d, fp32, &b);
+  // a forced sweep shape (MAZE_SWEEP_SHAPE) is the update shape as well
+  const bool fu = forced_update(d, fp32, &u) || forced_shape(d, fp32, &fs);
+  if (autotune_enabled() && !(fb && fu)) {
+    const TuneKey key{s->device, d.N, fp32 ? 1 : 0};
+    bool hit = false;
+    if (!fb && !fu) {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      auto it = g_tuned_sstep.find(key);
+      if (it != g_tuned_sstep.end()) {
+        b = it->second.basis;
+        u = it->second.update;
+        hit = true;
+      }
+    }
+    if (!hit) {
+      if (!fu) u = tune_update(s, b);
+      if (!fb) b = tune_basis(s, u);
+      if (!fu && !fb) u = tune_update(s, b);
+      if (!fb && !fu) {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tuned_sstep[key] = SstepShapes{b, u};
+      }
+    }
+  }
+  s->sbasis = b;
+  s->sweep = u;
 }
 
 extern "C" {
@@ -1611,8 +1637,8 @@ int maze_init(const maze_config* cfg, const double* charges_dev, const double* p
       }
     }
   }
-  s->sbasis = sstep_of(s) ? autotune_basis(s) : s->sweep;
-  if (sstep_of(s)) s->sweep = autotune_update(s);
+  if (sstep_of(s)) autotune_sstep(s);
+  else s->sbasis = s->sweep;
   if (hipMemsetAsync(base, 0, L.total, stream) != hipSuccess ||
       hipMemcpyAsync(d.Q, charges_dev, sizeof(double) * n, hipMemcpyDeviceToDevice, stream) !=
           hipSuccess) {
