@@ -335,6 +335,15 @@ static long long sweep_guard(int max_iter, int first_batch) {
 // depend only on the session, the precision and the parity, so one graph
 // serves every later chunk of every solve.
 static bool sstep_of(const maze_session* s) { return (s->cfg.flags & MAZE_FLAG_SSTEP) != 0; }
+// Iterations to queue before the first poll of a solve, from the iteration
+// count of the same solve in the previous step: short of it by an eighth
+// (at least two poll groups of sweeps), since iteration counts move by a
+// few percent from step to step and units queued past convergence run for
+// nothing, while the rest of the solve is queued in poll groups.
+static int first_batch_of(int last_iters) {
+  return std::max(0, last_iters - std::max(2 * kPollBatch, last_iters / 8));
+}
+
 // CG units queued between polls: sweeps, or two-iteration outer steps.
 // Enough for about 100 us of device work (a unit moves 24-64 B per point at
 // some 5 TB/s, plus about 10 us of launch and reduction latency), so the
@@ -927,7 +936,7 @@ static int solve_multi(std::vector<maze_session*>& ss, std::vector<double*>& xs,
         j.max_iter = ss[i]->cfg.max_iter;
         jobs.push_back(j);
         idx.push_back(i);
-        fb = std::min(fb, std::max(0, ss[i]->last_iters - 2 * kPollBatch));
+        fb = std::min(fb, first_batch_of(ss[i]->last_iters));
       }
     if (!jobs.empty()) {
       const int rc = run_cg_batch(jobs, false, false, fb);
@@ -1000,7 +1009,7 @@ static int solve_multi(std::vector<maze_session*>& ss, std::vector<double*>& xs,
       j.x = s->d.e32;
       j.max_iter = s->cfg.max_iter - total[i];
       jobs.push_back(j);
-      fb = std::min(fb, std::max(0, s->last_inner[s->refinements] - 2 * kPollBatch));
+      fb = std::min(fb, first_batch_of(s->last_inner[s->refinements]));
     }
     rc = run_cg_batch(jobs, true, true, fb);
     if (rc != MAZE_OK) return rc;
