@@ -246,18 +246,21 @@ int maze_profile_read(maze_session* s, double* out8);
  * the one with the longest runs and segments that fits (16 x planes, 1024
  * points). MAZE_SWEEP_SHAPE="ppt:cx" forces both. With MAZE_FLAG_SSTEP the
  * latency shape is that of the update kernel: the sweep shape or a
- * 512-thread shape, whichever the session times faster at maze_init
- * (cached like the others; MAZE_UPDATE_SHAPE="threads:ppt:cx" forces one,
- * and a forced MAZE_SWEEP_SHAPE or MAZE_AUTOTUNE=0 keeps the sweep shape).
+ * 512-thread shape, whichever runs the outer step faster with the basis
+ * kernel's shape (see maze_basis_shape; MAZE_UPDATE_SHAPE="threads:ppt:cx"
+ * forces one, and a forced MAZE_SWEEP_SHAPE or MAZE_AUTOTUNE=0 keeps the
+ * sweep shape).
  * out8 (HOST, 8 int32): {points per thread, x planes per workgroup,
  * workgroups, segment length} of the latency shape, then of the throughput
  * shape; threads per workgroup = segment length / points per thread. */
 int maze_launch_shape(const maze_session* s, int32_t* out8);
 
 /* Launch shape of the basis kernel of the two-iteration CG
- * (MAZE_FLAG_SSTEP): picked at maze_init by timing the session's latency
- * shape and 1024-thread shapes (longer segments, less halo work) on the
- * session's own buffers, cached per device, grid size and precision;
+ * (MAZE_FLAG_SSTEP): picked at maze_init together with the update kernel's
+ * shape (each kernel's best shape depends on the other's) by timing whole
+ * outer steps of the session's latency shape and of 512- and 1024-thread
+ * shapes (longer segments, less halo work) on the session's own buffers;
+ * the pair is cached per device, grid size and precision.
  * MAZE_BASIS_SHAPE="threads:ppt:cx" forces one, MAZE_AUTOTUNE=0 keeps the
  * latency shape. Without the flag it is the latency shape. out4 (HOST,
  * 4 int32): {threads per workgroup, points per thread, x planes per
