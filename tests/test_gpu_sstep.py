@@ -341,9 +341,10 @@ def test_sstep_profile_counts_outer_steps(maze):
 
 @pytest.mark.parametrize("N,shape,precision", [(100, "1024:2:8", 0), (64, "1024:4:16", 1),
                                                (36, "1024:1:8", 0), (100, "1024:1:32", 1),
-                                               (64, "1024:2:64", 1)])
+                                               (64, "1024:2:64", 1), (64, "512:4:8", 1),
+                                               (100, "512:2:16", 0)])
 def test_sstep_basis_shapes(maze, monkeypatch, N, shape, precision):
-    """Forced 1024-thread basis shapes (a segment that is a whole plane, a
+    """Forced 1024- and 512-thread basis shapes (a segment that is a whole plane, a
     ragged last segment, one x run): the same field as the oracle."""
     monkeypatch.setenv("MAZE_BASIS_SHAPE", shape)
     box = 0.4 * N
@@ -454,15 +455,19 @@ def test_sstep_update_shapes_512(maze, monkeypatch, N, update, precision):
     g.close()
 
 
-def test_sstep_tuned_basis_shape_is_cached(maze):
+def test_sstep_tuned_shapes_are_cached(maze):
     s = inputs.molten_nacl(8, seed=4)
     print("case: sstep tuned basis shape 128^3", flush=True)
     kw = dict(tol=1e-8, precision=maze.MAZE_MIXED, flags=maze.MAZE_FLAG_SSTEP)
     a = maze.Session(dev(s.charges), dev(s.pos), s.box, s.grid_spacing, **kw)
     b = maze.Session(dev(s.charges), dev(s.pos), s.box, s.grid_spacing, **kw)
     sa, sb = maze.maze_basis_shape(a.handle), maze.maze_basis_shape(b.handle)
-    print("basis shape", sa, flush=True)
-    assert sa == sb and sa["threads"] in (256, 1024) and sa["nwg"] >= 1
+    ua = maze.maze_launch_shape(a.handle)["latency"]
+    ub = maze.maze_launch_shape(b.handle)["latency"]
+    print("basis shape", sa, "update shape", ua, flush=True)
+    # the basis and update shapes are tuned and cached as a pair
+    assert sa == sb and sa["threads"] in (256, 512, 1024) and sa["nwg"] >= 1
+    assert ua == ub and ua["segment"] // ua["ppt"] in (256, 512)
     ra, rb = a.step(dev(s.pos + s.vel)), b.step(dev(s.pos + s.vel))
     assert ra["status"] == 0 and torch.equal(ra["forces"], rb["forces"])
     a.close()
