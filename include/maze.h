@@ -212,7 +212,8 @@ int maze_step_batch(maze_session* const* sessions, int32_t count,
 int maze_grid_n(const maze_session* s);
 
 /* Debug/inspection copy of one internal grid (N^3 doubles) into out_dev:
- * which = 0 phi^k, 1 phi^{k-1}, 2 y*, 3 q (projected), 4 sigma_p. */
+ * which = 0 phi^k, 1 phi^{k-1}, 2 y*, 3 q as assigned (the zero-mode
+ * projection is applied where q is read, not stored), 4 sigma_p. */
 int maze_get_grid(const maze_session* s, int which, double* out_dev);
 
 /* Checkpoint of the warm-start state (phi^k, phi^{k-1}, y*, step count and

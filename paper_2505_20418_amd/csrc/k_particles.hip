@@ -205,18 +205,24 @@ hipError_t launch_bin(const DeviceState& d, const double* pos, hipStream_t st) {
 }
 
 // ---- charge assignment -------------------------------------------------------
-// Candidate tiles along one axis whose ions can reach grid tile T: ions with
-// base cell c touch points c .. c+1 (order 2) or c-1 .. c+2 (order 4), so
-// the neighbouring tiles below (order 2) or on both sides (order 4).
-__device__ __forceinline__ int candidate_tiles(int T, int ntx, int order, int* out) {
+// Candidate tiles along one axis whose ions can reach grid tile T. An ion with
+// base cell c touches points c .. c+1 (order 2) or c-1 .. c+2 (order 4), mod
+// N, so the points p of tile T receive from the cells p-1 .. p (order 2) or
+// p-2 .. p+1 (order 4). The candidates are the tiles holding those cells,
+// walked cell by cell: where N leaves a last tile of a single plane, the two
+// cells below point 0 lie in two different tiles, so neighbouring tile
+// indices alone would miss one of them. At most four tiles.
+constexpr int kMaxCandAxis = 4;
+__device__ __forceinline__ int candidate_tiles(int T, int N, int order, int* out) {
   int n = 0;
-  const int lo = -1, hi = (order == 2) ? 0 : 1;
-  for (int o = lo; o <= hi; ++o) {
-    int c = T + o;
-    c = (c < 0) ? c + ntx : (c >= ntx ? c - ntx : c);
+  const int lo = T * kTile - (order == 2 ? 1 : 2);
+  const int hi = min(T * kTile + kTile - 1, N - 1) + (order == 2 ? 0 : 1);
+  for (int c = lo; c <= hi; ++c) {
+    const int w = (c < 0) ? c + N : (c >= N ? c - N : c);
+    const int t = w / kTile;
     bool dup = false;
-    for (int k = 0; k < n; ++k) dup |= (out[k] == c);
-    if (!dup) out[n++] = c;
+    for (int k = 0; k < n; ++k) dup |= (out[k] == t);
+    if (!dup && n < kMaxCandAxis) out[n++] = t;
   }
   // fixed ascending order so the summation order is canonical
   for (int a = 1; a < n; ++a) {
@@ -247,17 +253,18 @@ __global__ __launch_bounds__(kThreads) void k_spread(int N, int ntx, int order,
                                                      const Scalars* sc) {
 #pragma clang fp contract(off)
   __shared__ double red[8];
-  __shared__ int32_t cstart[27], cpre[28];
+  constexpr int kMaxCand = kMaxCandAxis * kMaxCandAxis * kMaxCandAxis;
+  __shared__ int32_t cstart[kMaxCand], cpre[kMaxCand + 1];
   __shared__ double lQ[kSpreadBatch];
   __shared__ int32_t lcell[kSpreadBatch * 3];
   __shared__ double lw[kSpreadBatch * 3 * kMaxOrder];
   if (ctl_ld(&sc->err)) return;
   const int T = blockIdx.x;
   const int TX = T / (ntx * ntx), TY = (T / ntx) % ntx, TZ = T % ntx;
-  int cx[3], cy[3], cz[3];
-  const int nx = candidate_tiles(TX, ntx, order, cx);
-  const int ny = candidate_tiles(TY, ntx, order, cy);
-  const int nz = candidate_tiles(TZ, ntx, order, cz);
+  int cx[kMaxCandAxis], cy[kMaxCandAxis], cz[kMaxCandAxis];
+  const int nx = candidate_tiles(TX, N, order, cx);
+  const int ny = candidate_tiles(TY, N, order, cy);
+  const int nz = candidate_tiles(TZ, N, order, cz);
   const int ncand = nx * ny * nz;
   const int off = (order == 2) ? 0 : 1;
   const int tid = threadIdx.x;

@@ -71,6 +71,25 @@ def test_spread_on_grid_point_is_one_hot(oracle_lib):
     assert abs(q4.sum() - 1) < 1e-14 and np.count_nonzero(q4) == 27
 
 
+@pytest.mark.parametrize("N", [25, 33])
+def test_spread_wraps_on_single_plane_last_tile(oracle_lib, N):
+    """N = 8k + 1: an ion in cell N - 2 spreads its cubic B-spline onto
+    points N-3, N-2, N-1 and 0 of each axis, with the centred B-spline's
+    closed-form weights at t = 0.25 (the GPU spreads by 8^3-point tiles, and
+    N - 1 alone is then the last tile)."""
+    box = 0.4 * N
+    h = box / N
+    t = 0.25
+    b = lambda s: (2 / 3 - s * s + abs(s) ** 3 / 2) if abs(s) < 1 else \
+        ((2 - abs(s)) ** 3 / 6 if abs(s) < 2 else 0.0)
+    w = np.array([b(1 + t), b(t), b(1 - t), b(2 - t)])
+    q = oracle_lib.spread_raw(np.array([[(N - 2 + t) * h] * 3]), np.array([1.0]), box, N, 4)
+    idx = [N - 3, N - 2, N - 1, 0]
+    np.testing.assert_allclose(q[np.ix_(idx, idx, idx)], np.einsum("i,j,k->ijk", w, w, w),
+                               rtol=0, atol=1e-15)
+    assert np.count_nonzero(q) == 64 and abs(q.sum() - 1.0) < 1e-14
+
+
 @pytest.mark.parametrize("order", [2, 4])
 def test_spread_translation_by_one_cell(oracle_lib, order):
     rng = np.random.default_rng(2)
