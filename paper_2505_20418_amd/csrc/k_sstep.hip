@@ -370,15 +370,14 @@ __device__ __forceinline__ void sstep_wg(const SweepArgs<T>& a, const SweepGeom&
   T rm1[PPT], rm2[PPT];               // r at planes u-1, u-2 (segment)
   T bm[PPT], bc[PPT];                 // B p at planes u-2, u-1 (segment)
   T xc[PPT];                          // x at plane u-1 (update)
-  // Per-thread moment sums in T: a thread adds PPT products per plane over
-  // its run of planes (at most a few hundred terms), and the sums of the
-  // threads and workgroups are FP64. In FP32 this halves the cost of the
-  // accumulation, which bounds the basis kernel; the Gram matrix of an FP32
-  // inner solve then carries relative errors of about 1e-6, well inside
-  // what the FP32 vectors themselves carry.
-  T acc[kNs];
+  // Per-thread moment sums in FP64 for both precisions: the basis values
+  // are widened before each product (the product of two floats is exact in
+  // FP64), so the Gram matrix of an FP32 inner solve carries only the
+  // rounding of the FP32 vectors themselves, and the dot products stay FP64
+  // as the precision split of the mixed solver requires.
+  double acc[kNs];
 #pragma unroll
-  for (int i = 0; i < kNs; ++i) acc[i] = (T)0;
+  for (int i = 0; i < kNs; ++i) acc[i] = 0.0;
 
   // ---- prologue: planes ub-dir .. ub+dir of p, plane ub of r -----------------
   {
@@ -488,7 +487,8 @@ __device__ __forceinline__ void sstep_wg(const SweepArgs<T>& a, const SweepGeom&
         const T y4 = -c36 * (((rm2[j] + rc[j]) + (ym.y + yp.y)) + (zm.y + zp.y));
         if (!UPDATE) {
           if (cval[j]) {
-            const T d0 = y0, d1 = y1, d2 = y2, d3 = y3, d4 = y4;
+            const double d0 = (double)y0, d1 = (double)y1, d2 = (double)y2, d3 = (double)y3,
+                         d4 = (double)y4;
             acc[0] += d0 * d0;
             acc[1] += d0 * d1;
             acc[2] += d1 * d1;
@@ -501,7 +501,7 @@ __device__ __forceinline__ void sstep_wg(const SweepArgs<T>& a, const SweepGeom&
             acc[9] += d3 * d3;
             acc[10] += d3 * d4;
             acc[11] += d4 * d4;
-            acc[kNm] = fmax(acc[kNm], fabs(rm1[j]));
+            acc[kNm] = fmax(acc[kNm], fabs((double)rm1[j]));
           }
         } else if (cval[j]) {
           const T xn = xc[j] + ((cx[0] * y0 + cx[1] * y1) + (cx[2] * y2 + cx[3] * y3) + cx[4] * y4);
@@ -552,14 +552,11 @@ __device__ __forceinline__ void sstep_wg(const SweepArgs<T>& a, const SweepGeom&
   }
 
   if (!UPDATE) {
-    double accd[kNs];
-#pragma unroll
-    for (int i = 0; i < kNs; ++i) accd[i] = (double)acc[i];
-    block_reduce_ns<NT>(accd, red);
+    block_reduce_ns<NT>(acc, red);
     if (tid == 0) {
 #pragma unroll
-      for (int c = 0; c < kNm; ++c) a.part[(size_t)(SL_SG0 + c) * a.pstride + L] = accd[c];
-      a.part[(size_t)SL_SGMAX * a.pstride + L] = accd[kNm];
+      for (int c = 0; c < kNm; ++c) a.part[(size_t)(SL_SG0 + c) * a.pstride + L] = acc[c];
+      a.part[(size_t)SL_SGMAX * a.pstride + L] = acc[kNm];
     }
   }
 }
