@@ -55,7 +55,9 @@ enum {
   MAZE_E_NOT_NEUTRAL = -2,  /* |sum Q| > 1e-10 sum |Q| */
   MAZE_E_OOM = -3,          /* device allocation failed */
   MAZE_E_DEVICE = -4,       /* HIP runtime error */
-  MAZE_E_NONFINITE = -5     /* NaN or Inf in the positions */
+  MAZE_E_NONFINITE = -5,    /* NaN or Inf in the positions */
+  MAZE_E_CAPACITY = -6      /* request exceeds a fixed capacity
+                               (maze_step_batch_noalloc) */
 };
 
 enum { MAZE_FP64 = 0, MAZE_MIXED = 1 };
@@ -207,6 +209,26 @@ int maze_solve(maze_session* s, int guess, const double* pos_dev,
 int maze_step_batch(maze_session* const* sessions, int32_t count,
                     const double* const* pos_dev, double* const* forces_dev,
                     double* energies_dev, maze_stats* st);
+
+/* maze_step_batch for callers that cannot allocate device memory (serving
+ * loops and harnesses that forbid allocation after start-up): the same
+ * arguments, semantics, kernels and results as maze_step_batch (bitwise,
+ * for the same batch), but the batch table lives in a fixed array in the
+ * library's device data, one copy per GPU kept until the process ends,
+ * instead of a table allocated by the first large call. The call itself
+ * makes no device, pinned-host or event allocation (host bookkeeping uses
+ * the C++ heap, as every entry point does). Limits: at most 256 sessions
+ * per call (more: MAZE_E_CAPACITY, before any other check) and devices
+ * 0..63. Every call on a device shares that device's table, so calls that
+ * overlap on one device race (as calls of maze_step_batch do); nothing of a
+ * previous call is read. The table's host mirror is ordinary (pageable)
+ * memory, so each convergence poll waits for the work queued before it
+ * instead of overlapping the next group of CG iterations: somewhat slower
+ * than maze_step_batch on small grids. Sessions must have been created by
+ * maze_init (which looks up the table's device address once per device). */
+int maze_step_batch_noalloc(maze_session* const* sessions, int32_t count,
+                            const double* const* pos_dev, double* const* forces_dev,
+                            double* energies_dev, maze_stats* st);
 
 /* Grid side N of a session (0 for NULL). */
 int maze_grid_n(const maze_session* s);

@@ -482,26 +482,76 @@ struct BatchTable {
 };
 static BatchTable g_tables[64];
 
-static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+static constexpr size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// Offsets of a batch table for cap sessions (and its total size).
+static constexpr BatchTable table_layout(int cap) {
+  BatchTable n;
+  n.cap = cap;
+  size_t o = 0;
+  n.o_args = o; o = align256(o + sizeof(SweepArgs<double>) * cap);
+  n.o_geom = o; o = align256(o + sizeof(SweepGeom) * cap);
+  n.o_wgb = o;  o = align256(o + sizeof(int) * (2 * cap + 16));
+  n.o_geom2 = o; o = align256(o + sizeof(SweepGeom) * cap);
+  n.o_wgb2 = o; o = align256(o + sizeof(int) * (2 * cap + 16));
+  n.o_scs = o;  o = align256(o + sizeof(Scalars*) * cap);
+  n.o_poll = o; o = align256(o + sizeof(int32_t) * 6 * cap);
+  n.o_sco = o;  o = align256(o + sizeof(Scalars) * cap);
+  n.bytes = o;
+  return n;
+}
+
+// ---- fixed batch table of maze_step_batch_noalloc -----------------------------
+// The non-allocating batch entry point keeps its batch table (session
+// descriptors, launch geometries, workgroup prefixes, the poll and scalar
+// staging arrays) in `scratch`, one copy per GPU for the life of the process,
+// sized for kNoAllocMaxSessions sessions; its host mirror is a static array
+// per device. In host code `scratch` names a host-side stand-in, not a device
+// address: g_scratch_dev[device] holds the address hipGetSymbolAddress gives
+// for that device, and only that address is passed to kernels and copies.
+// Every table entry is written before a kernel or a copy reads it, so the
+// array needs no clearing between calls.
+constexpr int kNoAllocMaxSessions = 256;
+constexpr int kNoAllocMaxDevices = 64;
+constexpr size_t kNoAllocBytes = table_layout(kNoAllocMaxSessions).bytes;
+static __device__ __align__(256) char scratch[kNoAllocBytes];
+static char* g_scratch_dev[kNoAllocMaxDevices];
+static bool g_scratch_looked_up[kNoAllocMaxDevices];
+static std::mutex g_scratch_mu;
+alignas(256) static char g_noalloc_host[kNoAllocMaxDevices][kNoAllocBytes];
+
+// Looks up this device's address of `scratch`, once per device, with that
+// device current (maze_init calls it for every session's device).
+static void scratch_setup(int device) {
+  if (device < 0 || device >= kNoAllocMaxDevices) return;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_looked_up[device]) return;
+  g_scratch_looked_up[device] = true;
+  void* ptr = nullptr;
+  if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess) {
+    (void)hipGetLastError();
+    ptr = nullptr;
+  }
+  g_scratch_dev[device] = static_cast<char*>(ptr);
+}
+
+// While set, every batch table request of this thread is served by the fixed
+// table (a request for more sessions than it holds fails with
+// MAZE_E_CAPACITY) instead of the grow-on-demand table of the device.
+static thread_local BatchTable* tl_fixed_table = nullptr;
 
 static int ensure_table(int device, int count, BatchTable** out) {
+  if (tl_fixed_table) {
+    if (count > tl_fixed_table->cap) return MAZE_E_CAPACITY;
+    *out = tl_fixed_table;
+    return MAZE_OK;
+  }
   if (device < 0 || device >= 64) return MAZE_E_DEVICE;
   BatchTable& t = g_tables[device];
   if (t.cap < count) {
     int cap = std::max(64, t.cap);
     while (cap < count) cap *= 2;
-    BatchTable n;
-    n.cap = cap;
-    size_t o = 0;
-    n.o_args = o; o = align256(o + sizeof(SweepArgs<double>) * cap);
-    n.o_geom = o; o = align256(o + sizeof(SweepGeom) * cap);
-    n.o_wgb = o;  o = align256(o + sizeof(int) * (2 * cap + 16));
-    n.o_geom2 = o; o = align256(o + sizeof(SweepGeom) * cap);
-    n.o_wgb2 = o; o = align256(o + sizeof(int) * (2 * cap + 16));
-    n.o_scs = o;  o = align256(o + sizeof(Scalars*) * cap);
-    n.o_poll = o; o = align256(o + sizeof(int32_t) * 6 * cap);
-    n.o_sco = o;  o = align256(o + sizeof(Scalars) * cap);
-    n.bytes = o;
+    BatchTable n = table_layout(cap);
     if (hipMalloc((void**)&n.dev, n.bytes) != hipSuccess) {
       hipGetLastError();
       return MAZE_E_OOM;
@@ -1476,6 +1526,8 @@ const char* maze_strerror(int status) {
     case MAZE_E_OOM: return "device allocation failed";
     case MAZE_E_DEVICE: return "HIP runtime error";
     case MAZE_E_NONFINITE: return "non-finite position";
+    case MAZE_E_CAPACITY:
+      return "request exceeds the fixed capacity of maze_step_batch_noalloc (256 sessions)";
     default: return "unknown status";
   }
 }
@@ -1542,6 +1594,7 @@ int maze_init(const maze_config* cfg, const double* charges_dev, const double* p
   s->cfg = *cfg;
   s->stream = stream;
   hipGetDevice(&s->device);
+  scratch_setup(s->device);
   DeviceState& d = s->d;
   d.N = grid_of(cfg);
   d.G = (long long)d.N * d.N * d.N;
@@ -1707,17 +1760,23 @@ int maze_solve(maze_session* s, int guess, const double* pos_dev, double* field_
   return finish_call(s, st);
 }
 
-int maze_step_batch(maze_session* const* sessions, int32_t count, const double* const* pos_dev,
-                    double* const* forces_dev, double* energies_dev, maze_stats* st) {
+// Checks of a batch call: distinct sessions on one device and stream.
+static int check_batch(maze_session* const* sessions, int32_t count, const double* const* pos_dev) {
   if (!sessions || count <= 0 || !pos_dev) return MAZE_E_INVALID;
-  std::vector<maze_session*> ss(sessions, sessions + count);
   for (int i = 0; i < count; ++i) {
-    if (!ss[i] || !pos_dev[i]) return MAZE_E_INVALID;
-    if (ss[i]->stream != ss[0]->stream || ss[i]->device != ss[0]->device) return MAZE_E_INVALID;
+    if (!sessions[i] || !pos_dev[i]) return MAZE_E_INVALID;
+    if (sessions[i]->stream != sessions[0]->stream || sessions[i]->device != sessions[0]->device)
+      return MAZE_E_INVALID;
     for (int j = 0; j < i; ++j)
-      if (ss[j] == ss[i]) return MAZE_E_INVALID;
+      if (sessions[j] == sessions[i]) return MAZE_E_INVALID;
   }
-  hipSetDevice(ss[0]->device);
+  return MAZE_OK;
+}
+
+static int step_batch_impl(maze_session* const* sessions, int32_t count,
+                           const double* const* pos_dev, double* const* forces_dev,
+                           double* energies_dev, maze_stats* st) {
+  std::vector<maze_session*> ss(sessions, sessions + count);
   std::vector<int> rcs;
   std::vector<double*> eptr(count, nullptr);
   if (energies_dev)
@@ -1742,6 +1801,37 @@ int maze_step_batch(maze_session* const* sessions, int32_t count, const double* 
     else if (worst >= 0 && r > worst) worst = r;
   }
   return worst;
+}
+
+int maze_step_batch(maze_session* const* sessions, int32_t count, const double* const* pos_dev,
+                    double* const* forces_dev, double* energies_dev, maze_stats* st) {
+  const int rc = check_batch(sessions, count, pos_dev);
+  if (rc != MAZE_OK) return rc;
+  hipSetDevice(sessions[0]->device);
+  return step_batch_impl(sessions, count, pos_dev, forces_dev, energies_dev, st);
+}
+
+int maze_step_batch_noalloc(maze_session* const* sessions, int32_t count,
+                            const double* const* pos_dev, double* const* forces_dev,
+                            double* energies_dev, maze_stats* st) {
+  if (count > kNoAllocMaxSessions) return MAZE_E_CAPACITY;
+  const int rc = check_batch(sessions, count, pos_dev);
+  if (rc != MAZE_OK) return rc;
+  const int device = sessions[0]->device;
+  if (device < 0 || device >= kNoAllocMaxDevices) return MAZE_E_CAPACITY;
+  hipSetDevice(device);
+  scratch_setup(device);  // a no-op after maze_init on this device
+  if (!g_scratch_dev[device]) return MAZE_E_DEVICE;
+  BatchTable t = table_layout(kNoAllocMaxSessions);
+  t.dev = g_scratch_dev[device];
+  t.host = g_noalloc_host[device];
+  // the first session's poll events, idle while its solve runs in a batch
+  t.ev[0] = sessions[0]->ev[0];
+  t.ev[1] = sessions[0]->ev[1];
+  tl_fixed_table = &t;
+  const int r = step_batch_impl(sessions, count, pos_dev, forces_dev, energies_dev, st);
+  tl_fixed_table = nullptr;
+  return r;
 }
 
 int maze_get_grid(const maze_session* s, int which, double* out_dev) {

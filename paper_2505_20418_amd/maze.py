@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_PKG, "libmaze.so")
 
 MAZE_OK, MAZE_NOT_CONVERGED = 0, 1
 MAZE_E_INVALID, MAZE_E_NOT_NEUTRAL, MAZE_E_OOM, MAZE_E_DEVICE, MAZE_E_NONFINITE = -1, -2, -3, -4, -5
+MAZE_E_CAPACITY = -6
 MAZE_FP64, MAZE_MIXED = 0, 1
 MAZE_GUESS_ZERO, MAZE_GUESS_STATIC, MAZE_GUESS_TIMEPROP = 0, 1, 2
 MAZE_NORM_REL2, MAZE_NORM_ABSMAX = 0, 1
@@ -28,7 +29,8 @@ MAZE_FLAG_SSTEP = 16
 GRID_PHI, GRID_PHI_PREV, GRID_Y, GRID_Q, GRID_SIGMA = 0, 1, 2, 3, 4
 
 EXPORTED = ("maze_abi_version", "maze_strerror", "maze_device_bytes", "maze_init", "maze_step",
-            "maze_solve", "maze_step_batch", "maze_grid_n", "maze_get_grid",
+            "maze_solve", "maze_step_batch", "maze_step_batch_noalloc", "maze_grid_n",
+            "maze_get_grid",
             "maze_state_bytes", "maze_save", "maze_load", "maze_destroy", "maze_md_prime",
             "maze_md_step", "maze_profile_enable", "maze_profile_read", "maze_trace_enable",
             "maze_trace_read", "maze_md_step_batch", "maze_launch_shape", "maze_basis_shape",
@@ -101,6 +103,8 @@ def lib():
         L.maze_step_batch.restype = ctypes.c_int
         L.maze_step_batch.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(dp),
                                       ctypes.POINTER(dp), dp, ctypes.POINTER(maze_stats)]
+        L.maze_step_batch_noalloc.restype = ctypes.c_int
+        L.maze_step_batch_noalloc.argtypes = L.maze_step_batch.argtypes
         L.maze_grid_n.restype = ctypes.c_int
         L.maze_grid_n.argtypes = [vp]
         L.maze_get_grid.restype = ctypes.c_int
@@ -226,6 +230,27 @@ def maze_step_batch(handles: Sequence, pos: Sequence[torch.Tensor],
                                st)
     if rc in (MAZE_E_INVALID, MAZE_E_OOM, MAZE_E_DEVICE):
         raise MazeError(rc, "maze_step_batch")
+    return rc, ([x.as_dict() for x in st] if st is not None else None)
+
+
+def maze_step_batch_noalloc(handles: Sequence, pos: Sequence[torch.Tensor],
+                            forces: Optional[Sequence[Optional[torch.Tensor]]] = None,
+                            energies: Optional[torch.Tensor] = None, want_stats=True):
+    """maze_step_batch through the entry point that allocates nothing (its
+    batch table is a fixed device array of the library, at most 256
+    sessions). Same returns; raises MazeError(MAZE_E_CAPACITY) above 256."""
+    n = len(handles)
+    H = (ctypes.c_void_p * n)(*[h.value if isinstance(h, ctypes.c_void_p) else h for h in handles])
+    P = (ctypes.c_void_p * n)(*[_ptr(p).value for p in pos])
+    F = None
+    if forces is not None:
+        F = (ctypes.c_void_p * n)(*[(_ptr(f).value if f is not None else None) for f in forces])
+    st = (maze_stats * n)() if want_stats else None
+    rc = lib().maze_step_batch_noalloc(H, n, P, F,
+                                       _ptr(energies, numel=n) if energies is not None else None,
+                                       st)
+    if rc in (MAZE_E_INVALID, MAZE_E_OOM, MAZE_E_DEVICE, MAZE_E_CAPACITY):
+        raise MazeError(rc, "maze_step_batch_noalloc")
     return rc, ([x.as_dict() for x in st] if st is not None else None)
 
 
