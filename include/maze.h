@@ -424,6 +424,60 @@ int maze_tcf_sample(maze_tcf* t, const double* pos_dev, const double* vel_dev);
 int maze_tcf_read(const maze_tcf* t, double* sums_host, int64_t* counts_host);
 void maze_tcf_destroy(maze_tcf* t);
 
+/* ---- continuous batches ------------------------------------------------
+ * Steps of many sessions in flight together, for serving: a step joins the
+ * batched CG launches already running as soon as it is added, and leaves
+ * them when its solve ends, so a short step does not wait for a long one and
+ * a step that arrives while others are on the device overlaps with them.
+ * Per session the kernels, launch shapes and stopping decisions are those of
+ * maze_step / maze_md_step alone (each session keeps its own latency
+ * shapes), so every result is bitwise the one the session gets stepped
+ * alone. Not for multigrid sessions. All sessions of a batch share its
+ * device and stream. */
+typedef struct maze_batch maze_batch;
+
+/* Creates a batch on the current device for at most max_sessions (1..4096)
+ * steps in flight, its work queued on `stream` (hipStream_t; the sessions'
+ * cfg.stream must be the same). Allocates the batch's launch tables and
+ * poll buffers (device and pinned host memory), freed by
+ * maze_batch_destroy. */
+int maze_batch_create(void* stream, int32_t max_sessions, maze_batch** out);
+
+/* Adds one step of session s (at most one step of a session in flight).
+ * With md non-NULL it is a full MD step as maze_md_step (kick and drift
+ * are queued now, the short range and the closing kick when the solve
+ * ends; *md is copied, and the buffers it names must stay valid until the
+ * step is taken); else a MaZe step at positions pos_dev (device, n*3 doubles) whose
+ * forces (forces_dev, n*3) and energy (energy_dev, 1 double) are written
+ * when it finishes (either may be NULL). The step's assignment, right-hand
+ * side and first CG unit are queued at once. tag is returned with the
+ * result. MAZE_E_CAPACITY when the batch is full; MAZE_E_INVALID for a
+ * session already in flight, on another device or stream, or multigrid. */
+int maze_batch_add(maze_batch* b, maze_session* s, const maze_md_state* md,
+                   const double* pos_dev, double* forces_dev, double* energy_dev, uint64_t tag);
+
+/* Queues one poll group of CG units (about 100 us of device work) in which
+ * one launch per kernel class covers every running solve, then acts on the
+ * status of the group before: solves that ended leave the launches and
+ * queue their finishing kernels (or, in mixed precision, their FP64
+ * refinement, after which another FP32 pass may join); steps whose
+ * finishing kernels have completed become ready. *n_ready (nullable)
+ * receives the number of ready steps. Call it repeatedly while steps are in
+ * flight; it blocks only on the status copy of the group before. */
+int maze_batch_advance(maze_batch* b, int32_t* n_ready);
+
+/* Removes up to max ready steps, oldest first: tags[i] (HOST, max entries)
+ * and st[i] (HOST, max entries, nullable; st[i].status holds the step's
+ * status, MAZE_E_NONFINITE for rejected positions, which leave the MaZe
+ * state unchanged). *n (nullable) receives the number removed. */
+int maze_batch_take(maze_batch* b, int32_t max, uint64_t* tags, maze_stats* st, int32_t* n);
+
+/* Steps added and not yet taken out of flight (ready steps excluded). */
+int maze_batch_in_flight(const maze_batch* b);
+
+/* Finishes the steps in flight, then frees the batch (NULL is a no-op). */
+void maze_batch_destroy(maze_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -481,7 +481,7 @@ __global__ __launch_bounds__(kThreads) void k_cg_sweep_batch(const SweepArgs<T>*
   }
   const SweepArgs<T> a = args[lo];
   const SweepGeom g = geoms[lo];
-  sweep_wg<T, FIRST, PPT, NH>(a, g, par, b - wg_begin[lo], smem_raw, red);
+  sweep_wg<T, FIRST, PPT, NH>(a, g, par ^ a.par_flip, b - wg_begin[lo], smem_raw, red);
 }
 
 // Status of every session of a batch in one compact array: done, iters, err.

@@ -587,7 +587,8 @@ __global__ __launch_bounds__(NT) void k_sstep_batch(const SweepArgs<T>* __restri
   }
   const SweepArgs<T> a = args[lo];
   const SweepGeom g = geoms[lo];
-  sstep_wg<T, FIRST, UPDATE, PPT, NH, NT, ROWS>(a, g, par, b - wg_begin[lo], smem_raw);
+  sstep_wg<T, FIRST, UPDATE, PPT, NH, NT, ROWS>(a, g, par ^ a.par_flip, b - wg_begin[lo],
+                                               smem_raw);
 }
 
 // Geometry of a two-iteration kernel with nt threads per workgroup

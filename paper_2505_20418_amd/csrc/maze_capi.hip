@@ -1513,6 +1513,376 @@ static void autotune_sstep(maze_session* s) {
   s->sweep = u;
 }
 
+
+// ---- continuous batches -------------------------------------------------------
+// A maze_batch holds the MaZe steps of many sessions in flight on one stream.
+// Adding a step queues its assignment, right-hand side and the first unit of
+// its solve at once; each advance queues one poll group of CG units in which
+// one batched launch per kernel class covers every session whose solve is
+// running, then copies every in-flight session's scalars to pinned memory and
+// acts on the copy of the group before (the device always has a group
+// queued). A session whose solve ends leaves the launches: an FP64 step queues
+// its finishing kernels (true residual, field update, energy, forces, the MD
+// short range and closing kick); a mixed step queues its FP64 refinement, and
+// the next poll decides from its true residual whether another FP32 pass joins
+// the launches. A step is handed back once a poll queued after its finishing
+// kernels has completed. Each session keeps its own latency shapes (the
+// basis, update and sweep shapes it uses alone) and the same per-workgroup
+// code, and the sessions' iterations are independent, so a step's result is
+// bitwise the one it gets stepped alone, whatever else is in flight.
+namespace {
+enum BatchPhase { kBatchCg = 0, kBatchCheck = 1, kBatchFinish = 2 };
+
+struct BatchJob {
+  maze_session* s = nullptr;
+  uint64_t tag = 0;
+  bool has_md = false;
+  maze_md_state md{};
+  const double* pos = nullptr;
+  double* forces = nullptr;
+  double* energy = nullptr;
+  long long md_step = 0;
+  int phase = kBatchCg;
+  bool fp32 = false;       // precision of the solve in flight
+  void* x = nullptr;       // its solution vector
+  long long k = 0;         // units of that solve issued so far (the next one's index)
+  long long guard = 0;     // host guard on k
+  int total = 0;           // CG iterations over the refinement passes
+  int refinements = 0;
+  long long ready = 0;     // first poll whose copy reflects the work queued last
+  int rc = MAZE_OK;
+  bool have_thr = false;   // mixed: the step's FP64 threshold, read at its first check
+  double thr = 0.0;
+  bool stop = false;       // mixed: a pass broke down without progress
+};
+
+struct BatchLaunch {
+  int kind;  // 0 sweep, 1 basis, 2 update
+  bool fp32;
+  int c0, c1, wgb0, nwg, nt, ppt, nh;
+  bool rows;
+  size_t lds;
+};
+}  // namespace
+
+struct maze_batch {
+  hipStream_t stream = nullptr;
+  int device = 0;
+  int cap = 0;
+  std::vector<BatchJob> jobs;
+  std::vector<std::pair<uint64_t, maze_stats>> done;
+  // launch tables, double-buffered: a table is rewritten only after the poll
+  // queued behind the launches that read it has completed
+  BatchTable tab[2];
+  int tab_cur = 1;
+  bool dirty = true;
+  std::vector<BatchLaunch> launches;
+  std::vector<int> members;  // jobs in the current table, in table order
+  long long unit = 0;        // batched units issued (their parity)
+  // polls, double-buffered: device list of scalar pointers, device and
+  // pinned host copies of the scalars
+  struct Poll {
+    char* dev = nullptr;
+    Scalars* host = nullptr;
+    hipEvent_t ev = nullptr;
+    std::vector<maze_session*> list;
+    long long seq = -1;
+  } poll[2];
+  long long polls = 0;       // polls queued
+  bool have_prev = false;
+};
+
+namespace {
+
+size_t batch_poll_bytes(int cap) { return align256(sizeof(Scalars*) * cap) + sizeof(Scalars) * cap; }
+
+// Queues the first unit of a solve of job j (its own shapes, as alone).
+int batch_first_unit(maze_batch* b, BatchJob& j, bool zero_x) {
+  maze_session* s = j.s;
+  HIP_TRY(launch_unit(s, 0, j.x, j.fp32, zero_x));
+  j.k = 1;
+  j.guard = sweep_guard(s->cfg.max_iter - j.total, 0);
+  j.phase = kBatchCg;
+  // polls queued before this solve started still show the status of the
+  // session's previous solve
+  j.ready = b->polls;
+  b->dirty = true;
+  return MAZE_OK;
+}
+
+// Queues the kernels that end a step (after its solve) and marks it to be
+// handed back after the next poll.
+int batch_finish(maze_batch* b, BatchJob& j, long long next_poll) {
+  maze_session* s = j.s;
+  DeviceState& d = s->d;
+  hipStream_t st = s->stream;
+  HIP_TRY(launch_update(d, nullptr, st));
+  HIP_TRY(launch_finalize(d, FIN_ENERGY, update_blocks(d.G), 0.0, 0.0, s->cfg.coulomb_k,
+                          j.has_md ? j.md.scalars_dev + 6 : j.energy, 0, 0, st));
+  double* F = j.has_md ? j.md.f_es_dev : j.forces;
+  if (F) HIP_TRY(launch_gather(d, d.phi_prev, s->cfg.coulomb_k, F, st));
+  std::swap(d.phi_cur, d.phi_prev);
+  s->step += 1;
+  if (j.has_md) {
+    HIP_TRY(launch_md_bmh(j.md, d, st));
+    HIP_TRY(launch_md_finish(j.md, d, j.md_step, st));
+  }
+  j.phase = kBatchFinish;
+  j.ready = next_poll;
+  return MAZE_OK;
+}
+
+// Rebuilds the launch table from the jobs whose solve is running: ordered by
+// (form, precision, template classes), one launch per run of equal class.
+int batch_rebuild(maze_batch* b) {
+  b->tab_cur ^= 1;
+  BatchTable& t = b->tab[b->tab_cur];
+  b->launches.clear();
+  b->members.clear();
+  for (int i = 0; i < (int)b->jobs.size(); ++i)
+    if (b->jobs[i].phase == kBatchCg && b->jobs[i].rc == MAZE_OK) b->members.push_back(i);
+  b->dirty = false;
+  if (b->members.empty()) return MAZE_OK;
+  auto job = [&](int q) -> BatchJob& { return b->jobs[b->members[q]]; };
+  auto cls = [](const SweepGeom& g, bool rows) {
+    return (((g.S / g.ppt) * 8 + g.ppt) * 16 + sweep_nh_class(g.nh)) * 2 + (rows ? 1 : 0);
+  };
+  auto key = [&](int q) {
+    BatchJob& j = job(q);
+    const bool ss = sstep_of(j.s);
+    const SweepGeom& g0 = ss ? j.s->sbasis : j.s->sweep;
+    const long long a = (ss ? 2 : 0) + (j.fp32 ? 1 : 0);
+    const long long c0 = cls(g0, ss && sstep_rows(g0));
+    const long long c1 = ss ? cls(j.s->sweep, sstep_rows(j.s->sweep)) : 0;
+    return (a << 40) | (c0 << 20) | c1;
+  };
+  std::vector<int> order(b->members.size());
+  for (size_t q = 0; q < order.size(); ++q) order[q] = (int)q;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return key(x) < key(y); });
+  std::vector<int> sorted;
+  for (int q : order) sorted.push_back(b->members[q]);
+  b->members = sorted;
+  char* H = t.host;
+  SweepGeom* hg = (SweepGeom*)(H + t.o_geom);
+  SweepGeom* hg2 = (SweepGeom*)(H + t.o_geom2);
+  int* hw = (int*)(H + t.o_wgb);
+  int* hw2 = (int*)(H + t.o_wgb2);
+  int wpos = 0, wpos2 = 0;
+  // open groups: index into launches of the last basis/sweep and update group
+  int gA = -1, gB = -1;
+  long long kA = -1, kB = -1;
+  for (int q = 0; q < (int)b->members.size(); ++q) {
+    BatchJob& j = job(q);
+    maze_session* s = j.s;
+    const bool ss = sstep_of(s);
+    const SweepGeom& ga = ss ? s->sbasis : s->sweep;
+    const bool ra = ss && sstep_rows(ga);
+    const long long ka = ((ss ? 2LL : 0LL) + (j.fp32 ? 1 : 0)) * 1000000007LL + cls(ga, ra);
+    if (gA < 0 || ka != kA) {
+      if (gA >= 0) hw[wpos++] = b->launches[gA].nwg;
+      b->launches.push_back({ss ? 1 : 0, j.fp32, q, q, wpos, 0, ga.S / ga.ppt, ga.ppt,
+                             sweep_nh_class(ga.nh), ra, 0});
+      gA = (int)b->launches.size() - 1;
+      kA = ka;
+    }
+    BatchLaunch& A = b->launches[gA];
+    hw[wpos++] = A.nwg;
+    A.nwg += ga.nwg;
+    A.c1 = q + 1;
+    A.lds = std::max(A.lds, ss ? sstep_lds_bytes(ga, j.fp32) : sweep_lds_bytes(ga, j.fp32, false));
+    hg[q] = ga;
+    if (ss) {
+      const SweepGeom& gu = s->sweep;
+      const bool ru = sstep_rows(gu);
+      const long long kb = (j.fp32 ? 1 : 0) * 1000000007LL + cls(gu, ru);
+      if (gB < 0 || kb != kB || b->launches[gB].c1 != q) {
+        if (gB >= 0) hw2[wpos2++] = b->launches[gB].nwg;
+        b->launches.push_back({2, j.fp32, q, q, wpos2, 0, gu.S / gu.ppt, gu.ppt,
+                               sweep_nh_class(gu.nh), ru, 0});
+        gB = (int)b->launches.size() - 1;
+        kB = kb;
+      }
+      BatchLaunch& B = b->launches[gB];
+      hw2[wpos2++] = B.nwg;
+      B.nwg += gu.nwg;
+      B.c1 = q + 1;
+      B.lds = std::max(B.lds, sstep_lds_bytes(gu, j.fp32));
+      hg2[q] = gu;
+    }
+    const int flip = (int)((b->unit ^ j.k) & 1);
+    const int nprev = ss ? ga.nwg : ga.nwg;
+    if (j.fp32) {
+      SweepArgs<float> a = make_sweep_args<float>(s->d, (float*)j.x, s->geom.nwg, nprev, false);
+      a.par_flip = flip;
+      ((SweepArgs<float>*)(H + t.o_args))[q] = a;
+    } else {
+      SweepArgs<double> a = make_sweep_args<double>(s->d, (double*)j.x, s->geom.nwg, nprev, false);
+      a.par_flip = flip;
+      ((SweepArgs<double>*)(H + t.o_args))[q] = a;
+    }
+  }
+  if (gA >= 0) hw[wpos++] = b->launches[gA].nwg;
+  if (gB >= 0) hw2[wpos2++] = b->launches[gB].nwg;
+  for (const BatchLaunch& L : b->launches)
+    if (L.nh == 0 || L.lds > 160 * 1024 - 2048) return MAZE_E_INVALID;
+  HIP_TRY(hipMemcpyAsync(t.dev, H, t.o_scs, hipMemcpyHostToDevice, b->stream));
+  return MAZE_OK;
+}
+
+// One unit of every running solve: the sweep launches, then the basis
+// launches, then the update launches.
+int batch_unit(maze_batch* b) {
+  BatchTable& t = b->tab[b->tab_cur];
+  const int par = (int)(b->unit & 1);
+  for (int pass = 0; pass < 3; ++pass)
+    for (const BatchLaunch& G : b->launches) {
+      if (G.kind != pass) continue;
+      SweepLaunch L{};
+      L.batch = true;
+      L.par = par;
+      L.ppt = G.ppt;
+      L.nh = G.nh;
+      L.args = t.dev + t.o_args + (size_t)G.c0 * sizeof(SweepArgs<double>);
+      L.geoms = (const SweepGeom*)(t.dev + (G.kind == 2 ? t.o_geom2 : t.o_geom)) + G.c0;
+      L.wg_begin = (const int*)(t.dev + (G.kind == 2 ? t.o_wgb2 : t.o_wgb)) + G.wgb0;
+      L.count = G.c1 - G.c0;
+      L.nwg_total = G.nwg;
+      L.lds = G.lds;
+      const hipError_t e = G.kind == 0
+                               ? launch_sweep(L, G.fp32, false, b->stream)
+                               : launch_sstep_batch(L, G.nt, G.rows, G.fp32, false, G.kind == 2,
+                                                    b->stream);
+      if (e != hipSuccess) return MAZE_E_DEVICE;
+    }
+  b->unit += 1;
+  for (int i : b->members) b->jobs[i].k += 1;
+  return MAZE_OK;
+}
+
+// Queues a copy of the scalars of every job in flight into poll slot
+// polls % 2.
+int batch_queue_poll(maze_batch* b) {
+  maze_batch::Poll& P = b->poll[b->polls & 1];
+  P.list.clear();
+  for (const BatchJob& j : b->jobs) P.list.push_back(j.s);
+  P.seq = b->polls;
+  const int n = (int)P.list.size();
+  b->polls += 1;
+  if (n == 0) return MAZE_OK;
+  std::vector<Scalars*> ptrs(n);
+  for (int i = 0; i < n; ++i) ptrs[i] = P.list[i]->d.sc;
+  HIP_TRY(hipMemcpyAsync(P.dev, ptrs.data(), sizeof(Scalars*) * n, hipMemcpyHostToDevice,
+                         b->stream));
+  Scalars* out_d = (Scalars*)(P.dev + align256(sizeof(Scalars*) * b->cap));
+  HIP_TRY(launch_batch_scalars((Scalars* const*)P.dev, n, out_d, b->stream));
+  HIP_TRY(hipMemcpyAsync(P.host, out_d, sizeof(Scalars) * n, hipMemcpyDeviceToHost, b->stream));
+  HIP_TRY(hipEventRecord(P.ev, b->stream));
+  return MAZE_OK;
+}
+
+// Acts on a completed poll: solves that ended, refinement decisions, steps
+// whose finishing kernels have run.
+int batch_process(maze_batch* b, const maze_batch::Poll& P) {
+  std::map<maze_session*, const Scalars*> sc;
+  for (size_t i = 0; i < P.list.size(); ++i) sc[P.list[i]] = &P.host[i];
+  const long long next_poll = b->polls;  // the next poll queued reflects work queued now
+  std::vector<BatchJob> keep;
+  for (BatchJob& j : b->jobs) {
+    auto it = sc.find(j.s);
+    if (it == sc.end() || P.seq < j.ready) {
+      keep.push_back(j);
+      continue;
+    }
+    const Scalars& h = *it->second;
+    maze_session* s = j.s;
+    if (h.err) {
+      // a rejected position: nothing was advanced beyond the MD drift
+      const int rc = recover_error(s);
+      maze_stats st{};
+      st.grid_n = s->d.N;
+      st.status = rc;
+      b->done.push_back({j.tag, st});
+      b->dirty = true;
+      continue;
+    }
+    if (j.phase == kBatchCg) {
+      const bool ended = h.done != 0 || j.k > j.guard;
+      if (!ended) {
+        keep.push_back(j);
+        continue;
+      }
+      const int code = h.done ? h.done : 3;
+      b->dirty = true;
+      if (!j.fp32) {
+        s->iters = h.iters;
+        s->converged = (code == 1);
+        s->refinements = 0;
+        HIP_TRY(launch_true_residual(s->d, s->geom, s->d.y, s->stream));
+        HIP_TRY(launch_finalize(s->d, FIN_SOLVE_END, s->geom.nwg, 0.0, 0.0, 0.0, nullptr, 0, 0,
+                                s->stream));
+        const int rc = batch_finish(b, j, next_poll);
+        if (rc != MAZE_OK) return rc;
+        keep.push_back(j);
+        continue;
+      }
+      // mixed: FP64 refinement with the correction of this pass
+      s->last_inner[std::min(j.refinements, kMaxRefinements - 1)] = h.iters;
+      j.total += h.iters;
+      j.refinements += 1;
+      HIP_TRY(launch_add_correction(s->d, s->d.y, s->stream));
+      HIP_TRY(launch_refine(s->d, s->geom, s->d.y, true, s->stream));
+      HIP_TRY(launch_finalize(s->d, FIN_SOLVE_END, s->geom.nwg, 0.0, 0.0, 0.0, nullptr, 0, 0,
+                              s->stream));
+      j.phase = kBatchCheck;
+      j.ready = next_poll;
+      // a breakdown without progress ends the step, unconverged
+      if (code == 2 && h.iters == 0) j.stop = true;
+      keep.push_back(j);
+      continue;
+    }
+    if (j.phase == kBatchCheck) {
+      const bool absmax = s->cfg.residual_norm == MAZE_NORM_ABSMAX;
+      const double res = absmax ? h.true_max : std::sqrt(h.true_rr);
+      if (!j.have_thr) {
+        j.thr = h.thr;  // set by the step's solve start, before any inner pass
+        j.have_thr = true;
+      }
+      const double thr = j.thr;
+      s->refinements = j.refinements;
+      s->iters = j.total;
+      if (j.stop || res <= thr || j.refinements >= kMaxRefinements ||
+          j.total >= s->cfg.max_iter) {
+        s->converged = !j.stop && res <= thr;
+        const int rc = batch_finish(b, j, next_poll);
+        if (rc != MAZE_OK) return rc;
+        keep.push_back(j);
+        continue;
+      }
+      const double inner = std::max(kInnerReduction * res, kInnerMargin * thr);
+      HIP_TRY(launch_finalize(s->d, FIN_INNER_START, 0, 0.0, inner, 0.0, nullptr,
+                              s->cfg.max_iter - j.total, s->cfg.residual_norm, s->stream));
+      j.fp32 = true;
+      j.x = s->d.e32;
+      const int rc = batch_first_unit(b, j, true);
+      if (rc != MAZE_OK) return rc;
+      keep.push_back(j);
+      continue;
+    }
+    // kBatchFinish: the poll ran after the finishing kernels
+    s->last_iters = s->iters;
+    maze_stats st{};
+    fill_stats(s, h, &st);
+    st.status = s->converged ? MAZE_OK : MAZE_NOT_CONVERGED;
+    b->done.push_back({j.tag, st});
+  }
+  // the table's members are indices into jobs: rebuild it after a removal
+  if (keep.size() != b->jobs.size()) b->dirty = true;
+  b->jobs.swap(keep);
+  return MAZE_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 int maze_abi_version(void) { return MAZE_ABI_VERSION; }
@@ -2049,6 +2419,165 @@ int maze_md_step_batch(maze_session* const* sessions, const maze_md_state* const
     else if (worst >= 0 && r > worst) worst = r;
   }
   return worst;
+}
+
+// ---- continuous batches -------------------------------------------------------
+int maze_batch_create(void* stream, int32_t max_sessions, maze_batch** out) {
+  if (!out) return MAZE_E_INVALID;
+  *out = nullptr;
+  if (max_sessions < 1 || max_sessions > 4096) return MAZE_E_INVALID;
+  maze_batch* b = new (std::nothrow) maze_batch();
+  if (!b) return MAZE_E_OOM;
+  b->stream = (hipStream_t)stream;
+  b->cap = max_sessions;
+  hipGetDevice(&b->device);
+  bool ok = true;
+  for (BatchTable& t : b->tab) {
+    t = table_layout(max_sessions);
+    ok = ok && hipMalloc((void**)&t.dev, t.bytes) == hipSuccess &&
+         hipHostMalloc((void**)&t.host, t.bytes, hipHostMallocDefault) == hipSuccess;
+  }
+  for (maze_batch::Poll& P : b->poll) {
+    ok = ok && hipMalloc((void**)&P.dev, batch_poll_bytes(max_sessions)) == hipSuccess &&
+         hipHostMalloc((void**)&P.host, sizeof(Scalars) * max_sessions, hipHostMallocDefault) ==
+             hipSuccess &&
+         hipEventCreateWithFlags(&P.ev, hipEventDisableTiming) == hipSuccess;
+  }
+  if (!ok) {
+    (void)hipGetLastError();
+    maze_batch_destroy(b);
+    return MAZE_E_OOM;
+  }
+  *out = b;
+  return MAZE_OK;
+}
+
+int maze_batch_add(maze_batch* b, maze_session* s, const maze_md_state* md,
+                   const double* pos_dev, double* forces_dev, double* energy_dev, uint64_t tag) {
+  if (!b || !s) return MAZE_E_INVALID;
+  if (s->stream != b->stream || s->device != b->device || s->d.mg.levels > 0)
+    return MAZE_E_INVALID;
+  for (const BatchJob& j : b->jobs)
+    if (j.s == s) return MAZE_E_INVALID;
+  if ((int)b->jobs.size() >= b->cap) return MAZE_E_CAPACITY;
+  if (md) {
+    const int rc = md_check(s, md);
+    if (rc != MAZE_OK) return rc;
+  } else if (!pos_dev) {
+    return MAZE_E_INVALID;
+  }
+  hipSetDevice(b->device);
+  BatchJob j;
+  j.s = s;
+  j.tag = tag;
+  DeviceState& d = s->d;
+  if (md) {
+    j.has_md = true;
+    j.md = *md;
+    j.md_step = s->step;
+    HIP_TRY(launch_md_kick_drift(*md, s->step, s->stream));
+    pos_dev = md->pos_dev;
+  } else {
+    j.pos = pos_dev;
+    j.forces = forces_dev;
+    j.energy = energy_dev;
+  }
+  s->iters = 0;
+  s->refinements = 0;
+  s->converged = 0;
+  int rc = assign(s, pos_dev);
+  if (rc != MAZE_OK) return rc;
+  const bool mixed = s->cfg.precision == MAZE_MIXED;
+  HIP_TRY(launch_rhs_maze(d, s->geom, mixed, s->stream));
+  HIP_TRY(launch_finalize(d, FIN_SOLVE_START, s->geom.nwg, s->cfg.tol, 0.0, 0.0, nullptr,
+                          s->cfg.max_iter, s->cfg.residual_norm, s->stream));
+  if (mixed) {
+    // the first poll after this decides whether an FP32 pass is needed
+    j.phase = kBatchCheck;
+    j.ready = b->polls;
+  } else {
+    j.fp32 = false;
+    j.x = d.y;
+    rc = batch_first_unit(b, j, false);
+    if (rc != MAZE_OK) return rc;
+  }
+  b->jobs.push_back(j);
+  return MAZE_OK;
+}
+
+int maze_batch_advance(maze_batch* b, int32_t* n_ready) {
+  if (!b) return MAZE_E_INVALID;
+  hipSetDevice(b->device);
+  if (b->dirty) {
+    const int rc = batch_rebuild(b);
+    if (rc != MAZE_OK) return rc;
+  }
+  const bool running = !b->members.empty();
+  if (running) {
+    int per = kPollBatch;
+    for (int i : b->members) per = std::min(per, poll_units(b->jobs[i].s, b->jobs[i].fp32));
+    for (int u = 0; u < per; ++u) {
+      const int rc = batch_unit(b);
+      if (rc != MAZE_OK) return rc;
+    }
+  }
+  if (!b->jobs.empty() || b->have_prev) {
+    int rc = batch_queue_poll(b);
+    if (rc != MAZE_OK) return rc;
+    const long long cur = b->polls - 1;
+    if (b->have_prev) {
+      const maze_batch::Poll& P = b->poll[(cur - 1) & 1];
+      HIP_TRY(hipEventSynchronize(P.ev));
+      rc = batch_process(b, P);
+      if (rc != MAZE_OK) return rc;
+    }
+    if (running) {
+      b->have_prev = true;
+    } else {
+      // nothing on the device to overlap with: act on this poll at once
+      const maze_batch::Poll& P = b->poll[cur & 1];
+      if (!P.list.empty()) HIP_TRY(hipEventSynchronize(P.ev));
+      rc = batch_process(b, P);
+      if (rc != MAZE_OK) return rc;
+      b->have_prev = false;
+    }
+  }
+  if (n_ready) *n_ready = (int32_t)b->done.size();
+  return MAZE_OK;
+}
+
+int maze_batch_take(maze_batch* b, int32_t max, uint64_t* tags, maze_stats* st, int32_t* n) {
+  if (!b || max < 0 || (max > 0 && !tags)) return MAZE_E_INVALID;
+  const int m = std::min<int>(max, (int)b->done.size());
+  for (int i = 0; i < m; ++i) {
+    tags[i] = b->done[i].first;
+    if (st) st[i] = b->done[i].second;
+  }
+  b->done.erase(b->done.begin(), b->done.begin() + m);
+  if (n) *n = m;
+  return MAZE_OK;
+}
+
+int maze_batch_in_flight(const maze_batch* b) { return b ? (int)b->jobs.size() : 0; }
+
+void maze_batch_destroy(maze_batch* b) {
+  if (!b) return;
+  hipSetDevice(b->device);
+  // finish the steps in flight, so that their sessions stay consistent
+  for (int guard = 0; !b->jobs.empty() && guard < (1 << 22); ++guard)
+    if (maze_batch_advance(b, nullptr) != MAZE_OK) break;
+  if (b->stream) hipStreamSynchronize(b->stream);
+  else hipDeviceSynchronize();
+  for (BatchTable& t : b->tab) {
+    if (t.dev) hipFree(t.dev);
+    if (t.host) hipHostFree(t.host);
+  }
+  for (maze_batch::Poll& P : b->poll) {
+    if (P.dev) hipFree(P.dev);
+    if (P.host) hipHostFree(P.host);
+    if (P.ev) hipEventDestroy(P.ev);
+  }
+  delete b;
 }
 
 }  // extern "C"

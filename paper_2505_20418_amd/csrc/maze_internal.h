@@ -224,7 +224,9 @@ struct SweepArgs {
   int nprev_sweep; // partials written by a sweep (its workgroup count)
   int zero_x;      // first sweep only: write x = 0 (start of an FP32 correction)
   int hist_cap;
-  int pad;
+  int par_flip;    // batched launches: this session's parity is the launch's
+                   // parity XOR par_flip (sessions that joined at different
+                   // iterations share one launch)
 };
 
 template <typename T>

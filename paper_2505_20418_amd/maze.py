@@ -36,7 +36,8 @@ EXPORTED = ("maze_abi_version", "maze_strerror", "maze_device_bytes", "maze_init
             "maze_trace_read", "maze_md_step_batch", "maze_launch_shape", "maze_basis_shape",
             "maze_langevin_noise",
             "maze_rdf_accumulate", "maze_tcf_create", "maze_tcf_sample", "maze_tcf_read",
-            "maze_tcf_destroy")
+            "maze_tcf_destroy", "maze_batch_create", "maze_batch_add", "maze_batch_advance",
+            "maze_batch_take", "maze_batch_in_flight", "maze_batch_destroy")
 
 
 class maze_config(ctypes.Structure):
@@ -105,6 +106,20 @@ def lib():
                                       ctypes.POINTER(dp), dp, ctypes.POINTER(maze_stats)]
         L.maze_step_batch_noalloc.restype = ctypes.c_int
         L.maze_step_batch_noalloc.argtypes = L.maze_step_batch.argtypes
+        L.maze_batch_create.restype = ctypes.c_int
+        L.maze_batch_create.argtypes = [vp, i32, ctypes.POINTER(vp)]
+        L.maze_batch_add.restype = ctypes.c_int
+        L.maze_batch_add.argtypes = [vp, vp, ctypes.POINTER(maze_md_state), dp, dp, dp,
+                                     ctypes.c_uint64]
+        L.maze_batch_advance.restype = ctypes.c_int
+        L.maze_batch_advance.argtypes = [vp, ctypes.POINTER(i32)]
+        L.maze_batch_take.restype = ctypes.c_int
+        L.maze_batch_take.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_uint64),
+                                      ctypes.POINTER(maze_stats), ctypes.POINTER(i32)]
+        L.maze_batch_in_flight.restype = ctypes.c_int
+        L.maze_batch_in_flight.argtypes = [vp]
+        L.maze_batch_destroy.restype = None
+        L.maze_batch_destroy.argtypes = [vp]
         L.maze_grid_n.restype = ctypes.c_int
         L.maze_grid_n.argtypes = [vp]
         L.maze_get_grid.restype = ctypes.c_int
@@ -412,6 +427,63 @@ class Session:
     def close(self):
         if getattr(self, "handle", None) is not None and self.handle.value:
             maze_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Continuous batch of steps in flight (maze_batch_*): steps join the
+    running batched CG launches when added and leave them when their solve
+    ends; each result is bitwise the one the session gets stepped alone."""
+
+    def __init__(self, max_sessions: int = 256, stream=None):
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        self.handle = ctypes.c_void_p()
+        _check(lib().maze_batch_create(ctypes.c_void_p(int(stream)), int(max_sessions),
+                                       ctypes.byref(self.handle)), "maze_batch_create")
+        self.cap = int(max_sessions)
+
+    def add_md(self, handle, md: "maze_md_state", tag: int):
+        """One MD step (maze_md_step) of the session; md's buffers stay in use
+        until the step is taken."""
+        _check(lib().maze_batch_add(self.handle, handle, ctypes.byref(md), None, None, None,
+                                    int(tag)), "maze_batch_add")
+
+    def add(self, handle, pos: torch.Tensor, forces: Optional[torch.Tensor] = None,
+            energy: Optional[torch.Tensor] = None, tag: int = 0):
+        """One MaZe step (maze_step) at pos; forces and energy are written
+        when the step finishes."""
+        _check(lib().maze_batch_add(self.handle, handle, None, _ptr(pos), _ptr(forces),
+                                    _ptr(energy, numel=1) if energy is not None else None,
+                                    int(tag)), "maze_batch_add")
+
+    def advance(self) -> int:
+        n = ctypes.c_int32(0)
+        _check(lib().maze_batch_advance(self.handle, ctypes.byref(n)), "maze_batch_advance")
+        return int(n.value)
+
+    def take(self, max_n: Optional[int] = None):
+        """Ready steps, oldest first: list of (tag, stats dict with "status")."""
+        m = self.cap if max_n is None else int(max_n)
+        tags = (ctypes.c_uint64 * max(m, 1))()
+        st = (maze_stats * max(m, 1))()
+        n = ctypes.c_int32(0)
+        _check(lib().maze_batch_take(self.handle, m, tags, st, ctypes.byref(n)),
+               "maze_batch_take")
+        return [(int(tags[i]), st[i].as_dict()) for i in range(n.value)]
+
+    def in_flight(self) -> int:
+        return int(lib().maze_batch_in_flight(self.handle))
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            lib().maze_batch_destroy(self.handle)
             self.handle = ctypes.c_void_p()
 
     def __del__(self):

@@ -1,0 +1,180 @@
+"""Continuous batching (maze_batch_*) through the C ABI.
+
+Steps join the batched CG launches while other steps are on the device and
+leave when their solve ends. Each session keeps its own launch shapes, so a
+step's result must be bitwise the one the session gets stepped alone,
+whatever is in flight with it: forces, energies, fields and iteration
+counts, for both CG forms and both precisions, for MaZe steps and for full
+MD steps; a rejected step must leave its session unchanged and the others
+unaffected.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from paper_2505_20418_amd import inputs  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+SSTEP = 16
+# (n_cells, grid N, precision, tolerance, flags)
+CASES = [(2, 32, 0, 1e-10, 0), (3, 48, 1, 1e-8, SSTEP), (4, 64, 0, 1e-9, SSTEP),
+         (2, 40, 1, 1e-7, 0), (3, 36, 1, 1e-6, SSTEP)]
+
+
+@pytest.fixture(scope="module")
+def maze():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2505_20418_amd import maze as m
+    m.lib()
+    assert m.MAZE_FLAG_SSTEP == SSTEP
+    return m
+
+
+def dev(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def make(maze, case, seed):
+    n_cells, N, prec, tol, flags = case
+    s = inputs.molten_nacl(n_cells, seed=seed)
+    s.grid_spacing = s.box / N
+    sess = maze.Session(dev(s.charges), dev(s.pos), s.box, s.grid_spacing, tol=tol,
+                        precision=prec, coulomb_k=inputs.COULOMB_K_EV_A, flags=flags)
+    assert sess.N == N
+    return s, sess
+
+
+def test_steps_join_running_batch_bitwise_alone(maze):
+    systems, alone, mix = [], [], []
+    for i, c in enumerate(CASES):
+        s, a = make(maze, c, seed=500 + i)
+        _, b = make(maze, c, seed=500 + i)
+        systems.append(s)
+        alone.append(a)
+        mix.append(b)
+    n = len(CASES)
+    steps = 3
+    # alone: every session steps on its own
+    ref = {}
+    for i in range(n):
+        for k in range(steps):
+            p = dev(systems[i].pos + (k + 1) * systems[i].vel)
+            out = alone[i].step(p, want_field=True)
+            ref[(i, k)] = (out["forces"].clone(), out["energy"].clone(), out["field"].clone(),
+                           out["stats"]["iters"], out["stats"]["refinements"])
+    # mixed in: steps are added one at a time while others are in flight,
+    # and each session's next step as soon as its previous one is taken
+    batch = maze.Batch(max_sessions=8)
+    done_k = [0] * n
+    outs = {}
+    next_k = [0] * n
+    joined_mid_solve = 0
+    pending = list(range(n))
+    bufs = {}
+
+    def add(i):
+        k = next_k[i]
+        p = dev(systems[i].pos + (k + 1) * systems[i].vel)
+        F = torch.empty(systems[i].n_ions, 3, dtype=torch.float64, device="cuda")
+        E = torch.empty(1, dtype=torch.float64, device="cuda")
+        bufs[(i, k)] = (p, F, E)
+        batch.add(mix[i].handle, p, F, E, tag=i * 100 + k)
+        next_k[i] += 1
+
+    print("case: continuous batch", CASES, flush=True)
+    add(pending.pop(0))
+    rounds = 0
+    while any(d < steps for d in done_k):
+        rounds += 1
+        assert rounds < 100000
+        if pending and rounds % 2 == 0:
+            joined_mid_solve += 1 if batch.in_flight() > 0 else 0
+            add(pending.pop(0))
+        batch.advance()
+        for tag, st in batch.take():
+            i, k = divmod(tag, 100)
+            assert st["status"] == maze.MAZE_OK, (i, k, st)
+            torch.cuda.synchronize()
+            outs[(i, k)] = (bufs[(i, k)][1], bufs[(i, k)][2], mix[i].grid(maze.GRID_PHI).clone(),
+                            st["iters"], st["refinements"])
+            done_k[i] += 1
+            if next_k[i] < steps:
+                add(i)
+    assert batch.in_flight() == 0
+    assert joined_mid_solve >= n - 1  # every later session joined a running batch
+    for key, r in ref.items():
+        o = outs[key]
+        assert torch.equal(o[0], r[0]), key
+        assert torch.equal(o[1], r[1]), key
+        assert torch.equal(o[2], r[2]), key
+        assert o[3] == r[3] and o[4] == r[4], key
+    batch.close()
+    for x in alone + mix:
+        x.close()
+
+
+def test_md_steps_in_batch_bitwise_alone(maze):
+    from paper_2505_20418_amd.md import MDRun
+    runs_a, runs_b = [], []
+    for i, (nc, N, prec, tol, flags) in enumerate([(2, 32, 1, 1e-8, SSTEP), (3, 48, 0, 1e-9, 0)]):
+        s = inputs.molten_nacl(nc, seed=600 + i)
+        s.grid_spacing = s.box / N
+        runs_a.append(MDRun(s, tol=tol, precision=prec, flags=flags))
+        runs_b.append(MDRun(s, tol=tol, precision=prec, flags=flags))
+    for r in runs_a:
+        for _ in range(3):
+            r.step()
+    print("case: continuous batch md", flush=True)
+    batch = maze.Batch(max_sessions=4)
+    left = [3, 3]
+    batch.add_md(runs_b[0].session.handle, runs_b[0].md, tag=0)
+    added1 = False
+    while any(left):
+        batch.advance()
+        if not added1:
+            batch.add_md(runs_b[1].session.handle, runs_b[1].md, tag=1)
+            added1 = True
+        for tag, st in batch.take():
+            assert st["status"] == maze.MAZE_OK
+            left[tag] -= 1
+            if left[tag]:
+                batch.add_md(runs_b[tag].session.handle, runs_b[tag].md, tag=tag)
+    torch.cuda.synchronize()
+    for a, b in zip(runs_a, runs_b):
+        for name in ("pos", "vel", "f_es", "f_sr", "scalars"):
+            assert torch.equal(getattr(a, name), getattr(b, name)), name
+    batch.close()
+    for r in runs_a + runs_b:
+        r.close()
+
+
+def test_rejected_step_leaves_session_unchanged(maze):
+    s0, g0 = make(maze, CASES[0], seed=700)
+    s1, g1 = make(maze, CASES[1], seed=701)
+    before = g0.grid(maze.GRID_PHI).clone()
+    bad = s0.pos.copy()
+    bad[3, 1] = np.inf
+    batch = maze.Batch(max_sessions=4)
+    p_bad, p_ok = dev(bad), dev(s1.pos + s1.vel)
+    batch.add(g0.handle, p_bad, tag=0)
+    batch.add(g1.handle, p_ok, tag=1)
+    got = {}
+    for _ in range(100000):
+        if len(got) == 2:
+            break
+        batch.advance()
+        for tag, st in batch.take():
+            got[tag] = st["status"]
+    assert got == {0: maze.MAZE_E_NONFINITE, 1: maze.MAZE_OK}
+    assert torch.equal(before, g0.grid(maze.GRID_PHI))
+    out = g0.step(dev(s0.pos + s0.vel))  # the session still works
+    assert out["status"] == maze.MAZE_OK
+    with pytest.raises(maze.MazeError):
+        batch.add(g1.handle, p_ok, tag=2)
+        batch.add(g1.handle, p_ok, tag=3)  # a second step of a session in flight
+    batch.close()
+    g0.close()
+    g1.close()
