@@ -409,10 +409,12 @@ def bench_observables(system, tol, steps, warmup, flags=0):
     return out
 
 
-def bench_serving(full: bool, rate_hz: float = 200.0, flags: int = 0):
+def bench_serving(full: bool, rate_hz: float = 200.0, flags: int = 0, continuous: bool = True):
     """Poisson stream (mean 200 requests/s) of MD-step requests over molten-
     NaCl sessions of log-uniform size, half mixed at 1e-6, half FP64 at
-    1e-10, admitted by HBM budget and served with continuous batching."""
+    1e-10, admitted by HBM budget. continuous: steps in flight join and
+    leave the running batched CG launches (maze_batch); else rounds of
+    batched MD steps grouped by cost class."""
     from paper_2505_20418_amd import serve
 
     if full:
@@ -420,7 +422,8 @@ def bench_serving(full: bool, rate_hz: float = 200.0, flags: int = 0):
     else:
         n_sess, max_cells, n_req, budget = 64, 8, 400, 16 << 30
     specs = serve.specs_from_inputs(count=n_sess, seed=5, max_cells=max_cells)
-    srv = serve.Server(serve.GpuBackend(flags=flags), specs, budget, max_batch=64)
+    srv = serve.Server(serve.GpuBackend(flags=flags, continuous=continuous), specs, budget,
+                       max_batch=64)
     t0 = time.perf_counter()
     resident = srv.prefill()
     t_prefill = time.perf_counter() - t0
@@ -433,8 +436,13 @@ def bench_serving(full: bool, rate_hz: float = 200.0, flags: int = 0):
     rep.update({"sessions": n_sess, "max_ions": 8 * max_cells ** 3,
                 "max_grid": inputs_grid(max_cells), "arrival_rate_hz": rate_hz,
                 "prefilled_resident": resident, "prefill_s": round(t_prefill, 2),
-                "mix": "full" if full else "reduced (sessions up to 4096 ions, 128^3)",
+                "mix": "full (256 sessions, 64-32768 ions, 32^3-256^3)" if full
+                else "reduced (sessions up to 4096 ions, 128^3)",
                 "cg_form": "two-iteration" if flags else "one-iteration"})
+    if continuous:
+        rep["mean_in_flight"] = rep.pop("mean_batch")
+        rep["max_in_flight"] = rep.pop("max_batch")
+        rep["poll_groups"] = rep.pop("rounds")
     return rep
 
 
@@ -469,8 +477,11 @@ def main():
                     help="also record an FP64 trajectory of this many steps and compare the "
                          "mixed path with it every 50 steps (not part of the default run)")
     ap.add_argument("--no-serving", action="store_true")
-    ap.add_argument("--serving-full", action="store_true",
-                    help="serve the full 256-session mix (up to 32768 ions) instead of 64")
+    ap.add_argument("--serving-reduced", action="store_true",
+                    help="serve a reduced mix (64 sessions up to 4096 ions, 128^3) instead of "
+                         "the full one (256 sessions, 64-32768 ions, 32^3-256^3)")
+    ap.add_argument("--serving-rounds", action="store_true",
+                    help="also serve the stream in rounds of batched MD steps (cost classes)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -631,8 +642,13 @@ def main():
         log(f"bench: ensemble {line['ensemble']}")
     if not args.no_serving:
         log("bench: serving")
-        line["serving"] = bench_serving(args.serving_full, args.serving_rate, flags=cg_flags)
+        line["serving"] = bench_serving(not args.serving_reduced, args.serving_rate,
+                                        flags=cg_flags)
         log(f"bench: serving {line['serving']}")
+        if args.serving_rounds:
+            line["serving_rounds"] = bench_serving(not args.serving_reduced, args.serving_rate,
+                                                   flags=cg_flags, continuous=False)
+            log(f"bench: serving in rounds {line['serving_rounds']}")
     line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)
 

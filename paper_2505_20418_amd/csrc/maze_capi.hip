@@ -1554,6 +1554,7 @@ struct BatchJob {
   bool have_thr = false;   // mixed: the step's FP64 threshold, read at its first check
   double thr = 0.0;
   bool stop = false;       // mixed: a pass broke down without progress
+  bool tp = false;         // the solve in flight runs in the throughput shapes
 };
 
 struct BatchLaunch {
@@ -1596,10 +1597,34 @@ namespace {
 
 size_t batch_poll_bytes(int cap) { return align256(sizeof(Scalars*) * cap) + sizeof(Scalars) * cap; }
 
-// Queues the first unit of a solve of job j (its own shapes, as alone).
+// Shapes of a solve that starts now: the session's latency shapes (its
+// result is then bitwise the one it gets alone) while the running solves
+// together with it need fewer than kThroughputWgs workgroups in their
+// throughput shapes, else the throughput shapes (its result then meets its
+// tolerance, summed in another order), as maze_step_batch decides for a
+// whole batch; MAZE_BATCH_MODE=latency or =throughput forces one. A solve
+// keeps its shapes to its end.
+bool batch_solve_tp(const maze_batch* b, const maze_session* s) {
+  const char* e = std::getenv("MAZE_BATCH_MODE");
+  if (e && std::strcmp(e, "latency") == 0) return false;
+  if (e && std::strcmp(e, "throughput") == 0) return true;
+  long long w = s->sweep_tp.nwg;
+  for (const BatchJob& j : b->jobs)
+    if (j.phase == kBatchCg && j.s != s) w += j.s->sweep_tp.nwg;
+  return w >= kThroughputWgs;
+}
+
+// Queues the first unit of a solve of job j, in the shapes chosen for it.
 int batch_first_unit(maze_batch* b, BatchJob& j, bool zero_x) {
   maze_session* s = j.s;
-  HIP_TRY(launch_unit(s, 0, j.x, j.fp32, zero_x));
+  j.tp = batch_solve_tp(b, s);
+  if (!j.tp) {
+    HIP_TRY(launch_unit(s, 0, j.x, j.fp32, zero_x));
+  } else if (sstep_of(s)) {
+    HIP_TRY(launch_sstep_outer(s->d, s->sweep_tp, s->sweep_tp, 0, j.x, j.fp32, zero_x, s->stream));
+  } else {
+    HIP_TRY(launch_cg_sweep(s->d, s->sweep_tp, 0, s->geom.nwg, j.x, j.fp32, zero_x, s->stream));
+  }
   j.k = 1;
   j.guard = sweep_guard(s->cfg.max_iter - j.total, 0);
   j.phase = kBatchCg;
@@ -1647,13 +1672,24 @@ int batch_rebuild(maze_batch* b) {
   auto cls = [](const SweepGeom& g, bool rows) {
     return (((g.S / g.ppt) * 8 + g.ppt) * 16 + sweep_nh_class(g.nh)) * 2 + (rows ? 1 : 0);
   };
+  // shapes of a job's solve: basis (or sweep) and update; the flat layout
+  // in the throughput shapes, as in a throughput-mode maze_step_batch
+  auto geo_a = [](const BatchJob& j) -> const SweepGeom& {
+    return j.tp ? j.s->sweep_tp : (sstep_of(j.s) ? j.s->sbasis : j.s->sweep);
+  };
+  auto geo_u = [](const BatchJob& j) -> const SweepGeom& {
+    return j.tp ? j.s->sweep_tp : j.s->sweep;
+  };
+  auto rows_of = [](const BatchJob& j, const SweepGeom& g) {
+    return !j.tp && sstep_of(j.s) && sstep_rows(g);
+  };
   auto key = [&](int q) {
     BatchJob& j = job(q);
     const bool ss = sstep_of(j.s);
-    const SweepGeom& g0 = ss ? j.s->sbasis : j.s->sweep;
+    const SweepGeom& g0 = geo_a(j);
     const long long a = (ss ? 2 : 0) + (j.fp32 ? 1 : 0);
-    const long long c0 = cls(g0, ss && sstep_rows(g0));
-    const long long c1 = ss ? cls(j.s->sweep, sstep_rows(j.s->sweep)) : 0;
+    const long long c0 = cls(g0, rows_of(j, g0));
+    const long long c1 = ss ? cls(geo_u(j), rows_of(j, geo_u(j))) : 0;
     return (a << 40) | (c0 << 20) | c1;
   };
   std::vector<int> order(b->members.size());
@@ -1675,8 +1711,8 @@ int batch_rebuild(maze_batch* b) {
     BatchJob& j = job(q);
     maze_session* s = j.s;
     const bool ss = sstep_of(s);
-    const SweepGeom& ga = ss ? s->sbasis : s->sweep;
-    const bool ra = ss && sstep_rows(ga);
+    const SweepGeom& ga = geo_a(j);
+    const bool ra = rows_of(j, ga);
     const long long ka = ((ss ? 2LL : 0LL) + (j.fp32 ? 1 : 0)) * 1000000007LL + cls(ga, ra);
     if (gA < 0 || ka != kA) {
       if (gA >= 0) hw[wpos++] = b->launches[gA].nwg;
@@ -1692,8 +1728,8 @@ int batch_rebuild(maze_batch* b) {
     A.lds = std::max(A.lds, ss ? sstep_lds_bytes(ga, j.fp32) : sweep_lds_bytes(ga, j.fp32, false));
     hg[q] = ga;
     if (ss) {
-      const SweepGeom& gu = s->sweep;
-      const bool ru = sstep_rows(gu);
+      const SweepGeom& gu = geo_u(j);
+      const bool ru = rows_of(j, gu);
       const long long kb = (j.fp32 ? 1 : 0) * 1000000007LL + cls(gu, ru);
       if (gB < 0 || kb != kB || b->launches[gB].c1 != q) {
         if (gB >= 0) hw2[wpos2++] = b->launches[gB].nwg;
@@ -1709,8 +1745,11 @@ int batch_rebuild(maze_batch* b) {
       B.lds = std::max(B.lds, sstep_lds_bytes(gu, j.fp32));
       hg2[q] = gu;
     }
+    if (ga.nwg > s->d.part_stride || (ss && (!sstep_basis_shape_ok(ga, j.fp32) ||
+                                             !sstep_update_shape_ok(geo_u(j), j.fp32))))
+      return MAZE_E_INVALID;
     const int flip = (int)((b->unit ^ j.k) & 1);
-    const int nprev = ss ? ga.nwg : ga.nwg;
+    const int nprev = ga.nwg;
     if (j.fp32) {
       SweepArgs<float> a = make_sweep_args<float>(s->d, (float*)j.x, s->geom.nwg, nprev, false);
       a.par_flip = flip;
@@ -2514,8 +2553,12 @@ int maze_batch_advance(maze_batch* b, int32_t* n_ready) {
   }
   const bool running = !b->members.empty();
   if (running) {
-    int per = kPollBatch;
-    for (int i : b->members) per = std::min(per, poll_units(b->jobs[i].s, b->jobs[i].fp32));
+    // one poll per kPollBatch sweeps or half as many two-iteration units:
+    // a unit covers every running solve, and units queued after a solve has
+    // ended return at once
+    bool any_ss = false;
+    for (int i : b->members) any_ss |= sstep_of(b->jobs[i].s);
+    const int per = any_ss ? kPollBatch / 2 : kPollBatch;
     for (int u = 0; u < per; ++u) {
       const int rc = batch_unit(b);
       if (rc != MAZE_OK) return rc;

@@ -1,32 +1,35 @@
 """Continuous-batching service of MD-step requests over resident MaZe sessions.
 
 Requests ask to advance one session by one MD step and arrive over time.
-The scheduler works at step granularity:
+With a backend that keeps steps in flight (the GPU backend's default, the
+library's maze_batch), scheduling works at CG-iteration granularity:
 
-* every round it forms a batch from the requests that have arrived: at most
-  one request per session (its oldest), up to ``max_batch`` sessions. With
-  the default ``cost_class`` policy the sessions are grouped by estimated
-  step cost (powers of four of N^4, doubled for FP64) and a round serves
-  one class: the cheapest class with a waiting request, unless a request
-  has waited longer than ``max_wait_s``, whose class then goes first. A
-  batched step lasts as long as its most expensive member, so mixing a
-  32^3 session with a 256^3 one would make the small one wait for the big
-  one. The ``fifo`` policy batches every ready session, oldest first;
+* a request whose session is resident (or can be admitted) and has no step
+  in flight is added to the running batch at once: its step joins the
+  batched CG launches already on the device at their next poll group, and
+  leaves them when its solve ends, so a cheap step does not wait for an
+  expensive one and arrivals overlap with the work in flight. At most
+  ``max_batch`` steps are in flight, and at most one per session (a
+  session's steps depend on each other);
 * a session stays resident on the device between its steps, so its MaZe
   warm start (phi^k, phi^{k-1}, y*) and its particles persist;
 * a session that is not resident is admitted when its device bytes fit in
-  the HBM budget; otherwise resident sessions outside the batch are parked
-  least-recently-used first (their state copied to the host with the
-  library's checkpoint and restored exactly on their next admission);
-* one round is one batched MD step of all its sessions (the sessions' CG
-  iterations share their launches on the device); requests that arrive
-  while a round runs join the next round.
+  the HBM budget; otherwise resident sessions with no step in flight are
+  parked least-recently-used first (their state copied to the host with the
+  library's checkpoint and restored exactly on their next admission).
 
-Per request the server records latency (completion minus arrival) and the
-service time of its round. The backend does the device work; the GPU
-backend calls the library through ``maze_md_step_batch``. The clock and the
-sleep function are injectable so the scheduling logic can be exercised with
-a simulated clock.
+A backend without steps in flight is served in rounds, each one batched MD
+step of the sessions it holds; requests that arrive while a round runs join
+the next. With the default ``cost_class`` policy a round serves one class
+of sessions of similar step cost (powers of four of N^4, doubled for FP64),
+the cheapest with a waiting request unless one has waited longer than
+``max_wait_s``; ``fifo`` takes every ready session, oldest first.
+
+Per request the server records latency (completion minus arrival) and
+service time (completion minus the moment its step started). The backend
+does the device work; the GPU backend calls the library (maze_batch_* or
+maze_md_step_batch). The clock and the sleep function are injectable so the
+scheduling logic can be exercised with a simulated clock.
 """
 from __future__ import annotations
 
@@ -71,14 +74,35 @@ class Completion:
 
 class GpuBackend:
     """Sessions as device-resident MD runs of the library (flags: MAZE_FLAG_*
-    for every session, e.g. MAZE_FLAG_SSTEP for the two-iteration CG)."""
+    for every session, e.g. MAZE_FLAG_SSTEP for the two-iteration CG).
+    continuous=True keeps steps in flight in a maze_batch; False serves
+    rounds of maze_md_step_batch."""
 
-    def __init__(self, device: str = "cuda", dt: float = 1.0, flags: int = 0):
+    def __init__(self, device: str = "cuda", dt: float = 1.0, flags: int = 0,
+                 continuous: bool = True):
         from . import inputs, maze, md  # noqa: F401  (fails loudly without the library)
         self.device = device
         self.dt = dt
         self.flags = flags
+        self.continuous = bool(continuous)
         maze.lib()
+
+    # ---- steps in flight (continuous mode) ----
+    def open_batch(self, max_steps: int):
+        from . import maze
+        return maze.Batch(max_sessions=max_steps)
+
+    def add(self, batch, run, tag: int):
+        batch.add_md(run.session.handle, run.md, tag)
+
+    def advance(self, batch):
+        batch.advance()
+
+    def take(self, batch):
+        return batch.take()
+
+    def close_batch(self, batch):
+        batch.close()
 
     def _system(self, spec: SessionSpec):
         from . import inputs
@@ -230,6 +254,73 @@ class Server:
 
     # ---- serving loop ----------------------------------------------------------
     def serve(self, requests: Sequence[Request]) -> dict:
+        if getattr(self.backend, "continuous", False):
+            return self._serve_continuous(requests)
+        return self._serve_rounds(requests)
+
+    def _serve_continuous(self, requests: Sequence[Request]) -> dict:
+        """Steps in flight: arrivals join the running batch at once (see the
+        module docstring)."""
+        reqs = sorted(requests, key=lambda r: r.arrival_s)
+        pending = collections.deque(reqs)
+        queues: Dict[int, collections.deque] = collections.defaultdict(collections.deque)
+        in_flight: Dict[int, tuple] = {}  # sid -> (request, start time, steps in flight at add)
+        batch = self.backend.open_batch(self.max_batch)
+        self.mid_flight_joins = 0
+        t0 = self.clock()
+        n_queued = 0
+        try:
+            while pending or n_queued or in_flight:
+                now = self.clock() - t0
+                while pending and pending[0].arrival_s <= now:
+                    r = pending.popleft()
+                    if self._bytes(r.session) > self.budget:
+                        self.refused.append(r)
+                        continue
+                    queues[r.session].append(r)
+                    n_queued += 1
+                ready = sorted((q[0].arrival_s, sid) for sid, q in queues.items()
+                               if q and sid not in in_flight)
+                queued = {sid for sid, q in queues.items() if q}
+                for _, sid in ready:
+                    if len(in_flight) >= self.max_batch:
+                        break
+                    if not self.admit(sid, protect=set(in_flight), queued=queued):
+                        continue
+                    r = queues[sid].popleft()
+                    n_queued -= 1
+                    if in_flight:
+                        self.mid_flight_joins += 1
+                    t_add = self.clock() - t0
+                    self.backend.add(batch, self.slots[sid].obj, sid)
+                    in_flight[sid] = (r, t_add, len(in_flight) + 1)
+                if not in_flight:
+                    if n_queued:
+                        raise RuntimeError("no queued session fits in the HBM budget with the "
+                                           "resident sessions it cannot park")
+                    if pending:
+                        self.sleep(max(0.0, pending[0].arrival_s - (self.clock() - t0)))
+                    continue
+                self.rounds.append(len(in_flight))
+                self.backend.advance(batch)
+                for sid, st in self.backend.take(batch):
+                    r, t_add, width = in_flight.pop(sid)
+                    t_end = self.clock() - t0
+                    sl = self.slots[sid]
+                    sl.last_used = t_end
+                    sl.steps += 1
+                    self.completions.append(Completion(
+                        session=sid, arrival_s=r.arrival_s, done_s=t_end,
+                        service_s=t_end - t_add, batch_size=width,
+                        status=int(st.get("status", 0)), iters=int(st.get("iters", 0))))
+        finally:
+            self.backend.close_batch(batch)
+        rep = self.report(self.clock() - t0)
+        rep["mode"] = "continuous"
+        rep["mid_flight_joins"] = self.mid_flight_joins
+        return rep
+
+    def _serve_rounds(self, requests: Sequence[Request]) -> dict:
         reqs = sorted(requests, key=lambda r: r.arrival_s)
         pending = collections.deque(reqs)
         queues: Dict[int, collections.deque] = collections.defaultdict(collections.deque)
@@ -280,7 +371,9 @@ class Server:
                     session=sid, arrival_s=r.arrival_s, done_s=t_end - t0,
                     service_s=t_end - t_start, batch_size=len(batch),
                     status=int(st.get("status", 0)), iters=int(st.get("iters", 0))))
-        return self.report(self.clock() - t0)
+        rep = self.report(self.clock() - t0)
+        rep["mode"] = "rounds"
+        return rep
 
     def report(self, wall_s: float) -> dict:
         lat = np.array([c.latency_s for c in self.completions]) * 1e3

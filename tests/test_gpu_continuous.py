@@ -8,6 +8,8 @@ counts, for both CG forms and both precisions, for MaZe steps and for full
 MD steps; a rejected step must leave its session unchanged and the others
 unaffected.
 """
+import math
+
 import numpy as np
 import pytest
 
@@ -47,7 +49,8 @@ def make(maze, case, seed):
     return s, sess
 
 
-def test_steps_join_running_batch_bitwise_alone(maze):
+def test_steps_join_running_batch_bitwise_alone(maze, monkeypatch):
+    monkeypatch.setenv("MAZE_BATCH_MODE", "latency")
     systems, alone, mix = [], [], []
     for i, c in enumerate(CASES):
         s, a = make(maze, c, seed=500 + i)
@@ -116,7 +119,8 @@ def test_steps_join_running_batch_bitwise_alone(maze):
         x.close()
 
 
-def test_md_steps_in_batch_bitwise_alone(maze):
+def test_md_steps_in_batch_bitwise_alone(maze, monkeypatch):
+    monkeypatch.setenv("MAZE_BATCH_MODE", "latency")
     from paper_2505_20418_amd.md import MDRun
     runs_a, runs_b = [], []
     for i, (nc, N, prec, tol, flags) in enumerate([(2, 32, 1, 1e-8, SSTEP), (3, 48, 0, 1e-9, 0)]):
@@ -178,3 +182,40 @@ def test_rejected_step_leaves_session_unchanged(maze):
     batch.close()
     g0.close()
     g1.close()
+
+
+def test_throughput_shapes_meet_tolerance(maze, monkeypatch):
+    """Solves forced into the throughput shapes (another summation order):
+    every step meets its tolerance, and its field differs from the step
+    alone by at most the two solves' residuals through the inverse operator,
+    (4 pi / h) 2 tol ||q|| / lambda_min, lambda_min = 2 (1 - cos(2 pi / N))."""
+    monkeypatch.setenv("MAZE_BATCH_MODE", "throughput")
+    systems, alone, mix = [], [], []
+    for i, c in enumerate(CASES):
+        s, a = make(maze, c, seed=800 + i)
+        _, b = make(maze, c, seed=800 + i)
+        systems.append(s)
+        alone.append(a)
+        mix.append(b)
+    pos = [dev(s.pos + s.vel) for s in systems]
+    ref = [a.step(p, want_field=True) for a, p in zip(alone, pos)]
+    print("case: continuous batch, throughput shapes", flush=True)
+    batch = maze.Batch(max_sessions=8)
+    for i, b in enumerate(mix):
+        batch.add(b.handle, pos[i], tag=i)
+    got = {}
+    while len(got) < len(mix):
+        batch.advance()
+        for tag, st in batch.take():
+            got[tag] = st
+    for i, (r, b) in enumerate(zip(ref, mix)):
+        n_cells, N, prec, tol, flags = CASES[i]
+        assert got[i]["status"] == maze.MAZE_OK and got[i]["rel_residual"] <= tol, i
+        h = systems[i].box / N
+        qn = torch.linalg.norm(b.grid(maze.GRID_Q)).item()
+        bound = (4 * math.pi / h) * 2 * tol * qn / (2 * (1 - math.cos(2 * math.pi / N)))
+        d = torch.linalg.norm(b.grid(maze.GRID_PHI) - r["field"]).item()
+        assert d <= bound, (i, d, bound)
+    batch.close()
+    for x in alone + mix:
+        x.close()

@@ -26,7 +26,7 @@ def test_served_sessions_equal_alone(gpu):
     specs = [serve.SessionSpec(2, 11, False, 1e-10), serve.SessionSpec(3, 12, True, 1e-6),
              serve.SessionSpec(4, 13, False, 1e-10), serve.SessionSpec(2, 14, True, 1e-6),
              serve.SessionSpec(3, 15, False, 1e-10)]
-    be = serve.GpuBackend()
+    be = serve.GpuBackend(continuous=False)
     sizes = [be.bytes_needed(s) for s in specs]
     budget = int(sum(sorted(sizes)[-3:]) * 1.01)     # at most ~3 resident at once
     # arrival-order batching: with this budget and stream it parks and
@@ -62,7 +62,7 @@ def test_cost_class_served_sessions_equal_alone(gpu):
     from paper_2505_20418_amd import serve
     specs = [serve.SessionSpec(2, 21, True, 1e-6), serve.SessionSpec(4, 22, False, 1e-10),
              serve.SessionSpec(2, 23, False, 1e-10), serve.SessionSpec(3, 24, True, 1e-6)]
-    be = serve.GpuBackend()
+    be = serve.GpuBackend(continuous=False)
     srv = serve.Server(be, specs, 1 << 34, max_batch=8)
     reqs = serve.poisson_requests(30, len(specs), rate_hz=500.0, seed=4)
     print(f"case: cost-class serve {len(specs)} sessions, {len(reqs)} requests", flush=True)
@@ -79,4 +79,43 @@ def test_cost_class_served_sessions_equal_alone(gpu):
         assert torch.equal(sl.obj.pos, alone.pos), sid
         assert torch.equal(sl.obj.vel, alone.vel), sid
         alone.close()
+    srv.close()
+
+
+def test_continuous_served_sessions_equal_alone(gpu):
+    """Steps in flight (maze_batch): arrivals join the running batch, and
+    sessions are parked and restored under a tight budget; each session
+    still ends exactly where the same number of steps alone leaves it."""
+    from paper_2505_20418_amd import serve
+    specs = [serve.SessionSpec(2, 31, False, 1e-10), serve.SessionSpec(3, 32, True, 1e-6),
+             serve.SessionSpec(4, 33, False, 1e-10), serve.SessionSpec(2, 34, True, 1e-6),
+             serve.SessionSpec(3, 35, False, 1e-10)]
+    be = serve.GpuBackend()
+    assert be.continuous
+    sizes = [be.bytes_needed(s) for s in specs]
+    budget = int(sum(sorted(sizes)[-3:]) * 1.01)
+    srv = serve.Server(be, specs, budget, max_batch=4)
+    reqs = serve.poisson_requests(30, len(specs), rate_hz=800.0, seed=6)
+    print(f"case: continuous serve {len(specs)} sessions, {len(reqs)} requests", flush=True)
+    rep = srv.serve(reqs)
+    assert rep["mode"] == "continuous"
+    assert rep["requests_completed"] == len(reqs)
+    assert rep["mid_flight_joins"] >= 1, rep
+    assert rep["parked"] >= 1 and rep["restored"] >= 1, rep
+    assert rep["hbm_peak_used"] <= budget
+    assert set(rep["statuses"]) <= {0}
+    for sid, spec in enumerate(specs):
+        sl = srv.slots[sid]
+        if sl.steps == 0:
+            continue
+        run = sl.obj if sl.obj is not None else be.restore(spec, sl.parked)
+        alone = be.create(spec)
+        for _ in range(sl.steps):
+            alone.step()
+        assert torch.equal(run.pos, alone.pos), sid
+        assert torch.equal(run.vel, alone.vel), sid
+        assert torch.equal(run.scalars, alone.scalars), sid
+        alone.close()
+        if sl.obj is None:
+            run.close()
     srv.close()

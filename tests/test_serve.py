@@ -169,3 +169,123 @@ def test_cost_classes_do_not_starve_the_expensive_class():
     big = [x for x in srv.completions if x.session == 1][0]
     assert big.latency_s <= 0.01 + 0.002 + 0.060 + 1e-9
     assert srv.report(1.0)["requests_completed"] == len(reqs)
+
+
+# ---- steps in flight (continuous mode) ------------------------------------
+class FakeContinuous:
+    """A device that keeps steps in flight: each advance is one poll group of
+    `group` seconds, and a step of session s finishes after units[s] groups."""
+    continuous = True
+
+    def __init__(self, clock, sizes, units, group=0.001):
+        self.clock = clock
+        self.sizes = sizes
+        self.units = units
+        self.group = group
+        self.live = {}
+        self.flight = {}
+        self.ready = []
+        self.adds = []
+        self.max_flight = 0
+
+    def bytes_needed(self, spec):
+        return self.sizes[spec.seed]
+
+    def create(self, spec):
+        obj = {"sid": spec.seed, "steps": 0}
+        self.live[id(obj)] = obj
+        return obj
+
+    def park(self, obj):
+        assert obj["sid"] not in self.flight, "a session with a step in flight was parked"
+        del self.live[id(obj)]
+        return {"steps": obj["steps"], "sid": obj["sid"]}
+
+    def restore(self, spec, state):
+        obj = {"sid": state["sid"], "steps": state["steps"]}
+        self.live[id(obj)] = obj
+        return obj
+
+    def destroy(self, obj):
+        self.live.pop(id(obj), None)
+
+    def open_batch(self, n):
+        self.cap = n
+        return self
+
+    def add(self, batch, obj, tag):
+        assert tag not in self.flight
+        self.flight[tag] = [self.units[obj["sid"]], obj]
+        self.adds.append((self.clock.t, tag, len(self.flight)))
+        self.max_flight = max(self.max_flight, len(self.flight))
+        assert len(self.flight) <= self.cap
+
+    def advance(self, batch):
+        self.clock.t += self.group
+        for k in list(self.flight):
+            self.flight[k][0] -= 1
+            if self.flight[k][0] == 0:
+                self.flight[k][1]["steps"] += 1
+                self.ready.append(k)
+                del self.flight[k]
+
+    def take(self, batch):
+        out = [(k, {"status": 0, "iters": 10}) for k in self.ready]
+        self.ready = []
+        return out
+
+    def close_batch(self, batch):
+        pass
+
+
+def make_cont(n=3, units=None, sizes=None, budget=10**9, max_batch=64):
+    clock = FakeClock()
+    units = units or {i: 5 for i in range(n)}
+    sizes = sizes or {i: 100 for i in range(n)}
+    be = FakeContinuous(clock, sizes, units)
+    specs = [SessionSpec(n_cells=2, seed=i, mixed=False, tol=1e-9) for i in range(n)]
+    return Server(be, specs, budget, max_batch=max_batch, clock=clock, sleep=clock.sleep), be, clock
+
+
+def test_cheap_step_joins_and_leaves_before_an_expensive_one():
+    srv, be, clock = make_cont(n=2, units={0: 100, 1: 2})
+    rep = srv.serve([Request(0.0, 0), Request(0.005, 1)])
+    c = {x.session: x for x in srv.completions}
+    # session 1 was added while session 0's step was in flight and finished
+    # after its own two poll groups, long before session 0
+    assert rep["mode"] == "continuous" and rep["mid_flight_joins"] == 1
+    assert be.adds[1][1] == 1 and be.adds[1][2] == 2
+    assert c[1].done_s == pytest.approx(0.007)
+    assert c[1].service_s == pytest.approx(0.002)
+    assert c[0].done_s == pytest.approx(0.100)
+    assert c[1].done_s < c[0].done_s
+
+
+def test_one_step_per_session_in_flight():
+    srv, be, clock = make_cont(n=1, units={0: 3})
+    rep = srv.serve([Request(0.0, 0), Request(0.0, 0), Request(0.0, 0)])
+    assert rep["requests_completed"] == 3
+    assert [a[2] for a in be.adds] == [1, 1, 1]
+    done = sorted(x.done_s for x in srv.completions)
+    assert done == pytest.approx([0.003, 0.006, 0.009])
+    # latency counts from arrival, service from the step's start
+    assert sorted(x.latency_s for x in srv.completions) == pytest.approx([0.003, 0.006, 0.009])
+    assert all(x.service_s == pytest.approx(0.003) for x in srv.completions)
+
+
+def test_in_flight_cap_and_order():
+    srv, be, clock = make_cont(n=5, units={i: 4 for i in range(5)}, max_batch=2)
+    rep = srv.serve([Request(0.0, i) for i in range(5)])
+    assert rep["requests_completed"] == 5
+    assert be.max_flight == 2
+    assert [a[1] for a in be.adds] == [0, 1, 2, 3, 4]
+
+
+def test_parking_never_takes_a_session_in_flight():
+    sizes = {0: 60, 1: 60, 2: 60}
+    srv, be, clock = make_cont(n=3, units={0: 30, 1: 2, 2: 2}, sizes=sizes, budget=130)
+    reqs = [Request(0.0, 0), Request(0.001, 1), Request(0.002, 2), Request(0.010, 1)]
+    rep = srv.serve(reqs)
+    assert rep["requests_completed"] == 4
+    assert rep["parked"] >= 1 and rep["hbm_peak_used"] <= 130
+    assert srv.slots[0].steps == 1 and srv.slots[1].steps == 2 and srv.slots[2].steps == 1
