@@ -321,43 +321,57 @@ def copy_calibration(gib: float = 2.0, reps: int = 5):
 def bench_ensemble(steps: int, warmup: int, tol: float = 1e-8, flags: int = 0):
     """64 molten-NaCl replicas of uneven size (2..6 cells per side, 32^3 to
     96^3 grids, 1100-1400 K), mixed precision, advanced together with one
-    batched MD step per round; the same replicas stepped one by one for
-    comparison."""
+    batched MD step per round, with the batched poll groups launched
+    directly and replayed from captured HIP graphs (MAZE_FLAG_GRAPH_CHUNKS);
+    the same replicas stepped one by one for comparison."""
     import torch
     from paper_2505_20418_amd import inputs, maze, md
 
     reps = inputs.ensemble_replicas(64, master_seed=4)
-    runs = [md.MDRun(inputs.molten_nacl(r.n_cells, seed=r.seed, temperature=r.temperature),
-                     tol=tol, precision=maze.MAZE_MIXED, flags=flags) for r in reps]
-    for _ in range(warmup):
-        md.step_many(runs, want_stats=False)
-    torch.cuda.synchronize()
-    lat = []
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        a = time.perf_counter()
-        md.step_many(runs, want_stats=False)
-        torch.cuda.synchronize()
-        lat.append(time.perf_counter() - a)
-    t_batch = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        for r in runs:
-            r.step()
-    torch.cuda.synchronize()
-    t_serial = time.perf_counter() - t0
-    pts = sum((inputs.GRID_PER_CELL * r.n_cells) ** 3 for r in reps)
-    ions = sum(8 * r.n_cells ** 3 for r in reps)
+    stream = torch.cuda.Stream()  # graphs need a stream that can be captured
+
+    def timed(fl):
+        with torch.cuda.stream(stream):
+            runs = [md.MDRun(inputs.molten_nacl(r.n_cells, seed=r.seed,
+                                                temperature=r.temperature),
+                             tol=tol, precision=maze.MAZE_MIXED, flags=fl,
+                             stream=stream.cuda_stream) for r in reps]
+            for _ in range(warmup):
+                md.step_many(runs, want_stats=False)
+            stream.synchronize()
+            lat = []
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                a = time.perf_counter()
+                md.step_many(runs, want_stats=False)
+                stream.synchronize()
+                lat.append(time.perf_counter() - a)
+            return runs, time.perf_counter() - t0, np.array(lat) * 1e3
+
+    runs, t_batch, lat_ms = timed(flags)
+    with torch.cuda.stream(stream):
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            for r in runs:
+                r.step()
+        stream.synchronize()
+        t_serial = time.perf_counter() - t0
     for r in runs:
         r.close()
-    lat_ms = np.array(lat) * 1e3
+    runs_g, t_graph, lat_g = timed(flags | maze.MAZE_FLAG_GRAPH_CHUNKS)
+    for r in runs_g:
+        r.close()
+    pts = sum((inputs.GRID_PER_CELL * r.n_cells) ** 3 for r in reps)
+    ions = sum(8 * r.n_cells ** 3 for r in reps)
+    pct = lambda a, q: round(float(np.percentile(a, q)), 3)  # noqa: E731
     return {"replicas": len(reps), "ions_total": ions, "grid_points_total": pts,
             "tol_rel_residual": tol, "precision": "mixed", "steps": steps,
             "cg_form": "two-iteration" if flags & maze.MAZE_FLAG_SSTEP else "one-iteration",
             "replica_steps_per_s": round(len(reps) * steps / t_batch, 1),
             "ensemble_steps_per_s": round(steps / t_batch, 3),
-            "step_ms": {"p50": round(float(np.percentile(lat_ms, 50)), 3),
-                        "p99": round(float(np.percentile(lat_ms, 99)), 3)},
+            "step_ms": {"p50": pct(lat_ms, 50), "p99": pct(lat_ms, 99)},
+            "graph_replica_steps_per_s": round(len(reps) * steps / t_graph, 1),
+            "graph_step_ms": {"p50": pct(lat_g, 50), "p99": pct(lat_g, 99)},
             "serial_replica_steps_per_s": round(len(reps) * steps / t_serial, 1),
             "batching_speedup": round(t_serial / t_batch, 3)}
 

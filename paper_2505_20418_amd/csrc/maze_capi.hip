@@ -623,14 +623,66 @@ static bool batch_throughput_mode(const std::vector<CgJob>& jobs) {
   return w >= kThroughputWgs;
 }
 
+// ---- graph-captured poll groups of batched solves ----------------------------
+// A poll group of a batched solve (its units after the first one) depends on
+// the sessions only through the batch table, which the kernels read at run
+// time: the launch structure (the kernel classes with their table ranges,
+// workgroup counts and LDS), the table's device address, the parity of the
+// group's first unit and the number of units fix every launch. So a group
+// captured once into a HIP graph is replayed for every later group with the
+// same key, in this solve and in later calls, whatever sessions fill the
+// table. Graphs are kept per device, at most kBatchGraphMax (then all are
+// dropped and recaptured as needed).
+constexpr size_t kBatchGraphMax = 64;
+static std::map<std::vector<long long>, hipGraphExec_t> g_batch_graphs[64];
+static std::mutex g_batch_graph_mu;
+
+// Replays (capturing on first use) nb units from k0 through launch(k).
+template <class F>
+static hipError_t batch_graph_group(int device, std::vector<long long> key, long long k0, int nb,
+                                    hipStream_t st, F& launch) {
+  if (device < 0 || device >= 64) return hipErrorInvalidValue;
+  key.push_back(k0 & 1);
+  key.push_back(nb);
+  std::lock_guard<std::mutex> lk(g_batch_graph_mu);
+  auto& cache = g_batch_graphs[device];
+  auto it = cache.find(key);
+  hipGraphExec_t exec = nullptr;
+  if (it != cache.end()) {
+    exec = it->second;
+  } else {
+    if (cache.size() >= kBatchGraphMax) {
+      for (auto& kv : cache) (void)hipGraphExecDestroy(kv.second);
+      cache.clear();
+    }
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    for (int b = 0; b < nb && e == hipSuccess; ++b) e = launch(k0 + b);
+    const hipError_t e2 = hipStreamEndCapture(st, &g);
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess && g) e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return e;
+    }
+    cache[key] = exec;
+  }
+  return hipGraphLaunch(exec, st);
+}
+
 // The polling loop of a batched solve: queues `per` units (first call:
 // at least first_units) through launch(k), then copies every session's
 // status to pinned memory and waits for the copy of the group before, so
 // the device always has a group queued; returns once every session is done
-// (or the guard is reached), with iterations and codes in the jobs.
+// (or the guard is reached), with iterations and codes in the jobs. With a
+// graph key (non-empty), the groups after the first (which holds the first
+// unit of every solve) are replayed from captured graphs.
 template <class F>
 static int batch_loop(std::vector<CgJob>& jobs, const std::vector<int>& order, BatchTable* t,
-                      hipStream_t st, long long guard, int per, int first_units, F launch) {
+                      hipStream_t st, long long guard, int per, int first_units, F launch,
+                      const std::vector<long long>& graph_key = {}) {
   const int n = (int)jobs.size();
   char* H = t->host;
   int32_t* poll_h = (int32_t*)(H + t->o_poll);
@@ -640,7 +692,12 @@ static int batch_loop(std::vector<CgJob>& jobs, const std::vector<int>& order, B
   bool have_prev = false;
   for (;;) {
     const int nb = (batch == 0) ? std::max(per, first_units) : per;
-    for (int b = 0; b < nb; ++b, ++k) HIP_TRY(launch(k));
+    if (batch > 0 && !graph_key.empty()) {
+      HIP_TRY(batch_graph_group(jobs[0].s->device, graph_key, k, nb, st, launch));
+      k += nb;
+    } else {
+      for (int b = 0; b < nb; ++b, ++k) HIP_TRY(launch(k));
+    }
     const bool last = k > guard;
     const int slot = batch & 1;
     HIP_TRY(launch_batch_poll((Scalars* const*)(t->dev + t->o_scs), n, poll_d + 3 * n * slot, st));
@@ -679,6 +736,16 @@ static int batch_loop(std::vector<CgJob>& jobs, const std::vector<int>& order, B
 }
 
 static int run_sstep_batch(std::vector<CgJob>& jobs, bool fp32, bool zero_x, int first_batch);
+
+// Batched solves replay their poll groups from captured graphs when every
+// session asks for graph chunks (MAZE_FLAG_GRAPH_CHUNKS), the stream can be
+// captured and no session samples its timing.
+static bool batch_graphs(const std::vector<CgJob>& jobs, hipStream_t st) {
+  if (st == nullptr) return false;
+  for (const CgJob& j : jobs)
+    if (!(j.s->cfg.flags & MAZE_FLAG_GRAPH_CHUNKS) || j.s->prof) return false;
+  return true;
+}
 
 // Batched CG solves: one launch per sweep and template class covers every
 // session; a compact status array is polled.
@@ -752,6 +819,12 @@ static int run_cg_batch(std::vector<CgJob>& jobs, bool fp32, bool zero_x, int fi
   for (const Cls& c : classes)
     if (c.nh == 0 || c.lds > 160 * 1024 - 1024) return MAZE_E_INVALID;
   HIP_TRY(hipMemcpyAsync(t->dev, H, t->o_poll, hipMemcpyHostToDevice, st));
+  std::vector<long long> gkey;
+  if (batch_graphs(jobs, st)) {
+    gkey = {0, (long long)(uintptr_t)t->dev, fp32 ? 1 : 0, n};
+    for (const Cls& c : classes)
+      gkey.insert(gkey.end(), {c.c0, c.c1, c.wgb0, c.nwg, c.ppt, c.nh, (long long)c.lds});
+  }
   return batch_loop(jobs, order, t, st, guard, kPollBatch, first_batch, [&](long long k) {
     for (const Cls& c : classes) {
       SweepLaunch L{};
@@ -769,7 +842,7 @@ static int run_cg_batch(std::vector<CgJob>& jobs, bool fp32, bool zero_x, int fi
       if (e != hipSuccess) return e;
     }
     return hipSuccess;
-  });
+  }, gkey);
 }
 
 // Batched two-iteration solves. The sessions are ordered by the template
@@ -858,6 +931,15 @@ static int run_sstep_batch(std::vector<CgJob>& jobs, bool fp32, bool zero_x, int
     for (const Grp& g : *gs)
       if (g.nh == 0 || g.lds > 160 * 1024 - 2048) return MAZE_E_INVALID;
   HIP_TRY(hipMemcpyAsync(t->dev, H, t->o_poll, hipMemcpyHostToDevice, st));
+  std::vector<long long> gkey;
+  if (batch_graphs(jobs, st)) {
+    gkey = {1, (long long)(uintptr_t)t->dev, fp32 ? 1 : 0, n};
+    for (const std::vector<Grp>* gs : {&gbs, &gus})
+      for (const Grp& g : *gs)
+        gkey.insert(gkey.end(),
+                    {g.c0, g.c1, g.wgb0, g.nwg, g.nt, g.ppt, g.nh, g.rows ? 1 : 0,
+                     (long long)g.lds});
+  }
   return batch_loop(jobs, order, t, st, guard, kPollBatch / 2, first_batch / 2, [&](long long k) {
     for (int half = 0; half < 2; ++half) {
       const bool update = half == 1;
@@ -878,7 +960,7 @@ static int run_sstep_batch(std::vector<CgJob>& jobs, bool fp32, bool zero_x, int
       }
     }
     return hipSuccess;
-  });
+  }, gkey);
 }
 
 // Multigrid-preconditioned CG of one session on x (FP64): per iteration a

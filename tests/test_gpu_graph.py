@@ -5,6 +5,8 @@ direct launches, so MD runs with and without the flag must agree bit for
 bit over many replays (each step replays the chunk graphs several times),
 with unrelated eager work on the same stream in between, in both
 precisions. A session asking for graphs on the null stream is refused.
+Batched solves whose sessions all ask for graphs replay their poll groups
+from graphs captured per launch structure, on the same bar.
 """
 import numpy as np
 import pytest
@@ -86,3 +88,58 @@ def test_graph_chunks_follow_the_solution_vector(gpu):
             assert torch.equal(ra["forces"], rb["forces"]), k
         a.close()
         b.close()
+
+
+# seven sessions of uneven size, both precisions: (n_cells, grid N, precision, tolerance)
+BATCH_GRAPH_CASES = [(2, 32, 0, 1e-10), (3, 48, 1, 1e-8), (4, 64, 0, 1e-9), (2, 20, 1, 1e-7),
+                     (5, 76, 1, 1e-8), (3, 36, 0, 1e-11), (4, 64, 1, 1e-8)]
+
+
+@pytest.mark.parametrize("sstep,mode", [(True, "latency"), (False, "latency"),
+                                        (True, "throughput")])
+def test_batch_graph_groups_bitwise(gpu, monkeypatch, sstep, mode):
+    """Batched poll groups replayed from captured graphs (every session with
+    MAZE_FLAG_GRAPH_CHUNKS) give bitwise the results of direct launches, over
+    several calls with other work on the stream between them."""
+    maze = gpu
+    monkeypatch.setenv("MAZE_BATCH_MODE", mode)
+    st = torch.cuda.Stream()
+    base = maze.MAZE_FLAG_SSTEP if sstep else 0
+    print(f"case: batch graph groups sstep={sstep} mode={mode}", flush=True)
+    with torch.cuda.stream(st):
+        systems, direct, graph = [], [], []
+        for i, (n_cells, N, prec, tol) in enumerate(BATCH_GRAPH_CASES):
+            s = inputs.molten_nacl(n_cells, seed=900 + i)
+            s.grid_spacing = s.box / N
+            Q = torch.tensor(s.charges, dtype=torch.float64, device="cuda")
+            P = torch.tensor(s.pos, dtype=torch.float64, device="cuda")
+            kw = dict(tol=tol, precision=prec, coulomb_k=inputs.COULOMB_K_EV_A,
+                      stream=st.cuda_stream)
+            systems.append(s)
+            direct.append(maze.Session(Q, P, s.box, s.grid_spacing, flags=base, **kw))
+            graph.append(maze.Session(Q, P, s.box, s.grid_spacing,
+                                      flags=base | maze.MAZE_FLAG_GRAPH_CHUNKS, **kw))
+        junk = torch.zeros(1 << 20, dtype=torch.float64, device="cuda")
+        for k in range(4):
+            pos = [torch.tensor(np.ascontiguousarray(s.pos + (k + 1) * s.vel),
+                                dtype=torch.float64, device="cuda") for s in systems]
+            outs = []
+            for sess in (direct, graph):
+                F = [torch.empty(s.n_ions, 3, dtype=torch.float64, device="cuda")
+                     for s in systems]
+                E = torch.empty(len(systems), dtype=torch.float64, device="cuda")
+                rc, stats = maze.maze_step_batch([x.handle for x in sess], pos, F, E)
+                assert rc == maze.MAZE_OK
+                outs.append((F, E, stats))
+                junk.add_(1.0)
+                junk.sum()
+            (Fa, Ea, sa), (Fb, Eb, sb) = outs
+            st.synchronize()
+            assert torch.equal(Ea, Eb), k
+            for i in range(len(systems)):
+                assert sa[i]["iters"] == sb[i]["iters"] and sa[i]["iters"] > 8, (k, i)
+                assert torch.equal(Fa[i], Fb[i]), (k, i)
+                assert torch.equal(direct[i].grid(maze.GRID_PHI), graph[i].grid(maze.GRID_PHI))
+        assert float(junk[0]) == 8.0
+        for x in direct + graph:
+            x.close()
