@@ -14,21 +14,29 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "maze_oracle.c")
 _LIB = os.path.join(_HERE, "libmaze_oracle.so")
+# timing build: the same source with -fopenmp, its order-independent loops
+# threaded (bitwise the plain build's results)
+_LIB_OMP = os.path.join(_HERE, "libmaze_oracle_omp.so")
 
 GUESS_ZERO, GUESS_STATIC, GUESS_TIMEPROP = 0, 1, 2
 NORM_REL2, NORM_ABSMAX = 0, 1
 OK, NOT_CONVERGED, E_INVALID, E_NOT_NEUTRAL = 0, 1, -1, -2
 
 
+def _compile(out: str, extra) -> None:
+    tmp = out + ".tmp"
+    cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c99",
+           "-fPIC", "-shared"] + list(extra) + ["-o", tmp, _SRC, "-lm"]
+    subprocess.check_call(cmd, cwd=_HERE)
+    os.replace(tmp, out)
+
+
 def build(force: bool = True) -> str:
-    """Compile the oracle with plain gcc (no FMA contraction, no intrinsics)."""
-    if force or not os.path.exists(_LIB) or \
-            os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp"
-        cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c99",
-               "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"]
-        subprocess.check_call(cmd, cwd=_HERE)
-        os.replace(tmp, _LIB)
+    """Compile the oracle with plain gcc (no FMA contraction, no intrinsics),
+    and its OpenMP timing build."""
+    for out, extra in ((_LIB, []), (_LIB_OMP, ["-fopenmp"])):
+        if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(_SRC):
+            _compile(out, extra)
     return _LIB
 
 
@@ -51,6 +59,7 @@ class Stats(ctypes.Structure):
 
 
 _lib = None
+_lib_omp = None
 _dp = ctypes.POINTER(ctypes.c_double)
 _ip = ctypes.POINTER(ctypes.c_int32)
 
@@ -60,47 +69,61 @@ def lib():
     if _lib is None:
         if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
             build(force=True)
-        L = ctypes.CDLL(_LIB)
-        L.oracle_grid_n.restype = ctypes.c_int
-        L.oracle_grid_n.argtypes = [ctypes.c_double, ctypes.c_double]
-        L.oracle_axis_weights.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double,
-                                          ctypes.c_int, _ip, _dp]
-        L.oracle_spread_raw.argtypes = [ctypes.c_int, _dp, _dp, ctypes.c_double,
-                                        ctypes.c_int, ctypes.c_int, _dp]
-        L.oracle_project_mean.restype = ctypes.c_double
-        L.oracle_project_mean.argtypes = [ctypes.c_int, _dp]
-        L.oracle_apply_M.argtypes = [ctypes.c_int, _dp, _dp]
-        L.oracle_pcg.restype = ctypes.c_int
-        L.oracle_pcg.argtypes = [ctypes.c_int, _dp, _dp, ctypes.c_double, ctypes.c_int,
-                                 ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
-        for name in ("oracle_gather", "oracle_gather_weight_gradient"):
-            getattr(L, name).argtypes = [ctypes.c_int, _dp, _dp, ctypes.c_double,
-                                         ctypes.c_int, ctypes.c_int, _dp,
-                                         ctypes.c_double, _dp]
-        L.oracle_energy.restype = ctypes.c_double
-        L.oracle_energy.argtypes = [ctypes.c_int, _dp, _dp, ctypes.c_double]
-        L.oracle_init.restype = ctypes.c_int
-        L.oracle_init.argtypes = [ctypes.POINTER(Config), _dp, _dp,
-                                  ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(Stats)]
-        L.oracle_step.restype = ctypes.c_int
-        L.oracle_step.argtypes = [ctypes.c_void_p, _dp, _dp, _dp, _dp,
-                                  ctypes.POINTER(Stats)]
-        L.oracle_solve.restype = ctypes.c_int
-        L.oracle_solve.argtypes = [ctypes.c_void_p, ctypes.c_int, _dp, _dp, _dp, _dp,
-                                   ctypes.POINTER(Stats)]
-        L.oracle_get_state.argtypes = [ctypes.c_void_p, _dp, _dp, _dp, _dp, _dp]
-        L.oracle_grid_of.restype = ctypes.c_int
-        L.oracle_grid_of.argtypes = [ctypes.c_void_p]
-        L.oracle_destroy.argtypes = [ctypes.c_void_p]
-        L.oracle_bmh.argtypes = [ctypes.c_int, _dp, _ip, ctypes.c_double, _dp,
-                                 ctypes.c_double, _dp, _dp]
-        L.oracle_md_step.restype = ctypes.c_int
-        L.oracle_md_step.argtypes = [ctypes.c_void_p, ctypes.c_int, _dp, _dp, _dp, _ip,
-                                     _dp, ctypes.c_double, ctypes.c_double,
-                                     ctypes.c_double, _dp, _dp, _dp, _dp, _dp,
-                                     ctypes.POINTER(Stats)]
-        _lib = L
+        _lib = _load(_LIB)
     return _lib
+
+
+def lib_omp():
+    """The OpenMP timing build (threads from OMP_NUM_THREADS)."""
+    global _lib_omp
+    if _lib_omp is None:
+        if not os.path.exists(_LIB_OMP) or os.path.getmtime(_LIB_OMP) < os.path.getmtime(_SRC):
+            build(force=True)
+        _lib_omp = _load(_LIB_OMP)
+    return _lib_omp
+
+
+def _load(path):
+    L = ctypes.CDLL(path)
+    L.oracle_grid_n.restype = ctypes.c_int
+    L.oracle_grid_n.argtypes = [ctypes.c_double, ctypes.c_double]
+    L.oracle_axis_weights.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                      ctypes.c_int, _ip, _dp]
+    L.oracle_spread_raw.argtypes = [ctypes.c_int, _dp, _dp, ctypes.c_double,
+                                    ctypes.c_int, ctypes.c_int, _dp]
+    L.oracle_project_mean.restype = ctypes.c_double
+    L.oracle_project_mean.argtypes = [ctypes.c_int, _dp]
+    L.oracle_apply_M.argtypes = [ctypes.c_int, _dp, _dp]
+    L.oracle_pcg.restype = ctypes.c_int
+    L.oracle_pcg.argtypes = [ctypes.c_int, _dp, _dp, ctypes.c_double, ctypes.c_int,
+                             ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
+    for name in ("oracle_gather", "oracle_gather_weight_gradient"):
+        getattr(L, name).argtypes = [ctypes.c_int, _dp, _dp, ctypes.c_double,
+                                     ctypes.c_int, ctypes.c_int, _dp,
+                                     ctypes.c_double, _dp]
+    L.oracle_energy.restype = ctypes.c_double
+    L.oracle_energy.argtypes = [ctypes.c_int, _dp, _dp, ctypes.c_double]
+    L.oracle_init.restype = ctypes.c_int
+    L.oracle_init.argtypes = [ctypes.POINTER(Config), _dp, _dp,
+                              ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(Stats)]
+    L.oracle_step.restype = ctypes.c_int
+    L.oracle_step.argtypes = [ctypes.c_void_p, _dp, _dp, _dp, _dp,
+                              ctypes.POINTER(Stats)]
+    L.oracle_solve.restype = ctypes.c_int
+    L.oracle_solve.argtypes = [ctypes.c_void_p, ctypes.c_int, _dp, _dp, _dp, _dp,
+                               ctypes.POINTER(Stats)]
+    L.oracle_get_state.argtypes = [ctypes.c_void_p, _dp, _dp, _dp, _dp, _dp]
+    L.oracle_grid_of.restype = ctypes.c_int
+    L.oracle_grid_of.argtypes = [ctypes.c_void_p]
+    L.oracle_destroy.argtypes = [ctypes.c_void_p]
+    L.oracle_bmh.argtypes = [ctypes.c_int, _dp, _ip, ctypes.c_double, _dp,
+                             ctypes.c_double, _dp, _dp]
+    L.oracle_md_step.restype = ctypes.c_int
+    L.oracle_md_step.argtypes = [ctypes.c_void_p, ctypes.c_int, _dp, _dp, _dp, _ip,
+                                 _dp, ctypes.c_double, ctypes.c_double,
+                                 ctypes.c_double, _dp, _dp, _dp, _dp, _dp,
+                                 ctypes.POINTER(Stats)]
+    return L
 
 
 def _d(a):
@@ -191,7 +214,9 @@ class Session:
     """Host-side MaZe session with the same shape as the device C ABI."""
 
     def __init__(self, charges, pos0, box, grid_spacing, tol=1e-9, order=2,
-                 max_iter=100000, residual_norm=NORM_REL2, coulomb_k=1.0):
+                 max_iter=100000, residual_norm=NORM_REL2, coulomb_k=1.0, omp=False):
+        """omp: run on the OpenMP timing build (bitwise the same results)."""
+        self._L = lib_omp() if omp else lib()
         self.charges = _c(charges)
         self.cfg = Config(len(self.charges), order, box, grid_spacing, tol,
                           max_iter, residual_norm, coulomb_k)
@@ -199,13 +224,13 @@ class Session:
         self.order = order
         self._h = ctypes.c_void_p()
         st = Stats()
-        rc = lib().oracle_init(ctypes.byref(self.cfg), _d(self.charges), _d(_c(pos0)),
+        rc = self._L.oracle_init(ctypes.byref(self.cfg), _d(self.charges), _d(_c(pos0)),
                                ctypes.byref(self._h), ctypes.byref(st))
         if rc < 0:
             raise OracleError(f"oracle_init failed with status {rc}")
         self.init_status = rc
         self.init_stats = st.as_dict()
-        self.N = lib().oracle_grid_of(self._h)
+        self.N = self._L.oracle_grid_of(self._h)
 
     @property
     def n_ions(self):
@@ -217,7 +242,7 @@ class Session:
         forces = np.zeros((self.n_ions, 3))
         e = np.zeros(1)
         st = Stats()
-        rc = lib().oracle_step(self._h, _d(_c(pos)), _d(field), _d(forces), _d(e),
+        rc = self._L.oracle_step(self._h, _d(_c(pos)), _d(field), _d(forces), _d(e),
                                ctypes.byref(st))
         if rc < 0:
             raise OracleError(f"oracle_step failed with status {rc}")
@@ -230,7 +255,7 @@ class Session:
         forces = np.zeros((self.n_ions, 3))
         e = np.zeros(1)
         st = Stats()
-        rc = lib().oracle_solve(self._h, guess, _d(_c(pos)), _d(field), _d(forces),
+        rc = self._L.oracle_solve(self._h, guess, _d(_c(pos)), _d(field), _d(forces),
                                 _d(e), ctypes.byref(st))
         if rc < 0:
             raise OracleError(f"oracle_solve failed with status {rc}")
@@ -240,7 +265,7 @@ class Session:
     def state(self):
         G = self.N ** 3
         a = [np.zeros(G) for _ in range(5)]
-        lib().oracle_get_state(self._h, *[_d(x) for x in a])
+        self._L.oracle_get_state(self._h, *[_d(x) for x in a])
         names = ("phi_k", "phi_km1", "y", "q", "sigma_p")
         return {n: x.reshape((self.N,) * 3) for n, x in zip(names, a)}
 
@@ -250,7 +275,7 @@ class Session:
         e_c = ctypes.c_double(0.0)
         v_sr = ctypes.c_double(0.0)
         st = Stats()
-        rc = lib().oracle_md_step(self._h, self.n_ions, _d(pos), _d(vel), _d(masses),
+        rc = self._L.oracle_md_step(self._h, self.n_ions, _d(pos), _d(vel), _d(masses),
                                   _i(species), _d(_c(table)), cutoff, dt, accel_factor,
                                   _d(F_es), _d(F_sr), _d(work), ctypes.byref(v_sr),
                                   ctypes.byref(e_c), ctypes.byref(st))
@@ -260,7 +285,7 @@ class Session:
 
     def close(self):
         if self._h:
-            lib().oracle_destroy(self._h)
+            self._L.oracle_destroy(self._h)
             self._h = ctypes.c_void_p()
 
     def __del__(self):

@@ -23,6 +23,17 @@
 #define M_PI 3.14159265358979323846
 #endif
 
+/* Timing build only: loops whose iterations are independent (each writes
+ * its own element and reads nothing another iteration writes) run across
+ * threads when compiled with -fopenmp. Every reduction (dot products, norms,
+ * sums, the charge scatter, the pair forces) stays a plain sequential loop,
+ * so the threaded build returns bitwise the results of the plain one. */
+#ifdef _OPENMP
+#define ORACLE_PARALLEL_FOR _Pragma("omp parallel for schedule(static)")
+#else
+#define ORACLE_PARALLEL_FOR
+#endif
+
 static long long flat(int N, int i, int j, int k) {
   return ((long long)i * N + j) * N + k;
 }
@@ -151,6 +162,7 @@ double oracle_project_mean(int N, double* x) {
   double s = 0.0;
   for (long long n = 0; n < G; ++n) s += x[n];
   double mean = s / (double)G;
+  ORACLE_PARALLEL_FOR
   for (long long n = 0; n < G; ++n) x[n] -= mean;
   return mean;
 }
@@ -158,6 +170,7 @@ double oracle_project_mean(int N, double* x) {
 /* The matrix M of the footnote to equation "linearproblem": -6 on the
  * diagonal and +1 for each of the six axis neighbours, periodic. */
 void oracle_apply_M(int N, const double* x, double* out) {
+  ORACLE_PARALLEL_FOR
   for (int i = 0; i < N; ++i)
     for (int j = 0; j < N; ++j)
       for (int k = 0; k < N; ++k) {
@@ -204,8 +217,11 @@ int oracle_pcg(int N, const double* b, double* x, double thr, int norm,
   double* w = (double*)malloc(sizeof(double) * (size_t)G);
   /* r = b - A x = b + M x */
   oracle_apply_M(N, x, w);
+  ORACLE_PARALLEL_FOR
   for (long long n = 0; n < G; ++n) r[n] = b[n] + w[n];
+  ORACLE_PARALLEL_FOR
   for (long long n = 0; n < G; ++n) z[n] = r[n] / 6.0;
+  ORACLE_PARALLEL_FOR
   for (long long n = 0; n < G; ++n) p[n] = z[n];
   double rho = dot(G, r, z);
   double rr = dot(G, r, r);
@@ -214,19 +230,24 @@ int oracle_pcg(int N, const double* b, double* x, double thr, int norm,
   while (!ok && k < max_iter) {
     /* w = A p = -M p */
     oracle_apply_M(N, p, w);
+    ORACLE_PARALLEL_FOR
     for (long long n = 0; n < G; ++n) w[n] = -w[n];
     double pw = dot(G, p, w);
     if (!(pw > 0.0) || !isfinite(pw)) break;  /* breakdown */
     double alpha = rho / pw;
+    ORACLE_PARALLEL_FOR
     for (long long n = 0; n < G; ++n) x[n] += alpha * p[n];
+    ORACLE_PARALLEL_FOR
     for (long long n = 0; n < G; ++n) r[n] -= alpha * w[n];
     k += 1;
     rr = dot(G, r, r);
     ok = met(rr, r, G, thr, norm);
     if (ok) break;
+    ORACLE_PARALLEL_FOR
     for (long long n = 0; n < G; ++n) z[n] = r[n] / 6.0;
     double rho_new = dot(G, r, z);
     double beta = rho_new / rho;
+    ORACLE_PARALLEL_FOR
     for (long long n = 0; n < G; ++n) p[n] = z[n] + beta * p[n];
     rho = rho_new;
   }
@@ -325,6 +346,7 @@ static void true_residual(int N, const double* b, const double* x,
   /* r = b - A x = b + M x */
   long long G = grid_points(N);
   oracle_apply_M(N, x, scratch);
+  ORACLE_PARALLEL_FOR
   for (long long n = 0; n < G; ++n) scratch[n] = b[n] + scratch[n];
   *l2 = sqrt(dot(G, scratch, scratch));
   *amax = max_abs(G, scratch);
@@ -370,6 +392,7 @@ static int poisson_solve(oracle_session* s, double* phi, int* iters,
                          double* rel, double* amax) {
   long long G = grid_points(s->N);
   double* b = s->sigma;  /* reuse as the right-hand side */
+  ORACLE_PARALLEL_FOR
   for (long long n = 0; n < G; ++n) b[n] = 4.0 * M_PI * s->q[n] / s->h;
   double bn = l2norm(G, b);
   double thr = (s->cfg.residual_norm == ORACLE_NORM_ABSMAX) ? s->cfg.tol
@@ -446,13 +469,16 @@ int oracle_step(oracle_session* s, const double* pos, double* field,
   double net = spread_projected(s, pos);
 
   double* phi_p = s->work;
+  ORACLE_PARALLEL_FOR
   for (long long n = 0; n < G; ++n) phi_p[n] = 2.0 * s->phi_k[n] - s->phi_km1[n];
   oracle_apply_M(N, phi_p, s->sigma);
+  ORACLE_PARALLEL_FOR
   for (long long n = 0; n < G; ++n)
     s->sigma[n] = (h / (4.0 * M_PI)) * s->sigma[n] + s->q[n];
 
   /* (-M) y = -sigma_p */
   double* b = (double*)malloc(sizeof(double) * (size_t)G);
+  ORACLE_PARALLEL_FOR
   for (long long n = 0; n < G; ++n) b[n] = -s->sigma[n];
   double qn = l2norm(G, s->q);
   double thr = (s->cfg.residual_norm == ORACLE_NORM_ABSMAX) ? s->cfg.tol
@@ -465,6 +491,7 @@ int oracle_step(oracle_session* s, const double* pos, double* field,
   /* true residual M y - sigma_p */
   double* r = (double*)malloc(sizeof(double) * (size_t)G);
   oracle_apply_M(N, s->y, r);
+  ORACLE_PARALLEL_FOR
   for (long long n = 0; n < G; ++n) r[n] = r[n] - s->sigma[n];
   double l2 = l2norm(G, r);
   double amax = max_abs(G, r);
@@ -472,6 +499,7 @@ int oracle_step(oracle_session* s, const double* pos, double* field,
   free(b);
 
   /* phi^{k+1} = phi_p - (4 pi / h) y, stored over phi^{k-1} */
+  ORACLE_PARALLEL_FOR
   for (long long n = 0; n < G; ++n)
     s->phi_km1[n] = phi_p[n] - (4.0 * M_PI / h) * s->y[n];
   oracle_project_mean(N, s->phi_km1);
