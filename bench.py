@@ -61,13 +61,36 @@ def source_hash(path) -> str:
     return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
 
 
+# Launch shapes the benchmark pins for the 256^3 headline sessions of the
+# two-iteration CG (threads:points per thread:x planes), so that every run
+# times the shapes the committed counter summaries were taken in: the
+# session tuner's own picks for this grid, which vary between boxes among
+# shapes within 1% of each other (basis (256, 4, 22), (512, 4, 16) and
+# (1024, 4, 16) in FP32).
+PINNED_SHAPES = {
+    ("nacl32768_g256", "fp32"): {"MAZE_BASIS_SHAPE": "512:4:16", "MAZE_UPDATE_SHAPE": "512:4:32"},
+    ("nacl32768_g256", "fp64"): {"MAZE_BASIS_SHAPE": "512:2:64", "MAZE_UPDATE_SHAPE": "512:4:32"},
+}
+
+
 def run_md(system, tol, precision, steps, warmup, record_positions=False, order=2, flags=0,
-           gamma=0.0):
+           gamma=0.0, pin=None):
+    """pin: environment settings that force launch shapes while the session
+    is created (read by the library's tuner at maze_init)."""
     import torch
     from paper_2505_20418_amd import maze, md
 
-    run = md.MDRun(system, tol=tol, precision=precision, order=order, flags=flags, gamma=gamma,
-                   temperature=system.temperature, seed=7)
+    saved = {k: os.environ.get(k) for k in (pin or {})}
+    os.environ.update(pin or {})
+    try:
+        run = md.MDRun(system, tol=tol, precision=precision, order=order, flags=flags,
+                       gamma=gamma, temperature=system.temperature, seed=7)
+    finally:
+        for k, v in saved.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
     h = run.session.handle
     for _ in range(warmup):
         run.step()
@@ -160,6 +183,11 @@ def roofline(prof_key, prof, G, dtype_key, shape=None, sstep=False):
                              "frac": round(bb / b_s / 1e9 / HBM_PEAK_GBS, 4), "traffic": None}
         r["outer_step_us"] = round(ms / n * 1e3, 2)
         r["iterations_per_outer_step"] = 2
+        ob = bpl + bb
+        r["outer_step"] = {"kernels": "basis + update", "algorithmic_bytes": ob,
+                           "avg_us": round(ms / n * 1e3, 2),
+                           "achieved": round(ob / (ms / n / 1e3) / 1e9, 1),
+                           "frac": round(ob / (ms / n / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
         if shape is not None and "basis" in shape:
             bs = shape["basis"]
             r["basis_kernel"]["launch_shape"] = {
@@ -190,6 +218,25 @@ def attach_ceilings(r, copy_gbps):
         r["counter_frac_of_copy"] = round(g / copy_gbps, 4)
 
 
+def attach_outer(r, copy_gbps):
+    """The outer step (basis and update kernel, two iterations) against the
+    ceilings, on algorithmic bytes and, where both kernels' counter traffic
+    is known, on counted HBM bytes."""
+    o = r.get("outer_step")
+    if o is None:
+        return
+    o["copy_GBps"] = round(copy_gbps, 1)
+    o["frac_of_copy"] = round(o["achieved"] / copy_gbps, 4)
+    tb = (r.get("basis_kernel") or {}).get("traffic")
+    if r.get("traffic") and tb:
+        o["traffic"] = r["traffic"] + tb
+        g = o["traffic"] / (o["avg_us"] * 1e-6) / 1e9
+        o["counter_GBps"] = round(g, 1)
+        o["counter_frac"] = round(g / HBM_PEAK_GBS, 4)
+    else:
+        o["traffic"] = None
+
+
 def attach_traffic(r, key, form="sweep"):
     """HBM bytes per launch from the committed counter summary, if it was
     taken with the current kernel source and in the launch shape this run
@@ -218,61 +265,142 @@ def attach_traffic(r, key, form="sweep"):
         obj["traffic"] = t[k]["hbm_bytes_per_launch"]
 
 
-def cpu_baseline(system, tol, iters_per_step):
-    """Plain FP64 oracle on the host: one MD step with the solve capped at
-    zero iterations (assignment, constraint, residual, update, forces, short
-    range) plus a fixed number of CG iterations at full size, extrapolated
-    to the iterations per step the GPU FP64 path needed."""
+def cpu_worker(mode: str, workload: str, omp: bool, iters_per_step: float = 0.0,
+               steps: int = 5) -> dict:
+    """One CPU-oracle measurement, run in a process of its own (no torch; the
+    OpenMP build takes its threads from OMP_NUM_THREADS):
+      sample  the headline workload: one MD step with the solve capped at 0
+              iterations plus 60 PLCG iterations, extrapolated to
+              iters_per_step iterations per step;
+      run     the workload's cold solve, then `steps` warm MD steps, timed."""
     import oracle
     from paper_2505_20418_amd import inputs
 
-    oracle.build(force=False)
-    n_cg = 60
-    t_start = time.perf_counter()
-    sess = oracle.Session(system.charges, system.pos, system.box, system.grid_spacing, tol=tol,
-                          max_iter=0, coulomb_k=inputs.COULOMB_K_EV_A)
+    wl = inputs.WORKLOADS[workload]
+    system = inputs.workload(workload)
+    tol = wl["tol"]
+    common = dict(coulomb_k=inputs.COULOMB_K_EV_A, omp=omp)
     pos, vel = system.pos.copy(), system.vel.copy()
-    F_es = np.zeros_like(pos)
-    F_sr = np.zeros_like(pos)
+    F_sr, _ = oracle.bmh(pos, system.species, system.box, inputs.BMH_TABLE, inputs.BMH_CUTOFF)
     work = np.zeros(1)
+    args = (system.masses, system.species, inputs.BMH_TABLE, inputs.BMH_CUTOFF, 1.0,
+            inputs.ACCEL_FACTOR)
+    if mode == "sample":
+        n_cg = 60
+        sess = oracle.Session(system.charges, pos, system.box, system.grid_spacing, tol=tol,
+                              max_iter=0, **common)
+        F_es = np.zeros_like(pos)
+        t0 = time.perf_counter()
+        sess.md_step(pos, vel, *args, F_es, F_sr, work)
+        t_other = time.perf_counter() - t0
+        N = sess.N
+        b = 4 * np.pi * sess.state()["q"] / (system.box / N)
+        L = oracle.lib_omp() if omp else oracle.lib()
+        x = np.zeros_like(b)
+        it = oracle.ctypes.c_int(0)
+        t0 = time.perf_counter()
+        L.oracle_pcg(N, oracle._d(b.ravel()), oracle._d(x.ravel()), 0.0, oracle.NORM_REL2, n_cg,
+                     oracle.ctypes.byref(it))
+        t_iter = (time.perf_counter() - t0) / n_cg
+        sess.close()
+        per_step = t_other + iters_per_step * t_iter
+        return {"steps_per_s": 1.0 / per_step, "s_non_cg_per_step": t_other,
+                "s_per_cg_iteration": t_iter, "iters_per_step": iters_per_step, "grid": N}
     t0 = time.perf_counter()
-    sess.md_step(pos, vel, system.masses, system.species, inputs.BMH_TABLE, inputs.BMH_CUTOFF,
-                 1.0, inputs.ACCEL_FACTOR, F_es, F_sr, work)
-    t_other = time.perf_counter() - t0
-    N = sess.N
-    b = 4 * np.pi * sess.state()["q"] / (system.box / N)
+    sess = oracle.Session(system.charges, pos, system.box, system.grid_spacing, tol=tol,
+                          **common)
+    t_init = time.perf_counter() - t0
+    F_es = sess.step(pos)["forces"]  # forces at the start, as the MD prime step
+    iters = 0
     t0 = time.perf_counter()
-    oracle.pcg(b, thr=0.0, max_iter=n_cg)
-    t_iter = (time.perf_counter() - t0) / n_cg
+    for _ in range(steps):
+        st = sess.md_step(pos, vel, *args, F_es, F_sr, work)
+        iters += st["stats"]["iters"]
+    dt = time.perf_counter() - t0
     sess.close()
+    return {"steps_per_s": steps / dt, "steps": steps, "s_per_step": dt / steps,
+            "cg_iterations_per_step": iters / steps,
+            "s_per_cg_iteration": dt / max(iters, 1), "s_cold_solve": t_init,
+            "grid": inputs.GRID_PER_CELL * wl["n_cells"]}
+
+
+def _cpu_run(mode, workload, omp, threads, iters_per_step=0.0, steps=5):
+    """cpu_worker in a child process with `threads` OpenMP threads."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS=str(threads))
+    cmd = [sys.executable, os.path.abspath(__file__), "--cpu-worker",
+           json.dumps({"mode": mode, "workload": workload, "omp": omp,
+                       "iters_per_step": iters_per_step, "steps": steps})]
+    out = subprocess.run(cmd, env=env, capture_output=True, text=True, check=True).stdout
+    return json.loads(out.strip().splitlines()[-1])
+
+
+def cpu_baseline(workload, iters_per_step, full=False):
+    """The plain FP64 oracle on the host's cores: the plain build on one
+    thread and its OpenMP build (order-independent loops threaded, bitwise
+    the same results) on every core this process may use. Default: the
+    headline workload's step from a one-step sample plus 60 PLCG iterations
+    (extrapolated to the GPU FP64 path's iterations per step), and the
+    64-ion workload's 100 NVE steps measured in full. full: also 5 measured
+    warm steps of the 4096-ion and 32768-ion workloads after their cold
+    solves."""
+    from paper_2505_20418_amd import inputs
+
+    import oracle
+    oracle.build(force=False)
+    threads = len(os.sched_getaffinity(0))
+    t_start = time.perf_counter()
+    legs = [(1, False), (threads, True)]
+    sample = {t: _cpu_run("sample", workload, omp, t, iters_per_step) for t, omp in legs}
+    c1 = {t: _cpu_run("run", "nacl64_g32", omp, t, steps=inputs.WORKLOADS["nacl64_g32"]["steps"])
+          for t, omp in legs}
+    out = {"value": round(sample[threads]["steps_per_s"], 6), "unit": "MD steps/s",
+           "cores": threads, "kind": "oracle", **host_description()}
+    out["single_thread"] = {"value": round(sample[1]["steps_per_s"], 6), "cores": 1}
+    for t in sample:
+        sample[t] = {k: (round(v, 5) if isinstance(v, float) else v) for k, v in sample[t].items()}
+    out["headline_sample"] = {"1": sample[1], str(threads): sample[threads]}
+    out["nacl64_g32_100_steps"] = {
+        str(t): {k: (round(v, 5) if isinstance(v, float) else v) for k, v in c1[t].items()}
+        for t in c1}
+    if full:
+        for wl in ("nacl4096_g128", "nacl32768_g256"):
+            out[f"{wl}_warm_steps"] = {
+                str(t): {k: (round(v, 4) if isinstance(v, float) else v)
+                         for k, v in _cpu_run("run", wl, omp, t, steps=5).items()}
+                for t, omp in legs}
     total = time.perf_counter() - t_start
-    per_step = t_other + iters_per_step * t_iter
-    return {"value": round(1.0 / per_step, 6), "unit": "MD steps/s", "cores": 1, "kind": "oracle",
-            **host_description(),
-            "sample": (f"one oracle MD step at {N}^3 with the solve capped at 0 iterations "
-                       f"({t_other:.2f} s) plus {n_cg} oracle PLCG iterations at {N}^3 "
-                       f"({t_iter:.3f} s each), extrapolated to {iters_per_step:.1f} "
-                       f"iterations per step (GPU FP64 path); {total:.1f} s of CPU work, "
-                       f"single-threaded plain C, -O2 -ffp-contract=off")}
+    out["sample"] = (f"{workload}: one oracle MD step with the solve capped at 0 iterations plus "
+                     f"60 oracle PLCG iterations, extrapolated to {iters_per_step:.1f} iterations "
+                     f"per step (GPU FP64 path), on {threads} threads (OpenMP build: stencil, "
+                     f"AXPY and elementwise loops threaded, reductions sequential) and on 1 "
+                     f"thread; plus nacl64_g32's 100 NVE steps measured on both"
+                     + ("; plus 5 measured warm steps of nacl4096_g128 and nacl32768_g256"
+                        if full else "")
+                     + f"; {total:.1f} s of CPU work; plain C, -O2 -ffp-contract=off")
+    return out
 
 
-def copy_bandwidth(gib: float = 2.0, reps: int = 10) -> float:
-    """Device-to-device copy rate (bytes read + written per second, GB/s)
-    of a plain 2 GiB copy: the practical streaming ceiling beside the
-    vendor peak."""
+def copy_bandwidth(gib: float = 4.0, reps: int = 10) -> float:
+    """Rate (bytes read + written per second, GB/s) of the library's
+    streaming copy kernel (maze_stream_copy) between two 4 GiB buffers, an
+    8 GiB footprint far beyond the L2 and Infinity Cache: the practical HBM
+    ceiling for kernels that read and write every byte once."""
     import torch
+    from paper_2505_20418_amd import maze
     n = int(gib * (1 << 30)) // 8
     a = torch.ones(n, dtype=torch.float64, device="cuda")
     b = torch.empty_like(a)
-    b.copy_(a)
+    maze.maze_stream_copy(b, a)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     e0.record()
     for _ in range(reps):
-        b.copy_(a)
+        maze.maze_stream_copy(b, a)
     e1.record()
     torch.cuda.synchronize()
     t = e0.elapsed_time(e1) / reps * 1e-3
+    assert torch.equal(a[:1024], b[:1024]) and torch.equal(a[-1024:], b[-1024:])
     del a, b
     return 2.0 * n * 8 / t / 1e9
 
@@ -306,16 +434,45 @@ def host_description():
 
 
 def copy_calibration(gib: float = 2.0, reps: int = 5):
-    """A plain device copy of known size, for scaling the HBM counters."""
+    """The library's streaming copy (k_stream_copy) of known size, for
+    scaling the HBM counters."""
     import torch
+    from paper_2505_20418_amd import maze
     n = int(gib * (1 << 30)) // 8
     a = torch.ones(n, dtype=torch.float64, device="cuda")
     b = torch.empty_like(a)
     for _ in range(reps):
-        b.copy_(a)
+        maze.maze_stream_copy(b, a)
     torch.cuda.synchronize()
     print(json.dumps({"copy_bytes_read_per_launch": n * 8, "copy_bytes_written_per_launch": n * 8,
                       "launches": reps}))
+
+
+def bench_c2(steps: int, warmup: int, flags: int, copy_gbps: float):
+    """4096 ions (8^3 rock-salt cells), L = 51 A, 128^3 grid, FP64 MaZe at a
+    1e-9 relative residual with warm starts: MD steps/s and the roofline of
+    its CG kernels."""
+    from paper_2505_20418_amd import inputs, maze
+
+    name = "nacl4096_g128"
+    wl = inputs.WORKLOADS[name]
+    system = inputs.workload(name)
+    N = inputs.GRID_PER_CELL * wl["n_cells"]
+    ss = bool(flags & maze.MAZE_FLAG_SSTEP)
+    r = run_md(system, wl["tol"], maze.MAZE_FP64, steps, warmup, flags=flags)
+    rl = roofline("fp64_sweep", r["prof"], N ** 3, "fp64", r["shape"], sstep=ss)
+    attach_ceilings(rl, copy_gbps)
+    if ss and rl is not None:
+        attach_ceilings(rl.get("basis_kernel"), copy_gbps)
+        attach_outer(rl, copy_gbps)
+    return {"value": round(r["steps_per_s"], 4), "unit": "MD steps/s", "steps": steps,
+            "config": {"workload": name, "ions": system.n_ions, "grid": N, "box_A": system.box,
+                       "tol_rel_residual": wl["tol"], "precision": "fp64", "dt_fs": 1.0,
+                       "temperature_K": system.temperature},
+            "cg_iterations_per_step": round(r["prof"]["fp64_iters"] / steps, 1),
+            "latency_ms": {"p50": round(float(np.percentile(r["lat_ms"], 50)), 3),
+                           "p99": round(float(np.percentile(r["lat_ms"], 99)), 3)},
+            "roofline": rl}
 
 
 def bench_ensemble(steps: int, warmup: int, tol: float = 1e-8, flags: int = 0):
@@ -477,6 +634,14 @@ def main():
     ap.add_argument("--no-sweep-compare", action="store_true",
                     help="skip timing the one-iteration sweep beside the two-iteration form")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-pin", action="store_true",
+                    help="let the session tuner pick the headline sessions' launch shapes")
+    ap.add_argument("--no-c2", action="store_true",
+                    help="skip the 4096-ion, 128^3 FP64 leg")
+    ap.add_argument("--cpu-baseline-full", action="store_true",
+                    help="also time 5 warm oracle steps of the 4096- and 32768-ion workloads "
+                         "after their cold solves (minutes of CPU work)")
+    ap.add_argument("--cpu-worker", default=None, help=argparse.SUPPRESS)
     ap.add_argument("--mixed-only", action="store_true",
                     help="skip the FP64 side-by-side run (for profiling)")
     ap.add_argument("--replay", type=int, default=6, help="steps replayed for the error report")
@@ -487,9 +652,9 @@ def main():
     ap.add_argument("--no-observables", action="store_true")
     ap.add_argument("--serving-rate", type=float, default=200.0,
                     help="mean Poisson arrival rate of the serving leg [requests/s]")
-    ap.add_argument("--error-trajectory", type=int, default=0,
-                    help="also record an FP64 trajectory of this many steps and compare the "
-                         "mixed path with it every 50 steps (not part of the default run)")
+    ap.add_argument("--error-trajectory", type=int, default=500,
+                    help="record an FP64 trajectory of this many steps and compare the mixed "
+                         "path with it every 50 steps (0: off)")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-reduced", action="store_true",
                     help="serve a reduced mix (64 sessions up to 4096 ions, 128^3) instead of "
@@ -497,6 +662,11 @@ def main():
     ap.add_argument("--serving-rounds", action="store_true",
                     help="also serve the stream in rounds of batched MD steps (cost classes)")
     args = ap.parse_args()
+    if args.cpu_worker:
+        spec = json.loads(args.cpu_worker)
+        print(json.dumps(cpu_worker(spec["mode"], spec["workload"], spec["omp"],
+                                    spec["iters_per_step"], spec["steps"])))
+        return
 
     if args.gpus != 1:
         print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} is not supported "
@@ -519,13 +689,16 @@ def main():
     cg_flags = maze.MAZE_FLAG_SSTEP if ss else 0
     log(f"bench: {args.workload} ions={system.n_ions} grid={inputs.GRID_PER_CELL * wl['n_cells']}^3 "
         f"tol={tol} cg={args.cg} mixed: warmup {args.warmup}, {args.steps} timed steps")
-    mixed = run_md(system, tol, maze.MAZE_MIXED, args.steps, args.warmup, flags=cg_flags)
+    pin32 = PINNED_SHAPES.get((args.workload, "fp32")) if ss and not args.no_pin else None
+    pin64 = PINNED_SHAPES.get((args.workload, "fp64")) if ss and not args.no_pin else None
+    mixed = run_md(system, tol, maze.MAZE_MIXED, args.steps, args.warmup, flags=cg_flags,
+                   pin=pin32)
     log(f"bench: mixed {mixed['steps_per_s']:.3f} steps/s")
     fp64 = None
     errors = None
     if not args.mixed_only:
         fp64 = run_md(system, tol, maze.MAZE_FP64, args.steps, args.warmup,
-                      record_positions=True, flags=cg_flags)
+                      record_positions=True, flags=cg_flags, pin=pin64)
         log(f"bench: fp64 {fp64['steps_per_s']:.3f} steps/s")
         if args.replay > 0:
             errors = replay_errors(system, fp64["traj"], tol, args.replay, flags=cg_flags)
@@ -544,15 +717,19 @@ def main():
     attach_ceilings(r_mixed, copy_gbps)
     attach_ceilings(r_fp64, copy_gbps)
     if ss:
-        attach_ceilings(r_mixed and r_mixed.get("basis_kernel"), copy_gbps)
-        attach_ceilings(r_fp64 and r_fp64.get("basis_kernel"), copy_gbps)
+        for r in (r_mixed, r_fp64):
+            if r is None:
+                continue
+            attach_ceilings(r.get("basis_kernel"), copy_gbps)
+            attach_outer(r, copy_gbps)
+            r["shapes_pinned"] = bool(pin32)
 
     it_mixed = mixed["prof"]["fp32_iters"] / args.steps
     it_fp64 = fp64["prof"]["fp64_iters"] / args.steps if fp64 else None
     cpu = None
     if not args.no_cpu_baseline and it_fp64:
         log("bench: timing the CPU oracle sample")
-        cpu = cpu_baseline(system, tol, it_fp64)
+        cpu = cpu_baseline(args.workload, it_fp64, full=args.cpu_baseline_full)
 
     value = mixed["steps_per_s"]
     line = {
@@ -646,6 +823,10 @@ def main():
                                                        args.error_trajectory, every=50,
                                                        flags=cg_flags)
         log(f"bench: trajectory errors {line['mixed_error_trajectory']}")
+    if not args.no_c2 and args.workload != "nacl4096_g128":
+        log("bench: nacl4096_g128 (FP64, tol 1e-9)")
+        line["nacl4096_g128"] = bench_c2(args.steps, args.warmup, cg_flags, copy_gbps)
+        log(f"bench: nacl4096_g128 {line['nacl4096_g128']['value']} MD steps/s")
     if not args.no_observables:
         log("bench: Langevin dynamics and observables")
         line["observables"] = bench_observables(system, tol, args.steps, args.warmup, cg_flags)

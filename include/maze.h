@@ -478,6 +478,17 @@ int maze_batch_in_flight(const maze_batch* b);
 /* Finishes the steps in flight, then frees the batch (NULL is a no-op). */
 void maze_batch_destroy(maze_batch* b);
 
+/* ---- measurement ---------------------------------------------------------
+ * Streaming copy of `bytes` (a multiple of 16) from src_dev to dst_dev
+ * (DEVICE buffers that do not overlap), queued on `stream`: 16-byte vector
+ * loads and stores, a few workgroups per CU striding over the buffers. On
+ * footprints far beyond the caches its rate (2 * bytes / time) is the
+ * practical HBM ceiling for kernels that read and write every byte once,
+ * against which the solver kernels are compared. MAZE_E_INVALID for NULL
+ * pointers, pointers not 16-byte aligned or a size that is not a multiple of
+ * 16. */
+int maze_stream_copy(void* dst_dev, const void* src_dev, size_t bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -12,8 +12,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libmaze.so")
-SOURCES = ["k_cg.hip", "k_sstep.hip", "k_mg.hip", "k_stencil.hip", "k_particles.hip", "k_md.hip", "k_obs.hip",
-           "maze_capi.hip"]
+SOURCES = ["k_cg.hip", "k_sstep.hip", "k_mg.hip", "k_stencil.hip", "k_particles.hip", "k_md.hip",
+           "k_obs.hip", "k_stream.hip", "maze_capi.hip"]
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")

@@ -2705,4 +2705,12 @@ void maze_batch_destroy(maze_batch* b) {
   delete b;
 }
 
+// ---- measurement ---------------------------------------------------------------
+int maze_stream_copy(void* dst_dev, const void* src_dev, size_t bytes, void* stream) {
+  if (!dst_dev || !src_dev || bytes % 16 != 0 || ((uintptr_t)dst_dev | (uintptr_t)src_dev) % 16)
+    return MAZE_E_INVALID;
+  HIP_TRY(launch_stream_copy(dst_dev, src_dev, bytes, device_cus(), (hipStream_t)stream));
+  return MAZE_OK;
+}
+
 }  // extern "C"

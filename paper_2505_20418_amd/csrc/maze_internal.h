@@ -324,6 +324,10 @@ hipError_t launch_add_correction(const DeviceState& d, double* x, hipStream_t st
 int update_blocks(long long G);
 
 // MD driver
+// Streaming copy of bytes (a multiple of 16; device buffers) with about 8
+// workgroups per CU (cus: the device's CU count).
+hipError_t launch_stream_copy(void* dst, const void* src, size_t bytes, int cus,
+                              hipStream_t st);
 hipError_t launch_md_kick_drift(const maze_md_state& md, long long step, hipStream_t st);
 hipError_t launch_md_bmh(const maze_md_state& md, const DeviceState& d, hipStream_t st);
 hipError_t launch_md_finish(const maze_md_state& md, const DeviceState& d, long long step,

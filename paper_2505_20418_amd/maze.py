@@ -37,7 +37,8 @@ EXPORTED = ("maze_abi_version", "maze_strerror", "maze_device_bytes", "maze_init
             "maze_langevin_noise",
             "maze_rdf_accumulate", "maze_tcf_create", "maze_tcf_sample", "maze_tcf_read",
             "maze_tcf_destroy", "maze_batch_create", "maze_batch_add", "maze_batch_advance",
-            "maze_batch_take", "maze_batch_in_flight", "maze_batch_destroy")
+            "maze_batch_take", "maze_batch_in_flight", "maze_batch_destroy",
+            "maze_stream_copy")
 
 
 class maze_config(ctypes.Structure):
@@ -120,6 +121,8 @@ def lib():
         L.maze_batch_in_flight.argtypes = [vp]
         L.maze_batch_destroy.restype = None
         L.maze_batch_destroy.argtypes = [vp]
+        L.maze_stream_copy.restype = ctypes.c_int
+        L.maze_stream_copy.argtypes = [vp, vp, ctypes.c_size_t, vp]
         L.maze_grid_n.restype = ctypes.c_int
         L.maze_grid_n.argtypes = [vp]
         L.maze_get_grid.restype = ctypes.c_int
@@ -267,6 +270,17 @@ def maze_step_batch_noalloc(handles: Sequence, pos: Sequence[torch.Tensor],
     if rc in (MAZE_E_INVALID, MAZE_E_OOM, MAZE_E_DEVICE, MAZE_E_CAPACITY):
         raise MazeError(rc, "maze_step_batch_noalloc")
     return rc, ([x.as_dict() for x in st] if st is not None else None)
+
+
+def maze_stream_copy(dst: torch.Tensor, src: torch.Tensor, stream=None):
+    """Streaming copy src -> dst (same byte size, a multiple of 16)."""
+    nbytes = src.numel() * src.element_size()
+    assert dst.numel() * dst.element_size() == nbytes
+    if stream is None:
+        stream = torch.cuda.current_stream().cuda_stream
+    _check(lib().maze_stream_copy(ctypes.c_void_p(dst.data_ptr()),
+                                  ctypes.c_void_p(src.data_ptr()), nbytes,
+                                  ctypes.c_void_p(int(stream))), "maze_stream_copy")
 
 
 def maze_grid_n(handle) -> int:
