@@ -71,6 +71,11 @@ PINNED_SHAPES = {
     ("nacl32768_g256", "fp32"): {"MAZE_BASIS_SHAPE": "512:4:16", "MAZE_UPDATE_SHAPE": "512:4:32"},
     ("nacl32768_g256", "fp64"): {"MAZE_BASIS_SHAPE": "512:2:64", "MAZE_UPDATE_SHAPE": "512:4:32"},
 }
+# and of the one-iteration sweep (points per thread:x planes)
+PINNED_SWEEP = {
+    ("nacl32768_g256", "fp32"): {"MAZE_SWEEP_SHAPE": "4:22"},
+    ("nacl32768_g256", "fp64"): {"MAZE_SWEEP_SHAPE": "4:64"},
+}
 
 
 def run_md(system, tol, precision, steps, warmup, record_positions=False, order=2, flags=0,
@@ -689,8 +694,9 @@ def main():
     cg_flags = maze.MAZE_FLAG_SSTEP if ss else 0
     log(f"bench: {args.workload} ions={system.n_ions} grid={inputs.GRID_PER_CELL * wl['n_cells']}^3 "
         f"tol={tol} cg={args.cg} mixed: warmup {args.warmup}, {args.steps} timed steps")
-    pin32 = PINNED_SHAPES.get((args.workload, "fp32")) if ss and not args.no_pin else None
-    pin64 = PINNED_SHAPES.get((args.workload, "fp64")) if ss and not args.no_pin else None
+    pins = PINNED_SHAPES if ss else PINNED_SWEEP
+    pin32 = None if args.no_pin else pins.get((args.workload, "fp32"))
+    pin64 = None if args.no_pin else pins.get((args.workload, "fp64"))
     mixed = run_md(system, tol, maze.MAZE_MIXED, args.steps, args.warmup, flags=cg_flags,
                    pin=pin32)
     log(f"bench: mixed {mixed['steps_per_s']:.3f} steps/s")
@@ -773,7 +779,8 @@ def main():
                                     ("fp64", maze.MAZE_FP64, "fp64_sweep", "fp64")):
             if name == "fp64" and args.mixed_only:
                 continue
-            r = run_md(system, tol, prec, args.steps, args.warmup)
+            r = run_md(system, tol, prec, args.steps, args.warmup,
+                       pin=None if args.no_pin else PINNED_SWEEP.get((args.workload, dk)))
             rl = roofline(key, r["prof"], G, dk, r["shape"])
             attach_traffic(rl, key)
             attach_ceilings(rl, copy_gbps)

@@ -481,7 +481,8 @@ void maze_batch_destroy(maze_batch* b);
 /* ---- measurement ---------------------------------------------------------
  * Streaming copy of `bytes` (a multiple of 16) from src_dev to dst_dev
  * (DEVICE buffers that do not overlap), queued on `stream`: 16-byte vector
- * loads and stores, a few workgroups per CU striding over the buffers. On
+ * loads and stores, the buffer cut into contiguous chunks, one per
+ * workgroup (16384 workgroups). On
  * footprints far beyond the caches its rate (2 * bytes / time) is the
  * practical HBM ceiling for kernels that read and write every byte once,
  * against which the solver kernels are compared. MAZE_E_INVALID for NULL

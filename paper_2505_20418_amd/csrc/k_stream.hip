@@ -1,9 +1,12 @@
 // Streaming copy: the practical HBM ceiling of this device for a kernel
 // that reads and writes every byte once (the traffic pattern of the CG
 // sweeps and update kernels), measured on footprints far beyond the L2 and
-// the Infinity Cache. Each thread moves 16-byte vectors with plain vector
-// loads and stores; the grid is a few workgroups per CU, striding over the
-// buffer, so every wavefront keeps several loads in flight.
+// the Infinity Cache. The buffer is cut into kStreamChunks contiguous
+// chunks, one per workgroup (64 per CU on 256 CUs), and each thread moves
+// 16-byte vectors, four loads in flight before the stores. Measured on 4 GiB
+// buffers against other layouts: 5.25-5.29 TB/s, against 4.46-5.14 TB/s for
+// grid-stride loops of 2 to 64 workgroups per CU (with or without
+// non-temporal accesses) and 4.63 TB/s for hipMemcpy.
 #include <algorithm>
 
 #include "device_util.h"
@@ -14,33 +17,40 @@ namespace {
 
 constexpr int kStreamThreads = 256;
 constexpr int kStreamUnroll = 4;
+constexpr long long kStreamChunks = 16384;
+typedef unsigned int v4u __attribute__((ext_vector_type(4)));
 
-__global__ __launch_bounds__(kStreamThreads) void k_stream_copy(const uint4* __restrict__ src,
-                                                                uint4* __restrict__ dst,
-                                                                long long n) {
-  const long long stride = (long long)gridDim.x * kStreamThreads;
-  long long i = (long long)blockIdx.x * kStreamThreads + threadIdx.x;
-  for (; i + (kStreamUnroll - 1) * stride < n; i += kStreamUnroll * stride) {
-    uint4 v[kStreamUnroll];
+__global__ __launch_bounds__(kStreamThreads) void k_stream_copy(const v4u* __restrict__ src,
+                                                                v4u* __restrict__ dst,
+                                                                long long n, long long per) {
+  const long long b0 = (long long)blockIdx.x * per;
+  const long long b1 = std::min(n, b0 + per);
+  for (long long i = b0 + threadIdx.x; i < b1; i += (long long)kStreamThreads * kStreamUnroll) {
+    v4u v[kStreamUnroll];
 #pragma unroll
-    for (int u = 0; u < kStreamUnroll; ++u) v[u] = src[i + u * stride];
+    for (int u = 0; u < kStreamUnroll; ++u) {
+      const long long j = i + (long long)u * kStreamThreads;
+      if (j < b1) v[u] = src[j];
+    }
 #pragma unroll
-    for (int u = 0; u < kStreamUnroll; ++u) dst[i + u * stride] = v[u];
+    for (int u = 0; u < kStreamUnroll; ++u) {
+      const long long j = i + (long long)u * kStreamThreads;
+      if (j < b1) dst[j] = v[u];
+    }
   }
-  for (; i < n; i += stride) dst[i] = src[i];
 }
 
 }  // namespace
 
 hipError_t launch_stream_copy(void* dst, const void* src, size_t bytes, int cus,
                               hipStream_t st) {
-  const long long n = (long long)(bytes / sizeof(uint4));
+  (void)cus;
+  const long long n = (long long)(bytes / sizeof(v4u));
   if (n <= 0) return hipSuccess;
-  const long long want = (long long)std::max(cus, 1) * 8;
-  const long long need = (n + kStreamThreads - 1) / kStreamThreads;
-  const int blocks = (int)std::max(1LL, std::min(want, need));
+  const long long per = (n + kStreamChunks - 1) / kStreamChunks;
+  const int blocks = (int)((n + per - 1) / per);
   hipLaunchKernelGGL(k_stream_copy, dim3(blocks), dim3(kStreamThreads), 0, st,
-                     static_cast<const uint4*>(src), static_cast<uint4*>(dst), n);
+                     static_cast<const v4u*>(src), static_cast<v4u*>(dst), n, per);
   return hipGetLastError();
 }
 

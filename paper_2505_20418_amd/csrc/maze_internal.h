@@ -324,8 +324,8 @@ hipError_t launch_add_correction(const DeviceState& d, double* x, hipStream_t st
 int update_blocks(long long G);
 
 // MD driver
-// Streaming copy of bytes (a multiple of 16; device buffers) with about 8
-// workgroups per CU (cus: the device's CU count).
+// Streaming copy of bytes (a multiple of 16; 16-byte aligned device
+// buffers) in contiguous chunks, one per workgroup (cus is not used).
 hipError_t launch_stream_copy(void* dst, const void* src, size_t bytes, int cus,
                               hipStream_t st);
 hipError_t launch_md_kick_drift(const maze_md_state& md, long long step, hipStream_t st);
