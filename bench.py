@@ -62,13 +62,14 @@ def source_hash(path) -> str:
 
 
 # Launch shapes the benchmark pins for the 256^3 headline sessions of the
-# two-iteration CG (threads:points per thread:x planes), so that every run
-# times the shapes the committed counter summaries were taken in: the
-# session tuner's own picks for this grid, which vary between boxes among
-# shapes within 1% of each other (basis (256, 4, 22), (512, 4, 16) and
-# (1024, 4, 16) in FP32).
+# two-iteration CG (threads:points per thread:x planes, or zv:wavefronts:x
+# planes for the wavefront-row layout of the basis kernel), so that every
+# run times the shapes the committed counter summaries were taken in: the
+# fastest shapes in whole-MD-step timings of the tuner's candidates, which
+# the tuner's own short timings do not rank reliably between boxes (FP32
+# basis: zv:8:24 48.4 us, 512:4:16 49.8 us, 256:4:22 50.8 us).
 PINNED_SHAPES = {
-    ("nacl32768_g256", "fp32"): {"MAZE_BASIS_SHAPE": "512:4:16", "MAZE_UPDATE_SHAPE": "512:4:32"},
+    ("nacl32768_g256", "fp32"): {"MAZE_BASIS_SHAPE": "zv:8:24", "MAZE_UPDATE_SHAPE": "512:4:32"},
     ("nacl32768_g256", "fp64"): {"MAZE_BASIS_SHAPE": "512:2:64", "MAZE_UPDATE_SHAPE": "512:4:32"},
 }
 # and of the one-iteration sweep (points per thread:x planes)
@@ -122,6 +123,7 @@ def run_md(system, tol, precision, steps, warmup, record_positions=False, order=
     obs = run.observables()
     shape = maze.maze_launch_shape(h)["latency"]
     shape["basis"] = maze.maze_basis_shape(h)
+    shape["basis"]["layout"] = maze.maze_sstep_layout(h)["basis"]
     out = dict(steps_per_s=steps / (t1 - t0), wall_s=t1 - t0, lat_ms=lat, prof=prof,
                obs=obs, grid_n=run.session.N, traj=traj, shape=shape)
     run.close()
@@ -195,9 +197,12 @@ def roofline(prof_key, prof, G, dtype_key, shape=None, sstep=False):
                            "frac": round(ob / (ms / n / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
         if shape is not None and "basis" in shape:
             bs = shape["basis"]
+            # layout: wavefronts per workgroup of the wavefront-row layout, 0
+            # for the segment layout
             r["basis_kernel"]["launch_shape"] = {
                 "threads": bs["threads"], "ppt": bs["ppt"], "cx": bs["cx"],
-                "workgroups": bs["nwg"], "grid_threads": bs["nwg"] * bs["threads"]}
+                "workgroups": bs["nwg"], "grid_threads": bs["nwg"] * bs["threads"],
+                "layout": bs.get("layout", 0)}
     if shape is not None:
         # the launch shape the session swept in; a kernel trace of this run
         # also holds the autotuner's timing sweeps in other shapes, which
@@ -264,7 +269,8 @@ def attach_traffic(r, key, form="sweep"):
         have = obj.get("launch_shape", r.get("launch_shape"))
         if want is None or have is None:
             continue
-        shape_key = lambda x: (x.get("threads", 256), x["ppt"], x["cx"])  # noqa: E731
+        shape_key = lambda x: (x.get("threads", 256), x["ppt"], x["cx"],  # noqa: E731
+                               x.get("layout", 0))
         if shape_key(want) != shape_key(have):
             continue
         obj["traffic"] = t[k]["hbm_bytes_per_launch"]
@@ -311,16 +317,22 @@ def cpu_worker(mode: str, workload: str, omp: bool, iters_per_step: float = 0.0,
         per_step = t_other + iters_per_step * t_iter
         return {"steps_per_s": 1.0 / per_step, "s_non_cg_per_step": t_other,
                 "s_per_cg_iteration": t_iter, "iters_per_step": iters_per_step, "grid": N}
+    tag = f"cpu oracle {workload} ({'OpenMP' if omp else 'plain'}, " \
+          f"{os.environ.get('OMP_NUM_THREADS', '1') if omp else 1} threads)"
     t0 = time.perf_counter()
     sess = oracle.Session(system.charges, pos, system.box, system.grid_spacing, tol=tol,
                           **common)
     t_init = time.perf_counter() - t0
+    print(f"bench: {tag}: cold solve {t_init:.1f} s", file=sys.stderr, flush=True)
     F_es = sess.step(pos)["forces"]  # forces at the start, as the MD prime step
     iters = 0
     t0 = time.perf_counter()
-    for _ in range(steps):
+    for k in range(steps):
         st = sess.md_step(pos, vel, *args, F_es, F_sr, work)
         iters += st["stats"]["iters"]
+        if steps <= 10:
+            print(f"bench: {tag}: step {k + 1}/{steps}, {st['stats']['iters']} iterations, "
+                  f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     dt = time.perf_counter() - t0
     sess.close()
     return {"steps_per_s": steps / dt, "steps": steps, "s_per_step": dt / steps,
@@ -336,7 +348,8 @@ def _cpu_run(mode, workload, omp, threads, iters_per_step=0.0, steps=5):
     cmd = [sys.executable, os.path.abspath(__file__), "--cpu-worker",
            json.dumps({"mode": mode, "workload": workload, "omp": omp,
                        "iters_per_step": iters_per_step, "steps": steps})]
-    out = subprocess.run(cmd, env=env, capture_output=True, text=True, check=True).stdout
+    # the worker's progress lines go straight to this process's stderr
+    out = subprocess.run(cmd, env=env, stdout=subprocess.PIPE, text=True, check=True).stdout
     return json.loads(out.strip().splitlines()[-1])
 
 
@@ -369,19 +382,21 @@ def cpu_baseline(workload, iters_per_step, full=False):
         str(t): {k: (round(v, 5) if isinstance(v, float) else v) for k, v in c1[t].items()}
         for t in c1}
     if full:
-        for wl in ("nacl4096_g128", "nacl32768_g256"):
+        # the 256^3 cold solve alone takes minutes on one thread: there the
+        # one-thread figure is the headline sample's
+        for wl, wl_legs in (("nacl4096_g128", legs), ("nacl32768_g256", legs[1:])):
             out[f"{wl}_warm_steps"] = {
                 str(t): {k: (round(v, 4) if isinstance(v, float) else v)
                          for k, v in _cpu_run("run", wl, omp, t, steps=5).items()}
-                for t, omp in legs}
+                for t, omp in wl_legs}
     total = time.perf_counter() - t_start
     out["sample"] = (f"{workload}: one oracle MD step with the solve capped at 0 iterations plus "
                      f"60 oracle PLCG iterations, extrapolated to {iters_per_step:.1f} iterations "
                      f"per step (GPU FP64 path), on {threads} threads (OpenMP build: stencil, "
                      f"AXPY and elementwise loops threaded, reductions sequential) and on 1 "
                      f"thread; plus nacl64_g32's 100 NVE steps measured on both"
-                     + ("; plus 5 measured warm steps of nacl4096_g128 and nacl32768_g256"
-                        if full else "")
+                     + ("; plus 5 measured warm steps of nacl4096_g128 (both) and "
+                        "nacl32768_g256 (all threads)" if full else "")
                      + f"; {total:.1f} s of CPU work; plain C, -O2 -ffp-contract=off")
     return out
 

@@ -101,8 +101,9 @@ __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, uint32_t boff, T v)
 }
 
 // kNs per-thread values (the last a max) reduced over the NT threads of the
-// workgroup in a fixed order; every thread receives the results.
-// sm: kNs * NT / 64 doubles.
+// workgroup in a fixed order; every thread receives the results. Thread i
+// of the first kNs combines entry i over the wavefronts, so no thread holds
+// more than its own kNs values. sm: kNs * (NT / 64 + 1) doubles.
 template <int NT>
 __device__ __forceinline__ void block_reduce_ns(double v[kNs], double* sm) {
   constexpr int WV = NT / 64;
@@ -115,13 +116,16 @@ __device__ __forceinline__ void block_reduce_ns(double v[kNs], double* sm) {
     for (int i = 0; i < kNs; ++i) sm[i * WV + w] = v[i];
   }
   __syncthreads();
-#pragma unroll
-  for (int i = 0; i < kNs; ++i) {
+  double* tot = sm + kNs * WV;
+  if (threadIdx.x < kNs) {
+    const int i = threadIdx.x;
     double s = sm[i * WV];
-#pragma unroll
     for (int k = 1; k < WV; ++k) s = (i == kNs - 1) ? fmax(s, sm[i * WV + k]) : s + sm[i * WV + k];
-    v[i] = s;
+    tot[i] = s;
   }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < kNs; ++i) v[i] = tot[i];
 }
 
 // v^T G w for 5-vectors, G symmetric from its 15 upper entries.
@@ -144,6 +148,125 @@ __device__ __forceinline__ void ahat(const double* v, double* o) {
 }
 
 }  // namespace
+
+// The update kernel's scalar part: the Gram sums of the basis kernel
+// (nprev_sweep workgroup partials), then two CG iterations on the
+// coordinates of the basis; cx, cr, cp receive the combinations that form
+// x, r and p. Returns false where the workgroup has nothing to write (the
+// solve stopped; the leader has recorded why).
+template <typename T, bool FIRST, int NT>
+__device__ __forceinline__ bool sstep_coeffs(const SweepArgs<T>& a, int par, bool leader,
+                                             double* red, T (&cx)[5], T (&cr)[5], T (&cp)[5]) {
+  Scalars* sc = a.sc;
+  const int tid = threadIdx.x;
+  double v[kNs];
+#pragma unroll
+  for (int i = 0; i < kNs; ++i) v[i] = 0.0;
+  for (int i = tid; i < a.nprev_sweep; i += NT) {
+#pragma unroll
+    for (int c = 0; c < kNm; ++c) v[c] += a.part[(size_t)(SL_SG0 + c) * a.pstride + i];
+    v[kNm] = fmax(v[kNm], a.part[(size_t)SL_SGMAX * a.pstride + i]);
+  }
+  block_reduce_ns<NT>(v, red);
+  __syncthreads();  // red is reused for the planes below
+  double G[15];
+#pragma unroll
+  for (int aa = 0; aa < 5; ++aa)
+#pragma unroll
+    for (int b = aa; b < 5; ++b) G[gidx(aa, b)] = v[gmom(aa, b)];
+  const int it = ctl_ld(&sc->itp[par]);
+  const double thr = ctl_ld(&sc->thr);
+  const bool absmax = ctl_ld(&sc->norm) == MAZE_NORM_ABSMAX;
+  const int imax = ctl_ld(&sc->max_iter);
+  bool finite = true;
+#pragma unroll
+  for (int c = 0; c < kNs; ++c) finite = finite && isfinite(v[c]);
+  const double rr0 = G[gidx(3, 3)];
+  const double rn0 = 6.0 * sqrt(fmax(rr0, 0.0));
+  if (leader && it < a.hist_cap) a.hist[it] = rn0;
+  const bool conv0 = absmax ? (v[kNm] <= thr) : (rn0 <= thr);
+  int code = 0;
+  if (conv0) code = 1;
+  else if (!finite) code = 2;
+  else if (it >= imax) code = 3;
+  double xv[5] = {0, 0, 0, 0, 0}, rv[5] = {0, 0, 0, 1, 0}, pv[5] = {1, 0, 0, 0, 0};
+  double ap[5];
+  if (code == 0) {
+    ahat(pv, ap);
+    const double mu = gform(G, pv, ap);
+    if (!(mu > 0.0) || !isfinite(mu)) code = 2;
+    else {
+      const double al = rr0 / mu;
+#pragma unroll
+      for (int c = 0; c < 5; ++c) {
+        xv[c] += al * pv[c];
+        rv[c] -= al * ap[c];
+      }
+    }
+  }
+  int pend = 0, nsteps = 1;
+  if (code != 0) {
+    // no update in this outer step. A first step that starts x from zero
+    // still has to write x = 0: it runs with zero coefficients for x (r
+    // and p copied) and leaves the stop pending, so that no workgroup of
+    // this launch skips its points on seeing `done`.
+    if (!(FIRST && a.zero_x)) {
+      if (leader) {
+        ctl_st(&sc->iters, it);
+        ctl_st(&sc->done, code);
+      }
+      return false;
+    }
+#pragma unroll
+    for (int c = 0; c < 5; ++c) xv[c] = rv[c] = pv[c] = 0.0;
+    rv[3] = 1.0;
+    pv[0] = 1.0;
+    pend = code;
+    nsteps = 0;
+  }
+  // first inner iteration done (unless stopped above)
+  const double rr1 = fmax(gform(G, rv, rv), 0.0);
+  const double rn1 = 6.0 * sqrt(rr1);
+  if (pend == 0 && leader && it + 1 < a.hist_cap) a.hist[it + 1] = rn1;
+  if (pend == 0) {
+    if (!absmax && rn1 <= thr) pend = 1;
+    else if (it + 1 >= imax) pend = 3;
+  }
+  if (nsteps == 1) {
+    const double b1 = rr1 / rr0;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) pv[c] = rv[c] + b1 * pv[c];
+  }
+  if (pend == 0) {
+    ahat(pv, ap);
+    const double mu = gform(G, pv, ap);
+    if (!(mu > 0.0) || !isfinite(mu)) pend = 2;
+    else {
+      const double al = rr1 / mu;
+#pragma unroll
+      for (int c = 0; c < 5; ++c) {
+        xv[c] += al * pv[c];
+        rv[c] -= al * ap[c];
+      }
+      nsteps = 2;
+      const double rr2 = fmax(gform(G, rv, rv), 0.0);
+      const double b2 = rr2 / rr1;
+#pragma unroll
+      for (int c = 0; c < 5; ++c) pv[c] = rv[c] + b2 * pv[c];
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 5; ++c) {
+    cx[c] = (T)xv[c];
+    cr[c] = (T)(6.0 * rv[c]);
+    cp[c] = (T)pv[c];
+  }
+  if (leader) {
+    ctl_st(&sc->itp[par ^ 1], it + nsteps);
+    if (pend != 0) ctl_st(&sc->pend, pend);
+  }
+  return true;
+}
 
 // The work of one workgroup (logical index L) of a basis (UPDATE = false)
 // or update (UPDATE = true) kernel of outer step parity `par`. FIRST: the
@@ -184,112 +307,7 @@ __device__ __forceinline__ void sstep_wg(const SweepArgs<T>& a, const SweepGeom&
   // ---- update kernel: two CG iterations on the coordinates -----------------
   T cx[5], cr[5], cp[5];
   if (UPDATE) {
-    double v[kNs];
-#pragma unroll
-    for (int i = 0; i < kNs; ++i) v[i] = 0.0;
-    for (int i = tid; i < a.nprev_sweep; i += NT) {
-#pragma unroll
-      for (int c = 0; c < kNm; ++c) v[c] += a.part[(size_t)(SL_SG0 + c) * a.pstride + i];
-      v[kNm] = fmax(v[kNm], a.part[(size_t)SL_SGMAX * a.pstride + i]);
-    }
-    block_reduce_ns<NT>(v, red);
-    __syncthreads();  // red is reused for the planes below
-    double G[15];
-#pragma unroll
-    for (int aa = 0; aa < 5; ++aa)
-#pragma unroll
-      for (int b = aa; b < 5; ++b) G[gidx(aa, b)] = v[gmom(aa, b)];
-    const int it = ctl_ld(&sc->itp[par]);
-    const double thr = ctl_ld(&sc->thr);
-    const bool absmax = ctl_ld(&sc->norm) == MAZE_NORM_ABSMAX;
-    const int imax = ctl_ld(&sc->max_iter);
-    bool finite = true;
-#pragma unroll
-    for (int c = 0; c < kNs; ++c) finite = finite && isfinite(v[c]);
-    const double rr0 = G[gidx(3, 3)];
-    const double rn0 = 6.0 * sqrt(fmax(rr0, 0.0));
-    if (leader && it < a.hist_cap) a.hist[it] = rn0;
-    const bool conv0 = absmax ? (v[kNm] <= thr) : (rn0 <= thr);
-    int code = 0;
-    if (conv0) code = 1;
-    else if (!finite) code = 2;
-    else if (it >= imax) code = 3;
-    double xv[5] = {0, 0, 0, 0, 0}, rv[5] = {0, 0, 0, 1, 0}, pv[5] = {1, 0, 0, 0, 0};
-    double ap[5];
-    if (code == 0) {
-      ahat(pv, ap);
-      const double mu = gform(G, pv, ap);
-      if (!(mu > 0.0) || !isfinite(mu)) code = 2;
-      else {
-        const double al = rr0 / mu;
-#pragma unroll
-        for (int c = 0; c < 5; ++c) {
-          xv[c] += al * pv[c];
-          rv[c] -= al * ap[c];
-        }
-      }
-    }
-    int pend = 0, nsteps = 1;
-    if (code != 0) {
-      // no update in this outer step. A first step that starts x from zero
-      // still has to write x = 0: it runs with zero coefficients for x (r
-      // and p copied) and leaves the stop pending, so that no workgroup of
-      // this launch skips its points on seeing `done`.
-      if (!(FIRST && a.zero_x)) {
-        if (leader) {
-          ctl_st(&sc->iters, it);
-          ctl_st(&sc->done, code);
-        }
-        return;
-      }
-#pragma unroll
-      for (int c = 0; c < 5; ++c) xv[c] = rv[c] = pv[c] = 0.0;
-      rv[3] = 1.0;
-      pv[0] = 1.0;
-      pend = code;
-      nsteps = 0;
-    }
-    // first inner iteration done (unless stopped above)
-    const double rr1 = fmax(gform(G, rv, rv), 0.0);
-    const double rn1 = 6.0 * sqrt(rr1);
-    if (pend == 0 && leader && it + 1 < a.hist_cap) a.hist[it + 1] = rn1;
-    if (pend == 0) {
-      if (!absmax && rn1 <= thr) pend = 1;
-      else if (it + 1 >= imax) pend = 3;
-    }
-    if (nsteps == 1) {
-      const double b1 = rr1 / rr0;
-#pragma unroll
-      for (int c = 0; c < 5; ++c) pv[c] = rv[c] + b1 * pv[c];
-    }
-    if (pend == 0) {
-      ahat(pv, ap);
-      const double mu = gform(G, pv, ap);
-      if (!(mu > 0.0) || !isfinite(mu)) pend = 2;
-      else {
-        const double al = rr1 / mu;
-#pragma unroll
-        for (int c = 0; c < 5; ++c) {
-          xv[c] += al * pv[c];
-          rv[c] -= al * ap[c];
-        }
-        nsteps = 2;
-        const double rr2 = fmax(gform(G, rv, rv), 0.0);
-        const double b2 = rr2 / rr1;
-#pragma unroll
-        for (int c = 0; c < 5; ++c) pv[c] = rv[c] + b2 * pv[c];
-      }
-    }
-#pragma unroll
-    for (int c = 0; c < 5; ++c) {
-      cx[c] = (T)xv[c];
-      cr[c] = (T)(6.0 * rv[c]);
-      cp[c] = (T)pv[c];
-    }
-    if (leader) {
-      ctl_st(&sc->itp[par ^ 1], it + nsteps);
-      if (pend != 0) ctl_st(&sc->pend, pend);
-    }
+    if (!sstep_coeffs<T, FIRST, NT>(a, par, leader, red, cx, cr, cp)) return;
   }
 
   // ---- geometry of this workgroup -------------------------------------------
@@ -591,6 +609,326 @@ __global__ __launch_bounds__(NT) void k_sstep_batch(const SweepArgs<T>* __restri
                                                smem_raw);
 }
 
+// ---- wavefront-row layout -------------------------------------------------
+// Where N = 64 V (V = 1, 2, 4), a wavefront holds whole z rows: lane l the V
+// points z = l V .. l V + V - 1 of its row. The z neighbours of a lane's
+// points are its own values and, at the two ends, the values of lanes l - 1
+// and l + 1, moved by DPP rotations of the whole wavefront by one lane; the
+// periodic wrap in z is the rotation's own wrap between lanes 63 and 0. A
+// workgroup of WV wavefronts takes the WV consecutive rows y0 - 1 ..
+// y0 + WV - 2 of each plane and marches along x as the layouts above: every
+// wavefront forms B p on its row (stage U), the inner WV - 2 (the
+// workgroup's segment of rows) also B^2 p and B rhat and their Gram sums
+// (stage W), and the first and last wavefront also stage p of the rows
+// y0 - 2 and y0 + WV - 1. Each lane reads its V points as one 4- to 32-byte
+// access, and every LDS offset within a buffer is a compile-time constant
+// from the row. The stencil sums are formed in the order of the layouts
+// above, so B p, B^2 p and B rhat are the same values; only the grouping
+// of the Gram sums into partials differs. The layout serves the basis
+// kernel, which only reads: the update kernel, which also writes x, r and
+// p, streams at the copy rate in the segment layouts.
+
+template <typename T, int V>
+struct VecT {
+  using type = T __attribute__((ext_vector_type(V)));
+};
+template <typename T>
+struct VecT<T, 1> {
+  using type = T;
+};
+
+// lane l receives the value of lane l - 1 (lane 0 that of lane 63)
+__device__ __forceinline__ float from_lane_before(float v) {
+  return __builtin_bit_cast(
+      float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x13C, 0xF, 0xF, false));
+}
+// lane l receives the value of lane l + 1 (lane 63 that of lane 0)
+__device__ __forceinline__ float from_lane_after(float v) {
+  return __builtin_bit_cast(
+      float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x134, 0xF, 0xF, false));
+}
+__device__ __forceinline__ double from_lane_before(double v) {
+  using I2 = int __attribute__((ext_vector_type(2)));
+  I2 w = __builtin_bit_cast(I2, v);
+  w.x = __builtin_amdgcn_update_dpp(0, w.x, 0x13C, 0xF, 0xF, false);
+  w.y = __builtin_amdgcn_update_dpp(0, w.y, 0x13C, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, w);
+}
+__device__ __forceinline__ double from_lane_after(double v) {
+  using I2 = int __attribute__((ext_vector_type(2)));
+  I2 w = __builtin_bit_cast(I2, v);
+  w.x = __builtin_amdgcn_update_dpp(0, w.x, 0x134, 0xF, 0xF, false);
+  w.y = __builtin_amdgcn_update_dpp(0, w.y, 0x134, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, w);
+}
+
+// V consecutive values at byte offset boff of a plane, scaled by s
+template <typename T, int V>
+__device__ __forceinline__ void ldv(__amdgpu_buffer_rsrc_t r, uint32_t boff, T s, T (&o)[V]) {
+  using U4 = unsigned int __attribute__((ext_vector_type(4)));
+  constexpr int B = V * (int)sizeof(T);
+  struct Arr {
+    T v[V];
+  } w;
+  if constexpr (B == 4) {
+    w = __builtin_bit_cast(Arr, __builtin_amdgcn_raw_buffer_load_b32(r, boff, 0, 0));
+  } else if constexpr (B == 8) {
+    w = __builtin_bit_cast(Arr, __builtin_amdgcn_raw_buffer_load_b64(r, boff, 0, 0));
+  } else if constexpr (B == 16) {
+    w = __builtin_bit_cast(Arr, __builtin_amdgcn_raw_buffer_load_b128(r, boff, 0, 0));
+  } else {
+    static_assert(B == 32, "4 to 32 bytes per lane");
+    struct Two {
+      U4 a, b;
+    } t{__builtin_amdgcn_raw_buffer_load_b128(r, boff, 0, 0),
+        __builtin_amdgcn_raw_buffer_load_b128(r, boff + 16, 0, 0)};
+    w = __builtin_bit_cast(Arr, t);
+  }
+#pragma unroll
+  for (int i = 0; i < V; ++i) o[i] = s * w.v[i];
+}
+
+// LDS: V consecutive values at p (aligned to V * sizeof(T))
+template <typename T, int V>
+__device__ __forceinline__ void lds_ld(const T* p, T (&o)[V]) {
+  using TV = typename VecT<T, V>::type;
+  const TV w = *reinterpret_cast<const TV*>(p);
+  if constexpr (V == 1) {
+    o[0] = w;
+  } else {
+#pragma unroll
+    for (int i = 0; i < V; ++i) o[i] = w[i];
+  }
+}
+template <typename T, int V>
+__device__ __forceinline__ void lds_st(T* p, const T (&v)[V]) {
+  using TV = typename VecT<T, V>::type;
+  TV w;
+  if constexpr (V == 1) {
+    w = v[0];
+  } else {
+#pragma unroll
+    for (int i = 0; i < V; ++i) w[i] = v[i];
+  }
+  *reinterpret_cast<TV*>(p) = w;
+}
+
+// Plane buffers of the wavefront-row layout, in elements of T: p rows
+// y0 - 2 .. y0 + WV - 1, then B p and r rows y0 - 1 .. y0 + WV - 2, each
+// double-buffered.
+__host__ __device__ constexpr int zv_lds_elems(int N, int wv) { return 2 * (wv + 2) * N + 4 * wv * N; }
+
+template <typename T, bool FIRST, int V, int WV>
+__device__ __forceinline__ void sstep_zv_wg(const SweepArgs<T>& a, const SweepGeom& g, int par,
+                                            int L, unsigned char* smem_raw) {
+  constexpr int N = 64 * V, NT = 64 * WV, WO = WV - 2;
+  double* red = reinterpret_cast<double*>(smem_raw);
+  Scalars* sc = a.sc;
+  if (ctl_ld(&sc->done) != 0 || ctl_ld(&sc->err) != 0) return;
+  const int tid = threadIdx.x;
+  const bool leader = (L == 0) && (tid == 0);
+  const T* r_in = par ? a.r[1] : a.r[0];
+  const T* p_in = FIRST ? r_in : (par ? a.p[1] : a.p[0]);
+  const T sp = FIRST ? (T)(1.0 / 6.0) : (T)1;  // p = sp * (value read)
+
+  // a stop left pending by the update kernel before ends the solve here
+  if (!FIRST) {
+    const int pend = ctl_ld(&sc->pend);
+    if (pend != 0) {
+      if (leader) {
+        ctl_st(&sc->iters, ctl_ld(&sc->itp[par]));
+        ctl_st(&sc->done, pend);
+      }
+      return;
+    }
+  }
+
+  // ---- geometry: chunks of one segment first, odd chunks march down --------
+  const int chunk = L % g.nchunk, seg = L / g.nchunk;
+  const int y0 = seg * WO;
+  const int x0 = chunk * g.cx, x1 = min(N, x0 + g.cx);
+  const int dir = (chunk & 1) ? -1 : 1;
+  const int ub = (chunk & 1) ? x1 : x0 - 1;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int lo = (tid & 63) * V;
+  const int yr = (y0 - 1 + w) & (N - 1);
+  const bool outw = (w >= 1) && (w <= WO) && (y0 + w - 1 < N);  // row of the segment
+  const bool has_o = (w == 0) || (w == WV - 1);                  // stages an outer p row
+  const int yo = (w == 0 ? y0 - 2 : y0 - 1 + WV) & (N - 1);
+  const int orow = (w == 0) ? 0 : WV + 1;
+  const uint32_t bo = (uint32_t)((yr * N + lo) * (int)sizeof(T));
+  const uint32_t boo = (uint32_t)((yo * N + lo) * (int)sizeof(T));
+  T* P1 = reinterpret_cast<T*>(smem_raw);  // [2][WV + 2][N]
+  T* QB = P1 + 2 * (WV + 2) * N;           // [2][WV][N] B p
+  T* QS = QB + 2 * WV * N;                 // [2][WV][N] r
+
+  const T c6 = (T)(1.0 / 6.0);
+  const T c36 = (T)(1.0 / 36.0);
+  const size_t Ps = (size_t)N * N;
+  T pm[V], pc[V], pn[V], po[V];  // p of the row: planes u-1, u, u+1; outer row, plane u+1
+  T rc[V], rm1[V], rm2[V];       // r of the row: planes u, u-1, u-2
+  T bm[V], bc[V];                // B p of the row: planes u-2, u-1
+  double acc[kNm];
+#pragma unroll
+  for (int i = 0; i < kNm; ++i) acc[i] = 0.0;
+  T rmax = (T)0;
+
+  {
+    const auto r0 = pl_rsrc(r_in, wrap_pl(ub, N), Ps);
+    const auto pa = pl_rsrc(p_in, wrap_pl(ub - dir, N), Ps);
+    const auto pb = pl_rsrc(p_in, wrap_pl(ub, N), Ps);
+    const auto pd = pl_rsrc(p_in, wrap_pl(ub + dir, N), Ps);
+    ldv<T, V>(r0, bo, (T)1, rc);
+    ldv<T, V>(pa, bo, sp, pm);
+    ldv<T, V>(pb, bo, sp, pc);
+    ldv<T, V>(pd, bo, sp, pn);
+    lds_st<T, V>(P1 + (w + 1) * N + lo, pc);
+    if (has_o) {
+      T ob[V];
+      ldv<T, V>(pb, boo, sp, ob);
+      ldv<T, V>(pd, boo, sp, po);
+      lds_st<T, V>(P1 + orow * N + lo, ob);
+    }
+#pragma unroll
+    for (int j = 0; j < V; ++j) rm1[j] = rm2[j] = bm[j] = bc[j] = (T)0;
+  }
+  __syncthreads();
+
+  const int nsteps = x1 - x0 + 2;  // stage U on planes x0-1 .. x1, in march order
+  for (int t = 0; t < nsteps; ++t) {
+    const int u = ub + dir * t;
+    const bool more = t + 1 < nsteps;
+    T pf[V], pof[V], rf[V];
+    if (more) {
+      const auto rp = pl_rsrc(r_in, wrap_pl(u + dir, N), Ps);
+      const auto pp = pl_rsrc(p_in, wrap_pl(u + 2 * dir, N), Ps);
+      ldv<T, V>(rp, bo, (T)1, rf);
+      ldv<T, V>(pp, bo, sp, pf);
+      if (has_o) ldv<T, V>(pp, boo, sp, pof);
+    }
+
+    // stage U at plane u: B p of the row; (B p, r) staged
+    const int tb = t & 1;
+    T bk[V];
+    {
+      const T* pr = P1 + (tb * (WV + 2) + w) * N + lo;  // row y - 1; y + 1 is 2N further
+      T ym[V], yp[V];
+      lds_ld<T, V>(pr, ym);
+      lds_ld<T, V>(pr + 2 * N, yp);
+      const T zl = from_lane_before(pc[V - 1]), zr = from_lane_after(pc[0]);
+#pragma unroll
+      for (int i = 0; i < V; ++i) {
+        const T zm = (i == 0) ? zl : pc[i > 0 ? i - 1 : 0];
+        const T zp = (i == V - 1) ? zr : pc[i + 1 < V ? i + 1 : 0];
+        bk[i] = -c6 * (((pm[i] + pn[i]) + (ym[i] + yp[i])) + (zm + zp));
+      }
+      lds_st<T, V>(QB + (tb * WV + w) * N + lo, bk);
+      lds_st<T, V>(QS + (tb * WV + w) * N + lo, rc);
+    }
+
+    // stage W at plane u-dir: B^2 p, B rhat and the Gram sums on the rows of
+    // the segment
+    if (t >= 2 && outw) {
+      const int q = ((tb ^ 1) * WV + w - 1) * N + lo;  // row y - 1; y + 1 is 2N further
+      T bym[V], byp[V], sym[V], syp[V];
+      lds_ld<T, V>(QB + q, bym);
+      lds_ld<T, V>(QB + q + 2 * N, byp);
+      lds_ld<T, V>(QS + q, sym);
+      lds_ld<T, V>(QS + q + 2 * N, syp);
+      const T bl = from_lane_before(bc[V - 1]), br = from_lane_after(bc[0]);
+      const T sl = from_lane_before(rm1[V - 1]), sr = from_lane_after(rm1[0]);
+#pragma unroll
+      for (int j = 0; j < V; ++j) {
+        const T zmb = (j == 0) ? bl : bc[j > 0 ? j - 1 : 0];
+        const T zpb = (j == V - 1) ? br : bc[j + 1 < V ? j + 1 : 0];
+        const T zms = (j == 0) ? sl : rm1[j > 0 ? j - 1 : 0];
+        const T zps = (j == V - 1) ? sr : rm1[j + 1 < V ? j + 1 : 0];
+        const T y0v = pm[j];
+        const T y1 = bc[j];
+        const T y2 = -c6 * (((bm[j] + bk[j]) + (bym[j] + byp[j])) + (zmb + zpb));
+        const T y3 = c6 * rm1[j];
+        const T y4 = -c36 * (((rm2[j] + rc[j]) + (sym[j] + syp[j])) + (zms + zps));
+        const double d0 = (double)y0v, d1 = (double)y1, d2 = (double)y2, d3 = (double)y3,
+                     d4 = (double)y4;
+        acc[0] += d0 * d0;
+        acc[1] += d0 * d1;
+        acc[2] += d1 * d1;
+        acc[3] += d1 * d2;
+        acc[4] += d2 * d2;
+        acc[5] += d0 * d3;
+        acc[6] += d0 * d4;
+        acc[7] += d1 * d4;
+        acc[8] += d2 * d4;
+        acc[9] += d3 * d3;
+        acc[10] += d3 * d4;
+        acc[11] += d4 * d4;
+        rmax = fmax(rmax, fabs(rm1[j]));
+      }
+    }
+
+    // stage p of plane u+dir for the next step
+    if (more) {
+      T* pw = P1 + (tb ^ 1) * (WV + 2) * N + lo;
+      lds_st<T, V>(pw + (w + 1) * N, pn);
+      if (has_o) lds_st<T, V>(pw + orow * N, po);
+    }
+    __syncthreads();
+
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+      bm[j] = bc[j];
+      bc[j] = bk[j];
+      rm2[j] = rm1[j];
+      rm1[j] = rc[j];
+    }
+    if (more) {
+#pragma unroll
+      for (int j = 0; j < V; ++j) {
+        rc[j] = rf[j];
+        pm[j] = pc[j];
+        pc[j] = pn[j];
+        pn[j] = pf[j];
+        po[j] = pof[j];
+      }
+    }
+  }
+
+  double sums[kNs];
+#pragma unroll
+  for (int c = 0; c < kNm; ++c) sums[c] = acc[c];
+  sums[kNm] = (double)rmax;
+  block_reduce_ns<NT>(sums, red);
+  if (tid == 0) {
+#pragma unroll
+    for (int c = 0; c < kNm; ++c) a.part[(size_t)(SL_SG0 + c) * a.pstride + L] = sums[c];
+    a.part[(size_t)SL_SGMAX * a.pstride + L] = sums[kNm];
+  }
+}
+
+template <typename T, bool FIRST, int V, int WV>
+__global__ __launch_bounds__(64 * WV) void k_sstep_zv(SweepArgs<T> a, SweepGeom g, int par) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  sstep_zv_wg<T, FIRST, V, WV>(a, g, par, xcd_remap(blockIdx.x, g.nwg), smem_raw);
+}
+
+template <typename T, bool FIRST, int V, int WV>
+__global__ __launch_bounds__(64 * WV) void k_sstep_zv_batch(const SweepArgs<T>* __restrict__ args,
+                                                            const SweepGeom* __restrict__ geoms,
+                                                            const int* __restrict__ wg_begin,
+                                                            int count, int par) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int b = blockIdx.x;
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (wg_begin[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  const SweepArgs<T> a = args[lo];
+  const SweepGeom g = geoms[lo];
+  sstep_zv_wg<T, FIRST, V, WV>(a, g, par ^ a.par_flip, b - wg_begin[lo], smem_raw);
+}
+
 // Geometry of a two-iteration kernel with nt threads per workgroup
 // (segments of nt * ppt points, nh halo slots per thread for one row).
 SweepGeom make_sstep_geom(int N, int ppt, int cx, int nt) {
@@ -607,12 +945,34 @@ SweepGeom make_sstep_geom(int N, int ppt, int cx, int nt) {
   return g;
 }
 
-bool sstep_rows(const SweepGeom& g) { return (g.S / g.ppt) % g.N == 0; }
+SweepGeom make_sstep_zv_geom(int N, int cx, int wv) {
+  SweepGeom g;
+  const int wo = wv - 2;
+  g.N = N;
+  g.P = N * N;
+  g.ppt = N / 64;
+  g.S = wo * N;
+  g.nseg = (N + wo - 1) / wo;
+  g.cx = cx < 1 ? 1 : (cx > N ? N : cx);
+  g.nchunk = (N + g.cx - 1) / g.cx;
+  g.nwg = g.nseg * g.nchunk;
+  g.nh = 1;  // no halo slots; a valid class for the checks that read it
+  g.zv = wv;
+  return g;
+}
+
+int sstep_threads(const SweepGeom& g) { return g.zv ? 64 * g.zv : g.S / g.ppt; }
+
+bool sstep_rows(const SweepGeom& g) { return !g.zv && (g.S / g.ppt) % g.N == 0; }
 
 size_t sstep_lds_bytes(const SweepGeom& g, bool fp32) {
   const size_t es = fp32 ? sizeof(float) : sizeof(double);
+  if (g.zv) {
+    const size_t red = sizeof(double) * kNs * (size_t)(g.zv + 1);
+    return std::max(es * (size_t)zv_lds_elems(g.N, g.zv), red);
+  }
   const size_t e1 = (size_t)g.S + 4 * (size_t)g.N, e2 = (size_t)g.S + 2 * (size_t)g.N;
-  const size_t red = sizeof(double) * kNs * (size_t)(g.S / g.ppt / 64);
+  const size_t red = sizeof(double) * kNs * (size_t)(g.S / g.ppt / 64 + 1);
   return std::max(es * 2 * (e1 + 2 * e2), red);
 }
 
@@ -653,6 +1013,17 @@ struct SingleLaunch {
                        lds, st, a, g, par);
     return hipGetLastError();
   }
+  template <int V, int WV>
+  hipError_t run_zv() const {
+    static size_t allowed = 0;
+    const size_t lds = sstep_lds_bytes(g, sizeof(T) == 4);
+    const hipError_t e =
+        ensure_lds((const void*)k_sstep_zv<T, FIRST, V, WV>, lds, &allowed);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_sstep_zv<T, FIRST, V, WV>), dim3(g.nwg), dim3(64 * WV), lds, st,
+                       a, g, par);
+    return hipGetLastError();
+  }
 };
 
 // A batch of sessions of one template class (device arrays in L).
@@ -671,7 +1042,37 @@ struct BatchLaunch {
                        L.wg_begin, L.count, L.par);
     return hipGetLastError();
   }
+  template <int V, int WV>
+  hipError_t run_zv() const {
+    static size_t allowed = 0;
+    const hipError_t e =
+        ensure_lds((const void*)k_sstep_zv_batch<T, FIRST, V, WV>, L.lds, &allowed);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_sstep_zv_batch<T, FIRST, V, WV>), dim3(L.nwg_total),
+                       dim3(64 * WV), L.lds, st, static_cast<const SweepArgs<T>*>(L.args),
+                       L.geoms, L.wg_begin, L.count, L.par);
+    return hipGetLastError();
+  }
 };
+
+// Wavefront-row classes with an instantiation: basis kernels only (the
+// update kernels stream at the copy rate in the segment layouts), N = 64,
+// 128 or 256 (V = 1, 2, 4 points per lane), workgroups of 8 wavefronts.
+constexpr bool zv_class_ok(int v, int wv) { return (v == 1 || v == 2 || v == 4) && wv == 8; }
+
+template <bool UPDATE, class F>
+hipError_t sstep_zv_dispatch(int v, int wv, const F& f) {
+  if constexpr (UPDATE) {
+    return hipErrorInvalidValue;
+  } else {
+    switch (v * 100 + wv) {
+      case 108: return f.template run_zv<1, 8>();
+      case 208: return f.template run_zv<2, 8>();
+      case 408: return f.template run_zv<4, 8>();
+      default: return hipErrorInvalidValue;
+    }
+  }
+}
 
 // rows: the row-owning layout (N divides NT, so at most two halo slots)
 template <bool UPDATE, int PPT, int NT, class F>
@@ -729,12 +1130,14 @@ hipError_t sstep_dispatch(int nt, int ppt, int nh, bool rows, const F& f) {
 template <typename T, bool FIRST, bool UPDATE>
 hipError_t sstep_ppt(const SweepArgs<T>& a, const SweepGeom& g, int par, hipStream_t st) {
   const SingleLaunch<T, FIRST, UPDATE> f{a, g, par, st};
+  if (g.zv) return sstep_zv_dispatch<UPDATE>(g.ppt, g.zv, f);
   return sstep_dispatch<UPDATE>(g.S / g.ppt, g.ppt, sweep_nh_class(g.nh), sstep_rows(g), f);
 }
 
 template <typename T, bool FIRST, bool UPDATE>
 hipError_t sstep_batch_ppt(const SweepLaunch& L, int nt, bool rows, hipStream_t st) {
   const BatchLaunch<T, FIRST, UPDATE> f{L, st};
+  if (L.zv) return sstep_zv_dispatch<UPDATE>(L.ppt, L.zv, f);
   return sstep_dispatch<UPDATE>(nt, L.ppt, L.nh, rows, f);
 }
 
@@ -784,9 +1187,16 @@ hipError_t launch_sstep_batch(const SweepLaunch& L, int nt, bool rows, bool fp32
                 : sstep_batch_ppt<double, false, false>(L, nt, rows, st);
 }
 
+// Wavefront-row shapes with an instantiation whose LDS fits.
+static bool sstep_zv_shape_ok(const SweepGeom& g, bool fp32) {
+  return g.N == 64 * g.ppt && zv_class_ok(g.ppt, g.zv) && g.zv - 2 <= g.N &&
+         sstep_lds_bytes(g, fp32) <= 160 * 1024 - 2048;
+}
+
 // Update-kernel shapes with an instantiation: 256 threads in every class;
 // 512 threads with 2 or 4 points per thread and at most two halo slots.
 bool sstep_update_shape_ok(const SweepGeom& g, bool fp32) {
+  if (g.zv) return false;
   const int nt = g.S / g.ppt;
   const int nh = sweep_nh_class(g.nh);
   if (nh == 0 || sstep_lds_bytes(g, fp32) > 160 * 1024 - 2048) return false;
@@ -800,6 +1210,7 @@ bool sstep_update_shape_ok(const SweepGeom& g, bool fp32) {
 // thread with one halo slot (2 points with two), and for FP64 up to 2
 // points with one halo slot (1 point with two).
 bool sstep_basis_shape_ok(const SweepGeom& g, bool fp32) {
+  if (g.zv) return sstep_zv_shape_ok(g, fp32);
   const int nt = g.S / g.ppt;
   const int nh = sweep_nh_class(g.nh);
   if (nh == 0 || sstep_lds_bytes(g, fp32) > 160 * 1024 - 2048) return false;

@@ -867,7 +867,8 @@ static int run_sstep_batch(std::vector<CgJob>& jobs, bool fp32, bool zero_x, int
   // flat layout: fewer classes, fewer launches.
   auto rows = [tp](const SweepGeom& g) { return !tp && sstep_rows(g); };
   auto cls = [&rows](const SweepGeom& g) {
-    return (((g.S / g.ppt) * 8 + g.ppt) * 16 + sweep_nh_class(g.nh)) * 2 + (rows(g) ? 1 : 0);
+    return ((((sstep_threads(g)) * 8 + g.ppt) * 16 + sweep_nh_class(g.nh)) * 2 +
+            (rows(g) ? 1 : 0)) * 32 + g.zv;
   };
   std::vector<int> order(n);
   for (int i = 0; i < n; ++i) order[i] = i;
@@ -875,7 +876,7 @@ static int run_sstep_batch(std::vector<CgJob>& jobs, bool fp32, bool zero_x, int
     const int ca = cls(gb(a)), cb = cls(gb(b));
     return ca != cb ? ca < cb : cls(gu(a)) < cls(gu(b));
   });
-  struct Grp { int c0, c1, wgb0, nwg, nt, ppt, nh; bool rows; size_t lds; };
+  struct Grp { int c0, c1, wgb0, nwg, nt, ppt, nh; bool rows; size_t lds; int zv; };
   std::vector<Grp> gbs, gus;
   char* H = t->host;
   SweepGeom* hg = (SweepGeom*)(H + t->o_geom);
@@ -895,11 +896,13 @@ static int run_sstep_batch(std::vector<CgJob>& jobs, bool fp32, bool zero_x, int
     const int cb = cls(b), cu = cls(u);
     if (gbs.empty() || cls(hg[gbs.back().c0]) != cb) {
       if (!gbs.empty()) hw[wpos++] = gbs.back().nwg;
-      gbs.push_back({q, q, wpos, 0, b.S / b.ppt, b.ppt, sweep_nh_class(b.nh), rows(b), 0});
+      gbs.push_back({q, q, wpos, 0, sstep_threads(b), b.ppt, sweep_nh_class(b.nh), rows(b), 0,
+                     b.zv});
     }
     if (gus.empty() || cls(hg2[gus.back().c0]) != cu) {
       if (!gus.empty()) hw2[wpos2++] = gus.back().nwg;
-      gus.push_back({q, q, wpos2, 0, u.S / u.ppt, u.ppt, sweep_nh_class(u.nh), rows(u), 0});
+      gus.push_back({q, q, wpos2, 0, sstep_threads(u), u.ppt, sweep_nh_class(u.nh), rows(u), 0,
+                     u.zv});
     }
     hg[q] = b;
     hg2[q] = u;
@@ -938,7 +941,7 @@ static int run_sstep_batch(std::vector<CgJob>& jobs, bool fp32, bool zero_x, int
       for (const Grp& g : *gs)
         gkey.insert(gkey.end(),
                     {g.c0, g.c1, g.wgb0, g.nwg, g.nt, g.ppt, g.nh, g.rows ? 1 : 0,
-                     (long long)g.lds});
+                     (long long)g.lds, g.zv});
   }
   return batch_loop(jobs, order, t, st, guard, kPollBatch / 2, first_batch / 2, [&](long long k) {
     for (int half = 0; half < 2; ++half) {
@@ -949,6 +952,7 @@ static int run_sstep_batch(std::vector<CgJob>& jobs, bool fp32, bool zero_x, int
         L.par = (int)(k & 1);
         L.ppt = g.ppt;
         L.nh = g.nh;
+        L.zv = g.zv;
         L.args = t->dev + t->o_args + (size_t)g.c0 * sizeof(SweepArgs<double>);
         L.geoms = (const SweepGeom*)(t->dev + (update ? t->o_geom2 : t->o_geom)) + g.c0;
         L.wg_begin = (const int*)(t->dev + (update ? t->o_wgb2 : t->o_wgb)) + g.wgb0;
@@ -1393,8 +1397,36 @@ static SweepGeom autotune_sweep(maze_session* s) {
 // 6 timed outer steps (basis and update kernel) on a fill pattern of the
 // session's r and p. MAZE_BASIS_SHAPE="threads:ppt:cx" forces one.
 
+// "zv:wavefronts:cx": a wavefront-row shape
+static bool forced_zv(const char* e, const DeviceState& d, SweepGeom* out) {
+  int wv = 0, cx = 0;
+  if (!e || std::sscanf(e, "zv:%d:%d", &wv, &cx) != 2 || wv < 3 || cx < 1 || d.N % 64 != 0)
+    return false;
+  *out = make_sstep_zv_geom(d.N, cx, wv);
+  return true;
+}
+
+// Wavefront-row basis candidates of a grid (N = 64, 128 or 256;
+// workgroups of 8 wavefronts).
+static void zv_candidates(const DeviceState& d, bool fp32, std::vector<SweepGeom>* cand) {
+  if (d.N % 64 != 0) return;
+  int last = -1;
+  for (int cx : {6, 8, 10, 12, 16, 20, 24, 32, 48, 64}) {
+    const SweepGeom g = make_sstep_zv_geom(d.N, cx, 8);
+    if (g.nchunk == last || !sstep_basis_shape_ok(g, fp32) || g.nwg > d.part_stride) continue;
+    last = g.nchunk;
+    cand->push_back(g);
+  }
+}
+
 static bool forced_basis(const DeviceState& d, bool fp32, SweepGeom* out) {
   const char* e = std::getenv("MAZE_BASIS_SHAPE");
+  SweepGeom z;
+  if (forced_zv(e, d, &z)) {
+    if (!sstep_basis_shape_ok(z, fp32) || z.nwg > d.part_stride) return false;
+    *out = z;
+    return true;
+  }
   int nt = 0, ppt = 0, cx = 0;
   if (!e || std::sscanf(e, "%d:%d:%d", &nt, &ppt, &cx) != 3) return false;
   if ((nt != kThreads && nt != 512 && nt != 1024) || (ppt != 1 && ppt != 2 && ppt != 4) || cx < 1)
@@ -1424,6 +1456,7 @@ static SweepGeom tune_basis(maze_session* s, const SweepGeom& upd) {
         cand.push_back(g);
       }
     }
+  zv_candidates(d, fp32, &cand);
   if (cand.size() <= 1) return def;
   hipStream_t st = s->stream;
   void* r0 = fp32 ? (void*)d.r32 : (void*)d.r;
@@ -1645,6 +1678,7 @@ struct BatchLaunch {
   int c0, c1, wgb0, nwg, nt, ppt, nh;
   bool rows;
   size_t lds;
+  int zv;
 };
 }  // namespace
 
@@ -1752,7 +1786,8 @@ int batch_rebuild(maze_batch* b) {
   if (b->members.empty()) return MAZE_OK;
   auto job = [&](int q) -> BatchJob& { return b->jobs[b->members[q]]; };
   auto cls = [](const SweepGeom& g, bool rows) {
-    return (((g.S / g.ppt) * 8 + g.ppt) * 16 + sweep_nh_class(g.nh)) * 2 + (rows ? 1 : 0);
+    return ((((sstep_threads(g)) * 8 + g.ppt) * 16 + sweep_nh_class(g.nh)) * 2 + (rows ? 1 : 0)) *
+               32 + g.zv;
   };
   // shapes of a job's solve: basis (or sweep) and update; the flat layout
   // in the throughput shapes, as in a throughput-mode maze_step_batch
@@ -1798,8 +1833,8 @@ int batch_rebuild(maze_batch* b) {
     const long long ka = ((ss ? 2LL : 0LL) + (j.fp32 ? 1 : 0)) * 1000000007LL + cls(ga, ra);
     if (gA < 0 || ka != kA) {
       if (gA >= 0) hw[wpos++] = b->launches[gA].nwg;
-      b->launches.push_back({ss ? 1 : 0, j.fp32, q, q, wpos, 0, ga.S / ga.ppt, ga.ppt,
-                             sweep_nh_class(ga.nh), ra, 0});
+      b->launches.push_back({ss ? 1 : 0, j.fp32, q, q, wpos, 0, sstep_threads(ga), ga.ppt,
+                             sweep_nh_class(ga.nh), ra, 0, ss ? ga.zv : 0});
       gA = (int)b->launches.size() - 1;
       kA = ka;
     }
@@ -1815,8 +1850,8 @@ int batch_rebuild(maze_batch* b) {
       const long long kb = (j.fp32 ? 1 : 0) * 1000000007LL + cls(gu, ru);
       if (gB < 0 || kb != kB || b->launches[gB].c1 != q) {
         if (gB >= 0) hw2[wpos2++] = b->launches[gB].nwg;
-        b->launches.push_back({2, j.fp32, q, q, wpos2, 0, gu.S / gu.ppt, gu.ppt,
-                               sweep_nh_class(gu.nh), ru, 0});
+        b->launches.push_back({2, j.fp32, q, q, wpos2, 0, sstep_threads(gu), gu.ppt,
+                               sweep_nh_class(gu.nh), ru, 0, gu.zv});
         gB = (int)b->launches.size() - 1;
         kB = kb;
       }
@@ -1863,6 +1898,7 @@ int batch_unit(maze_batch* b) {
       L.par = par;
       L.ppt = G.ppt;
       L.nh = G.nh;
+      L.zv = G.zv;
       L.args = t.dev + t.o_args + (size_t)G.c0 * sizeof(SweepArgs<double>);
       L.geoms = (const SweepGeom*)(t.dev + (G.kind == 2 ? t.o_geom2 : t.o_geom)) + G.c0;
       L.wg_begin = (const int*)(t.dev + (G.kind == 2 ? t.o_wgb2 : t.o_wgb)) + G.wgb0;
@@ -2430,9 +2466,16 @@ int maze_launch_shape(const maze_session* s, int32_t* out8) {
   return MAZE_OK;
 }
 
+int maze_sstep_layout(const maze_session* s, int32_t* out2) {
+  if (!s || !out2) return MAZE_E_INVALID;
+  out2[0] = s->sbasis.zv;
+  out2[1] = s->sweep.zv;
+  return MAZE_OK;
+}
+
 int maze_basis_shape(const maze_session* s, int32_t* out4) {
   if (!s || !out4) return MAZE_E_INVALID;
-  out4[0] = s->sbasis.S / s->sbasis.ppt;
+  out4[0] = sstep_threads(s->sbasis);
   out4[1] = s->sbasis.ppt;
   out4[2] = s->sbasis.cx;
   out4[3] = s->sbasis.nwg;

@@ -106,6 +106,10 @@ struct SweepGeom {
   int nwg;
   int ppt;
   int nh;
+  // two-iteration kernels only: wavefronts per workgroup of the
+  // wavefront-row layout (N = 64 ppt; S = (zv - 2) N points of zv - 2 rows
+  // per segment), 0 for the segment layouts
+  int zv = 0;
 };
 
 SweepGeom make_sweep_geom(int N, int ppt, int cx);
@@ -240,6 +244,7 @@ struct SweepLaunch {
   bool batch;
   int par;
   int ppt, nh;        // template class shared by every session of the launch
+  int zv = 0;         // two-iteration kernels: wavefront-row layout class
   const void* args;
   SweepGeom g;
   const SweepGeom* geoms;
@@ -284,6 +289,12 @@ bool sstep_update_shape_ok(const SweepGeom& g, bool fp32);
 size_t sstep_lds_bytes(const SweepGeom& g, bool fp32);
 // Geometry of a two-iteration kernel with nt threads per workgroup.
 SweepGeom make_sstep_geom(int N, int ppt, int cx, int nt);
+// Geometry of a two-iteration kernel in the wavefront-row layout (N a
+// multiple of 64, at most 256): wv wavefronts per workgroup, each holding
+// one z row of N / 64 points per lane; segments of wv - 2 rows.
+SweepGeom make_sstep_zv_geom(int N, int cx, int wv);
+// Threads per workgroup of a two-iteration shape.
+int sstep_threads(const SweepGeom& g);
 // Fills x (G elements) with a fixed finite pattern.
 hipError_t launch_fill_pattern(void* x, long long G, bool fp32, hipStream_t st);
 // Batch helpers: {done, iters, err} of every session into out[3 * count];

@@ -34,6 +34,7 @@ EXPORTED = ("maze_abi_version", "maze_strerror", "maze_device_bytes", "maze_init
             "maze_state_bytes", "maze_save", "maze_load", "maze_destroy", "maze_md_prime",
             "maze_md_step", "maze_profile_enable", "maze_profile_read", "maze_trace_enable",
             "maze_trace_read", "maze_md_step_batch", "maze_launch_shape", "maze_basis_shape",
+            "maze_sstep_layout",
             "maze_langevin_noise",
             "maze_rdf_accumulate", "maze_tcf_create", "maze_tcf_sample", "maze_tcf_read",
             "maze_tcf_destroy", "maze_batch_create", "maze_batch_add", "maze_batch_advance",
@@ -147,6 +148,8 @@ def lib():
         L.maze_launch_shape.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
         L.maze_basis_shape.restype = ctypes.c_int
         L.maze_basis_shape.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
+        L.maze_sstep_layout.restype = ctypes.c_int
+        L.maze_sstep_layout.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
         L.maze_md_step_batch.restype = ctypes.c_int
         L.maze_md_step_batch.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(vp), i32,
                                          ctypes.POINTER(maze_stats)]
@@ -368,6 +371,14 @@ def maze_basis_shape(handle) -> dict:
     out = (ctypes.c_int32 * 4)()
     _check(lib().maze_basis_shape(handle, out), "maze_basis_shape")
     return dict(threads=out[0], ppt=out[1], cx=out[2], nwg=out[3])
+
+
+def maze_sstep_layout(handle) -> dict:
+    """Wavefronts per workgroup of the two-iteration kernels' wavefront-row
+    layout (0: segment layout), basis and update kernel."""
+    out = (ctypes.c_int32 * 2)()
+    _check(lib().maze_sstep_layout(handle, out), "maze_sstep_layout")
+    return dict(basis=out[0], update=out[1])
 
 
 def maze_trace_enable(handle, on: bool = True):

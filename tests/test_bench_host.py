@@ -55,10 +55,11 @@ def test_traffic_needs_matching_source_and_shape(tmp_path, monkeypatch):
     f.write_text(json.dumps(t))
     monkeypatch.setitem(bench.TRAFFIC, "sstep", (str(f), str(src)))
 
-    def fresh(cx, basis_threads=1024):
+    def fresh(cx, basis_threads=1024, layout=0):
         r = bench.roofline("fp32_sweep", prof(10, 1.5, 0.9), G, "fp32",
                            {"ppt": 4, "cx": cx, "nwg": 768,
-                            "basis": {"threads": basis_threads, "ppt": 4, "cx": 16, "nwg": 256}},
+                            "basis": {"threads": basis_threads, "ppt": 4, "cx": 16, "nwg": 256,
+                                      "layout": layout}},
                            sstep=True)
         bench.attach_traffic(r, "fp32", "sstep")
         return r
@@ -69,6 +70,9 @@ def test_traffic_needs_matching_source_and_shape(tmp_path, monkeypatch):
     assert r["traffic"] is None and r["basis_kernel"]["traffic"] == 22
     r = fresh(22, basis_threads=256)  # another basis shape
     assert r["traffic"] == 111 and r["basis_kernel"]["traffic"] is None
+    r = fresh(22, layout=16)  # the same numbers in the wavefront-row layout
+    assert r["traffic"] == 111 and r["basis_kernel"]["traffic"] is None
+    assert r["basis_kernel"]["launch_shape"]["layout"] == 16
     src.write_text("changed kernel source")  # counters taken with other code
     r = fresh(22)
     assert r["traffic"] is None and r["basis_kernel"]["traffic"] is None
