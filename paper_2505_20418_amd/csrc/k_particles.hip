@@ -208,33 +208,62 @@ hipError_t launch_bin(const DeviceState& d, const double* pos, hipStream_t st) {
 // Candidate tiles along one axis whose ions can reach grid tile T. An ion with
 // base cell c touches points c .. c+1 (order 2) or c-1 .. c+2 (order 4), mod
 // N, so the points p of tile T receive from the cells p-1 .. p (order 2) or
-// p-2 .. p+1 (order 4). The candidates are the tiles holding those cells,
-// walked cell by cell: where N leaves a last tile of a single plane, the two
+// p-2 .. p+1 (order 4). Those cells are the tile's own, the one (order 2)
+// or two (order 4) below its first point and, for order 4, the one above
+// its last, each taken mod N: the candidates are the tiles holding these at
+// most four cells. Where N leaves a last tile of a single plane, the two
 // cells below point 0 lie in two different tiles, so neighbouring tile
-// indices alone would miss one of them. At most four tiles.
-constexpr int kMaxCandAxis = 4;
+// indices alone would miss one of them. The set is returned in ascending
+// order, so the summation order is canonical. It depends on N and the order
+// only: a session builds the table of it once (k_cand_table), since each
+// workgroup of the assignment forming it anew, on the scalar unit of every
+// wavefront, cost more than the assignment itself.
 __device__ __forceinline__ int candidate_tiles(int T, int N, int order, int* out) {
-  int n = 0;
-  const int lo = T * kTile - (order == 2 ? 1 : 2);
-  const int hi = min(T * kTile + kTile - 1, N - 1) + (order == 2 ? 0 : 1);
-  for (int c = lo; c <= hi; ++c) {
-    const int w = (c < 0) ? c + N : (c >= N ? c - N : c);
-    const int t = w / kTile;
-    bool dup = false;
-    for (int k = 0; k < n; ++k) dup |= (out[k] == t);
-    if (!dup && n < kMaxCandAxis) out[n++] = t;
+  auto tile_of = [N](int c) {
+    c = (c < 0) ? c + N : (c >= N ? c - N : c);
+    return c / kTile;
+  };
+  const int first = T * kTile, last = min(first + kTile - 1, N - 1);
+  int v0 = T, v1 = tile_of(first - 1), v2 = v1, v3 = v1;  // repeats are dropped below
+  if (order != 2) {
+    v2 = tile_of(first - 2);
+    v3 = tile_of(last + 1);
   }
-  // fixed ascending order so the summation order is canonical
-  for (int a = 1; a < n; ++a) {
-    const int v = out[a];
-    int b = a - 1;
-    while (b >= 0 && out[b] > v) {
-      out[b + 1] = out[b];
-      --b;
-    }
-    out[b + 1] = v;
-  }
+  auto order2 = [](int& a, int& b) {
+    const int lo = min(a, b), hi = max(a, b);
+    a = lo;
+    b = hi;
+  };
+  order2(v0, v1);
+  order2(v2, v3);
+  order2(v0, v2);
+  order2(v1, v3);
+  order2(v1, v2);
+  int n = 1;
+  out[0] = v0;
+  if (v1 != v0) out[n++] = v1;
+  if (v2 != v1) out[n++] = v2;
+  if (v3 != v2) out[n++] = v3;
   return n;
+}
+
+__global__ __launch_bounds__(kThreads) void k_cand_table(int ntx, int N, int order,
+                                                         int32_t* __restrict__ tab) {
+  const int T = blockIdx.x * kThreads + threadIdx.x;
+  if (T >= ntx) return;
+  int out[kMaxCandAxis];
+  const int n = candidate_tiles(T, N, order, out);
+  int32_t* row = tab + (size_t)T * (1 + kMaxCandAxis);
+  row[0] = n;
+#pragma unroll
+  for (int k = 0; k < kMaxCandAxis; ++k) row[1 + k] = (k < n) ? out[k] : 0;
+}
+
+hipError_t launch_cand_table(const DeviceState& d, hipStream_t st) {
+  if (!d.cand || d.ntx < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_cand_table, dim3((d.ntx + kThreads - 1) / kThreads), dim3(kThreads), 0, st,
+                     d.ntx, d.N, d.order, d.cand);
+  return hipGetLastError();
 }
 
 // One workgroup per tile of kTile^3 grid points, two points per thread.
@@ -245,6 +274,7 @@ __device__ __forceinline__ int candidate_tiles(int T, int N, int order, int* out
 // loads of a batch are issued together instead of one ion after another.
 constexpr int kSpreadBatch = 128;
 __global__ __launch_bounds__(kThreads) void k_spread(int N, int ntx, int order,
+                                                     const int32_t* __restrict__ cand,
                                                      const int32_t* __restrict__ tile_start,
                                                      const int32_t* __restrict__ s_cell,
                                                      const double* __restrict__ s_w,
@@ -261,10 +291,10 @@ __global__ __launch_bounds__(kThreads) void k_spread(int N, int ntx, int order,
   if (ctl_ld(&sc->err)) return;
   const int T = blockIdx.x;
   const int TX = T / (ntx * ntx), TY = (T / ntx) % ntx, TZ = T % ntx;
-  int cx[kMaxCandAxis], cy[kMaxCandAxis], cz[kMaxCandAxis];
-  const int nx = candidate_tiles(TX, N, order, cx);
-  const int ny = candidate_tiles(TY, N, order, cy);
-  const int nz = candidate_tiles(TZ, N, order, cz);
+  const int32_t* cx = cand + (size_t)TX * (1 + kMaxCandAxis) + 1;
+  const int32_t* cy = cand + (size_t)TY * (1 + kMaxCandAxis) + 1;
+  const int32_t* cz = cand + (size_t)TZ * (1 + kMaxCandAxis) + 1;
+  const int nx = cx[-1], ny = cy[-1], nz = cz[-1];
   const int ncand = nx * ny * nz;
   const int off = (order == 2) ? 0 : 1;
   const int tid = threadIdx.x;
@@ -339,7 +369,7 @@ __global__ __launch_bounds__(kThreads) void k_spread(int N, int ntx, int order,
 
 hipError_t launch_spread(const DeviceState& d, hipStream_t st) {
   hipLaunchKernelGGL(k_spread, dim3(d.ntiles), dim3(kThreads), 0, st, d.N, d.ntx, d.order,
-                     d.tile_start, d.s_cell, d.s_w, d.s_Q, d.q,
+                     d.cand, d.tile_start, d.s_cell, d.s_w, d.s_Q, d.q,
                      d.part + (size_t)SL_QSUM * d.part_stride, (const Scalars*)d.sc);
   return hipGetLastError();
 }

@@ -765,9 +765,14 @@ __device__ __forceinline__ void sstep_zv_wg(const SweepArgs<T>& a, const SweepGe
   const T c6 = (T)(1.0 / 6.0);
   const T c36 = (T)(1.0 / 36.0);
   const size_t Ps = (size_t)N * N;
-  T pm[V], pc[V], pn[V], po[V];  // p of the row: planes u-1, u, u+1; outer row, plane u+1
-  T rc[V], rm1[V], rm2[V];       // r of the row: planes u, u-1, u-2
-  T bm[V], bc[V];                // B p of the row: planes u-2, u-1
+  // Plane windows of the row, as rings indexed by the step's phase F =
+  // t mod 4 (the march is unrolled four steps deep, so a step renames its
+  // windows instead of moving registers). At phase F, plane u:
+  //   p:    PW[F] plane u-1, PW[F+1] u, PW[F+2] u+1; loads of u+2 to PW[F+3]
+  //   r:    RW[F] plane u-2, RW[F+1] u-1, RW[F+2] u; loads of u+1 to RW[F+3]
+  //   B p:  BW[F] plane u-2, BW[F+1] u-1; stage U writes BW[F+2] (plane u)
+  //   outer p row: OW[F & 1] plane u+1; loads of u+2 to OW[(F+1) & 1]
+  T PW[4][V], RW[4][V], BW[4][V], OW[2][V];
   double acc[kNm];
 #pragma unroll
   for (int i = 0; i < kNm; ++i) acc[i] = 0.0;
@@ -778,27 +783,41 @@ __device__ __forceinline__ void sstep_zv_wg(const SweepArgs<T>& a, const SweepGe
     const auto pa = pl_rsrc(p_in, wrap_pl(ub - dir, N), Ps);
     const auto pb = pl_rsrc(p_in, wrap_pl(ub, N), Ps);
     const auto pd = pl_rsrc(p_in, wrap_pl(ub + dir, N), Ps);
-    ldv<T, V>(r0, bo, (T)1, rc);
-    ldv<T, V>(pa, bo, sp, pm);
-    ldv<T, V>(pb, bo, sp, pc);
-    ldv<T, V>(pd, bo, sp, pn);
-    lds_st<T, V>(P1 + (w + 1) * N + lo, pc);
+    ldv<T, V>(r0, bo, (T)1, RW[2]);
+    ldv<T, V>(pa, bo, sp, PW[0]);
+    ldv<T, V>(pb, bo, sp, PW[1]);
+    ldv<T, V>(pd, bo, sp, PW[2]);
+    lds_st<T, V>(P1 + (w + 1) * N + lo, PW[1]);
     if (has_o) {
       T ob[V];
       ldv<T, V>(pb, boo, sp, ob);
-      ldv<T, V>(pd, boo, sp, po);
+      ldv<T, V>(pd, boo, sp, OW[0]);
       lds_st<T, V>(P1 + orow * N + lo, ob);
     }
 #pragma unroll
-    for (int j = 0; j < V; ++j) rm1[j] = rm2[j] = bm[j] = bc[j] = (T)0;
+    for (int j = 0; j < V; ++j) RW[0][j] = RW[1][j] = BW[0][j] = BW[1][j] = (T)0;
   }
   __syncthreads();
 
   const int nsteps = x1 - x0 + 2;  // stage U on planes x0-1 .. x1, in march order
-  for (int t = 0; t < nsteps; ++t) {
+  auto step = [&](auto phase, const int t) __attribute__((always_inline)) {
+    constexpr int F = decltype(phase)::value;
+    constexpr int F1 = (F + 1) & 3, F2 = (F + 2) & 3, F3 = (F + 3) & 3, tb = F & 1;
+    T(&pm)[V] = PW[F];
+    T(&pc)[V] = PW[F1];
+    T(&pn)[V] = PW[F2];
+    T(&pf)[V] = PW[F3];
+    T(&rm2)[V] = RW[F];
+    T(&rm1)[V] = RW[F1];
+    T(&rc)[V] = RW[F2];
+    T(&rf)[V] = RW[F3];
+    T(&bm)[V] = BW[F];
+    T(&bc)[V] = BW[F1];
+    T(&bk)[V] = BW[F2];
+    T(&po)[V] = OW[tb];
+    T(&pof)[V] = OW[tb ^ 1];
     const int u = ub + dir * t;
     const bool more = t + 1 < nsteps;
-    T pf[V], pof[V], rf[V];
     if (more) {
       const auto rp = pl_rsrc(r_in, wrap_pl(u + dir, N), Ps);
       const auto pp = pl_rsrc(p_in, wrap_pl(u + 2 * dir, N), Ps);
@@ -808,8 +827,6 @@ __device__ __forceinline__ void sstep_zv_wg(const SweepArgs<T>& a, const SweepGe
     }
 
     // stage U at plane u: B p of the row; (B p, r) staged
-    const int tb = t & 1;
-    T bk[V];
     {
       const T* pr = P1 + (tb * (WV + 2) + w) * N + lo;  // row y - 1; y + 1 is 2N further
       T ym[V], yp[V];
@@ -873,25 +890,24 @@ __device__ __forceinline__ void sstep_zv_wg(const SweepArgs<T>& a, const SweepGe
       if (has_o) lds_st<T, V>(pw + orow * N, po);
     }
     __syncthreads();
-
-#pragma unroll
-    for (int j = 0; j < V; ++j) {
-      bm[j] = bc[j];
-      bc[j] = bk[j];
-      rm2[j] = rm1[j];
-      rm1[j] = rc[j];
-    }
-    if (more) {
-#pragma unroll
-      for (int j = 0; j < V; ++j) {
-        rc[j] = rf[j];
-        pm[j] = pc[j];
-        pc[j] = pn[j];
-        pn[j] = pf[j];
-        po[j] = pof[j];
-      }
-    }
+    // keep the scheduler from interleaving consecutive steps, which would
+    // hold two steps' temporaries at once
+    __builtin_amdgcn_sched_barrier(0);
+  };
+  using Ph0 = std::integral_constant<int, 0>;
+  using Ph1 = std::integral_constant<int, 1>;
+  using Ph2 = std::integral_constant<int, 2>;
+  using Ph3 = std::integral_constant<int, 3>;
+  int t = 0;
+  for (; t + 4 <= nsteps; t += 4) {
+    step(Ph0{}, t);
+    step(Ph1{}, t + 1);
+    step(Ph2{}, t + 2);
+    step(Ph3{}, t + 3);
   }
+  if (t < nsteps) step(Ph0{}, t);
+  if (t + 1 < nsteps) step(Ph1{}, t + 1);
+  if (t + 2 < nsteps) step(Ph2{}, t + 2);
 
   double sums[kNs];
 #pragma unroll

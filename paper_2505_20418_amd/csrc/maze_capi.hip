@@ -250,14 +250,15 @@ static Layout layout_for(const maze_config* c, int N, int* ntx_out, int* ntiles_
   L.add(sizeof(double) * n);              // 22 s_Q
   L.add(sizeof(double) * (n + 1));        // 23 md_epart
   L.add(sizeof(double) * kHistCap);       // 24 residual history
+  L.add(sizeof(int32_t) * (size_t)ntx * (1 + kMaxCandAxis));  // 25 spreading candidates
   if (mg) {
     int Ns[kMgMaxLevels];
     const int levels = mg_plan(N, Ns, kMgMaxLevels);
     const size_t es = (c->precision == MAZE_MIXED) ? sizeof(float) : sizeof(double);
     const bool f32 = es == sizeof(float);
-    L.add(f32 ? es * (size_t)G : 0);  // 25 z (FP64 uses the second r buffer)
-    L.add(f32 ? es * (size_t)G : 0);  // 26 rounded level-0 right-hand side
-    L.add(es * (size_t)G);            // 27 level-0 residual
+    L.add(f32 ? es * (size_t)G : 0);  // 26 z (FP64 uses the second r buffer)
+    L.add(f32 ? es * (size_t)G : 0);  // 27 rounded level-0 right-hand side
+    L.add(es * (size_t)G);            // 28 level-0 residual
     for (int l = 1; l < levels; ++l) {
       const size_t gl = (size_t)Ns[l] * Ns[l] * Ns[l];
       L.add(es * gl);  // x_l
@@ -2168,6 +2169,7 @@ int maze_init(const maze_config* cfg, const double* charges_dev, const double* p
   d.md_epart = (double*)at(23);
   d.hist = (double*)at(24);
   d.hist_cap = kHistCap;
+  d.cand = (int32_t*)at(25);
   d.weight_gradient_force = (cfg->flags & MAZE_FLAG_WEIGHT_GRADIENT_FORCE) ? 1 : 0;
   if (mg) {
     MgHierarchy& m = d.mg;
@@ -2179,13 +2181,13 @@ int maze_init(const maze_config* cfg, const double* charges_dev, const double* p
       m.G[l] = (long long)Ns[l] * Ns[l] * Ns[l];
       m.c[l] = std::pow(0.25, l);
     }
-    m.z = m.fp32 ? at(25) : (void*)(d.r + d.G);
-    m.b[0] = m.fp32 ? at(26) : nullptr;
-    m.r[0] = at(27);
+    m.z = m.fp32 ? at(26) : (void*)(d.r + d.G);
+    m.b[0] = m.fp32 ? at(27) : nullptr;
+    m.r[0] = at(28);
     for (int l = 1; l < m.levels; ++l) {
-      m.x[l] = at(28 + 3 * (l - 1));
-      m.b[l] = at(29 + 3 * (l - 1));
-      m.r[l] = at(30 + 3 * (l - 1));
+      m.x[l] = at(29 + 3 * (l - 1));
+      m.b[l] = at(30 + 3 * (l - 1));
+      m.r[l] = at(31 + 3 * (l - 1));
     }
   }
   if (hipHostMalloc((void**)&s->host_sc, 2 * sizeof(Scalars), hipHostMallocDefault) !=
@@ -2230,7 +2232,8 @@ int maze_init(const maze_config* cfg, const double* charges_dev, const double* p
   else s->sbasis = s->sweep;
   if (hipMemsetAsync(base, 0, L.total, stream) != hipSuccess ||
       hipMemcpyAsync(d.Q, charges_dev, sizeof(double) * n, hipMemcpyDeviceToDevice, stream) !=
-          hipSuccess) {
+          hipSuccess ||
+      launch_cand_table(d, stream) != hipSuccess) {
     maze_destroy(s);
     return MAZE_E_DEVICE;
   }

@@ -15,6 +15,7 @@ namespace maze {
 constexpr int kThreads = 256;   // threads per workgroup everywhere
 constexpr int kTile = 8;        // binning / spreading tile edge (grid points)
 constexpr int kMaxOrder = 4;
+constexpr int kMaxCandAxis = 4;  // spreading: candidate tiles per axis of a tile
 
 // Slots of the per-workgroup partial-sum table. Every kernel that reduces
 // writes one double per workgroup into a slot; the consumer sums the slot in
@@ -166,6 +167,10 @@ struct DeviceState {
   int32_t* tile_count = nullptr;  // ntiles
   int32_t* tile_start = nullptr;  // ntiles + 1
   int32_t* tile_cursor = nullptr; // ntiles
+  // ntx * (1 + kMaxCandAxis): for each tile index along an axis, the number
+  // of tiles whose ions reach it, then those tiles in ascending order (a
+  // function of N and the order only, built once)
+  int32_t* cand = nullptr;
   int32_t* ion_cell = nullptr;    // n*3 base cell per axis (input order)
   double* ion_t = nullptr;        // n*3 fractional offsets (input order)
   int32_t* sorted_idx = nullptr;  // n, ion index in tile order
@@ -188,6 +193,8 @@ constexpr int kHistCap = 16384;
 // ---- launch wrappers (each queues work on `st`, returns hipError_t) ----
 hipError_t launch_bin(const DeviceState& d, const double* pos, hipStream_t st);
 hipError_t launch_spread(const DeviceState& d, hipStream_t st);
+// Builds d.cand (once per session, before the first spread).
+hipError_t launch_cand_table(const DeviceState& d, hipStream_t st);
 hipError_t launch_gather(const DeviceState& d, const double* phi, double coulomb_k,
                          double* forces, hipStream_t st);
 
