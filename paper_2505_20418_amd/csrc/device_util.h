@@ -89,4 +89,18 @@ __device__ __forceinline__ void ctl_st(T* p, T v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Whether either of two control words (the done and error flags of a
+// solve) is set, decided once for the whole workgroup: thread 0 reads them
+// and shares the answer through LDS. A solve's leader may set its done flag
+// while other workgroups of the same launch are starting; if each thread
+// read it for itself, part of a workgroup could leave while the rest went
+// on to a workgroup reduction short of the leavers' shares. Every thread of
+// the workgroup must call it (it holds a barrier).
+__device__ __forceinline__ bool wg_flags_set(const int32_t* a, const int32_t* b) {
+  __shared__ int32_t flag;
+  if (threadIdx.x == 0) flag = (ctl_ld(a) != 0 || ctl_ld(b) != 0) ? 1 : 0;
+  __syncthreads();
+  return flag != 0;
+}
+
 }  // namespace maze

@@ -1410,7 +1410,8 @@ static bool forced_zv(const char* e, const DeviceState& d, SweepGeom* out) {
 // Wavefront-row basis candidates of a grid (N = 64, 128 or 256;
 // workgroups of 8 wavefronts).
 static void zv_candidates(const DeviceState& d, bool fp32, std::vector<SweepGeom>* cand) {
-  if (d.N % 64 != 0) return;
+  const char* e = std::getenv("MAZE_ZV");
+  if (d.N % 64 != 0 || (e && std::strcmp(e, "0") == 0)) return;
   int last = -1;
   for (int cx : {6, 8, 10, 12, 16, 20, 24, 32, 48, 64}) {
     const SweepGeom g = make_sstep_zv_geom(d.N, cx, 8);

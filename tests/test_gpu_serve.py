@@ -119,3 +119,29 @@ def test_continuous_served_sessions_equal_alone(gpu):
         if sl.obj is None:
             run.close()
     srv.close()
+
+
+def test_continuous_serving_large_sessions_all_converge(gpu):
+    """Sessions of 64^3 to 192^3 (throughput-mode batched kernels, many
+    workgroups per session) served with steps in flight: every step
+    converges and every session's positions stay finite. A solve's leader
+    sets its done flag while other workgroups of the same launch start, so
+    every workgroup must take one decision for all its threads: a workgroup
+    split by that flag once wrote a finished solve's vectors from partial
+    Gram sums."""
+    from paper_2505_20418_amd import serve
+    specs = [serve.SessionSpec(4 + 2 * (i % 5), 900 + i, i % 2 == 0, 1e-6 if i % 2 == 0 else 1e-10)
+             for i in range(20)]
+    be = serve.GpuBackend()
+    srv = serve.Server(be, specs, 64 << 30, max_batch=32)
+    srv.prefill()
+    reqs = serve.poisson_requests(300, len(specs), rate_hz=2000.0, seed=7)
+    print(f"case: continuous serve {len(specs)} sessions up to 192^3, {len(reqs)} requests",
+          flush=True)
+    rep = srv.serve(reqs)
+    assert rep["requests_completed"] == len(reqs)
+    assert set(rep["statuses"]) <= {0}, rep["statuses"]
+    for sl in srv.slots:
+        if sl.obj is not None:
+            assert torch.isfinite(sl.obj.pos).all()
+    srv.close()
