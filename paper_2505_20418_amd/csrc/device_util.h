@@ -91,16 +91,20 @@ __device__ __forceinline__ void ctl_st(T* p, T v) {
 
 // Whether either of two control words (the done and error flags of a
 // solve) is set, decided once for the whole workgroup: thread 0 reads them
-// and shares the answer through LDS. A solve's leader may set its done flag
+// and shares the answer through a word of the caller's LDS (slot), which
+// is the caller's again on return. A solve's leader may set its done flag
 // while other workgroups of the same launch are starting; if each thread
 // read it for itself, part of a workgroup could leave while the rest went
-// on to a workgroup reduction short of the leavers' shares. Every thread of
-// the workgroup must call it (it holds a barrier).
-__device__ __forceinline__ bool wg_flags_set(const int32_t* a, const int32_t* b) {
-  __shared__ int32_t flag;
-  if (threadIdx.x == 0) flag = (ctl_ld(a) != 0 || ctl_ld(b) != 0) ? 1 : 0;
+// on to a workgroup reduction short of the leavers' shares. The slot is
+// borrowed rather than declared: a static LDS word would raise a kernel's
+// LDS just past what lets four 256-thread workgroups share a CU. Every
+// thread of the workgroup must call it (it holds two barriers).
+__device__ __forceinline__ bool wg_flags_set(const int32_t* a, const int32_t* b, int32_t* slot) {
+  if (threadIdx.x == 0) *slot = (ctl_ld(a) != 0 || ctl_ld(b) != 0) ? 1 : 0;
   __syncthreads();
-  return flag != 0;
+  const bool set = *slot != 0;
+  __syncthreads();
+  return set;
 }
 
 }  // namespace maze

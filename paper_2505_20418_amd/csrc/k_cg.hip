@@ -159,7 +159,7 @@ template <typename T, bool FIRST, int PPT, int NH>
 __device__ __forceinline__ void sweep_wg(const SweepArgs<T>& a, const SweepGeom& g, int par,
                                          int L, unsigned char* smem_raw, double* red) {
   Scalars* sc = a.sc;
-  if (wg_flags_set(&sc->done, &sc->err)) return;
+  if (wg_flags_set(&sc->done, &sc->err, reinterpret_cast<int32_t*>(red))) return;
   const int tid = threadIdx.x;
   const bool leader = (L == 0) && (tid == 0);
   // buffers by parity, selected rather than indexed (an indexed copy of the

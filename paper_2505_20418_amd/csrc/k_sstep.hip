@@ -283,7 +283,7 @@ __device__ __forceinline__ void sstep_wg(const SweepArgs<T>& a, const SweepGeom&
   // workgroup needs no LDS beyond its plane buffers
   double* red = reinterpret_cast<double*>(smem_raw);
   Scalars* sc = a.sc;
-  if (wg_flags_set(&sc->done, &sc->err)) return;
+  if (wg_flags_set(&sc->done, &sc->err, reinterpret_cast<int32_t*>(smem_raw))) return;
   const int tid = threadIdx.x;
   const bool leader = (L == 0) && (tid == 0);
   const T* r_in = par ? a.r[1] : a.r[0];
@@ -724,7 +724,7 @@ __device__ __forceinline__ void sstep_zv_wg(const SweepArgs<T>& a, const SweepGe
   constexpr int N = 64 * V, NT = 64 * WV, WO = WV - 2;
   double* red = reinterpret_cast<double*>(smem_raw);
   Scalars* sc = a.sc;
-  if (wg_flags_set(&sc->done, &sc->err)) return;
+  if (wg_flags_set(&sc->done, &sc->err, reinterpret_cast<int32_t*>(smem_raw))) return;
   const int tid = threadIdx.x;
   const bool leader = (L == 0) && (tid == 0);
   const T* r_in = par ? a.r[1] : a.r[0];
