@@ -430,11 +430,24 @@ def host_description():
     (a = b + s c over 3 x 800 MB; 24 bytes per element) as the oracle's own
     bandwidth roofline."""
     model = None
+    ident = {}
+    keys = {"vendor_id": "vendor", "cpu family": "family", "model": "model_number",
+            "stepping": "stepping", "cpu MHz": "mhz", "cache size": "cache"}
     try:
         for line in open("/proc/cpuinfo"):
-            if line.startswith("model name"):
-                model = line.split(":", 1)[1].strip()
-                break
+            if ":" not in line:
+                if ident:
+                    break  # the first processor's block is enough
+                continue
+            k, v = (x.strip() for x in line.split(":", 1))
+            if k == "model name" and model is None:
+                model = v
+            elif k in keys and keys[k] not in ident:
+                ident[keys[k]] = v
+            elif k == "flags" and "vector_isa" not in ident:
+                have = set(v.split())
+                ident["vector_isa"] = [f for f in ("avx2", "fma", "avx512f", "avx512_bf16")
+                                       if f in have]
     except OSError:
         pass
     n = 100_000_000
@@ -449,7 +462,9 @@ def host_description():
         dt = time.perf_counter() - t0
         best = dt if best is None else min(best, dt)
     # multiply reads c, writes a; add reads a and b, writes a: 40 B/element
-    return {"cpu_model": model, "host_threads": os.cpu_count(),
+    # the model name is what the host reports (virtual machines often give
+    # a generic one); the identification fields below pin it down further
+    return {"cpu_model": model, "cpu_id": ident, "host_threads": os.cpu_count(),
             "host_triad_GBps": round(40.0 * n / best / 1e9, 1)}
 
 
