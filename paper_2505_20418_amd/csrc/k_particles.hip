@@ -266,12 +266,15 @@ hipError_t launch_cand_table(const DeviceState& d, hipStream_t st) {
   return hipGetLastError();
 }
 
-// One workgroup per tile of kTile^3 grid points, two points per thread.
-// The ions of the candidate tiles are read cooperatively into LDS in
-// batches, in the canonical order (candidate tiles in (x, y, z) order, ions
-// in tile order), and every thread then sums their weights at its points
-// in that order: the result is independent of scheduling, and the global
-// loads of a batch are issued together instead of one ion after another.
+// One workgroup per tile of kTile^3 grid points. The ions of the candidate
+// tiles are read cooperatively into LDS in batches, in the canonical order
+// (candidate tiles in (x, y, z) order, ions in tile order). The first
+// wavefront then takes them one at a time, a lane for each of the ion's
+// order^3 support points, and adds the weights that land in this tile to an
+// LDS copy of it: every point sums its contributions in that order, so the
+// result is independent of scheduling (a wavefront's LDS accesses complete
+// in order, and one ion's points are distinct since N >= 4 >= order). Each
+// (ion, point) pair costs one lane, not one test per point per ion.
 constexpr int kSpreadBatch = 128;
 __global__ __launch_bounds__(kThreads) void k_spread(int N, int ntx, int order,
                                                      const int32_t* __restrict__ cand,
@@ -284,10 +287,12 @@ __global__ __launch_bounds__(kThreads) void k_spread(int N, int ntx, int order,
 #pragma clang fp contract(off)
   __shared__ double red[8];
   constexpr int kMaxCand = kMaxCandAxis * kMaxCandAxis * kMaxCandAxis;
+  constexpr int kTilePts = kTile * kTile * kTile;
   __shared__ int32_t cstart[kMaxCand], cpre[kMaxCand + 1];
   __shared__ double lQ[kSpreadBatch];
   __shared__ int32_t lcell[kSpreadBatch * 3];
   __shared__ double lw[kSpreadBatch * 3 * kMaxOrder];
+  __shared__ double lq[kTilePts];
   if (ctl_ld(&sc->err)) return;
   const int T = blockIdx.x;
   const int TX = T / (ntx * ntx), TY = (T / ntx) % ntx, TZ = T % ntx;
@@ -304,6 +309,8 @@ __global__ __launch_bounds__(kThreads) void k_spread(int N, int ntx, int order,
     cstart[tid] = tile_start[ct];
     cpre[tid + 1] = tile_start[ct + 1] - tile_start[ct];
   }
+#pragma unroll
+  for (int j = 0; j < kTilePts / kThreads; ++j) lq[tid + j * kThreads] = 0.0;
   __syncthreads();
   if (tid == 0) {
     cpre[0] = 0;
@@ -312,17 +319,11 @@ __global__ __launch_bounds__(kThreads) void k_spread(int N, int ntx, int order,
   __syncthreads();
   const int total = cpre[ncand];
 
-  int gp[2][3];
-  bool valid[2];
-  double acc[2] = {0.0, 0.0};
-#pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    const int pt = tid + j * kThreads;
-    gp[j][0] = TX * kTile + (pt >> 6);
-    gp[j][1] = TY * kTile + ((pt >> 3) & 7);
-    gp[j][2] = TZ * kTile + (pt & 7);
-    valid[j] = gp[j][0] < N && gp[j][1] < N && gp[j][2] < N;
-  }
+  // lane l of the first wavefront: support offset (dx, dy, dz) of an ion
+  const int o2 = order * order;
+  const bool lane_on = tid < o2 * order;
+  const int dx = tid / o2, dy = (tid / order) % order, dz = tid % order;
+  const int t0x = TX * kTile, t0y = TY * kTile, t0z = TZ * kTile;
   for (int base = 0; base < total; base += kSpreadBatch) {
     const int m = min(kSpreadBatch, total - base);
     if (tid < m) {
@@ -336,33 +337,38 @@ __global__ __launch_bounds__(kThreads) void k_spread(int N, int ntx, int order,
       for (int e = 0; e < 3 * order; ++e) lw[tid * 3 * kMaxOrder + e] = s_w[(size_t)3 * s * order + e];
     }
     __syncthreads();
-    for (int i = 0; i < m; ++i) {
-      const double Qs = lQ[i];
-      const int bx = lcell[3 * i] - off, by = lcell[3 * i + 1] - off, bz = lcell[3 * i + 2] - off;
-      const double* w = lw + i * 3 * kMaxOrder;
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        int dx = gp[j][0] - bx, dy = gp[j][1] - by, dz = gp[j][2] - bz;
-        dx = (dx < 0) ? dx + N : (dx >= N ? dx - N : dx);
-        dy = (dy < 0) ? dy + N : (dy >= N ? dy - N : dy);
-        dz = (dz < 0) ? dz + N : (dz >= N ? dz - N : dz);
-        if (dx < order && dy < order && dz < order) {
-          double v = Qs * w[dx];
+    if (lane_on) {
+      for (int i = 0; i < m; ++i) {
+        int px = lcell[3 * i] - off + dx, py = lcell[3 * i + 1] - off + dy,
+            pz = lcell[3 * i + 2] - off + dz;
+        px = (px < 0) ? px + N : (px >= N ? px - N : px);
+        py = (py < 0) ? py + N : (py >= N ? py - N : py);
+        pz = (pz < 0) ? pz + N : (pz >= N ? pz - N : pz);
+        const int lx = px - t0x, ly = py - t0y, lz = pz - t0z;
+        if ((unsigned)lx < (unsigned)kTile && (unsigned)ly < (unsigned)kTile &&
+            (unsigned)lz < (unsigned)kTile) {
+          const double* w = lw + i * 3 * kMaxOrder;
+          double v = lQ[i] * w[dx];
           v = v * w[order + dy];
           v = v * w[2 * order + dz];
-          acc[j] += v;
+          const int li = (lx * kTile + ly) * kTile + lz;
+          lq[li] = lq[li] + v;
         }
       }
     }
-    __syncthreads();  // the batch buffers are refilled next
+    __syncthreads();  // the batch buffers are refilled next; the tile is complete
   }
   double local = 0.0;
 #pragma unroll
-  for (int j = 0; j < 2; ++j)
-    if (valid[j]) {
-      q[((long long)gp[j][0] * N + gp[j][1]) * N + gp[j][2]] = acc[j];
-      local += acc[j];
+  for (int j = 0; j < kTilePts / kThreads; ++j) {
+    const int pt = tid + j * kThreads;
+    const int gx = t0x + (pt >> 6), gy = t0y + ((pt >> 3) & 7), gz = t0z + (pt & 7);
+    if (gx < N && gy < N && gz < N) {
+      const double v = lq[pt];
+      q[((long long)gx * N + gy) * N + gz] = v;
+      local += v;
     }
+  }
   const double tot = block_sum(local, red);
   if (tid == 0) part[T] = tot;
 }
