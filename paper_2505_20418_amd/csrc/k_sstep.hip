@@ -84,6 +84,19 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t pl_rsrc(const T* g, int p, siz
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(base), 0, (int)(Ps * sizeof(T)),
                                            0x00020000);
 }
+// As pl_rsrc, with no records unless `on` (uniform): loads through it return
+// zero without a memory access. A wavefront that issues the same loads on
+// every path keeps the compiler's waits for earlier loads from covering
+// later ones.
+template <typename T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t pl_rsrc_if(const T* g, int p, size_t Ps, bool on) {
+  const T* base = g + (size_t)__builtin_amdgcn_readfirstlane(p) * Ps;
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(base), 0, on ? (int)(Ps * sizeof(T)) : 0,
+                                           0x00020000);
+}
+// A byte offset past the records of every plane resource: a buffer store
+// there is dropped.
+constexpr uint32_t kDropOffset = 0x80000000u;
 template <typename T>
 __device__ __forceinline__ T ld(__amdgpu_buffer_rsrc_t r, uint32_t boff) {
   if constexpr (sizeof(T) == 4)
@@ -429,6 +442,11 @@ __device__ __forceinline__ void sstep_wg(const SweepArgs<T>& a, const SweepGeom&
   __builtin_amdgcn_s_waitcnt(0);
 
   const int nsteps = x1 - x0 + 2;  // stage U on planes x0-1 .. x1, in march order
+  // Uniform memory operations: loads and stores issued alike at every step.
+  // Measured per 256^3 launch: the FP32 update kernel 80.8 -> 77.5 us; the
+  // FP64 update kernel, which then forms stage W on two more planes, 140.2
+  // -> 142.2 us, so it keeps the conditional form.
+  constexpr bool kUniformVm = !UPDATE || sizeof(T) == 4;
   // The compiler does not unroll a loop with a barrier and a run-time trip
   // count, so the plane windows rotate by register moves (about 20 per
   // step); the kernels are not bound by their vector ALU work.
@@ -436,11 +454,13 @@ __device__ __forceinline__ void sstep_wg(const SweepArgs<T>& a, const SweepGeom&
     const int u = ub + dir * t;
     const bool more = t + 1 < nsteps;
     const bool own_u = (u >= x0) && (u < x1);
-    // issue the loads of the next step
+    // issue the loads of the next step. With kUniformVm every step issues the
+    // same loads (those with nothing to fetch read zeros), so that waiting
+    // for them never waits for the stores of stage W issued after them.
     T pf[NU], pof[NH], rf[NU], xf[PPT];
-    if (more) {
-      const auto rp = pl_rsrc(r_in, wrap_pl(u + dir, N), Ps);
-      const auto pp = pl_rsrc(p_in, wrap_pl(u + 2 * dir, N), Ps);
+    if (kUniformVm || more) {
+      const auto rp = pl_rsrc_if(r_in, wrap_pl(u + dir, N), Ps, more);
+      const auto pp = pl_rsrc_if(p_in, wrap_pl(u + 2 * dir, N), Ps, more);
 #pragma unroll
       for (int i = 0; i < NU; ++i) {
         rf[i] = ld<T>(rp, bo[i]);
@@ -448,8 +468,9 @@ __device__ __forceinline__ void sstep_wg(const SweepArgs<T>& a, const SweepGeom&
       }
 #pragma unroll
       for (int k = 0; k < NH; ++k) pof[k] = sp * ld<T>(pp, boo[k]);
-      if (UPDATE && !(FIRST && a.zero_x) && own_u) {
-        const auto xp = pl_rsrc((const T*)a.x, u, Ps);
+      const bool xon = !(FIRST && a.zero_x) && own_u;
+      if (UPDATE && (kUniformVm || xon)) {
+        const auto xp = pl_rsrc_if((const T*)a.x, wrap_pl(u, N), Ps, more && xon);
 #pragma unroll
         for (int j = 0; j < PPT; ++j) xf[j] = ld<T>(xp, bo[j]);
       }
@@ -475,13 +496,17 @@ __device__ __forceinline__ void sstep_wg(const SweepArgs<T>& a, const SweepGeom&
       if (i < PPT) bk[i] = bp;
     }
 
-    // stage W at plane u-dir: B^2 p and B rhat on the segment
-    if (t >= 2) {
+    // stage W at plane u-dir: B^2 p and B rhat on the segment, stored from
+    // the third step on (plane u-dir then lies in [x0, x1)). With kUniformVm
+    // the update kernel forms it at every step and its stores before the
+    // third write nothing, so every step issues the same stores.
+    if ((UPDATE && kUniformVm) || t >= 2) {
       const T2* QRr = QR + (tb ^ 1) * E2;
-      // plane u-dir lies in [x0, x1) here
-      const auto xo = pl_rsrc((const T*)a.x, u - dir, Ps);
-      const auto ro = pl_rsrc((const T*)r_out, u - dir, Ps);
-      const auto po = pl_rsrc((const T*)p_out, u - dir, Ps);
+      const bool wr = t >= 2;
+      const int uo = wrap_pl(u - dir, N);
+      const auto xo = pl_rsrc_if((const T*)a.x, uo, Ps, wr);
+      const auto ro = pl_rsrc_if((const T*)r_out, uo, Ps, wr);
+      const auto po = pl_rsrc_if((const T*)p_out, uo, Ps, wr);
 #pragma unroll
       for (int j = 0; j < PPT; ++j) {
         const T y0 = pm[j];
@@ -521,13 +546,16 @@ __device__ __forceinline__ void sstep_wg(const SweepArgs<T>& a, const SweepGeom&
             acc[11] += d4 * d4;
             acc[kNm] = fmax(acc[kNm], fabs((double)rm1[j]));
           }
-        } else if (cval[j]) {
+        } else if (kUniformVm || cval[j]) {
           const T xn = xc[j] + ((cx[0] * y0 + cx[1] * y1) + (cx[2] * y2 + cx[3] * y3) + cx[4] * y4);
           const T rn = (cr[0] * y0 + cr[1] * y1) + (cr[2] * y2 + cr[3] * y3) + cr[4] * y4;
           const T pnw = (cp[0] * y0 + cp[1] * y1) + (cp[2] * y2 + cp[3] * y3) + cp[4] * y4;
-          st<T>(xo, bo[j], xn);
-          st<T>(ro, bo[j], rn);
-          st<T>(po, bo[j], pnw);
+          // a lane past the end of the grid stores out of the buffer's
+          // range, which drops it: no branch around the stores
+          const uint32_t so = cval[j] ? bo[j] : kDropOffset;
+          st<T>(xo, so, xn);
+          st<T>(ro, so, rn);
+          st<T>(po, so, pnw);
         }
       }
     }
@@ -564,7 +592,8 @@ __device__ __forceinline__ void sstep_wg(const SweepArgs<T>& a, const SweepGeom&
       for (int k = 0; k < NH; ++k) pon[k] = pof[k];
       if (UPDATE) {
 #pragma unroll
-        for (int j = 0; j < PPT; ++j) xc[j] = ((FIRST && a.zero_x) || !own_u) ? (T)0 : xf[j];
+        for (int j = 0; j < PPT; ++j)
+          xc[j] = (kUniformVm || !((FIRST && a.zero_x) || !own_u)) ? xf[j] : (T)0;
       }
     }
   }
@@ -783,17 +812,18 @@ __device__ __forceinline__ void sstep_zv_wg(const SweepArgs<T>& a, const SweepGe
     const auto pa = pl_rsrc(p_in, wrap_pl(ub - dir, N), Ps);
     const auto pb = pl_rsrc(p_in, wrap_pl(ub, N), Ps);
     const auto pd = pl_rsrc(p_in, wrap_pl(ub + dir, N), Ps);
+    // the outer rows of a wavefront that stages none fetch nothing
+    const auto qb = pl_rsrc_if(p_in, wrap_pl(ub, N), Ps, has_o);
+    const auto qd = pl_rsrc_if(p_in, wrap_pl(ub + dir, N), Ps, has_o);
+    T ob[V];
     ldv<T, V>(r0, bo, (T)1, RW[2]);
     ldv<T, V>(pa, bo, sp, PW[0]);
     ldv<T, V>(pb, bo, sp, PW[1]);
     ldv<T, V>(pd, bo, sp, PW[2]);
+    ldv<T, V>(qb, boo, sp, ob);
+    ldv<T, V>(qd, boo, sp, OW[0]);
     lds_st<T, V>(P1 + (w + 1) * N + lo, PW[1]);
-    if (has_o) {
-      T ob[V];
-      ldv<T, V>(pb, boo, sp, ob);
-      ldv<T, V>(pd, boo, sp, OW[0]);
-      lds_st<T, V>(P1 + orow * N + lo, ob);
-    }
+    if (has_o) lds_st<T, V>(P1 + orow * N + lo, ob);
 #pragma unroll
     for (int j = 0; j < V; ++j) RW[0][j] = RW[1][j] = BW[0][j] = BW[1][j] = (T)0;
   }
@@ -818,20 +848,35 @@ __device__ __forceinline__ void sstep_zv_wg(const SweepArgs<T>& a, const SweepGe
     T(&pof)[V] = OW[tb ^ 1];
     const int u = ub + dir * t;
     const bool more = t + 1 < nsteps;
-    if (more) {
-      const auto rp = pl_rsrc(r_in, wrap_pl(u + dir, N), Ps);
-      const auto pp = pl_rsrc(p_in, wrap_pl(u + 2 * dir, N), Ps);
+    {
+      // the same three loads on every path: the last step's, and the outer
+      // row's of a wavefront that stages none, fetch nothing
+      const auto rp = pl_rsrc_if(r_in, wrap_pl(u + dir, N), Ps, more);
+      const auto pp = pl_rsrc_if(p_in, wrap_pl(u + 2 * dir, N), Ps, more);
+      const auto pq = pl_rsrc_if(p_in, wrap_pl(u + 2 * dir, N), Ps, more && has_o);
       ldv<T, V>(rp, bo, (T)1, rf);
       ldv<T, V>(pp, bo, sp, pf);
-      if (has_o) ldv<T, V>(pp, boo, sp, pof);
+      ldv<T, V>(pq, boo, sp, pof);
+    }
+
+    // LDS reads of both stages, issued together so that the reads of
+    // stage W are in flight while stage U computes (a wavefront outside the
+    // segment reads the rows of its nearest segment row and ignores them)
+    T ym[V], yp[V], bym[V], byp[V], sym[V], syp[V];
+    {
+      const T* pr = P1 + (tb * (WV + 2) + w) * N + lo;  // row y - 1; y + 1 is 2N further
+      lds_ld<T, V>(pr, ym);
+      lds_ld<T, V>(pr + 2 * N, yp);
+      const int wc = min(max(w, 1), WO);
+      const int q = ((tb ^ 1) * WV + wc - 1) * N + lo;  // row y - 1; y + 1 is 2N further
+      lds_ld<T, V>(QB + q, bym);
+      lds_ld<T, V>(QB + q + 2 * N, byp);
+      lds_ld<T, V>(QS + q, sym);
+      lds_ld<T, V>(QS + q + 2 * N, syp);
     }
 
     // stage U at plane u: B p of the row; (B p, r) staged
     {
-      const T* pr = P1 + (tb * (WV + 2) + w) * N + lo;  // row y - 1; y + 1 is 2N further
-      T ym[V], yp[V];
-      lds_ld<T, V>(pr, ym);
-      lds_ld<T, V>(pr + 2 * N, yp);
       const T zl = from_lane_before(pc[V - 1]), zr = from_lane_after(pc[0]);
 #pragma unroll
       for (int i = 0; i < V; ++i) {
@@ -846,12 +891,6 @@ __device__ __forceinline__ void sstep_zv_wg(const SweepArgs<T>& a, const SweepGe
     // stage W at plane u-dir: B^2 p, B rhat and the Gram sums on the rows of
     // the segment
     if (t >= 2 && outw) {
-      const int q = ((tb ^ 1) * WV + w - 1) * N + lo;  // row y - 1; y + 1 is 2N further
-      T bym[V], byp[V], sym[V], syp[V];
-      lds_ld<T, V>(QB + q, bym);
-      lds_ld<T, V>(QB + q + 2 * N, byp);
-      lds_ld<T, V>(QS + q, sym);
-      lds_ld<T, V>(QS + q + 2 * N, syp);
       const T bl = from_lane_before(bc[V - 1]), br = from_lane_after(bc[0]);
       const T sl = from_lane_before(rm1[V - 1]), sr = from_lane_after(rm1[0]);
 #pragma unroll
