@@ -1408,12 +1408,28 @@ static bool forced_zv(const char* e, const DeviceState& d, SweepGeom* out) {
 }
 
 // Wavefront-row basis candidates of a grid (N = 64, 128 or 256;
-// workgroups of 8 wavefronts).
-static void zv_candidates(const DeviceState& d, bool fp32, std::vector<SweepGeom>* cand) {
+// workgroups of 8 wavefronts): a list of x runs, and the shortest runs
+// whose grid fits the device's CUs in one round at one and at two
+// workgroups per CU (FP64 kernels hold one per CU, FP32 kernels two; at
+// 256^3 that is x runs of 52 and 24 planes).
+static void zv_candidates(const DeviceState& d, bool fp32, int device,
+                          std::vector<SweepGeom>* cand) {
   const char* e = std::getenv("MAZE_ZV");
   if (d.N % 64 != 0 || (e && std::strcmp(e, "0") == 0)) return;
+  std::vector<int> cxs{6, 8, 10, 12, 16, 20, 24, 32, 48, 64};
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) {
+    (void)hipGetLastError();
+    cus = 0;
+  }
+  const int nseg = make_sstep_zv_geom(d.N, 1, 8).nseg;
+  for (int k : {1, 2}) {
+    const int nch = (k * cus) / nseg;
+    if (nch >= 1) cxs.push_back((d.N + nch - 1) / nch);
+  }
+  std::sort(cxs.begin(), cxs.end());
   int last = -1;
-  for (int cx : {6, 8, 10, 12, 16, 20, 24, 32, 48, 64}) {
+  for (int cx : cxs) {
     const SweepGeom g = make_sstep_zv_geom(d.N, cx, 8);
     if (g.nchunk == last || !sstep_basis_shape_ok(g, fp32) || g.nwg > d.part_stride) continue;
     last = g.nchunk;
@@ -1458,7 +1474,7 @@ static SweepGeom tune_basis(maze_session* s, const SweepGeom& upd) {
         cand.push_back(g);
       }
     }
-  zv_candidates(d, fp32, &cand);
+  zv_candidates(d, fp32, s->device, &cand);
   if (cand.size() <= 1) return def;
   hipStream_t st = s->stream;
   void* r0 = fp32 ? (void*)d.r32 : (void*)d.r;
