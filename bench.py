@@ -67,11 +67,11 @@ def source_hash(path) -> str:
 # run times the shapes the committed counter summaries were taken in: the
 # fastest shapes in whole-MD-step timings of the tuner's candidates, which
 # the tuner's own short timings do not rank reliably between boxes. Basis
-# kernel, FP32: zv:8:24 42.8 us, zv:8:52 49.0 us; FP64: zv:8:52 71.5 us,
-# zv:8:64 83.0 us, 512:2:64 86.5 us. Update kernel, FP32: 512:4:32 77.8 us,
-# 512:4:16 82.7 us, 512:2:32 86.4 us.
+# kernel, FP32: zv:16:20 41.7 us, zv:8:24 42.8 us, zv:16:22 43.8 us, zv:8:52
+# 49.0 us; FP64: zv:8:52 71.5 us, zv:8:64 83.0 us, 512:2:64 86.5 us. Update
+# kernel, FP32: 512:4:32 77.8 us, 512:4:16 82.7 us, 512:2:32 86.4 us.
 PINNED_SHAPES = {
-    ("nacl32768_g256", "fp32"): {"MAZE_BASIS_SHAPE": "zv:8:24", "MAZE_UPDATE_SHAPE": "512:4:32"},
+    ("nacl32768_g256", "fp32"): {"MAZE_BASIS_SHAPE": "zv:16:20", "MAZE_UPDATE_SHAPE": "512:4:32"},
     ("nacl32768_g256", "fp64"): {"MAZE_BASIS_SHAPE": "zv:8:52", "MAZE_UPDATE_SHAPE": "512:4:32"},
 }
 # and of the one-iteration sweep (points per thread:x planes)

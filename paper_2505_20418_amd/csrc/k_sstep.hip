@@ -1050,6 +1050,16 @@ hipError_t ensure_lds(const void* fn, size_t lds, size_t* allowed) {
   return e;
 }
 
+// Wavefront-row classes with an instantiation: basis kernels only (the
+// update kernels stream at the copy rate in the segment layouts), N = 64,
+// 128 or 256 (V = 1, 2, 4 points per lane), workgroups of 8 wavefronts;
+// at N = 256 in FP32 also of 16 (14 rows per segment, one workgroup per CU:
+// fewer halo rows per row than two workgroups of 8; in FP64 its LDS does
+// not fit).
+constexpr bool zv_class_ok(int v, int wv, bool fp32) {
+  return ((v == 1 || v == 2 || v == 4) && wv == 8) || (fp32 && v == 4 && wv == 16);
+}
+
 // One session: args and geometry on the host.
 template <typename T, bool FIRST, bool UPDATE>
 struct SingleLaunch {
@@ -1070,14 +1080,18 @@ struct SingleLaunch {
   }
   template <int V, int WV>
   hipError_t run_zv() const {
-    static size_t allowed = 0;
-    const size_t lds = sstep_lds_bytes(g, sizeof(T) == 4);
-    const hipError_t e =
-        ensure_lds((const void*)k_sstep_zv<T, FIRST, V, WV>, lds, &allowed);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_sstep_zv<T, FIRST, V, WV>), dim3(g.nwg), dim3(64 * WV), lds, st,
-                       a, g, par);
-    return hipGetLastError();
+    if constexpr (!zv_class_ok(V, WV, sizeof(T) == 4)) {
+      return hipErrorInvalidValue;
+    } else {
+      static size_t allowed = 0;
+      const size_t lds = sstep_lds_bytes(g, sizeof(T) == 4);
+      const hipError_t e =
+          ensure_lds((const void*)k_sstep_zv<T, FIRST, V, WV>, lds, &allowed);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL((k_sstep_zv<T, FIRST, V, WV>), dim3(g.nwg), dim3(64 * WV), lds, st,
+                         a, g, par);
+      return hipGetLastError();
+    }
   }
 };
 
@@ -1099,21 +1113,21 @@ struct BatchLaunch {
   }
   template <int V, int WV>
   hipError_t run_zv() const {
-    static size_t allowed = 0;
-    const hipError_t e =
-        ensure_lds((const void*)k_sstep_zv_batch<T, FIRST, V, WV>, L.lds, &allowed);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_sstep_zv_batch<T, FIRST, V, WV>), dim3(L.nwg_total),
-                       dim3(64 * WV), L.lds, st, static_cast<const SweepArgs<T>*>(L.args),
-                       L.geoms, L.wg_begin, L.count, L.par);
-    return hipGetLastError();
+    if constexpr (!zv_class_ok(V, WV, sizeof(T) == 4)) {
+      return hipErrorInvalidValue;
+    } else {
+      static size_t allowed = 0;
+      const hipError_t e =
+          ensure_lds((const void*)k_sstep_zv_batch<T, FIRST, V, WV>, L.lds, &allowed);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL((k_sstep_zv_batch<T, FIRST, V, WV>), dim3(L.nwg_total),
+                         dim3(64 * WV), L.lds, st, static_cast<const SweepArgs<T>*>(L.args),
+                         L.geoms, L.wg_begin, L.count, L.par);
+      return hipGetLastError();
+    }
   }
 };
 
-// Wavefront-row classes with an instantiation: basis kernels only (the
-// update kernels stream at the copy rate in the segment layouts), N = 64,
-// 128 or 256 (V = 1, 2, 4 points per lane), workgroups of 8 wavefronts.
-constexpr bool zv_class_ok(int v, int wv) { return (v == 1 || v == 2 || v == 4) && wv == 8; }
 
 template <bool UPDATE, class F>
 hipError_t sstep_zv_dispatch(int v, int wv, const F& f) {
@@ -1124,6 +1138,7 @@ hipError_t sstep_zv_dispatch(int v, int wv, const F& f) {
       case 108: return f.template run_zv<1, 8>();
       case 208: return f.template run_zv<2, 8>();
       case 408: return f.template run_zv<4, 8>();
+      case 416: return f.template run_zv<4, 16>();
       default: return hipErrorInvalidValue;
     }
   }
@@ -1244,7 +1259,7 @@ hipError_t launch_sstep_batch(const SweepLaunch& L, int nt, bool rows, bool fp32
 
 // Wavefront-row shapes with an instantiation whose LDS fits.
 static bool sstep_zv_shape_ok(const SweepGeom& g, bool fp32) {
-  return g.N == 64 * g.ppt && zv_class_ok(g.ppt, g.zv) && g.zv - 2 <= g.N &&
+  return g.N == 64 * g.ppt && zv_class_ok(g.ppt, g.zv, fp32) && g.zv - 2 <= g.N &&
          sstep_lds_bytes(g, fp32) <= 160 * 1024 - 2048;
 }
 

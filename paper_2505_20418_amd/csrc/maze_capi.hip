@@ -1407,11 +1407,12 @@ static bool forced_zv(const char* e, const DeviceState& d, SweepGeom* out) {
   return true;
 }
 
-// Wavefront-row basis candidates of a grid (N = 64, 128 or 256;
-// workgroups of 8 wavefronts): a list of x runs, and the shortest runs
-// whose grid fits the device's CUs in one round at one and at two
-// workgroups per CU (FP64 kernels hold one per CU, FP32 kernels two; at
-// 256^3 that is x runs of 52 and 24 planes).
+// Wavefront-row basis candidates of a grid (N = 64, 128 or 256): with
+// workgroups of 8 wavefronts, a list of x runs and the shortest runs whose
+// grid fits the device's CUs in one round at one and at two workgroups per
+// CU (FP64 kernels hold one per CU, FP32 kernels two; at 256^3 x runs of 52
+// and 24 planes); with workgroups of 16 (FP32, 256^3), the shortest
+// one-round run at one per CU (20 planes).
 static void zv_candidates(const DeviceState& d, bool fp32, int device,
                           std::vector<SweepGeom>* cand) {
   const char* e = std::getenv("MAZE_ZV");
@@ -1434,6 +1435,12 @@ static void zv_candidates(const DeviceState& d, bool fp32, int device,
     if (g.nchunk == last || !sstep_basis_shape_ok(g, fp32) || g.nwg > d.part_stride) continue;
     last = g.nchunk;
     cand->push_back(g);
+  }
+  const int nseg16 = make_sstep_zv_geom(d.N, 1, 16).nseg;
+  if (cus >= nseg16) {
+    const int nch = cus / nseg16;
+    const SweepGeom g = make_sstep_zv_geom(d.N, (d.N + nch - 1) / nch, 16);
+    if (sstep_basis_shape_ok(g, fp32) && g.nwg <= d.part_stride) cand->push_back(g);
   }
 }
 

@@ -145,8 +145,8 @@ def test_zv_fixed_iteration_count(maze, monkeypatch, max_iter):
     o.close()
 
 
-@pytest.mark.parametrize("precision", [0, 1])
-def test_zv_full_size_256(maze, monkeypatch, precision):
+@pytest.mark.parametrize("precision,shape", [(0, "zv:8:24"), (1, "zv:8:24"), (1, "zv:16:20")])
+def test_zv_full_size_256(maze, monkeypatch, precision, shape):
     """32768 ions on 256^3, the basis kernel in the wavefront-row layout
     against the segment layout (the same update shape): the same iterates up
     to the rounding order of the Gram sums, and the field meets the discrete
@@ -154,10 +154,10 @@ def test_zv_full_size_256(maze, monkeypatch, precision):
     s = inputs.molten_nacl(16, seed=3)
     tol = 1e-9 if precision == 0 else 1e-8
     kw = dict(tol=tol, precision=precision, coulomb_k=inputs.COULOMB_K_EV_A, flags=SSTEP)
-    print(f"case: zv nacl32768 256^3 precision {precision}", flush=True)
-    force_shapes(monkeypatch, "zv:8:24", "512:4:32")
+    print(f"case: zv nacl32768 256^3 precision {precision} {shape}", flush=True)
+    force_shapes(monkeypatch, shape, "512:4:32")
     g = maze.Session(dev(s.charges), dev(s.pos), s.box, s.grid_spacing, **kw)
-    assert maze.maze_sstep_layout(g.handle) == {"basis": 8, "update": 0}
+    assert maze.maze_sstep_layout(g.handle) == {"basis": zv_waves(shape), "update": 0}
     # a segment-layout basis shape valid for the precision (the tuner may
     # pick either layout)
     force_shapes(monkeypatch, "512:2:64" if precision == 0 else "512:4:16", "512:4:32")
@@ -183,7 +183,8 @@ def test_zv_full_size_256(maze, monkeypatch, precision):
 
 # (n_cells, N, precision, tol, basis, update)
 BATCH = [(4, 64, 0, 1e-10, "zv:8:8", ""), (4, 64, 1, 1e-8, "zv:8:16", "512:2:16"),
-         (8, 128, 0, 1e-9, "zv:8:12", ""), (3, 48, 1, 1e-8, "", "")]
+         (8, 128, 0, 1e-9, "zv:8:12", ""), (3, 48, 1, 1e-8, "", ""),
+         (16, 256, 1, 1e-8, "zv:16:20", "512:4:32")]
 
 
 def _sessions(maze, monkeypatch, seed):
