@@ -294,13 +294,15 @@ int maze_basis_shape(const maze_session* s, int32_t* out4);
  * 128 or 256 the shape tuner also times a wavefront-row layout of the basis
  * kernel: each wavefront holds whole z rows (N / 64 consecutive points per
  * lane), takes its z neighbours from its own lanes and its y neighbours
- * from LDS, and a workgroup of W = 8 wavefronts covers W - 2 rows of the
- * plane (the stencil of Appendix B's matrix-vector product, unchanged).
+ * from LDS, and a workgroup of W wavefronts covers W - 2 rows of the
+ * plane (the stencil of Appendix B's matrix-vector product, unchanged);
+ * W = 8, and at N = 256 in mixed precision also W = 16.
  * out2 (HOST, 2 int32):
  * {wavefronts per workgroup of the basis kernel, of the update kernel}, 0
  * for the segment layout (the update kernel has no wavefront-row form, so
  * its entry is 0). In the wavefront-row layout maze_basis_shape's points
- * per thread is N / 64. MAZE_BASIS_SHAPE="zv:8:cx" forces one. */
+ * per thread is N / 64. MAZE_BASIS_SHAPE="zv:W:cx" (cx planes per x run)
+ * forces one. */
 int maze_sstep_layout(const maze_session* s, int32_t* out2);
 
 /* Residual trace of the last solve (for convergence studies such as the
