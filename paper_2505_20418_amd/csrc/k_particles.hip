@@ -655,6 +655,30 @@ __global__ __launch_bounds__(kThreads) void k_finalize(int mode, int count, long
       ctl_st(&sc->energy, 0.5 * coulomb_k * e);
       if (energy_out) *energy_out = 0.5 * coulomb_k * e;
     }
+  } else if (mode == FIN_INNER_FIRST) {
+    // The step's first inner solve decided on the device, as the host decides
+    // the later ones: converged already if the true residual of the
+    // right-hand side meets thr, else an inner tolerance of
+    // max(tol * residual, param * thr) (tol, param: the reduction and margin
+    // of the mixed refinement).
+    if (threadIdx.x == 0) {
+      const double thr = ctl_ld(&sc->thr);
+      const double res = (ctl_ld(&sc->norm) == MAZE_NORM_ABSMAX) ? ctl_ld(&sc->true_max)
+                                                                 : sqrt(ctl_ld(&sc->true_rr));
+      ctl_st(&sc->thr_outer, thr);
+      ctl_st(&sc->max_iter, imax);
+      ctl_st(&sc->itp[0], 0);
+      ctl_st(&sc->itp[1], 0);
+      ctl_st(&sc->pend, 0);
+      ctl_st(&sc->iters, 0);
+      if (res <= thr) {
+        ctl_st(&sc->done, 4);
+      } else {
+        const double a = tol * res, b = param * thr;
+        ctl_st(&sc->thr, (a < b) ? b : a);
+        ctl_st(&sc->done, 0);
+      }
+    }
   } else if (mode == FIN_INNER_START) {
     if (threadIdx.x == 0) {
       ctl_st(&sc->thr, param);

@@ -1100,19 +1100,90 @@ static int solve_multi(std::vector<maze_session*>& ss, std::vector<double*>& xs,
   for (int i = 0; i < n; ++i)
     if (ss[i]->cfg.precision == MAZE_MIXED && !is_mg[i]) act.push_back(i);
   if (act.empty()) return MAZE_OK;
-  std::vector<maze_session*> as;
-  for (int i : act) as.push_back(ss[i]);
   std::vector<Scalars> h;
-  int rc = gather_scalars(as, h);
-  if (rc != MAZE_OK) return rc;
   std::vector<double> thr(n, 0.0);
   std::vector<int> total(n, 0);
   std::vector<Scalars> hs(n);
-  for (size_t q = 0; q < act.size(); ++q) {
-    hs[act[q]] = h[q];
-    thr[act[q]] = h[q].thr;
+  int rc = MAZE_OK;
+  // After an inner solve of session i (job j): the FP64 correction and
+  // residual; returns whether another pass may follow.
+  auto after_pass = [&](int i, const CgJob& j, bool* more) -> int {
+    maze_session* s = ss[i];
+    *more = false;
+    if (j.err) {
+      rcs[i] = MAZE_E_NONFINITE;
+      return MAZE_OK;
+    }
+    const int it = j.iters;
+    s->last_inner[s->refinements] = it;
+    total[i] += it;
+    s->refinements += 1;
+    HIP_TRY(launch_add_correction(s->d, xs[i], s->stream));
+    HIP_TRY(launch_refine(s->d, s->geom, xs[i], true, s->stream));
+    HIP_TRY(launch_finalize(s->d, FIN_SOLVE_END, s->geom.nwg, 0.0, 0.0, 0.0, nullptr, 0, 0,
+                            s->stream));
+    *more = !(j.code == 2 && it == 0);  // breakdown without progress
+    return MAZE_OK;
+  };
+  // The first pass is decided on the device (FIN_INNER_FIRST, the same
+  // test and tolerance as below), so no host round trip precedes it, unless
+  // a session records a residual trace or allows no iteration.
+  bool dev_first = true;
+  for (int i : act)
+    if (ss[i]->trace || ss[i]->cfg.max_iter <= 0) dev_first = false;
+  if (dev_first) {
+    std::vector<CgJob> jobs;
+    int fb = 1 << 30;
+    for (int i : act) {
+      maze_session* s = ss[i];
+      s->trace_pass = 0;
+      HIP_TRY(launch_finalize(s->d, FIN_INNER_FIRST, 0, kInnerReduction, kInnerMargin, 0.0,
+                              nullptr, s->cfg.max_iter, s->cfg.residual_norm, s->stream));
+      CgJob j;
+      j.s = s;
+      j.x = s->d.e32;
+      j.max_iter = s->cfg.max_iter;
+      jobs.push_back(j);
+      fb = std::min(fb, first_batch_of(s->last_inner[0]));
+    }
+    rc = run_cg_batch(jobs, true, true, fb);
+    if (rc != MAZE_OK) return rc;
+    std::vector<int> keep;
+    std::vector<maze_session*> ks;
+    for (size_t q = 0; q < act.size(); ++q) {
+      const int i = act[q];
+      if (!jobs[q].err && jobs[q].code == 4) {  // the right-hand side's residual met thr
+        ss[i]->converged = 1;
+        continue;
+      }
+      bool more = false;
+      rc = after_pass(i, jobs[q], &more);
+      if (rc != MAZE_OK) return rc;
+      if (more) {
+        keep.push_back(i);
+        ks.push_back(ss[i]);
+      }
+    }
+    if (!ks.empty()) {
+      rc = gather_scalars(ks, h);
+      if (rc != MAZE_OK) return rc;
+    }
+    for (size_t q = 0; q < keep.size(); ++q) {
+      hs[keep[q]] = h[q];
+      thr[keep[q]] = h[q].thr_outer;
+    }
+    act = keep;
+  } else {
+    std::vector<maze_session*> as;
+    for (int i : act) as.push_back(ss[i]);
+    rc = gather_scalars(as, h);
+    if (rc != MAZE_OK) return rc;
+    for (size_t q = 0; q < act.size(); ++q) {
+      hs[act[q]] = h[q];
+      thr[act[q]] = h[q].thr;
+    }
   }
-  for (;;) {
+  while (!act.empty()) {
     std::vector<int> next;
     for (int i : act) {
       maze_session* s = ss[i];
@@ -1156,23 +1227,13 @@ static int solve_multi(std::vector<maze_session*>& ss, std::vector<double*>& xs,
     std::vector<int> keep;
     std::vector<maze_session*> ks;
     for (size_t q = 0; q < next.size(); ++q) {
-      const int i = next[q];
-      maze_session* s = ss[i];
-      if (jobs[q].err) {
-        rcs[i] = MAZE_E_NONFINITE;
-        continue;
+      bool more = false;
+      rc = after_pass(next[q], jobs[q], &more);
+      if (rc != MAZE_OK) return rc;
+      if (more) {
+        keep.push_back(next[q]);
+        ks.push_back(ss[next[q]]);
       }
-      const int it = jobs[q].iters;
-      s->last_inner[s->refinements] = it;
-      total[i] += it;
-      s->refinements += 1;
-      HIP_TRY(launch_add_correction(s->d, xs[i], s->stream));
-      HIP_TRY(launch_refine(s->d, s->geom, xs[i], true, s->stream));
-      HIP_TRY(launch_finalize(s->d, FIN_SOLVE_END, s->geom.nwg, 0.0, 0.0, 0.0, nullptr, 0, 0,
-                              s->stream));
-      if (jobs[q].code == 2 && it == 0) continue;  // breakdown without progress
-      keep.push_back(i);
-      ks.push_back(s);
     }
     if (keep.empty()) break;
     rc = gather_scalars(ks, h);

@@ -73,7 +73,9 @@ struct alignas(64) Scalars {
   double mg_rho;       // multigrid-preconditioned CG: <r, z>
   double mg_alpha;     // rho / <p, A p>
   double mg_beta;      // rho / rho of the previous iteration (0 first)
-  double pad[2];
+  double thr_outer;    // mixed step: the step's threshold, kept by
+                       // FIN_INNER_FIRST while thr holds the inner one
+  double pad[1];
 };
 
 // Geometry of a marching stencil launch: each workgroup owns a contiguous
@@ -205,6 +207,8 @@ enum FinalizeMode : int {
   FIN_SOLVE_END,     // xbar (from SL_XSUM), true residual
   FIN_ENERGY,        // energy from SL_ENERGY, writes energy_out
   FIN_INNER_START,   // mixed inner solve: thr from `param`, resets counters
+  FIN_INNER_FIRST,   // first inner solve of a mixed step: thr from the true
+                     // residual (done = 4 if it already meets thr)
   FIN_MG_CHECK0,     // multigrid CG: stopping test of the first residual
   FIN_MG_RHO,        // rho = <r, z>, beta (from SL_MGRZ)
   FIN_MG_MU,         // alpha = rho / <p, A p> (from SL_MU0)
