@@ -23,6 +23,8 @@
 // to a slot of the partial table. The next kernel sums the slot in a fixed
 // order (identically in every workgroup). No atomics anywhere, so results
 // are bitwise reproducible.
+#include <type_traits>
+
 #include "device_util.h"
 
 namespace maze {
@@ -44,8 +46,13 @@ MarchGeom make_march_geom(int N, int ppt, int cx) {
 // ---------------------------------------------------------------------------
 // The marching template.
 // Op supplies: T (LDS element type), K (staged fields), NACC (accumulators),
-//   skip(), prepare(sm) -> bool, load(g, T[K]), point(g, c, xm, xp, ym, yp,
-//   zm, zp, acc), acc_is_max(i), acc_slot(i), finish_wg0().
+//   KS (values of its own point that point() reads, 0 to 2), skip(),
+//   prepare(sm) -> bool, load(g, T[K]), side(g, double[KS]), point(g, c, xm,
+//   xp, ym, yp, zm, zp, sv, acc), acc_is_max(i), acc_slot(i), finish_wg0().
+// A plane step loads the side values of its own points first, then the
+// plane two ahead (the same loads on every lane: the halo addresses of idle
+// lanes are valid points), so that waiting for the side values leaves that
+// prefetch in flight while the points are formed.
 // ---------------------------------------------------------------------------
 template <int PPT, int NH, class Op>
 __global__ __launch_bounds__(kThreads) void march_kernel(Op op, MarchGeom g) {
@@ -154,23 +161,28 @@ __global__ __launch_bounds__(kThreads) void march_kernel(Op op, MarchGeom g) {
   }
   __syncthreads();
 
-  for (int x = x0; x < x1; ++x) {
+  constexpr int KS = Op::KS;
+  constexpr int KSA = KS > 0 ? KS : 1;
+  // one plane step; PC / PH: the centre / halo of plane x + 2 are loaded
+  auto step = [&](auto pc, auto ph, int x, T (&lc)[PPT][K], T (&lh)[NH][K])
+                  __attribute__((always_inline)) {
+    constexpr bool PC = decltype(pc)::value, PH = decltype(ph)::value;
     const int buf = (x - x0) & 1;
-    const bool need_c = (x + 2 <= x1);
-    const bool need_h = (x + 2 < x1);
-    T lc[PPT][K];
-    T lh[NH][K];
-    if (need_c) {
+    const long long bx = (long long)x * P;
+    double sv[PPT][KSA];
+    if constexpr (KS > 0) {
+#pragma unroll
+      for (int j = 0; j < PPT; ++j) op.side(bx + fl[j], sv[j]);
+    }
+    if constexpr (PC) {
       const long long b = pbase(x + 2);
 #pragma unroll
       for (int j = 0; j < PPT; ++j) op.load(b + fl[j], lc[j]);
-      if (need_h) {
+      if constexpr (PH) {
 #pragma unroll
-        for (int k = 0; k < NH; ++k)
-          if (hv[k]) op.load(b + hg[k], lh[k]);
+        for (int k = 0; k < NH; ++k) op.load(b + hg[k], lh[k]);
       }
     }
-    const long long bx = (long long)x * P;
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
       if (valid[j]) {
@@ -183,9 +195,22 @@ __global__ __launch_bounds__(kThreads) void march_kernel(Op op, MarchGeom g) {
           zm[f] = LDSAT(buf, f, ezm[j]);
           zp[f] = LDSAT(buf, f, ezp[j]);
         }
-        op.point(bx + fl[j], cur[j], prv[j], nxt[j], ym, yp, zm, zp, acc);
+        op.point(bx + fl[j], cur[j], prv[j], nxt[j], ym, yp, zm, zp, sv[j], acc);
       }
     }
+  };
+  using True = std::integral_constant<bool, true>;
+  using False = std::integral_constant<bool, false>;
+
+  for (int x = x0; x < x1; ++x) {
+    const int buf = (x - x0) & 1;
+    const bool need_c = (x + 2 <= x1);
+    const bool need_h = (x + 2 < x1);
+    T lc[PPT][K];
+    T lh[NH][K];
+    if (need_h) step(True{}, True{}, x, lc, lh);
+    else if (need_c) step(True{}, False{}, x, lc, lh);
+    else step(False{}, False{}, x, lc, lh);
     __syncthreads();
     if (need_h) {
 #pragma unroll
@@ -254,16 +279,18 @@ struct OpRhsMaze {
     qbar = ctl_ld(&sc->qbar);
     return true;
   }
+  static constexpr int KS = 1;
   __device__ void load(long long g, double v[2]) const {
     v[0] = 2.0 * phik[g] - phikm1[g];
     v[1] = y[g];
   }
+  __device__ void side(long long g, double sv[1]) const { sv[0] = q[g]; }
   __device__ void point(long long g, const double* c, const double* xm, const double* xp,
                         const double* ym, const double* yp, const double* zm,
-                        const double* zp, double* a) const {
+                        const double* zp, const double* sv, double* a) const {
     const double mphi = nbr_sum(xm[0], xp[0], ym[0], yp[0], zm[0], zp[0]) - 6.0 * c[0];
     const double my = nbr_sum(xm[1], xp[1], ym[1], yp[1], zm[1], zp[1]) - 6.0 * c[1];
-    const double qv = q[g] - qbar;
+    const double qv = sv[0] - qbar;
     const double s = c1 * mphi + qv;
     sigma[g] = s;
     const double rv = my - s;
@@ -321,15 +348,17 @@ struct OpRhsPoisson {
     qbar = ctl_ld(&sc->qbar);
     return true;
   }
+  static constexpr int KS = 1;
   __device__ void load(long long g, double v[1]) const {
     v[0] = (guess == MAZE_GUESS_ZERO) ? 0.0
          : (guess == MAZE_GUESS_STATIC) ? phik[g] : 2.0 * phik[g] - phikm1[g];
   }
+  __device__ void side(long long g, double sv[1]) const { sv[0] = q[g]; }
   __device__ void point(long long g, const double* c, const double* xm, const double* xp,
                         const double* ym, const double* yp, const double* zm,
-                        const double* zp, double* a) const {
+                        const double* zp, const double* sv, double* a) const {
     const double mx = nbr_sum(xm[0], xp[0], ym[0], yp[0], zm[0], zp[0]) - 6.0 * c[0];
-    const double s = c4 * (q[g] - qbar);
+    const double s = c4 * (sv[0] - qbar);
     sigma[g] = s;
     x[g] = c[0];
     const double rv = mx - s;
@@ -381,13 +410,15 @@ struct OpMgDir {
     beta = ctl_ld(&sc->mg_beta);
     return true;
   }
+  static constexpr int KS = 0;
   __device__ void load(long long g, double v[1]) const {
     const double zv = (double)z[g];
     v[0] = (beta == 0.0) ? zv : zv + beta * pold[g];
   }
+  __device__ void side(long long, double*) const {}
   __device__ void point(long long g, const double* c, const double* xm, const double* xp,
                         const double* ym, const double* yp, const double* zm, const double* zp,
-                        double* a) const {
+                        const double*, double* a) const {
     const double ap = 6.0 * c[0] - nbr_sum(xm[0], xp[0], ym[0], yp[0], zm[0], zp[0]);
     p[g] = c[0];
     a[0] += c[0] * ap;
@@ -417,13 +448,18 @@ struct OpMgUpd {
     alpha = ctl_ld(&sc->mg_alpha);
     return true;
   }
+  static constexpr int KS = 2;
   __device__ void load(long long g, double v[1]) const { v[0] = p[g]; }
+  __device__ void side(long long g, double sv[2]) const {
+    sv[0] = x[g];
+    sv[1] = r[g];
+  }
   __device__ void point(long long g, const double* c, const double* xm, const double* xp,
                         const double* ym, const double* yp, const double* zm, const double* zp,
-                        double* a) const {
+                        const double* sv, double* a) const {
     const double ap = 6.0 * c[0] - nbr_sum(xm[0], xp[0], ym[0], yp[0], zm[0], zp[0]);
-    x[g] += alpha * c[0];
-    const double rv = r[g] - alpha * ap;
+    x[g] = sv[0] + alpha * c[0];
+    const double rv = sv[1] - alpha * ap;
     r[g] = rv;
     a[0] += rv * rv;
     a[1] = fmax(a[1], fabs(rv));
@@ -453,11 +489,13 @@ struct OpResidual {
 
   __device__ bool skip() const { return ctl_ld(&sc->err) != 0; }
   __device__ bool prepare(double*) { return true; }
+  static constexpr int KS = 1;
   __device__ void load(long long g, double v[1]) const { v[0] = x[g]; }
+  __device__ void side(long long g, double sv[1]) const { sv[0] = s[g]; }
   __device__ void point(long long g, const double* c, const double* xm, const double* xp,
                         const double* ym, const double* yp, const double* zm,
-                        const double* zp, double* a) const {
-    const double rv = (nbr_sum(xm[0], xp[0], ym[0], yp[0], zm[0], zp[0]) - 6.0 * c[0]) - s[g];
+                        const double* zp, const double* sv, double* a) const {
+    const double rv = (nbr_sum(xm[0], xp[0], ym[0], yp[0], zm[0], zp[0]) - 6.0 * c[0]) - sv[0];
     a[0] += rv * rv;
     a[1] = fmax(a[1], fabs(rv));
     a[2] += c[0];
