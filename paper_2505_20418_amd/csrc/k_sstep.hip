@@ -443,9 +443,10 @@ __device__ __forceinline__ void sstep_wg(const SweepArgs<T>& a, const SweepGeom&
 
   const int nsteps = x1 - x0 + 2;  // stage U on planes x0-1 .. x1, in march order
   // Uniform memory operations: loads and stores issued alike at every step.
-  // Measured per 256^3 launch: the FP32 update kernel 80.8 -> 77.5 us; the
-  // FP64 update kernel, which then forms stage W on two more planes, 140.2
-  // -> 142.2 us, so it keeps the conditional form.
+  // Measured per 256^3 launch: the FP32 update kernel 80.8 -> 77.5 us (77.4
+  // with stage W skipped on the first two planes); the FP64 update kernel
+  // 140.2 -> 142.2 us (148.4 against 147.5 in the second form), so it keeps
+  // the conditional form.
   constexpr bool kUniformVm = !UPDATE || sizeof(T) == 4;
   // The compiler does not unroll a loop with a barrier and a run-time trip
   // count, so the plane windows rotate by register moves (about 20 per
@@ -498,7 +499,7 @@ __device__ __forceinline__ void sstep_wg(const SweepArgs<T>& a, const SweepGeom&
 
     // stage W at plane u-dir: B^2 p and B rhat on the segment, stored from
     // the third step on (plane u-dir then lies in [x0, x1)). With kUniformVm
-    // the update kernel forms it at every step and its stores before the
+    // the update kernel enters it at every step and its stores before the
     // third write nothing, so every step issues the same stores.
     if ((UPDATE && kUniformVm) || t >= 2) {
       const T2* QRr = QR + (tb ^ 1) * E2;
@@ -509,6 +510,10 @@ __device__ __forceinline__ void sstep_wg(const SweepArgs<T>& a, const SweepGeom&
       const auto po = pl_rsrc_if((const T*)p_out, uo, Ps, wr);
 #pragma unroll
       for (int j = 0; j < PPT; ++j) {
+        // the update kernel's first two steps store zeros that are dropped
+        // (nothing to form there)
+        T xn = (T)0, rn = (T)0, pnw = (T)0;
+        if (!UPDATE || wr) {
         const T y0 = pm[j];
         const T y1 = bc[j];
         T2 ym, yp;
@@ -546,16 +551,21 @@ __device__ __forceinline__ void sstep_wg(const SweepArgs<T>& a, const SweepGeom&
             acc[11] += d4 * d4;
             acc[kNm] = fmax(acc[kNm], fabs((double)rm1[j]));
           }
-        } else if (kUniformVm || cval[j]) {
-          const T xn = xc[j] + ((cx[0] * y0 + cx[1] * y1) + (cx[2] * y2 + cx[3] * y3) + cx[4] * y4);
-          const T rn = (cr[0] * y0 + cr[1] * y1) + (cr[2] * y2 + cr[3] * y3) + cr[4] * y4;
-          const T pnw = (cp[0] * y0 + cp[1] * y1) + (cp[2] * y2 + cp[3] * y3) + cp[4] * y4;
-          // a lane past the end of the grid stores out of the buffer's
-          // range, which drops it: no branch around the stores
-          const uint32_t so = cval[j] ? bo[j] : kDropOffset;
-          st<T>(xo, so, xn);
-          st<T>(ro, so, rn);
-          st<T>(po, so, pnw);
+        } else {
+          xn = xc[j] + ((cx[0] * y0 + cx[1] * y1) + (cx[2] * y2 + cx[3] * y3) + cx[4] * y4);
+          rn = (cr[0] * y0 + cr[1] * y1) + (cr[2] * y2 + cr[3] * y3) + cr[4] * y4;
+          pnw = (cp[0] * y0 + cp[1] * y1) + (cp[2] * y2 + cp[3] * y3) + cp[4] * y4;
+        }
+        }
+        if constexpr (UPDATE) {
+          if (kUniformVm || cval[j]) {
+            // with kUniformVm a lane past the end of the grid stores out of
+            // the buffer's range, which drops it: no branch around the stores
+            const uint32_t so = cval[j] ? bo[j] : kDropOffset;
+            st<T>(xo, so, xn);
+            st<T>(ro, so, rn);
+            st<T>(po, so, pnw);
+          }
         }
       }
     }
