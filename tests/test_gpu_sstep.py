@@ -472,3 +472,34 @@ def test_sstep_tuned_shapes_are_cached(maze):
     assert ra["status"] == 0 and torch.equal(ra["forces"], rb["forces"])
     a.close()
     b.close()
+
+
+@pytest.mark.parametrize("tol", [1e-9, 0.5])
+def test_first_pass_on_device_matches_host_decided(maze, tol):
+    """A mixed step sets its first FP32 pass up on the device; a session that
+    records a residual trace decides it on the host. Both take the same test
+    and inner tolerance, so the steps agree bit for bit. At tol 0.5 the
+    right-hand side's residual already meets the threshold (no pass)."""
+    s = inputs.molten_nacl(4, seed=13)
+    print(f"case: first pass on device against host, nacl 512 ions tol {tol}", flush=True)
+    kw = dict(tol=tol, precision=maze.MAZE_MIXED, flags=maze.MAZE_FLAG_SSTEP)
+    a = maze.Session(dev(s.charges), dev(s.pos), s.box, s.grid_spacing, **kw)
+    b = maze.Session(dev(s.charges), dev(s.pos), s.box, s.grid_spacing, **kw)
+    maze.maze_trace_enable(b.handle, True)
+    passes = []
+    for k in range(3):
+        p = dev(s.pos + (k + 1) * s.vel)
+        x, y = a.step(p, want_field=True), b.step(p, want_field=True)
+        assert x["status"] == maze.MAZE_OK and y["status"] == maze.MAZE_OK, k
+        assert x["stats"]["iters"] == y["stats"]["iters"], k
+        assert x["stats"]["refinements"] == y["stats"]["refinements"], k
+        assert torch.equal(x["field"], y["field"]), k
+        assert torch.equal(x["forces"], y["forces"]), k
+        passes.append(x["stats"]["refinements"])
+    print(f"  passes per step {passes}", flush=True)
+    if tol == 0.5:
+        assert passes == [0, 0, 0]
+    else:
+        assert min(passes) >= 1
+    a.close()
+    b.close()
