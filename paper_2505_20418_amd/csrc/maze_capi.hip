@@ -349,17 +349,20 @@ static int first_batch_of(int last_iters) {
 }
 
 // CG units queued between polls: sweeps, or two-iteration outer steps.
-// Enough for about 100 us of device work (a unit moves 24-64 B per point at
-// some 5 TB/s, plus about 10 us of launch and reduction latency), so the
-// device stays busy through the host's poll; no more, because the units
-// queued after convergence run for nothing (at 256^3 a group of four outer
-// steps left about eight such launches per solve).
+// Enough for about 100 us (sweeps) or 200 us (outer steps) of device work (a
+// unit moves 24-64 B per point at some 5 TB/s, plus about 10 us of launch
+// and reduction latency), so the device stays busy through the host's poll;
+// no more, because the units queued after convergence run for nothing (at
+// 256^3 a group of four outer steps left about eight such launches per
+// solve). At 256^3 the FP32 outer steps go two to a group instead of one
+// (mixed MD steps/s 64.55 -> 64.68; FP64 outer steps stay one to a group).
 static int poll_units(const maze_session* s, bool fp32) {
   const bool ss = sstep_of(s);
   const double bytes = (ss ? 32.0 : 24.0) * (fp32 ? 1.0 : 2.0);
   const double unit_us = (double)s->d.G * bytes / 5.0e6 + 10.0;
   const int cap = ss ? kPollBatch / 2 : kPollBatch;
-  return std::max(1, std::min(cap, (int)std::ceil(100.0 / unit_us)));
+  const double target_us = ss ? 200.0 : 100.0;
+  return std::max(1, std::min(cap, (int)std::ceil(target_us / unit_us)));
 }
 
 // Unit k of a solve: sweep k, or outer step k of the two-iteration form.
